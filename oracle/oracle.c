@@ -1,0 +1,598 @@
+/*
+ * CPU oracle for the GATE search path (test infrastructure only).
+ *
+ * This file is a plain, slow, deliberately unoptimised restatement of what the
+ * search path computes.  It is compiled with -O2 -ffp-contract=off so that
+ * every FP64 expression is evaluated exactly as written (no fused
+ * multiply-add).  Only the test suite, the smoke check and the benchmark's CPU
+ * baseline load it; the product library never does, and the two share no
+ * code.  OpenMP is used only across independent queries / rows, never inside a
+ * reduction.
+ *
+ * Conventions
+ *  - squared L2 distance d2(x,y) = sum_j (x_j - y_j)^2 in FP64, j ascending
+ *    (the l2 distance of the notation table; squaring is monotone so every
+ *    ranking is the one the paper's delta induces);
+ *  - every ordering is by the key (value, id): ties go to the smaller id;
+ *  - graphs are N x R int32 rows, -1 marks an empty slot.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef int32_t i32;
+typedef int64_t i64;
+
+/* ------------------------------------------------------------------------ */
+/* Distances (notation table: delta is l2).                                  */
+
+static double d2(const float *x, const float *y, int d)
+{
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double t = (double)x[j] - (double)y[j];
+        s = s + t * t;
+    }
+    return s;
+}
+
+static double d2_mixed(const float *x, const double *mu, int d)
+{
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double t = (double)x[j] - mu[j];
+        s = s + t * t;
+    }
+    return s;
+}
+
+double oracle_sqdist(const float *x, const float *y, int d) { return d2(x, y, d); }
+
+/* key order: (value, id) */
+static int key_less(double a, i32 ia, double b, i32 ib)
+{
+    return a < b || (a == b && ia < ib);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact k nearest neighbours (recall definition, Eq. 1; graph candidates).  */
+/* For query i: all N distances, the k smallest keys (d2, id) in order.       */
+/* exclude_self != 0 means query i is base row i and id i is skipped.          */
+
+void oracle_knn(const float *base, i64 n, int d, const float *q, i64 nq, int k,
+                int exclude_self, i32 *out_ids, double *out_d2)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (i64 i = 0; i < nq; ++i) {
+        i32 *ids = out_ids + i * k;
+        double *dd = out_d2 + i * k;
+        int cnt = 0;
+        for (i64 p = 0; p < n; ++p) {
+            if (exclude_self && p == i) continue;
+            double v = d2(q + i * d, base + p * d, d);
+            if (cnt == k && !key_less(v, (i32)p, dd[k - 1], ids[k - 1])) continue;
+            int pos = cnt < k ? cnt : k - 1;
+            while (pos > 0 && key_less(v, (i32)p, dd[pos - 1], ids[pos - 1])) {
+                dd[pos] = dd[pos - 1];
+                ids[pos] = ids[pos - 1];
+                --pos;
+            }
+            dd[pos] = v;
+            ids[pos] = (i32)p;
+            if (cnt < k) ++cnt;
+        }
+        for (int t = cnt; t < k; ++t) { ids[t] = -1; dd[t] = INFINITY; }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alpha-RNG pruning of a sorted candidate list (the triangle-inequality     */
+/* pruning that NSG/MRNG uses; alpha = 1 is the MRNG rule).                   */
+/* Candidate c survives iff no already kept o has alpha^2 * d2(o,c) <= d2(p,c) */
+/* where alpha^2 is formed in FP64 from the FP32 alpha.  At most R-2 are kept; */
+/* slots R-2 and R-1 stay -1 (they are reserved for connectivity repair).      */
+
+void oracle_alpha_prune(const float *base, i64 n, int d, const i32 *cand,
+                        const double *cand_d2, int K, int R, float alpha, i32 *graph)
+{
+    (void)n;
+    const double a2 = (double)alpha * (double)alpha;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (i64 p = 0; p < n; ++p) {
+        i32 *row = graph + p * R;
+        for (int s = 0; s < R; ++s) row[s] = -1;
+        int kept = 0;
+        for (int t = 0; t < K && kept < R - 2; ++t) {
+            i32 c = cand[p * K + t];
+            if (c < 0) break;
+            double dpc = cand_d2[p * K + t];
+            int dominated = 0;
+            for (int u = 0; u < kept && !dominated; ++u) {
+                double doc = d2(base + (i64)row[u] * d, base + (i64)c * d, d);
+                if (a2 * doc <= dpc) dominated = 1;
+            }
+            if (!dominated) row[kept++] = c;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Medoid: the base point nearest the dataset mean.  The mean is the FP64     */
+/* column sum (taken in row order) divided by n; distances to it are FP64 in  */
+/* j order.  argmin over (d2, id).                                            */
+
+static void column_mean(const float *base, i64 n, int d, const i32 *rows, i64 nrows,
+                        double *mu)
+{
+    for (int j = 0; j < d; ++j) mu[j] = 0.0;
+    for (i64 r = 0; r < nrows; ++r) {
+        const float *x = base + (i64)(rows ? rows[r] : r) * d;
+        for (int j = 0; j < d; ++j) mu[j] = mu[j] + (double)x[j];
+    }
+    for (int j = 0; j < d; ++j) mu[j] = mu[j] / (double)nrows;
+    (void)n;
+}
+
+i32 oracle_medoid(const float *base, i64 n, int d)
+{
+    double *mu = (double *)malloc(sizeof(double) * d);
+    column_mean(base, n, d, NULL, n, mu);
+    double best = INFINITY;
+    i32 bi = -1;
+    for (i64 i = 0; i < n; ++i) {
+        double v = d2_mixed(base + i * d, mu, d);
+        if (bi < 0 || key_less(v, (i32)i, best, bi)) { best = v; bi = (i32)i; }
+    }
+    free(mu);
+    return bi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Connectivity repair.  The paper relies on NSG's connectivity but does not */
+/* say how it is obtained; this is the repair the kNN + alpha graph needs.     */
+/*  forward: BFS from the medoid; while a node is unreached take the smallest */
+/*           unreached id u, link it from the reached node v with slot R-2    */
+/*           still empty that minimises (d2(u,v), v), continue the BFS from u. */
+/*  reverse: BFS over reversed edges from the medoid; while a node w cannot   */
+/*           reach the medoid (smallest id first), link w -> t where t        */
+/*           minimises (d2(w,t), t) over the nodes that can reach it.          */
+/* Returns the number of forward and reverse bridges through the pointers.    */
+
+static void bfs_from(const i32 *graph, i64 n, int R, i32 src, unsigned char *mark,
+                     i32 *queue)
+{
+    if (mark[src]) return;
+    i64 head = 0, tail = 0;
+    mark[src] = 1;
+    queue[tail++] = src;
+    while (head < tail) {
+        i32 v = queue[head++];
+        for (int s = 0; s < R; ++s) {
+            i32 w = graph[(i64)v * R + s];
+            if (w >= 0 && !mark[w]) { mark[w] = 1; queue[tail++] = w; }
+        }
+    }
+    (void)n;
+}
+
+/* reverse adjacency in CSR form */
+static void reverse_csr(const i32 *graph, i64 n, int R, i64 **off_out, i32 **adj_out)
+{
+    i64 *off = (i64 *)calloc((size_t)n + 1, sizeof(i64));
+    for (i64 v = 0; v < n; ++v)
+        for (int s = 0; s < R; ++s) {
+            i32 w = graph[v * R + s];
+            if (w >= 0) off[w + 1]++;
+        }
+    for (i64 v = 0; v < n; ++v) off[v + 1] += off[v];
+    i32 *adj = (i32 *)malloc(sizeof(i32) * (size_t)(off[n] > 0 ? off[n] : 1));
+    i64 *fill = (i64 *)malloc(sizeof(i64) * (size_t)n);
+    for (i64 v = 0; v < n; ++v) fill[v] = off[v];
+    for (i64 v = 0; v < n; ++v)
+        for (int s = 0; s < R; ++s) {
+            i32 w = graph[v * R + s];
+            if (w >= 0) adj[fill[w]++] = (i32)v;
+        }
+    free(fill);
+    *off_out = off;
+    *adj_out = adj;
+}
+
+static void rbfs_from(const i64 *off, const i32 *adj, i32 src, unsigned char *mark,
+                      i32 *queue)
+{
+    if (mark[src]) return;
+    i64 head = 0, tail = 0;
+    mark[src] = 1;
+    queue[tail++] = src;
+    while (head < tail) {
+        i32 v = queue[head++];
+        for (i64 e = off[v]; e < off[v + 1]; ++e) {
+            i32 w = adj[e];
+            if (!mark[w]) { mark[w] = 1; queue[tail++] = w; }
+        }
+    }
+}
+
+void oracle_repair(const float *base, i64 n, int d, i32 *graph, int R, i32 medoid,
+                   i32 *n_forward, i32 *n_reverse)
+{
+    unsigned char *mark = (unsigned char *)calloc((size_t)n, 1);
+    i32 *queue = (i32 *)malloc(sizeof(i32) * (size_t)n);
+    int nf = 0, nr = 0;
+
+    bfs_from(graph, n, R, medoid, mark, queue);
+    for (i64 u = 0; u < n; ++u) {
+        if (mark[u]) continue;
+        double best = INFINITY;
+        i32 bv = -1;
+        for (i64 v = 0; v < n; ++v) {
+            if (!mark[v] || graph[v * R + (R - 2)] >= 0) continue;
+            double t = d2(base + u * d, base + v * d, d);
+            if (bv < 0 || key_less(t, (i32)v, best, bv)) { best = t; bv = (i32)v; }
+        }
+        graph[(i64)bv * R + (R - 2)] = (i32)u;
+        ++nf;
+        bfs_from(graph, n, R, (i32)u, mark, queue);
+    }
+
+    i64 *off;
+    i32 *adj;
+    reverse_csr(graph, n, R, &off, &adj);
+    memset(mark, 0, (size_t)n);
+    rbfs_from(off, adj, medoid, mark, queue);
+    for (i64 w = 0; w < n; ++w) {
+        if (mark[w]) continue;
+        double best = INFINITY;
+        i32 bt = -1;
+        for (i64 t = 0; t < n; ++t) {
+            if (!mark[t]) continue;
+            double v = d2(base + w * d, base + t * d, d);
+            if (bt < 0 || key_less(v, (i32)t, best, bt)) { best = v; bt = (i32)t; }
+        }
+        graph[w * R + (R - 1)] = bt;
+        ++nr;
+        /* everything that reaches w now reaches the medoid through w -> bt */
+        rbfs_from(off, adj, (i32)w, mark, queue);
+    }
+    free(off);
+    free(adj);
+    free(mark);
+    free(queue);
+    *n_forward = nf;
+    *n_reverse = nr;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Best-first (beam) search, Algorithm 1 read as the standard bounded-pool    */
+/* search: a candidate pool of at most L entries kept sorted by (d2, id); the */
+/* first k pool entries are the result.  Each loop step expands the best     */
+/* not yet expanded pool entry; each of its neighbours not seen before is     */
+/* marked visited, its distance computed (one distance computation, "ndc"),  */
+/* and it enters the pool if the pool has room or it beats the last entry.    */
+/* The search stops when every pool entry has been expanded.                  */
+/*                                                                            */
+/* Optional outputs:                                                          */
+/*   stats[3*i..]  ndc, hops, ndc_hit (see below)                             */
+/*   trace[i*trace_cap ..] the ids expanded, in order (-1 padded)             */
+/*   visited_out[i*n ..] 0/1 per node (tiny inputs only)                      */
+/* Label support: if truth != NULL (nq x kt ids), ndc_hit is the value of ndc */
+/* right after the c_hit-th id of truth[i] had its distance computed (-1 if  */
+/* that never happens).                                                       */
+
+typedef struct { double v; i32 id; int expanded; } entry_t;
+
+static void search_one(const float *base, i64 n, int d, const i32 *graph, int R,
+                       const float *q, i32 entry, int k, int L, int k_max,
+                       i32 *out_ids, double *out_d2, i64 *stats, i32 *trace,
+                       int trace_cap, unsigned char *visited, const i32 *truth,
+                       int kt, int c_hit, unsigned char *visited_out)
+{
+    entry_t *pool = (entry_t *)malloc(sizeof(entry_t) * (size_t)(L + 1));
+    i32 *touched = (i32 *)malloc(sizeof(i32) * 1024);
+    i64 touched_cap = 1024, ntouched = 0;
+    int cnt = 0;
+    i64 ndc = 0, hops = 0, ndc_hit = -1, hits = 0;
+
+#define VISIT(id_)                                                              \
+    do {                                                                        \
+        visited[(id_)] = 1;                                                     \
+        if (ntouched == touched_cap) {                                          \
+            touched_cap *= 2;                                                   \
+            touched = (i32 *)realloc(touched, sizeof(i32) * (size_t)touched_cap);\
+        }                                                                       \
+        touched[ntouched++] = (id_);                                            \
+    } while (0)
+
+    /* entry */
+    VISIT(entry);
+    pool[0].v = d2(q, base + (i64)entry * d, d);
+    pool[0].id = entry;
+    pool[0].expanded = 0;
+    cnt = 1;
+    ndc = 1;
+    if (truth) {
+        for (int t = 0; t < kt; ++t)
+            if (truth[t] == entry) { ++hits; break; }
+        if (hits >= c_hit && ndc_hit < 0) ndc_hit = ndc;
+    }
+
+    for (;;) {
+        int pi = -1;
+        for (int t = 0; t < cnt; ++t)
+            if (!pool[t].expanded) { pi = t; break; }
+        if (pi < 0) break;
+        pool[pi].expanded = 1;
+        i32 p = pool[pi].id;
+        if (trace && hops < trace_cap) trace[hops] = p;
+        ++hops;
+        for (int s = 0; s < R; ++s) {
+            i32 nb = graph[(i64)p * R + s];
+            if (nb < 0 || visited[nb]) continue;
+            VISIT(nb);
+            double v = d2(q, base + (i64)nb * d, d);
+            ++ndc;
+            if (truth) {
+                for (int t = 0; t < kt; ++t)
+                    if (truth[t] == nb) { ++hits; break; }
+                if (hits >= c_hit && ndc_hit < 0) ndc_hit = ndc;
+            }
+            if (cnt < L || key_less(v, nb, pool[cnt - 1].v, pool[cnt - 1].id)) {
+                int pos = cnt < L ? cnt : L - 1;
+                while (pos > 0 && key_less(v, nb, pool[pos - 1].v, pool[pos - 1].id)) {
+                    pool[pos] = pool[pos - 1];
+                    --pos;
+                }
+                pool[pos].v = v;
+                pool[pos].id = nb;
+                pool[pos].expanded = 0;
+                if (cnt < L) ++cnt;
+            }
+        }
+    }
+#undef VISIT
+    for (int t = 0; t < k_max; ++t) {
+        if (t < k && t < cnt) { out_ids[t] = pool[t].id; out_d2[t] = pool[t].v; }
+        else { out_ids[t] = -1; out_d2[t] = INFINITY; }
+    }
+    if (stats) { stats[0] = ndc; stats[1] = hops; stats[2] = ndc_hit; }
+    if (trace)
+        for (i64 t = hops; t < trace_cap; ++t) trace[t] = -1;
+    if (visited_out)
+        for (i64 t = 0; t < ntouched; ++t) visited_out[touched[t]] = 1;
+    for (i64 t = 0; t < ntouched; ++t) visited[touched[t]] = 0;
+    free(touched);
+    free(pool);
+    (void)n;
+}
+
+void oracle_search(const float *base, i64 n, int d, const i32 *graph, int R,
+                   const float *queries, i64 nq, const i32 *entry, const i32 *k,
+                   const i32 *L, int k_max, i32 *out_ids, double *out_d2, i64 *stats,
+                   i32 *trace, int trace_cap, const i32 *truth, int kt, int c_hit,
+                   unsigned char *visited_out, int n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel
+    {
+        unsigned char *visited = (unsigned char *)calloc((size_t)n, 1);
+#pragma omp for schedule(dynamic, 1)
+        for (i64 i = 0; i < nq; ++i) {
+            search_one(base, n, d, graph, R, queries + i * d, entry[i], k[i], L[i],
+                       k_max, out_ids + i * k_max, out_d2 + i * k_max,
+                       stats ? stats + 3 * i : NULL, trace ? trace + i * trace_cap : NULL,
+                       trace_cap, visited, truth ? truth + i * kt : NULL, kt, c_hit,
+                       visited_out ? visited_out + i * n : NULL);
+        }
+        free(visited);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hub nodes (Definition 3) on Lloyd k-means clusters.                       */
+/* init_ids: the n_h starting centroids (given, so both sides start alike).  */
+/* Per iteration: assign every point to argmin_c (d2(x, mu_c), c) [FP64, j   */
+/* order]; mu_c = FP64 member sum (in id order) / count, an empty cluster    */
+/* keeps its centroid; stop once an assignment step changes nothing.        */
+/* Hub of cluster c = argmin over members of (d2(x, mu_c), id); an empty     */
+/* cluster takes the nearest point that is not yet a hub (cluster order).    */
+/* Returns the number of assignment steps run.                               */
+
+int oracle_kmeans_hubs(const float *base, i64 n, int d, int nh, int iters,
+                       const i32 *init_ids, i32 *hub_ids, double *centroids,
+                       i32 *assign, double *objective)
+{
+    double *mu = centroids;
+    for (int c = 0; c < nh; ++c)
+        for (int j = 0; j < d; ++j)
+            mu[(i64)c * d + j] = (double)base[(i64)init_ids[c] * d + j];
+    for (i64 i = 0; i < n; ++i) assign[i] = -1;
+    i64 *count = (i64 *)malloc(sizeof(i64) * nh);
+    double *sum = (double *)malloc(sizeof(double) * (size_t)nh * d);
+    int steps = 0;
+    for (int t = 0; t < iters; ++t) {
+        int changed = 0;
+        double obj = 0.0;
+#pragma omp parallel for schedule(static) reduction(| : changed)
+        for (i64 i = 0; i < n; ++i) {
+            double best = INFINITY;
+            int bc = -1;
+            for (int c = 0; c < nh; ++c) {
+                double v = d2_mixed(base + i * d, mu + (i64)c * d, d);
+                if (bc < 0 || key_less(v, c, best, bc)) { best = v; bc = c; }
+            }
+            if (assign[i] != bc) { changed = 1; assign[i] = bc; }
+        }
+        ++steps;
+        /* objective of this assignment w.r.t. the centroids it used */
+        for (i64 i = 0; i < n; ++i) obj += d2_mixed(base + i * d, mu + (i64)assign[i] * d, d);
+        if (objective) objective[t] = obj;
+        memset(count, 0, sizeof(i64) * nh);
+        memset(sum, 0, sizeof(double) * (size_t)nh * d);
+        for (i64 i = 0; i < n; ++i) {
+            int c = assign[i];
+            count[c]++;
+            for (int j = 0; j < d; ++j) sum[(i64)c * d + j] = sum[(i64)c * d + j] + (double)base[i * d + j];
+        }
+        for (int c = 0; c < nh; ++c)
+            if (count[c] > 0)
+                for (int j = 0; j < d; ++j) mu[(i64)c * d + j] = sum[(i64)c * d + j] / (double)count[c];
+        if (!changed) break;
+    }
+    /* hubs */
+    double *best = (double *)malloc(sizeof(double) * nh);
+    for (int c = 0; c < nh; ++c) { hub_ids[c] = -1; best[c] = INFINITY; }
+    for (i64 i = 0; i < n; ++i) {
+        int c = assign[i];
+        double v = d2_mixed(base + i * d, mu + (i64)c * d, d);
+        if (hub_ids[c] < 0 || key_less(v, (i32)i, best[c], hub_ids[c])) { best[c] = v; hub_ids[c] = (i32)i; }
+    }
+    unsigned char *is_hub = (unsigned char *)calloc((size_t)n, 1);
+    for (int c = 0; c < nh; ++c) if (hub_ids[c] >= 0) is_hub[hub_ids[c]] = 1;
+    for (int c = 0; c < nh; ++c) {
+        if (hub_ids[c] >= 0) continue;
+        double bv = INFINITY;
+        i32 bi = -1;
+        for (i64 i = 0; i < n; ++i) {
+            if (is_hub[i]) continue;
+            double v = d2_mixed(base + i * d, mu + (i64)c * d, d);
+            if (bi < 0 || key_less(v, (i32)i, bv, bi)) { bv = v; bi = (i32)i; }
+        }
+        hub_ids[c] = bi;
+        is_hub[bi] = 1;
+    }
+    free(is_hub);
+    free(best);
+    free(count);
+    free(sum);
+    return steps;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Navigation graph over hubs: each hub links to the s hubs of largest        */
+/* cosine similarity (self excluded), ordered by (-cos, index).  emb rows are */
+/* already unit-normalised, so the cosine is the FP64 dot product.            */
+
+void oracle_hub_graph(const float *emb, int nh, int e, int s, i32 *hg)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nh; ++i) {
+        i32 *row = hg + (i64)i * s;
+        double *val = (double *)malloc(sizeof(double) * s);
+        int cnt = 0;
+        for (int j = 0; j < nh; ++j) {
+            if (j == i) continue;
+            double v = 0.0;
+            for (int t = 0; t < e; ++t) v = v + (double)emb[(i64)i * e + t] * (double)emb[(i64)j * e + t];
+            double key = -v;
+            if (cnt == s && !key_less(key, j, val[s - 1], row[s - 1])) continue;
+            int pos = cnt < s ? cnt : s - 1;
+            while (pos > 0 && key_less(key, j, val[pos - 1], row[pos - 1])) {
+                val[pos] = val[pos - 1];
+                row[pos] = row[pos - 1];
+                --pos;
+            }
+            val[pos] = key;
+            row[pos] = j;
+            if (cnt < s) ++cnt;
+        }
+        for (int t = cnt; t < s; ++t) row[t] = -1;
+        free(val);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Entry selection over the hub navigation graph: the bounded-pool search    */
+/* above, run on the hub graph with key (-cos(e_q, e_h), h), entered at the  */
+/* hub-medoid (the hub of largest cosine with the normalised mean of the hub  */
+/* embeddings).  The best hub's base id is the entry point, unless its cosine */
+/* is below theta, in which case the medoid is used.                          */
+
+static double neg_dot(const float *a, const float *b, int e)
+{
+    double v = 0.0;
+    for (int t = 0; t < e; ++t) v = v + (double)a[t] * (double)b[t];
+    return -v;
+}
+
+i32 oracle_hub_medoid(const float *emb, int nh, int e)
+{
+    double *m = (double *)calloc((size_t)e, sizeof(double));
+    for (int i = 0; i < nh; ++i)
+        for (int t = 0; t < e; ++t) m[t] = m[t] + (double)emb[(i64)i * e + t];
+    double nrm = 0.0;
+    for (int t = 0; t < e; ++t) nrm = nrm + m[t] * m[t];
+    nrm = sqrt(nrm);
+    double best = INFINITY;
+    i32 bi = -1;
+    for (int i = 0; i < nh; ++i) {
+        double v = 0.0;
+        for (int t = 0; t < e; ++t) v = v + (double)emb[(i64)i * e + t] * (m[t] / nrm);
+        double key = -v;
+        if (bi < 0 || key_less(key, i, best, bi)) { best = key; bi = i; }
+    }
+    free(m);
+    return bi;
+}
+
+void oracle_entry_select(const float *qemb, i64 nq, const float *hemb, int nh, int e,
+                         const i32 *hg, int s, const i32 *hub_ids, i32 hub_entry,
+                         int Lh, double theta, i32 medoid, i32 *entry_ids,
+                         double *entry_score, i32 *best_hub)
+{
+#pragma omp parallel
+    {
+        entry_t *pool = (entry_t *)malloc(sizeof(entry_t) * (size_t)(Lh + 1));
+        unsigned char *vis = (unsigned char *)malloc((size_t)nh);
+#pragma omp for schedule(dynamic, 16)
+        for (i64 qi = 0; qi < nq; ++qi) {
+            const float *q = qemb + qi * e;
+            memset(vis, 0, (size_t)nh);
+            int cnt = 0;
+            vis[hub_entry] = 1;
+            pool[0].v = neg_dot(q, hemb + (i64)hub_entry * e, e);
+            pool[0].id = hub_entry;
+            pool[0].expanded = 0;
+            cnt = 1;
+            for (;;) {
+                int pi = -1;
+                for (int t = 0; t < cnt; ++t) if (!pool[t].expanded) { pi = t; break; }
+                if (pi < 0) break;
+                pool[pi].expanded = 1;
+                i32 p = pool[pi].id;
+                for (int u = 0; u < s; ++u) {
+                    i32 nb = hg[(i64)p * s + u];
+                    if (nb < 0 || vis[nb]) continue;
+                    vis[nb] = 1;
+                    double v = neg_dot(q, hemb + (i64)nb * e, e);
+                    if (cnt < Lh || key_less(v, nb, pool[cnt - 1].v, pool[cnt - 1].id)) {
+                        int pos = cnt < Lh ? cnt : Lh - 1;
+                        while (pos > 0 && key_less(v, nb, pool[pos - 1].v, pool[pos - 1].id)) {
+                            pool[pos] = pool[pos - 1];
+                            --pos;
+                        }
+                        pool[pos].v = v;
+                        pool[pos].id = nb;
+                        pool[pos].expanded = 0;
+                        if (cnt < Lh) ++cnt;
+                    }
+                }
+            }
+            double cosv = -pool[0].v;
+            best_hub[qi] = pool[0].id;
+            entry_score[qi] = cosv;
+            entry_ids[qi] = (cosv < theta) ? medoid : hub_ids[pool[0].id];
+        }
+        free(vis);
+        free(pool);
+    }
+}

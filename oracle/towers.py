@@ -1,0 +1,120 @@
+"""Two-tower entry model, contrastive loss and Adam in NumPy float64
+(test infrastructure only).
+
+Model (two-tower score, Preliminaries; projection network of the high-tier
+graph section): each tower is a two-layer MLP with ReLU whose output is
+L2-normalised, so the score of a query/hub pair is their cosine.
+
+    tower(x) = normalise( W2 . relu(W1 . x + b1) + b2 )
+
+The query tower reads the query vector; the hub tower reads the hub vector
+concatenated with its topology features.  Loss: the contrastive objective of
+Eq. 2 / Eq. 4 taken query-anchored over all hubs, with the positive inside the
+denominator (standard InfoNCE):
+
+    L = (1/B) sum_i [ logsumexp_h(s_ih) - s_i,y_i ],  s_ih = <e_q_i, e_h> / tau
+
+BF16 reading: weights are held as FP32 masters; each matrix product takes its
+two operands rounded to bfloat16 (round to nearest even) and accumulates in
+higher precision (here FP64).  The operands that are rounded are: the weights,
+the tower input, the hidden activation after ReLU and, in the backward pass,
+the pre-activation gradients that enter the weight/input products.  Bias adds,
+ReLU, normalisation, the logits and softmax stay unrounded.  With
+``bf16=False`` every rounding is the identity (used for finite differences).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest bfloat16 value (ties to even), returned as float64.
+
+    Works from the float64 value: bfloat16 keeps 8 significant bits, so the
+    value is rounded at 2**(e-7) where 2**e <= |x| < 2**(e+1)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = (x != 0) & np.isfinite(x)
+    m, e = np.frexp(x[nz])            # x = m * 2**e, 0.5 <= |m| < 1
+    # 8 significant bits: scale mantissa to [128, 256)
+    scaled = m * 256.0
+    r = np.round(scaled)              # numpy rounds half to even
+    out[nz] = np.ldexp(r, e - 8)
+    out[~nz] = x[~nz]
+    return out
+
+
+def _rnd(x, bf16):
+    return bf16_round(x) if bf16 else np.asarray(x, dtype=np.float64)
+
+
+def tower_forward(params, x, bf16=True):
+    """params = (W1 [h x din], b1 [h], W2 [e x h], b2 [e]) float32 masters.
+
+    Returns (e_hat [n x e], cache)."""
+    W1, b1, W2, b2 = [np.asarray(p, np.float64) for p in params]
+    W1r, W2r = _rnd(W1, bf16), _rnd(W2, bf16)
+    xr = _rnd(x, bf16)
+    z1 = xr @ W1r.T + b1
+    a1 = np.maximum(z1, 0.0)
+    a1r = _rnd(a1, bf16)
+    z2 = a1r @ W2r.T + b2
+    nrm = np.sqrt(np.sum(z2 * z2, axis=1, keepdims=True))
+    e = z2 / nrm
+    return e, dict(xr=xr, z1=z1, a1r=a1r, z2=z2, nrm=nrm, e=e, W1r=W1r, W2r=W2r)
+
+
+def tower_backward(cache, de, bf16=True):
+    """Gradient of the tower parameters given dL/d e_hat.  Returns
+    (dW1, db1, dW2, db2)."""
+    e, nrm = cache["e"], cache["nrm"]
+    # d/dz of z/|z|: (de - e <e, de>) / |z|
+    dz2 = (de - e * np.sum(e * de, axis=1, keepdims=True)) / nrm
+    dz2r = _rnd(dz2, bf16)
+    dW2 = dz2r.T @ cache["a1r"]
+    db2 = dz2.sum(axis=0)
+    da1 = dz2r @ cache["W2r"]
+    dz1 = da1 * (cache["z1"] > 0)
+    dz1r = _rnd(dz1, bf16)
+    dW1 = dz1r.T @ cache["xr"]
+    db1 = dz1.sum(axis=0)
+    return dW1, db1, dW2, db2
+
+
+def infonce(eq, eh, labels, tau):
+    """Loss and gradients w.r.t. both embedding sets."""
+    s = (eq @ eh.T) / tau
+    smax = s.max(axis=1, keepdims=True)
+    ex = np.exp(s - smax)
+    den = ex.sum(axis=1, keepdims=True)
+    lse = np.log(den) + smax
+    B = eq.shape[0]
+    loss = float(np.mean(lse[:, 0] - s[np.arange(B), labels]))
+    p = ex / den
+    ds = p.copy()
+    ds[np.arange(B), labels] -= 1.0
+    ds /= B
+    deq = ds @ eh / tau
+    deh = ds.T @ eq / tau
+    return loss, deq, deh, ds
+
+
+def train_step_grads(qparams, hparams, xq, xh, labels, tau, bf16=True):
+    """Full forward/backward of one batch: returns (loss, q grads, h grads,
+    eq, eh)."""
+    eq, cq = tower_forward(qparams, xq, bf16)
+    eh, ch = tower_forward(hparams, xh, bf16)
+    loss, deq, deh, _ = infonce(eq, eh, labels, tau)
+    gq = tower_backward(cq, deq, bf16)
+    gh = tower_backward(ch, deh, bf16)
+    return loss, gq, gh, eq, eh
+
+
+def adam_update(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba) on float64 copies; t counts from 1."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    p = p - lr * mh / (np.sqrt(vh) + eps)
+    return p, m, v

@@ -1,0 +1,203 @@
+"""Pins for the oracle's graph-side functions: distances, exact kNN, alpha
+pruning, medoid and connectivity repair.  Each test checks the oracle against
+something other than itself: a closed form, an invariant, or an independent
+brute force in exact arithmetic."""
+from collections import deque
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_15986_amd import synth
+
+
+def grid_data(n, d, seed, G=19, bound=16.0):
+    r = np.random.default_rng(seed)
+    x = r.normal(0, 3, size=(n, d))
+    m = np.clip(np.rint(x * 2 ** G), -bound * 2 ** G, bound * 2 ** G - 1)
+    return (m / 2 ** G).astype(np.float32)
+
+
+# ---------------------------------------------------------------- distances
+def test_sqdist_hand_value():
+    assert oracle.sqdist([0, 0, 0], [3, 4, 0]) == 25.0
+    assert oracle.sqdist([1.5, -2.0], [1.5, -2.0]) == 0.0
+
+
+def test_sqdist_exact_on_grid_any_order():
+    # On the dyadic grid every partial sum is exact, so a reversed-order sum
+    # and an exact rational sum give the same bits.
+    x = grid_data(50, 32, 1)
+    for i in range(0, 50, 7):
+        a, b = x[i], x[(i * 3 + 1) % 50]
+        rev = 0.0
+        for j in reversed(range(32)):
+            t = float(a[j]) - float(b[j])
+            rev += t * t
+        exact = sum((Fraction(float(u)) - Fraction(float(v))) ** 2 for u, v in zip(a, b))
+        assert oracle.sqdist(a, b) == rev == float(exact)
+
+
+# ---------------------------------------------------------------- kNN
+def test_knn_matches_exact_rational_bruteforce():
+    base = grid_data(120, 8, 2)
+    q = grid_data(6, 8, 3)
+    ids, dd = oracle.knn(base, q, 10)
+    for i in range(q.shape[0]):
+        exact = [(sum((Fraction(float(u)) - Fraction(float(v))) ** 2
+                      for u, v in zip(q[i], base[p])), p) for p in range(base.shape[0])]
+        exact.sort()
+        assert [p for _, p in exact[:10]] == ids[i].tolist()
+        assert [float(v) for v, _ in exact[:10]] == dd[i].tolist()
+
+
+def test_knn_ties_break_by_smaller_id_and_self_excluded():
+    base = np.zeros((6, 2), np.float32)
+    base[[1, 4]] = [1.0, 0.0]     # two points at distance 1 from the origin
+    base[[2, 5]] = [0.0, 2.0]
+    base[3] = [5.0, 5.0]
+    ids, dd = oracle.knn(base, base[:1], 5)
+    # ids 0 (itself, d=0), then 1,4 (d=1), then 2,5 (d=4)
+    assert ids[0].tolist() == [0, 1, 4, 2, 5]
+    ids, dd = oracle.knn(base, base, 3, exclude_self=True)
+    assert ids[0].tolist() == [1, 4, 2]
+    # 1 and 4 coincide: d2(1,4)=0, then origin 0 (d=1), then 2 vs 5 both d2=5
+    assert ids[1].tolist() == [4, 0, 2]
+
+
+# ---------------------------------------------------------------- alpha prune
+def _line(n, seed):
+    """n collinear points x = i (first coordinate), ids shuffled."""
+    perm = np.random.default_rng(seed).permutation(n)
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)          # node perm[i] sits at coordinate i
+    base = np.zeros((n, 4), np.float32)
+    base[:, 0] = pos
+    return base, pos
+
+
+@pytest.mark.parametrize("alpha,expected", [
+    (1.0, [1]),                       # MRNG: only the adjacent node per side
+    (2.0, [1, 3, 7, 15]),             # "<=" keeps 2^t - 1 (a "<" rule would keep 1,2,4,8)
+    (1.2, [1, 6]),                    # FP32 1.2 squared in FP64 is > 1.44: offset 6 survives
+])
+def test_alpha_prune_collinear_closed_form(alpha, expected):
+    n = 30
+    base, pos = _line(n, 5)
+    cand, cd2 = oracle.knn(base, base, n - 1, exclude_self=True)
+    g = oracle.alpha_prune(base, cand, cd2, R=n, alpha=alpha)
+    node = int(np.where(pos == 15)[0][0])          # interior point at x = 15
+    kept = [int(pos[c]) - 15 for c in g[node] if c >= 0]
+    left = sorted(-o for o in kept if o < 0)
+    right = sorted(o for o in kept if o > 0)
+    exp_left = [m for m in expected if m <= 15]
+    exp_right = [m for m in expected if m <= 14]
+    assert left == exp_left and right == exp_right
+    assert (g[:, -2:] == -1).all()
+
+
+def test_alpha_exact_144_would_prune_offset_6():
+    # a2 = 1.2f^2 is strictly above 1.44, which is why offset 6 survives;
+    # with a2 == 1.44 exactly, 1.44 * 25 == 36 and "<=" would prune it.
+    a2 = float(np.float32(1.2)) ** 2
+    assert a2 * 25 > 36.0
+    assert 1.44 * 25 <= 36.0 + 1e-12
+
+
+def test_alpha_prune_properties_random():
+    base = grid_data(400, 6, 7)
+    K, R, alpha = 24, 10, 1.2
+    cand, cd2 = oracle.knn(base, base, K, exclude_self=True)
+    g = oracle.alpha_prune(base, cand, cd2, R, alpha)
+    a2 = float(np.float32(alpha)) ** 2
+    for p in range(0, 400, 13):
+        kept = [c for c in g[p] if c >= 0]
+        assert len(kept) == len(set(kept)) and p not in kept and len(kept) <= R - 2
+        # kept list is a prefix-respecting subsequence of the candidates
+        order = [int(c) for c in cand[p]]
+        idx = [order.index(c) for c in kept]
+        assert idx == sorted(idx)
+        last = idx[-1]
+        for t in range(last + 1):
+            c = order[t]
+            prev = [o for o in kept if order.index(o) < t]
+            dom = any(a2 * oracle.sqdist(base[o], base[c]) <= cd2[p, t] for o in prev)
+            assert dom == (c not in kept)
+
+
+# ---------------------------------------------------------------- medoid
+def test_medoid_symmetric_cross():
+    d = 5
+    pts = [np.zeros(d)]
+    for j in range(d):
+        for s in (1.0, -1.0):
+            e = np.zeros(d)
+            e[j] = s
+            pts.append(e)
+    base = np.array(pts, np.float32)
+    perm = np.random.default_rng(0).permutation(len(base))
+    shuffled = base[perm]
+    assert oracle.medoid(shuffled) == int(np.where(perm == 0)[0][0])
+
+
+def test_medoid_equals_exact_rational_argmin():
+    for seed in range(3):
+        base = grid_data(60, 6, 10 + seed)
+        n = base.shape[0]
+        mu = [sum(Fraction(float(base[i, j])) for i in range(n)) / n for j in range(6)]
+        exact = min((sum((Fraction(float(base[i, j])) - mu[j]) ** 2 for j in range(6)), i)
+                    for i in range(n))
+        assert oracle.medoid(base) == exact[1]
+
+
+# ---------------------------------------------------------------- repair
+def _reach(graph, src, reverse=False):
+    n = graph.shape[0]
+    adj = [[] for _ in range(n)]
+    for v in range(n):
+        for w in graph[v]:
+            if w >= 0:
+                (adj[w] if reverse else adj[v]).append(v if reverse else w)
+    seen = {src}
+    dq = deque([src])
+    while dq:
+        v = dq.popleft()
+        for w in adj[v]:
+            if w not in seen:
+                seen.add(w)
+                dq.append(w)
+    return seen
+
+
+def test_repair_two_cycles_by_hand():
+    # cluster A = {0,1,2} near the origin, cluster B = {3,4,5} near x = 100;
+    # each cluster is a directed cycle in slot 0.  R = 4 (slots 2,3 for repair).
+    base = np.array([[0, 0], [1, 0], [0, 1], [100, 0], [101, 0], [100, 1]], np.float32)
+    g = -np.ones((6, 4), np.int32)
+    g[0, 0], g[1, 0], g[2, 0] = 1, 2, 0
+    g[3, 0], g[4, 0], g[5, 0] = 4, 5, 3
+    rg, nf, nr = oracle.repair(base, g, 0)
+    # forward: smallest unreached is 3; nearest reached node is 1 (d2 = 99^2)
+    assert nf == 1 and rg[1, 2] == 3
+    # reverse: 3 cannot reach 0; nearest node that can is 1 again
+    assert nr == 1 and rg[3, 3] == 1
+    assert _reach(rg, 0) == set(range(6)) and _reach(rg, 0, reverse=True) == set(range(6))
+    # nothing else changed
+    mask = np.ones_like(g, bool)
+    mask[1, 2] = mask[3, 3] = False
+    assert (rg[mask] == g[mask]).all()
+
+
+def test_build_graph_strongly_connected_tiny():
+    w = synth.scaled(synth.WORKLOADS["tiny"], n=1500)
+    base = synth.base(w)
+    g, med, nf, nr, cand, _ = oracle.build_graph(base, knn_k=64, R=16, alpha=1.2)
+    assert _reach(g, med) == set(range(1500))
+    assert _reach(g, med, reverse=True) == set(range(1500))
+    assert nf > 0        # the separated mixture needs forward bridges
+    # pruned slots hold only candidates of the row, in candidate order
+    for p in range(0, 1500, 37):
+        kept = [c for c in g[p, :14] if c >= 0]
+        order = cand[p].tolist()
+        assert [order.index(c) for c in kept] == sorted(order.index(c) for c in kept)

@@ -1,0 +1,177 @@
+"""Pins for the oracle's hub selection (Lloyd k-means + Definition 3) and the
+two-tower model / InfoNCE / Adam (towers.py)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import towers
+from paper_2506_15986_amd import synth
+
+
+# ---------------------------------------------------------------- k-means hubs
+def _mix(n=900, d=6, comps=5, seed=0, sep=40.0):
+    r = np.random.default_rng(seed)
+    mu = r.uniform(-sep, sep, size=(comps, d))
+    lab = r.integers(0, comps, size=n)
+    x = mu[lab] + r.normal(size=(n, d))
+    m = np.rint(x * 2 ** 16)
+    return (m / 2 ** 16).astype(np.float32), lab
+
+
+def test_lloyd_objective_non_increasing():
+    x, _ = _mix(seed=1, sep=3.0)
+    init = np.random.default_rng(2).permutation(len(x))[:12].astype(np.int32)
+    r = oracle.kmeans_hubs(x, 12, 30, init)
+    obj = r["objective"]
+    assert len(obj) >= 2
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(obj, obj[1:]))
+
+
+def test_single_hub_is_medoid():
+    x, _ = _mix(seed=3)
+    r = oracle.kmeans_hubs(x, 1, 5, np.array([17], np.int32))
+    assert r["hub_ids"][0] == oracle.medoid(x)
+
+
+def test_every_point_its_own_hub():
+    x, _ = _mix(n=50, seed=4)
+    init = np.random.default_rng(5).permutation(50).astype(np.int32)
+    r = oracle.kmeans_hubs(x, 50, 5, init)
+    assert (r["hub_ids"] == init).all()
+
+
+def test_matches_sklearn_lloyd():
+    from sklearn.cluster import KMeans
+    x, _ = _mix(n=600, seed=6, sep=4.0)
+    nh, T = 8, 50
+    init = np.random.default_rng(7).permutation(len(x))[:nh].astype(np.int32)
+    r = oracle.kmeans_hubs(x, nh, T, init)
+    km = KMeans(n_clusters=nh, init=x[init].astype(np.float64), n_init=1, max_iter=T,
+                tol=0.0, algorithm="lloyd").fit(x.astype(np.float64))
+    assert (km.labels_ == r["assign"]).mean() > 0.99
+    # Definition 3: each hub is the member nearest its cluster mean
+    for c in range(nh):
+        mem = np.where(r["assign"] == c)[0]
+        mu = x[mem].astype(np.float64).mean(0)
+        dd = ((x[mem].astype(np.float64) - mu) ** 2).sum(1)
+        assert r["hub_ids"][c] == mem[np.argmin(dd)]
+
+
+def test_separated_mixture_one_seed_per_component_is_pure():
+    x, lab = _mix(n=1000, comps=6, seed=8, sep=50.0)
+    init = np.array([np.where(lab == c)[0][0] for c in range(6)], np.int32)
+    r = oracle.kmeans_hubs(x, 6, 10, init)
+    for c in range(6):
+        assert len(set(lab[r["assign"] == c].tolist())) == 1
+        assert lab[r["hub_ids"][c]] == c
+
+
+def test_empty_cluster_gets_nearest_non_hub():
+    # points 0 and 1 coincide and seed clusters 0 and 1; ties go to the lower
+    # cluster index, so cluster 1 never gets a member
+    x = np.array([[0, 0], [0, 0], [10, 0], [11, 0]], np.float32)
+    r = oracle.kmeans_hubs(x, 3, 5, np.array([0, 1, 2], np.int32))
+    assert r["assign"].tolist() == [0, 0, 2, 2]
+    # cluster 0 = {0,1}: both at distance 0 from the mean, id 0 wins;
+    # cluster 2 = {2,3}: both 0.5 from the mean, id 2 wins;
+    # empty cluster 1 keeps centroid (0,0): nearest non-hub point is 1
+    assert r["hub_ids"].tolist() == [0, 1, 2]
+
+
+# ---------------------------------------------------------------- towers
+def test_bf16_round_matches_torch_rne():
+    r = np.random.default_rng(9)
+    x = np.concatenate([r.normal(size=4000) * 10 ** r.uniform(-3, 3, size=4000),
+                        [0.0, 1.0, -1.0, 1.00390625, 1.01171875, 3.0e-5]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    # torch rounds the float32 value; compare on inputs exact in float32
+    x32 = x.astype(np.float32).astype(np.float64)
+    assert (towers.bf16_round(x32) == ref).all()
+
+
+def _params(r, din, h, e):
+    return [r.uniform(-.3, .3, size=(h, din)), r.uniform(-.1, .1, size=h),
+            r.uniform(-.3, .3, size=(e, h)), r.uniform(-.1, .1, size=e)]
+
+
+def _loss(qp, hp, xq, xh, y, tau):
+    eq, _ = towers.tower_forward(qp, xq, bf16=False)
+    eh, _ = towers.tower_forward(hp, xh, bf16=False)
+    return towers.infonce(eq, eh, y, tau)[0]
+
+
+def test_gradients_match_finite_differences():
+    r = np.random.default_rng(10)
+    din, dh, h, e, B, nh, tau = 7, 9, 6, 5, 8, 11, 0.07
+    qp, hp = _params(r, din, h, e), _params(r, dh, h, e)
+    xq, xh = r.normal(size=(B, din)), r.normal(size=(nh, dh))
+    y = r.integers(0, nh, size=B)
+    loss, gq, gh, _, _ = towers.train_step_grads(qp, hp, xq, xh, y, tau, bf16=False)
+    eps = 1e-6
+    for params, grads in ((qp, gq), (hp, gh)):
+        for P, G in zip(params, grads):
+            flat = P.reshape(-1)
+            gflat = np.asarray(G).reshape(-1)
+            for idx in range(0, flat.size, max(1, flat.size // 7)):
+                old = flat[idx]
+                flat[idx] = old + eps
+                lp = _loss(qp, hp, xq, xh, y, tau)
+                flat[idx] = old - eps
+                lm = _loss(qp, hp, xq, xh, y, tau)
+                flat[idx] = old
+                fd = (lp - lm) / (2 * eps)
+                assert abs(fd - gflat[idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8
+
+
+def test_gradients_match_torch_autograd_with_bf16_operands():
+    # torch autograd through the same bf16-valued operands, with the rounding
+    # of activations / gradients treated as identity in the backward pass
+    r = np.random.default_rng(11)
+    din, dh, h, e, B, nh, tau = 12, 15, 16, 8, 10, 13, 0.07
+    qp, hp = _params(r, din, h, e), _params(r, dh, h, e)
+    xq, xh = r.normal(size=(B, din)), r.normal(size=(nh, dh))
+    y = r.integers(0, nh, size=B)
+    loss, gq, gh, _, _ = towers.train_step_grads(qp, hp, xq, xh, y, tau, bf16=False)
+
+    def tower(params, x):
+        W1, b1, W2, b2 = params
+        z = torch.relu(x @ W1.T + b1) @ W2.T + b2
+        return z / z.norm(dim=1, keepdim=True)
+
+    tq = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in qp]
+    th = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in hp]
+    eq = tower(tq, torch.tensor(xq))
+    eh = tower(th, torch.tensor(xh))
+    s = eq @ eh.T / tau
+    L = torch.nn.functional.cross_entropy(s, torch.tensor(y))
+    L.backward()
+    assert abs(L.item() - loss) < 1e-12
+    for t, g in zip(tq + th, list(gq) + list(gh)):
+        assert np.allclose(t.grad.numpy(), g, rtol=1e-10, atol=1e-12)
+
+
+def test_infonce_closed_form_equal_hub_embeddings():
+    r = np.random.default_rng(12)
+    B, nh, e = 6, 1024, 8
+    eq = r.normal(size=(B, e))
+    eq /= np.linalg.norm(eq, axis=1, keepdims=True)
+    one = r.normal(size=e)
+    eh = np.tile(one / np.linalg.norm(one), (nh, 1))
+    y = r.integers(0, nh, size=B)
+    loss, deq, deh, ds = towers.infonce(eq, eh, y, 0.07)
+    assert abs(loss - math.log(nh)) < 1e-12          # ln 1024 = 6.9315
+    expect = np.full((B, nh), 1.0 / nh)
+    expect[np.arange(B), y] -= 1.0
+    assert np.allclose(ds, expect / B, atol=1e-15)
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    r = np.random.default_rng(13)
+    p = r.normal(size=20)
+    g = r.normal(size=20)
+    p1, m, v = towers.adam_update(p, g, np.zeros(20), np.zeros(20), 1, 1e-3)
+    # bias-corrected m = g and v = g^2 after one step
+    assert np.allclose(p - p1, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
