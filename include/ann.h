@@ -1,0 +1,130 @@
+/*
+ * ann.h — C ABI of libann, the MI355X (gfx950) implementation of the GATE
+ * query path: best-first beam search over a proximity graph (Algorithm 1),
+ * entered at a query-aware hub chosen by a two-tower model through a
+ * navigation graph over hub nodes (high-tier graph section).
+ *
+ * Conventions for every entry point
+ *  - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *    allocates and owns every buffer (typically PyTorch tensors); the library
+ *    never frees caller memory.  Opaque handles are the only library-owned
+ *    objects and are released by the matching *_destroy call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls validate their arguments on the host, enqueue work on `stream` and
+ *    return without synchronising, unless the comment says the call
+ *    synchronises (calls that return host values do).
+ *  - Scratch memory is caller-provided (`workspace`, `ws_bytes`); the size a
+ *    call needs is returned by ann_workspace_size() for the same arguments.
+ *  - On any status other than ANN_OK nothing has been enqueued and no output
+ *    has been written, except where a comment says otherwise (device-side
+ *    per-query checks are reported through per-query flags).
+ *  - Nothing crosses the ABI except status codes: no exceptions, no exit(),
+ *    no printing.  ann_last_error() returns the text of the last non-OK
+ *    status raised on the calling thread.
+ *  - Ordering convention: every "nearest" list is ordered by the key
+ *    (squared L2 distance, id) — ties go to the smaller id.
+ */
+#ifndef ANN_H
+#define ANN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ANN_OK = 0,
+    ANN_EINVAL = 1,   /* bad argument (null, out of range, misaligned, ...) */
+    ANN_ENOMEM = 2,   /* workspace too small */
+    ANN_EDEVICE = 3,  /* HIP error; the HIP error text is in ann_last_error() */
+    ANN_ENOTSUP = 4   /* valid but beyond the compiled kernel limits */
+} ann_status;
+
+/* Text of the last non-OK status on this thread ("" if none).  The pointer
+ * stays valid until the next call on the same thread. */
+const char *ann_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int32_t ann_version(void);
+
+/* Operation codes for ann_workspace_size(). */
+enum {
+    ANN_OP_SEARCH = 1,
+    ANN_OP_BUILD_GRAPH = 2,
+    ANN_OP_GT_KNN = 3,
+    ANN_OP_SELECT_HUBS = 4,
+    ANN_OP_ENTRY_SELECT = 5,
+    ANN_OP_MAKE_LABELS = 6,
+    ANN_OP_HUB_FEATURES = 7,
+    ANN_OP_TRAIN_STEP = 8
+};
+
+/* Bytes of workspace the operation needs.  Arguments per op:
+ *   SEARCH        n, dim, p0 = nq,        p1 = unused
+ *   BUILD_GRAPH   n, dim, p0 = knn_k,     p1 = R
+ *   GT_KNN        n, dim, p0 = nq,        p1 = k
+ *   SELECT_HUBS   n, dim, p0 = n_hubs,    p1 = unused
+ *   ENTRY_SELECT  nq, dim, p0 = hidden,   p1 = embed dim
+ *   MAKE_LABELS   n, dim, p0 = nq,        p1 = M (candidates per query)
+ *   HUB_FEATURES  n, dim, p0 = n_hubs,    p1 = R
+ *   TRAIN_STEP    batch, dim, p0 = n_hubs, p1 = hidden
+ * Returns 0 for an unknown op. */
+size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t p0, int32_t p1);
+
+/* ------------------------------------------------------------------------ */
+/* Beam search (Algorithm 1, read as the bounded-pool best-first search).    */
+
+/* Launch plan: how one batched search launch maps onto the GPU.  Obtain
+ * defaults from ann_default_plan() or tuned values from
+ * ann_autotune_search(); all fields are plain values. */
+typedef struct ann_search_plan {
+    int32_t pool_cap;        /* largest beam width L the launch supports (<= 512) */
+    int32_t visited_log2;    /* LDS visited table = 2^visited_log2 id slots (8..14) */
+    int32_t group;           /* lanes that cooperate on one vector gather: 8 or 16 */
+    int32_t waves_per_block; /* 1, 2 or 4 independent wavefronts per workgroup */
+    int32_t blocks;          /* persistent grid size; 0 = as many as fit on the GPU */
+    int32_t fp64;            /* 1 = FP64 distances (diagnostic mode), 0 = FP32 */
+} ann_search_plan;
+
+/* Fills *plan with the default plan for (n, dim, R, L_max).  host pointer. */
+ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_t L_max,
+                            ann_search_plan *plan);
+
+/* Batched best-first search.
+ *   base      n x dim FP32 row-major, 16-byte aligned, dim % 4 == 0, dim <= 1024
+ *   graph     n x R int32 neighbour ids, -1 = empty slot, 1 <= R <= 64
+ *   queries   nq x dim FP32 row-major, 16-byte aligned
+ *   entry_ids nq entry node ids, or NULL = `medoid` for every query
+ *   k, L      nq int32 each: result count and beam width per query;
+ *             1 <= k[i] <= L[i] <= plan->pool_cap and k[i] <= k_max
+ *   out_ids   nq x k_max int32 (row i: the k[i] best ids, then -1)
+ *   out_dist  nq x k_max FP32 squared L2 distances (then +inf)
+ *   stats     nq x 4 int32 or NULL: [ndc_unique, ndc_exec, hops, flags];
+ *             flags bit0 = the LDS visited table overflowed (results are still
+ *             exact, ndc_unique may over-count), bit1 = invalid per-query
+ *             arguments (k/L/entry out of range: the row is left -1/+inf)
+ *   trace     nq x trace_cap int32 or NULL: ids expanded, in order, -1 padded
+ *   plan      host pointer or NULL (= default plan for L_max = max over L is not
+ *             known on the host, so NULL means pool_cap 256)
+ *   workspace ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0) bytes
+ * With nq == 0 the per-query pointers may be NULL and nothing is enqueued.
+ * Each query expands the best not-yet-expanded pool entry until none is left;
+ * the FP32 (or FP64) distance of every newly seen neighbour is one distance
+ * computation.  Ties are broken by the smaller id. */
+ann_status ann_search(const float *base, int64_t n, int32_t dim,
+                      const int32_t *graph, int32_t R,
+                      const float *queries, int32_t nq,
+                      const int32_t *entry_ids, int32_t medoid,
+                      const int32_t *k, const int32_t *L, int32_t k_max,
+                      int32_t *out_ids, float *out_dist, int32_t *stats,
+                      int32_t *trace, int32_t trace_cap,
+                      const ann_search_plan *plan,
+                      void *workspace, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANN_H */

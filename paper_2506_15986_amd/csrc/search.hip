@@ -1,0 +1,240 @@
+// Batched best-first beam search on a proximity graph (Algorithm 1 read as
+// the bounded-pool search), one wavefront per query, persistent grid.
+//
+// Per hop a wavefront: picks the best unexpanded pool entry (ballot over the
+// sorted pool), loads its adjacency row with one coalesced load, test-and-sets
+// every neighbour in the LDS visited filter, compacts the unseen ones (slot
+// order is kept), gathers their vectors in groups of G lanes with 16-byte
+// loads (G*16 contiguous bytes per group and instruction), reduces the FP32
+// (or FP64) squared L2 distance with xor shuffles, sorts the new keys with a
+// wave bitonic sort and merges them into the pool (binary-search ranks,
+// ping-pong buffers).  Keys are (distance, id), so ties go to the smaller id.
+//
+// When the visited filter is a hash table that had to drop an id, a dropped
+// node may be seen again.  Its key is recomputed bit-identically, so it is
+// either still in the pool (found by the merge's rank search and dropped as
+// a duplicate) or it was rejected or evicted while the pool was full, and
+// since the pool's last key only decreases once the pool is full it is
+// rejected again: the expansion order and results are those of an exact
+// visited set; only the executed distance count grows.
+#include "beam.h"
+#include "common.h"
+#include "search_core.h"
+
+namespace ann {
+namespace {
+
+using namespace beam;
+
+__global__ void reset_counter(uint32_t *c) { *c = 0u; }
+
+template <int G, int CPL, bool F64>
+__global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    using S = Searcher<G, CPL, F64, L2, false>;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    S s;
+    s.setup(smem + (size_t)wave * a.wave_lds, a.pool_cap, a.visited_log2, a.n, a.base,
+            a.dim, a.graph, a.R);
+    for (;;) {
+        int qi = 0;
+        if (lane == 0) qi = (int)atomicAdd(a.counter, 1u);
+        qi = __shfl(qi, 0);
+        if (qi >= a.nq) break;
+        const int kq = a.k[qi];
+        const int Lq = a.L[qi];
+        const int entry = a.entry ? a.entry[qi] : a.medoid;
+        int32_t *oid = a.out_ids + (size_t)qi * a.k_max;
+        float *odist = a.out_dist + (size_t)qi * a.k_max;
+        int32_t *trace = a.trace ? a.trace + (size_t)qi * a.trace_cap : nullptr;
+        if (kq < 1 || kq > Lq || Lq > a.pool_cap || kq > a.k_max || entry < 0 ||
+            (int64_t)entry >= a.n) {
+            for (int t = lane; t < a.k_max; t += 64) {
+                oid[t] = -1;
+                odist[t] = __int_as_float(0x7f800000);
+            }
+            for (int t = lane; trace && t < a.trace_cap; t += 64) trace[t] = -1;
+            if (a.stats && lane == 0) {
+                int32_t *st = a.stats + (size_t)qi * 4;
+                st[0] = 0; st[1] = 0; st[2] = 0; st[3] = 2;
+            }
+            continue;
+        }
+        s.load_query(a.queries + (size_t)qi * a.dim);
+        SearchResult r = s.run((uint32_t)entry, Lq, trace, a.trace_cap, nullptr, 0, 0, 0x7fffffff);
+        s.write_topk(kq, a.k_max, oid, odist);
+        for (int t = (int)r.hops + lane; trace && t < a.trace_cap; t += 64) trace[t] = -1;
+        if (a.stats && lane == 0) {
+            int32_t *st = a.stats + (size_t)qi * 4;
+            st[0] = r.ndc_exec - r.dups;
+            st[1] = r.ndc_exec;
+            st[2] = r.hops;
+            st[3] = r.lost ? 1 : 0;
+        }
+    }
+}
+
+template <int G, int CPL, bool F64>
+ann_status launch_search(const SearchArgs &a, int blocks, int wpb, hipStream_t st)
+{
+    auto kern = search_kernel<G, CPL, F64>;
+    size_t lds = (size_t)wpb * a.wave_lds;
+    if (lds > 65536) ANN_HIP(hipFuncSetAttribute((const void *)kern,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds));
+    if (blocks <= 0) {
+        int per_cu = 0;
+        ANN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds));
+        if (per_cu < 1) return fail(ANN_ENOTSUP, "search plan does not fit on a CU (%zu B LDS)", lds);
+        blocks = per_cu * device_cus();
+    }
+    int need = (a.nq + wpb - 1) / wpb;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, a.counter);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, st, a);
+    ANN_LAUNCHED();
+    return ANN_OK;
+}
+
+template <bool F64>
+ann_status dispatch(const SearchArgs &a, int group, int blocks, int wpb, hipStream_t st)
+{
+    const int chunks = a.dim / 4;
+    if (group == 8) {
+        int cpl = (chunks + 7) / 8;
+        switch (cpl) {
+        case 1: return launch_search<8, 1, F64>(a, blocks, wpb, st);
+        case 2: return launch_search<8, 2, F64>(a, blocks, wpb, st);
+        case 3: return launch_search<8, 3, F64>(a, blocks, wpb, st);
+        case 4: return launch_search<8, 4, F64>(a, blocks, wpb, st);
+        default: break;
+        }
+        return fail(ANN_ENOTSUP, "group 8 supports dim <= 128 (got %d)", a.dim);
+    }
+    int cpl = (chunks + 15) / 16;
+    if (cpl <= 1) return launch_search<16, 1, F64>(a, blocks, wpb, st);
+    if (cpl <= 2) return launch_search<16, 2, F64>(a, blocks, wpb, st);
+    if (cpl <= 4) return launch_search<16, 4, F64>(a, blocks, wpb, st);
+    if (cpl <= 8) return launch_search<16, 8, F64>(a, blocks, wpb, st);
+    if (cpl <= 15) return launch_search<16, 15, F64>(a, blocks, wpb, st);
+    if (cpl <= 16) return launch_search<16, 16, F64>(a, blocks, wpb, st);
+    return fail(ANN_ENOTSUP, "dim %d exceeds 1024", a.dim);
+}
+
+}  // namespace
+
+ann_status validate_plan(const ann_search_plan &p)
+{
+    ANN_REQUIRE(p.pool_cap >= 1 && p.pool_cap <= 512, "plan.pool_cap must be in [1,512]");
+    ANN_REQUIRE(p.visited_log2 >= 8 && p.visited_log2 <= 14, "plan.visited_log2 must be in [8,14]");
+    ANN_REQUIRE(p.group == 8 || p.group == 16, "plan.group must be 8 or 16");
+    ANN_REQUIRE(p.waves_per_block == 1 || p.waves_per_block == 2 || p.waves_per_block == 4,
+                "plan.waves_per_block must be 1, 2 or 4");
+    ANN_REQUIRE(p.blocks >= 0, "plan.blocks must be >= 0");
+    ANN_REQUIRE(p.fp64 == 0 || p.fp64 == 1, "plan.fp64 must be 0 or 1");
+    return ANN_OK;
+}
+
+size_t search_wave_lds(const ann_search_plan &p, int64_t n)
+{
+    return wave_lds_bytes(p.pool_cap, p.visited_log2, n, p.fp64 != 0);
+}
+
+ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                         int32_t R, const float *queries, int32_t nq, const int32_t *entry_ids,
+                         int32_t medoid, const int32_t *k, const int32_t *L, int32_t k_max,
+                         int32_t *out_ids, float *out_dist, int32_t *stats, int32_t *trace,
+                         int32_t trace_cap, const ann_search_plan &p, uint32_t *counter,
+                         hipStream_t st)
+{
+    SearchArgs a{};
+    a.base = base;
+    a.n = n;
+    a.dim = dim;
+    a.graph = graph;
+    a.R = R;
+    a.queries = queries;
+    a.nq = nq;
+    a.entry = entry_ids;
+    a.medoid = medoid;
+    a.k = k;
+    a.L = L;
+    a.k_max = k_max;
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    a.stats = stats;
+    a.trace = trace;
+    a.trace_cap = trace ? trace_cap : 0;
+    a.pool_cap = p.pool_cap;
+    a.visited_log2 = p.visited_log2;
+    a.counter = counter;
+    a.wave_lds = search_wave_lds(p, n);
+    if (p.fp64) return dispatch<true>(a, p.group, p.blocks, p.waves_per_block, st);
+    return dispatch<false>(a, p.group, p.blocks, p.waves_per_block, st);
+}
+
+}  // namespace ann
+
+using namespace ann;
+
+extern "C" ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_t L_max,
+                                       ann_search_plan *plan)
+{
+    ANN_REQUIRE(plan != nullptr, "plan is NULL");
+    ANN_REQUIRE(n >= 1 && dim >= 1 && R >= 1 && L_max >= 1, "n, dim, R, L_max must be >= 1");
+    ANN_SUPPORTED(L_max <= 512, "L_max %d exceeds 512", L_max);
+    ann_search_plan p{};
+    p.pool_cap = L_max <= 64 ? 64 : (L_max <= 128 ? 128 : (L_max <= 256 ? 256 : 512));
+    p.visited_log2 = 12;
+    p.group = dim <= 128 ? 8 : 16;
+    p.waves_per_block = 1;
+    p.blocks = 0;
+    p.fp64 = 0;
+    (void)R;
+    *plan = p;
+    return ANN_OK;
+}
+
+extern "C" ann_status ann_search(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                                 int32_t R, const float *queries, int32_t nq,
+                                 const int32_t *entry_ids, int32_t medoid, const int32_t *k,
+                                 const int32_t *L, int32_t k_max, int32_t *out_ids,
+                                 float *out_dist, int32_t *stats, int32_t *trace,
+                                 int32_t trace_cap, const ann_search_plan *plan, void *workspace,
+                                 size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(base && graph && workspace, "a required pointer is NULL");
+    ANN_REQUIRE(nq == 0 || (queries && k && L && out_ids && out_dist),
+                "a required pointer is NULL");
+    ANN_REQUIRE(n >= 1 && n <= 0x7FFFFFFF, "n must be in [1, 2^31)");
+    ANN_REQUIRE(dim >= 1, "dim must be >= 1");
+    ANN_SUPPORTED(dim % 4 == 0, "dim must be a multiple of 4 (got %d)", dim);
+    ANN_SUPPORTED(dim <= 1024, "dim must be <= 1024 (got %d)", dim);
+    ANN_REQUIRE(R >= 1, "R must be >= 1");
+    ANN_SUPPORTED(R <= 64, "R must be <= 64 (got %d)", R);
+    ANN_REQUIRE(nq >= 0, "nq must be >= 0");
+    ANN_REQUIRE(k_max >= 1, "k_max must be >= 1");
+    ANN_REQUIRE(entry_ids != nullptr || (medoid >= 0 && (int64_t)medoid < n),
+                "medoid out of range");
+    ANN_REQUIRE(aligned(base, 16) && aligned(queries, 16), "base/queries must be 16-byte aligned");
+    ANN_REQUIRE(trace == nullptr || trace_cap >= 1, "trace_cap must be >= 1 with a trace buffer");
+    ANN_REQUIRE(ws_bytes >= ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0),
+                "workspace too small");
+    ann_search_plan p{};
+    if (plan) {
+        p = *plan;
+    } else {
+        ann_status s = ann_default_plan(n, dim, R, 256, &p);
+        if (s != ANN_OK) return s;
+    }
+    ann_status s = validate_plan(p);
+    if (s != ANN_OK) return s;
+    if (nq == 0) return ANN_OK;
+    return search_launch(base, n, dim, graph, R, queries, nq, entry_ids, medoid, k, L, k_max,
+                         out_ids, out_dist, stats, trace, trace_cap, p,
+                         static_cast<uint32_t *>(workspace), static_cast<hipStream_t>(stream));
+}

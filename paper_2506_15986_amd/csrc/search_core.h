@@ -1,0 +1,340 @@
+// The per-wavefront search engine used by the search, entry-selection and
+// label kernels.  See search.hip for the algorithm and its invariants.
+#pragma once
+
+#include "beam.h"
+
+namespace ann {
+
+struct SearchArgs {
+    const float *base;
+    int64_t n;
+    int dim;
+    const int32_t *graph;
+    int R;
+    const float *queries;
+    int nq;
+    const int32_t *entry;
+    int medoid;
+    const int32_t *k;
+    const int32_t *L;
+    int k_max;
+    int32_t *out_ids;
+    float *out_dist;
+    int32_t *stats;
+    int32_t *trace;
+    int trace_cap;
+    int pool_cap;
+    int visited_log2;
+    uint32_t *counter;
+    size_t wave_lds;
+};
+
+struct SearchResult {
+    int ndc_exec;
+    int dups;
+    int hops;
+    bool lost;
+    int ndc_hit;   // label mode: ndc when the c-th true neighbour was evaluated, else -1
+};
+
+// LDS bytes one wavefront needs.
+inline size_t wave_lds_bytes(int pool_cap, int visited_log2, int64_t n, bool f64)
+{
+    size_t ks = f64 ? 8 : 4;
+    size_t words = (size_t)1 << visited_log2;
+    size_t bitset_words = (size_t)((n + 31) / 32);
+    if (bitset_words <= words) words = bitset_words;
+    size_t b = 2 * (size_t)pool_cap * ks + 64 * ks + 2 * (size_t)pool_cap * 4 + 64 * 4 + 64 + words * 4;
+    return (b + 15) / 16 * 16;
+}
+
+template <int G, int CPL, bool F64, int METRIC, bool LABEL>
+struct Searcher {
+    using KT = beam::Key<F64>;
+    using K = typename KT::K;
+    using D = typename KT::D;
+    static constexpr int VPB = 64 / G;
+    static constexpr int U0 = 32 / VPB;
+    static constexpr int U1 = 16 / CPL;
+    static constexpr int U = (U0 < U1 ? U0 : U1) < 1 ? 1 : (U0 < U1 ? U0 : U1);
+
+    K *pk0, *pk1;
+    uint32_t *pi0, *pi1;
+    K *sk;
+    uint32_t *si;
+    uint32_t *truth;   // label mode: up to 16 true neighbour ids
+    beam::Visited vis;
+    int pool_cap;
+    int64_t n;
+    const float4 *base4;
+    int chunks;
+    const int32_t *graph;
+    int R;
+    float4 q[CPL];
+    int cur;
+    int cnt;
+
+    __device__ void setup(unsigned char *lds, int pcap, int vlog2, int64_t n_, const float *base,
+                          int dim, const int32_t *graph_, int R_)
+    {
+        const size_t ks = sizeof(K);
+        unsigned char *p = lds;
+        pk0 = reinterpret_cast<K *>(p);
+        p += pcap * ks;
+        pk1 = reinterpret_cast<K *>(p);
+        p += pcap * ks;
+        sk = reinterpret_cast<K *>(p);
+        p += 64 * ks;
+        pi0 = reinterpret_cast<uint32_t *>(p);
+        p += pcap * 4;
+        pi1 = reinterpret_cast<uint32_t *>(p);
+        p += pcap * 4;
+        si = reinterpret_cast<uint32_t *>(p);
+        p += 64 * 4;
+        truth = reinterpret_cast<uint32_t *>(p);
+        p += 64;
+        size_t words = (size_t)1 << vlog2;
+        size_t bw = (size_t)((n_ + 31) / 32);
+        vis.t = reinterpret_cast<uint32_t *>(p);
+        vis.log2cap = vlog2;
+        vis.bitset = bw <= words;
+        vis.words = (int)(vis.bitset ? bw : words);
+        pool_cap = pcap;
+        n = n_;
+        base4 = reinterpret_cast<const float4 *>(base);
+        chunks = dim / 4;
+        graph = graph_;
+        R = R_;
+    }
+
+    __device__ void load_query(const float *qp)
+    {
+        const int gl = beam::lane_id() % G;
+        const float4 *q4 = reinterpret_cast<const float4 *>(qp);
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            int ch = gl + G * t;
+            q[t] = ch < chunks ? q4[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+
+    __device__ inline K *keys(int c) const { return c ? pk1 : pk0; }
+    __device__ inline uint32_t *ids(int c) const { return c ? pi1 : pi0; }
+
+    __device__ static inline D partial(const float4 &x, const float4 &y)
+    {
+        if (METRIC == beam::L2) {
+            D a = (D)x.x - (D)y.x, b = (D)x.y - (D)y.y, c = (D)x.z - (D)y.z, d = (D)x.w - (D)y.w;
+            return a * a + b * b + c * c + d * d;
+        } else {
+            return (D)x.x * (D)y.x + (D)x.y * (D)y.y + (D)x.z * (D)y.z + (D)x.w * (D)y.w;
+        }
+    }
+
+    // keys of the m candidates si[0..m) into sk[0..m)
+    __device__ void distances(int m)
+    {
+        const int lane = beam::lane_id();
+        const int gi = lane / G, gl = lane % G;
+        for (int b0 = 0; b0 < m; b0 += VPB * U) {
+            float4 xv[U][CPL];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int c = b0 + u * VPB + gi;
+                bool ok = c < m;
+                uint32_t id = ok ? si[c] : 0u;
+                const float4 *row = base4 + (size_t)id * chunks;
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) {
+                    int ch = gl + G * t;
+                    xv[u][t] = (ok && ch < chunks) ? row[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                D acc = 0;
+#pragma unroll
+                for (int t = 0; t < CPL; ++t) acc += partial(xv[u][t], q[t]);
+#pragma unroll
+                for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+                int c = b0 + u * VPB + gi;
+                if (gl == 0 && c < m) sk[c] = KT::of(METRIC == beam::L2 ? acc : -acc);
+            }
+        }
+        beam::wave_sync();
+    }
+
+    // label mode: count distinct true neighbours among si[0..m)
+    __device__ void count_hits(int m, int kt, int c_hit, uint32_t &found, int ndc_before,
+                               int &ndc_hit)
+    {
+        const int lane = beam::lane_id();
+        int idx = -1;
+        if (lane < m) {
+            uint32_t c = si[lane];
+            for (int t = 0; t < kt; ++t)
+                if (truth[t] == c) idx = t;
+        }
+        bool h = idx >= 0 && !((found >> idx) & 1u);
+        uint64_t hb = __ballot(h);
+        // OR of the found bits across lanes
+        uint32_t mybit = h ? (1u << idx) : 0u;
+        for (int o = 32; o > 0; o >>= 1) mybit |= __shfl_xor(mybit, o);
+        int before = __popc(found);
+        int nh = __popcll(hb);
+        if (ndc_hit < 0 && before + nh >= c_hit) {
+            int need = c_hit - before;   // >= 1
+            uint64_t b = hb;
+            for (int t = 1; t < need; ++t) b &= b - 1;
+            ndc_hit = ndc_before + (__ffsll((unsigned long long)b) - 1) + 1;
+        }
+        found |= mybit;
+    }
+
+    // Runs one query from `entry` with beam width Lq.  trace (nullable)
+    // receives the expanded ids.  Label mode: kt true ids in truth[], stop once
+    // ndc exceeds abort_ndc.
+    __device__ SearchResult run(uint32_t entry, int Lq, int32_t *trace, int trace_cap, const int32_t *truth_g,
+                                int kt, int c_hit, int abort_ndc)
+    {
+        const int lane = beam::lane_id();
+        SearchResult r{0, 0, 0, false, -1};
+        uint32_t found = 0;
+        vis.clear();
+        if (LABEL) {
+            if (lane < kt) truth[lane] = (uint32_t)truth_g[lane];
+        }
+        bool lost = false;
+        if (lane == 0) {
+            vis.insert(entry, lost);
+            si[0] = entry;
+        }
+        beam::wave_sync();
+        distances(1);
+        cur = 0;
+        if (lane == 0) {
+            pk0[0] = sk[0];
+            pi0[0] = entry;
+        }
+        cnt = 1;
+        r.ndc_exec = 1;
+        if (LABEL) count_hits(1, kt, c_hit, found, 0, r.ndc_hit);
+        beam::wave_sync();
+        int cursor = 0;
+        for (;;) {
+            if (LABEL && (r.ndc_hit >= 0 || r.ndc_exec > abort_ndc)) break;
+            // best unexpanded pool entry at or after the cursor
+            int ppos = -1;
+            for (int b = cursor; b < cnt; b += 64) {
+                int j = b + lane;
+                bool un = j < cnt && !(ids(cur)[j] & beam::kExpanded);
+                uint64_t bal = __ballot(un);
+                if (bal) {
+                    ppos = b + __ffsll((unsigned long long)bal) - 1;
+                    break;
+                }
+            }
+            if (ppos < 0) break;
+            cursor = ppos;
+            const uint32_t p = ids(cur)[ppos] & beam::kIdMask;
+            beam::wave_sync();
+            if (lane == 0) {
+                ids(cur)[ppos] = p | beam::kExpanded;
+                if (trace && r.hops < trace_cap) trace[r.hops] = (int32_t)p;
+            }
+            r.hops++;
+            // adjacency row, visited filter, compaction in slot order
+            int nb = -1;
+            if (lane < R) nb = graph[(size_t)p * R + lane];
+            bool fresh = false;
+            if (nb >= 0 && (int64_t)nb < n) fresh = vis.insert((uint32_t)nb, lost);
+            uint64_t fb = __ballot(fresh);
+            const int m = __popcll(fb);
+            if (fresh) si[__popcll(fb & ((1ull << lane) - 1ull))] = (uint32_t)nb;
+            beam::wave_sync();
+            if (m == 0) continue;
+            distances(m);
+            if (LABEL) count_hits(m, kt, c_hit, found, r.ndc_exec, r.ndc_hit);
+            r.ndc_exec += m;
+            // ---- merge the new keys into the pool
+            K *ak = keys(cur);
+            uint32_t *ai = ids(cur);
+            K kk = KT::kMax;
+            uint32_t ii = beam::kEmpty;
+            bool valid = lane < m;
+            if (valid) {
+                kk = sk[lane];
+                ii = si[lane];
+            }
+            if (valid && cnt == Lq && !beam::key_less(kk, ii, ak[cnt - 1], ai[cnt - 1])) valid = false;
+            bool dup = false;
+            if (valid) {
+                int pos = beam::lower_bound(ak, ai, cnt, kk, ii);
+                if (pos < cnt && ak[pos] == kk && (ai[pos] & beam::kIdMask) == ii) dup = true;
+            }
+            valid = valid && !dup;
+            r.dups += __popcll(__ballot(dup));
+            const int mv = __popcll(__ballot(valid));
+            if (mv == 0) continue;
+            if (!valid) {
+                kk = KT::kMax;
+                ii = beam::kEmpty;
+            }
+            beam::wave_sort(kk, ii);
+            beam::wave_sync();
+            sk[lane] = kk;
+            si[lane] = ii;
+            beam::wave_sync();
+            K *bk = keys(cur ^ 1);
+            uint32_t *bi = ids(cur ^ 1);
+            int f0 = 0x7fffffff;
+            if (lane < mv) {
+                int f = lane + beam::lower_bound(ak, ai, cnt, kk, ii);
+                if (f < Lq) {
+                    bk[f] = kk;
+                    bi[f] = ii;
+                }
+                f0 = f;
+            }
+            for (int j = lane; j < cnt; j += 64) {
+                K kj = ak[j];
+                uint32_t ij = ai[j];
+                int f = j + beam::lower_bound(sk, si, mv, kj, ij);
+                if (f < Lq) {
+                    bk[f] = kj;
+                    bi[f] = ij;
+                }
+            }
+            f0 = __shfl(f0, 0);
+            int oc = cnt;
+            if (cursor < cnt) oc = cursor + beam::lower_bound(sk, si, mv, ak[cursor], ai[cursor]);
+            cursor = f0 < oc ? f0 : oc;
+            cnt = (cnt + mv < Lq) ? cnt + mv : Lq;
+            cur ^= 1;
+            beam::wave_sync();
+        }
+        r.lost = __ballot(lost) != 0;
+        return r;
+    }
+
+    __device__ void write_topk(int kq, int k_max, int32_t *oid, float *odist)
+    {
+        const int lane = beam::lane_id();
+        const K *ak = keys(cur);
+        const uint32_t *ai = ids(cur);
+        for (int t = lane; t < k_max; t += 64) {
+            int32_t id = -1;
+            float dv = __int_as_float(0x7f800000);
+            if (t < kq && t < cnt) {
+                id = (int32_t)(ai[t] & beam::kIdMask);
+                float v = KT::value(ak[t]);
+                dv = METRIC == beam::L2 ? v : -v;
+            }
+            oid[t] = id;
+            odist[t] = dv;
+        }
+    }
+};
+
+}  // namespace ann

@@ -1,0 +1,80 @@
+"""Shared fixtures for the GPU parity tests: seeded workloads and the oracle's
+index for them (built once per session, on the CPU)."""
+import functools
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2506_15986_amd import synth
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=None)
+def tiny_index(n=10_000, nq=100):
+    """The tiny workload (10k x 32 Gaussian mixture on the 2^-19 grid), its
+    kNN(64) -> alpha 1.2 -> R=16 graph, medoid and exact top-10."""
+    w = synth.scaled(synth.WORKLOADS["tiny"], n=n, n_queries=nq)
+    base = synth.base(w)
+    q = synth.queries(w)
+    g, med, nf, nr, cand, cd2 = oracle.build_graph(base, knn_k=64, R=16, alpha=1.2)
+    truth, td2 = oracle.knn(base, q, 10)
+    return dict(w=w, base=base, q=q, graph=g, medoid=med, cand=cand, cand_d2=cd2,
+                truth=truth, truth_d2=td2, nf=nf, nr=nr)
+
+
+@functools.lru_cache(maxsize=None)
+def int_index(n=20_000, nq=200, R=32, knn_k=64):
+    """Integer-valued data (the 1M x 128 recipe at reduced N: values 0..255),
+    where FP32 squared distances are exact."""
+    w = synth.scaled(synth.WORKLOADS["sift1m"], n=n, n_queries=nq)
+    base = synth.base(w)
+    q = synth.queries(w)
+    g, med, nf, nr, cand, cd2 = oracle.build_graph(base, knn_k=knn_k, R=R, alpha=1.2)
+    truth, td2 = oracle.knn(base, q, 10)
+    return dict(w=w, base=base, q=q, graph=g, medoid=med, cand=cand, cand_d2=cd2,
+                truth=truth, truth_d2=td2, nf=nf, nr=nr)
+
+
+def first_divergence(tr_a, tr_b):
+    """Index of the first differing expansion of two traces (or -1)."""
+    m = min(len(tr_a), len(tr_b))
+    for t in range(m):
+        if tr_a[t] != tr_b[t]:
+            return t
+    return -1 if len(tr_a) == len(tr_b) else m
+
+
+def near_tie_certificate(base, graph, q, entry, L, tr_gpu, tr_cpu, tol=1e-5):
+    """Divergence certificate for an FP32 search against the FP64 oracle.
+
+    Up to the first differing expansion both sides expanded the same nodes, so
+    they saw the same visited set S and each pool is the L best keys of S under
+    its own distances.  The two choices can then differ only through a near
+    tie: between the two chosen nodes, or between a chosen node and the L-th
+    best exact key of S (pool admission).  Returns True when the first
+    difference is such a tie within `tol` (relative)."""
+    tr_gpu = [int(x) for x in tr_gpu if x >= 0]
+    tr_cpu = [int(x) for x in tr_cpu if x >= 0]
+    t = first_divergence(tr_gpu, tr_cpu)
+    if t < 0:
+        return True
+    seen = {int(entry)}
+    for p in tr_cpu[:t]:
+        seen.update(int(v) for v in graph[p] if v >= 0)
+    keys = sorted(oracle.sqdist(q, base[v]) for v in seen)
+    kL = keys[L - 1] if len(keys) >= L else float("inf")
+
+    def close(x, y):
+        return abs(x - y) <= tol * max(abs(x), abs(y), 1e-30)
+
+    picks = [oracle.sqdist(q, base[v]) for v in
+             (tr_gpu[t] if t < len(tr_gpu) else None, tr_cpu[t] if t < len(tr_cpu) else None)
+             if v is not None]
+    if len(picks) == 2 and close(picks[0], picks[1]):
+        return True
+    return any(close(d, kL) for d in picks)

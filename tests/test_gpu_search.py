@@ -1,0 +1,186 @@
+"""GPU parity of ann_search (C-ABI) against the CPU oracle's beam search."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.common import int_index, near_tie_certificate, say, tiny_index
+
+pytestmark = pytest.mark.gpu
+
+
+def _ann():
+    from paper_2506_15986_amd import ann
+    return ann
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _run(ix, entries, ks, Ls, plan, trace_cap=0, k_max=None):
+    ann = _ann()
+    base, g, q = _dev(ix["base"]), _dev(ix["graph"]), _dev(ix["q"])
+    ent = _dev(np.asarray(entries, np.int32)) if entries is not None else None
+    k = _dev(np.asarray(ks, np.int32))
+    L = _dev(np.asarray(Ls, np.int32))
+    ids, dist, st, tr = ann.ann_search(base, g, q, ent, ix["medoid"], k, L, k_max=k_max,
+                                       plan=plan, trace_cap=trace_cap)
+    torch.cuda.synchronize()
+    out = dict(ids=ids.cpu().numpy(), dist=dist.cpu().numpy(), stats=st.cpu().numpy())
+    if tr is not None:
+        out["trace"] = tr.cpu().numpy()
+    return out
+
+
+def _plan(ix, L_max, **kw):
+    ann = _ann()
+    n, d = ix["base"].shape
+    p = ann.default_plan(n, d, ix["graph"].shape[1], L_max)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("L", [10, 32, 100])
+def test_fp64_mode_bitwise_on_tiny(L):
+    ix = tiny_index()
+    nq = ix["q"].shape[0]
+    say("case: fp64 tiny L=%d nq=%d" % (L, nq))
+    plan = _plan(ix, L, fp64=1)
+    got = _run(ix, None, [10] * nq, [L] * nq, plan, trace_cap=2048)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L, trace_cap=2048)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["dist"] == ref["d2"].astype(np.float32)).all()
+    assert (got["stats"][:, 0] == ref["ndc"]).all()
+    assert (got["stats"][:, 1] == ref["ndc"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    assert (got["stats"][:, 3] == 0).all()
+    assert (got["trace"] == ref["trace"]).all()
+
+
+def test_fp32_mode_tiny_within_tolerance_and_certified():
+    ix = tiny_index()
+    nq, L = ix["q"].shape[0], 32
+    say("case: fp32 tiny L=%d" % L)
+    plan = _plan(ix, L)
+    got = _run(ix, None, [10] * nq, [L] * nq, plan, trace_cap=2048)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L, trace_cap=2048)
+    uncertified = 0
+    for i in range(nq):
+        if (got["trace"][i] == ref["trace"][i]).all():
+            # same trajectory: same ids up to swaps of near-equal distances
+            rd = ref["d2"][i]
+            gd = got["dist"][i].astype(np.float64)
+            assert np.all(np.abs(gd - rd) <= 1e-5 * np.maximum(rd, 1e-6))
+            for t in range(10):
+                if got["ids"][i, t] != ref["ids"][i, t]:
+                    j = list(ref["ids"][i]).index(got["ids"][i, t]) if got["ids"][i, t] in ref["ids"][i] else -1
+                    assert j >= 0 and abs(rd[j] - rd[t]) <= 1e-5 * rd[t]
+        elif not near_tie_certificate(ix["base"], ix["graph"], ix["q"][i], ix["medoid"], L,
+                                      got["trace"][i], ref["trace"][i]):
+            uncertified += 1
+    assert uncertified == 0
+
+
+@pytest.mark.parametrize("L", [10, 64, 200])
+def test_fp32_bitwise_on_integer_data(L):
+    ix = int_index()
+    nq = ix["q"].shape[0]
+    say("case: fp32 int20k L=%d" % L)
+    plan = _plan(ix, L)
+    got = _run(ix, None, [10] * nq, [L] * nq, plan, trace_cap=4096)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L, trace_cap=4096)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["dist"] == ref["d2"].astype(np.float32)).all()
+    assert (got["stats"][:, 1] == ref["ndc"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    assert (got["trace"] == ref["trace"]).all()
+
+
+def test_uneven_k_L_and_entries():
+    ix = int_index()
+    nq = ix["q"].shape[0]
+    r = np.random.default_rng(0)
+    ks = r.choice([1, 5, 10, 37], size=nq)
+    Ls = np.maximum(ks, r.choice([8, 40, 77, 129, 250], size=nq))
+    ents = r.integers(0, ix["base"].shape[0], size=nq).astype(np.int32)
+    say("case: uneven k/L with entries")
+    plan = _plan(ix, 256)
+    got = _run(ix, ents, ks, Ls, plan, k_max=40)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ents, ks, Ls, k_max=40)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["stats"][:, 1] == ref["ndc"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    assert np.isinf(got["dist"][ref["ids"] < 0]).all()
+
+
+def test_lossy_visited_table_keeps_results_exact():
+    # 10k ids need 313 bitset words; 2^8 slots forces the hash table, which
+    # overflows and forgets ids: results, hops and the unique count stay exact
+    ix = int_index()
+    nq, L = ix["q"].shape[0], 100
+    say("case: lossy visited L=%d" % L)
+    plan = _plan(ix, L, visited_log2=8)
+    got = _run(ix, None, [10] * nq, [L] * nq, plan, trace_cap=4096)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L, trace_cap=4096)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    assert (got["trace"] == ref["trace"]).all()
+    assert (got["stats"][:, 1] >= ref["ndc"]).all()
+    over = got["stats"][:, 3] & 1
+    assert over.any()
+    # without overflow the unique count is exact
+    ok = over == 0
+    assert (got["stats"][ok, 0] == ref["ndc"][ok]).all()
+
+
+def test_ragged_batches_and_invalid_rows():
+    ix = int_index()
+    base, g = ix["base"], ix["graph"]
+    ann = _ann()
+    for nq in (1, 3, 65):
+        say("case: ragged nq=%d" % nq)
+        q = ix["q"][:nq]
+        sub = dict(ix, q=q)
+        got = _run(sub, None, [10] * nq, [32] * nq, _plan(ix, 32))
+        ref = oracle.search(base, g, q, ix["medoid"], 10, 32)
+        assert (got["ids"] == ref["ids"]).all()
+    # empty batch is a no-op
+    say("case: nq=0")
+    ids, dist, st, _ = ann.ann_search(_dev(base), _dev(g), _dev(ix["q"][:0]), None, ix["medoid"], 1, 1,
+                                      k_max=1)
+    torch.cuda.synchronize()
+    assert ids.shape == (0, 1)
+    # per-query invalid arguments: k > L, L > pool_cap, entry out of range
+    say("case: invalid rows")
+    q = ix["q"][:4]
+    plan = _plan(ix, 64)
+    got = _run(dict(ix, q=q), [0, 0, base.shape[0], 5], [10, 20, 5, 5], [5, 20, 10, 400], plan)
+    assert (got["stats"][:, 3] == np.array([2, 0, 2, 2])).all()
+    assert (got["ids"][[0, 2, 3]] == -1).all()
+    assert (got["ids"][1] >= 0).all()
+
+
+def test_k_equals_L_equals_1():
+    ix = int_index()
+    nq = ix["q"].shape[0]
+    say("case: k=L=1")
+    got = _run(ix, None, [1] * nq, [1] * nq, _plan(ix, 1))
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 1, 1)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+
+
+def test_group16_and_multiwave_blocks_agree():
+    ix = int_index()
+    nq, L = ix["q"].shape[0], 64
+    say("case: group16 / wpb=4")
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L)
+    for kw in (dict(group=16), dict(waves_per_block=4), dict(waves_per_block=2, blocks=3)):
+        got = _run(ix, None, [10] * nq, [L] * nq, _plan(ix, L, **kw))
+        assert (got["ids"] == ref["ids"]).all(), kw
+        assert (got["stats"][:, 1] == ref["ndc"]).all(), kw
