@@ -123,6 +123,47 @@ ann_status ann_search(const float *base, int64_t n, int32_t dim,
                       const ann_search_plan *plan,
                       void *workspace, size_t ws_bytes, void *stream);
 
+
+/* ------------------------------------------------------------------------ */
+/* Graph construction (the proximity graph G of Definition 1).              */
+
+/* Exact k nearest neighbours of each query among the base vectors (the
+ * ground truth of the recall of Eq. 1).  Rows ordered by (squared L2, id).
+ *   base        n x dim FP32; queries nq x dim FP32
+ *   exclude_self  nonzero: query i is base row i and id i is skipped
+ *   out_ids     nq x k int32 (-1 padded when n < k), out_dist nq x k FP32
+ *   workspace   ann_workspace_size(ANN_OP_GT_KNN, n, dim, nq, k) bytes
+ * Data whose values are all integers in [0,255] with dim % 32 == 0 run on the
+ * int8 matrix cores (exact); other data use FP64 distances (exact on data
+ * held on a dyadic grid).  Synchronises `stream`. */
+ann_status ann_gt_knn(const float *base, int64_t n, int32_t dim, const float *queries,
+                      int32_t nq, int32_t k, int32_t exclude_self, int32_t *out_ids,
+                      float *out_dist, void *workspace, size_t ws_bytes, void *stream);
+
+/* The medoid (navigating node): the base point nearest the FP64 mean, by
+ * (squared distance summed in dimension order, id).  *medoid is a host
+ * pointer.  workspace: ann_workspace_size(ANN_OP_BUILD_GRAPH, n, dim, 1, 3)
+ * is always enough.  Synchronises `stream`. */
+ann_status ann_medoid(const float *base, int64_t n, int32_t dim, int32_t *medoid,
+                      void *workspace, size_t ws_bytes, void *stream);
+
+/* Proximity graph: exact kNN (knn_k, self excluded) -> alpha-RNG pruning to
+ * at most R-2 neighbours (candidate c is dropped when a kept o has
+ * alpha^2 d2(o,c) <= d2(p,c); alpha^2 is formed in FP64 from the FP32 alpha)
+ * -> medoid -> connectivity repair: slot R-2 receives forward bridges (the
+ * smallest unreached id, linked from its nearest reached node with that slot
+ * free) and slot R-1 reverse bridges (the smallest id that cannot reach the
+ * medoid, linked to its nearest node that can).  Afterwards every node is
+ * reachable from the medoid and reaches it.
+ *   graph    n x R int32 output, -1 padded
+ *   medoid   host int32 output
+ *   bridges  host int32[2] output (forward, reverse bridge counts) or NULL
+ *   workspace ann_workspace_size(ANN_OP_BUILD_GRAPH, n, dim, knn_k, R)
+ * Requires 3 <= R <= 64, R-2 <= knn_k < n, alpha >= 1.  Synchronises. */
+ann_status ann_build_graph(const float *base, int64_t n, int32_t dim, int32_t knn_k, int32_t R,
+                           float alpha, int32_t *graph, int32_t *medoid, int32_t *bridges,
+                           void *workspace, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

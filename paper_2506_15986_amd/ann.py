@@ -66,6 +66,12 @@ _sig("ann_search", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _I32, _P, _P, _
      _P, _I32, ctypes.POINTER(ann_search_plan), _P, _SZ, _P)
 
 
+_sig("ann_gt_knn", _I32, _P, _I64, _I32, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P)
+_sig("ann_medoid", _I32, _P, _I64, _I32, ctypes.POINTER(_I32), _P, _SZ, _P)
+_sig("ann_build_graph", _I32, _P, _I64, _I32, _I32, _I32, _F32, _P, ctypes.POINTER(_I32),
+     ctypes.POINTER(_I32 * 2), _P, _SZ, _P)
+
+
 def last_error() -> str:
     return _lib.ann_last_error().decode()
 
@@ -154,3 +160,44 @@ def ann_search(base: torch.Tensor, graph: torch.Tensor, queries: torch.Tensor,
                            ctypes.byref(plan) if plan is not None else None,
                            _ptr(ws), ws.numel(), _stream(stream)))
     return ids, dist, stats, trace
+
+
+def ann_gt_knn(base: torch.Tensor, queries: torch.Tensor, k: int, exclude_self: bool = False,
+               stream=None):
+    """Exact top-k by (squared L2, id).  Returns (ids int32 [nq,k], dist float32)."""
+    _dev(base, torch.float32)
+    _dev(queries, torch.float32)
+    n, dim = base.shape
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=base.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=base.device)
+    ws = workspace("gt_knn", n, dim, nq, k, device=base.device)
+    _check(_lib.ann_gt_knn(_ptr(base), n, dim, _ptr(queries), nq, k, int(exclude_self),
+                           _ptr(ids), _ptr(dist), _ptr(ws), ws.numel(), _stream(stream)))
+    return ids, dist
+
+
+def ann_medoid(base: torch.Tensor, stream=None) -> int:
+    _dev(base, torch.float32)
+    n, dim = base.shape
+    ws = workspace("build_graph", n, dim, 1, 3, device=base.device)
+    m = _I32(-1)
+    _check(_lib.ann_medoid(_ptr(base), n, dim, ctypes.byref(m), _ptr(ws), ws.numel(),
+                           _stream(stream)))
+    return int(m.value)
+
+
+def ann_build_graph(base: torch.Tensor, knn_k: int, R: int, alpha: float, stream=None):
+    """kNN -> alpha prune -> medoid -> repair.  Returns (graph int32 [n,R],
+    medoid, (forward bridges, reverse bridges))."""
+    _dev(base, torch.float32)
+    n, dim = base.shape
+    graph = torch.empty((n, R), dtype=torch.int32, device=base.device)
+    ws = workspace("build_graph", n, dim, knn_k, R, device=base.device)
+    m = _I32(-1)
+    br = (_I32 * 2)()
+    _check(_lib.ann_build_graph(_ptr(base), n, dim, knn_k, R, float(alpha), _ptr(graph),
+                                ctypes.byref(m), ctypes.byref(br), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    del ws
+    return graph, int(m.value), (int(br[0]), int(br[1]))

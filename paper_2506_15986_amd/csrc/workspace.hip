@@ -1,5 +1,7 @@
 // Workspace sizing for every operation (caller-allocated scratch).
-#include "common.h"
+#include "internal.h"
+
+using namespace ann;
 
 extern "C" size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t p0, int32_t p1)
 {
@@ -7,6 +9,10 @@ extern "C" size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t
     switch (op) {
     case ANN_OP_SEARCH:
         return 256;
+    case ANN_OP_BUILD_GRAPH:
+        return build_graph_ws(n, dim, p0, p1);
+    case ANN_OP_GT_KNN:
+        return knn_workspace(n, p0, dim, p1);
     default:
         break;
     }

@@ -1,0 +1,107 @@
+"""GPU parity of the graph-construction entry points (exact kNN, medoid,
+alpha pruning + repair) against the CPU oracle: bit-exact ids."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_15986_amd import synth
+from tests.common import int_index, say, tiny_index
+
+pytestmark = pytest.mark.gpu
+
+
+def _ann():
+    from paper_2506_15986_amd import ann
+    return ann
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_gt_knn_fp64_engine_tiny_exact():
+    ix = tiny_index()
+    say("case: gt_knn fp64 tiny")
+    ids, dist = _ann().ann_gt_knn(_dev(ix["base"]), _dev(ix["q"]), 10)
+    torch.cuda.synchronize()
+    assert (ids.cpu().numpy() == ix["truth"]).all()
+    assert (dist.cpu().numpy() == ix["truth_d2"].astype(np.float32)).all()
+
+
+def test_gt_knn_int8_engine_exact():
+    ix = int_index()
+    say("case: gt_knn int8 20k")
+    ids, dist = _ann().ann_gt_knn(_dev(ix["base"]), _dev(ix["q"]), 10)
+    torch.cuda.synchronize()
+    assert (ids.cpu().numpy() == ix["truth"]).all()
+    assert (dist.cpu().numpy() == ix["truth_d2"].astype(np.float32)).all()
+
+
+@pytest.mark.parametrize("n,nq,d,k,ints", [(1000, 77, 32, 13, False), (999, 65, 64, 130, True),
+                                             (300, 1, 96, 300, False), (257, 200, 128, 5, True)])
+def test_gt_knn_ragged_shapes(n, nq, d, k, ints):
+    r = np.random.default_rng(n + nq)
+    if ints:
+        base = r.integers(0, 256, size=(n, d)).astype(np.float32)
+        q = r.integers(0, 256, size=(nq, d)).astype(np.float32)
+    else:
+        base = (np.rint(r.normal(size=(n, d)) * 2 ** 12) / 2 ** 12).astype(np.float32)
+        q = (np.rint(r.normal(size=(nq, d)) * 2 ** 12) / 2 ** 12).astype(np.float32)
+    say("case: gt_knn n=%d nq=%d d=%d k=%d ints=%s" % (n, nq, d, k, ints))
+    ids, dist = _ann().ann_gt_knn(_dev(base), _dev(q), k)
+    torch.cuda.synchronize()
+    ref_ids, ref_d2 = oracle.knn(base, q, k)
+    assert (ids.cpu().numpy() == ref_ids).all()
+    assert (dist.cpu().numpy()[ref_ids >= 0] == ref_d2[ref_ids >= 0].astype(np.float32)).all()
+
+
+def test_gt_knn_duplicates_tie_by_id_and_exclude_self():
+    r = np.random.default_rng(3)
+    base = r.integers(0, 4, size=(500, 32)).astype(np.float32)   # many exact ties
+    base[100:110] = base[7]
+    say("case: gt_knn ties")
+    ids, dist = _ann().ann_gt_knn(_dev(base), _dev(base), 20, exclude_self=True)
+    torch.cuda.synchronize()
+    ref_ids, _ = oracle.knn(base, base, 20, exclude_self=True)
+    assert (ids.cpu().numpy() == ref_ids).all()
+
+
+def test_medoid_matches_oracle():
+    ix = tiny_index()
+    say("case: medoid")
+    assert _ann().ann_medoid(_dev(ix["base"])) == ix["medoid"]
+    ii = int_index()
+    assert _ann().ann_medoid(_dev(ii["base"])) == ii["medoid"]
+
+
+def test_build_graph_tiny_bit_exact():
+    ix = tiny_index()
+    say("case: build_graph tiny")
+    g, med, (nf, nr) = _ann().ann_build_graph(_dev(ix["base"]), 64, 16, 1.2)
+    torch.cuda.synchronize()
+    assert med == ix["medoid"]
+    assert (nf, nr) == (ix["nf"], ix["nr"])
+    assert (g.cpu().numpy() == ix["graph"]).all()
+
+
+def test_build_graph_int_bit_exact():
+    ix = int_index()
+    say("case: build_graph int 20k")
+    g, med, (nf, nr) = _ann().ann_build_graph(_dev(ix["base"]), 64, 32, 1.2)
+    torch.cuda.synchronize()
+    assert med == ix["medoid"]
+    assert (nf, nr) == (ix["nf"], ix["nr"])
+    assert (g.cpu().numpy() == ix["graph"]).all()
+
+
+def test_build_graph_small_alpha_variants():
+    w = synth.scaled(synth.WORKLOADS["tiny"], n=1200)
+    base = synth.base(w)
+    for alpha, K, R in ((1.0, 24, 8), (2.0, 40, 12)):
+        say("case: build_graph alpha=%.1f K=%d R=%d" % (alpha, K, R))
+        ref, med, nf, nr, _, _ = oracle.build_graph(base, K, R, alpha)
+        g, gm, (gf, gr) = _ann().ann_build_graph(_dev(base), K, R, alpha)
+        torch.cuda.synchronize()
+        assert gm == med and (gf, gr) == (nf, nr)
+        assert (g.cpu().numpy() == ref).all()
