@@ -164,6 +164,53 @@ ann_status ann_build_graph(const float *base, int64_t n, int32_t dim, int32_t kn
                            float alpha, int32_t *graph, int32_t *medoid, int32_t *bridges,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Hub nodes and their topology features (hub extraction and feature         */
+/* distillation sections).                                                   */
+
+/* Hub nodes (Definition 3) on Lloyd k-means clusters.  init_ids (n_hubs
+ * base ids, device) seed the centroids.  Each step assigns every point to
+ * argmin_c (d2(x, mu_c), c) with d2 the FP64 sum over dimensions in order
+ * without fused multiply-add, then sets mu_c to the FP64 mean of its members
+ * (an empty cluster keeps its centroid); the loop stops after a step that
+ * changes no assignment or after `iters` steps.  hub_ids[c] is the member of
+ * cluster c nearest mu_c by (d2, id); an empty cluster takes the nearest
+ * point that is not yet a hub, in cluster order.
+ *   centroids  n_hubs x dim FP64 output or NULL; assign n int32 output or NULL
+ *   steps      host int32 output (assignment steps run) or NULL
+ *   workspace  ann_workspace_size(ANN_OP_SELECT_HUBS, n, dim, n_hubs, 0)
+ * Synchronises `stream`. */
+ann_status ann_select_hubs(const float *base, int64_t n, int32_t dim, int32_t n_hubs,
+                           int32_t iters, const int32_t *init_ids, int32_t *hub_ids,
+                           double *centroids, int32_t *assign, int32_t *steps,
+                           void *workspace, size_t ws_bytes, void *stream);
+
+/* 32 topology features per hub, standardised per column across hubs
+ * (population std; a constant column becomes 0) unless standardise == 0.
+ * A guided walk of at most h hops and wcap nodes samples, at each node u,
+ * the ceil(x/2) nearest and floor(x/2) farthest neighbours with
+ * x = max(2, ceil(MinDeg * deg(u) / MaxDeg)).  With nu the mean distance of
+ * a node to its first neighbour slot, the columns are:
+ *   0 out-degree / R            1 in-degree / mean in-degree
+ *   2-6 log2(1 + walk nodes first reached at hop 1..5)
+ *   7 log2(1 + sampled walk edges)
+ *   8-11 mean, min, max, std of dist(hub, out-neighbour) / nu
+ *   12-15 the same over the walk nodes
+ *   16 cluster size / (n / n_hubs)   17 dist(hub, centroid) / nu
+ *   18 dist(hub, medoid) / nu        19 share of walk nodes in other clusters
+ *   20 mean out-degree / R and 21 mean in-degree / mean in-degree of walk nodes
+ *   22 mean sampled-edge length / nu  23 deepest walk hop / h   24-31 zero
+ *   assign     n int32 cluster of each point; centroids n_hubs x dim FP64
+ *   features   n_hubs x 32 FP32 output; walk_sizes n_hubs x 6 int32 or NULL
+ *              (walk nodes per hop 0..5)
+ *   workspace  ann_workspace_size(ANN_OP_HUB_FEATURES, n, dim, n_hubs, R) */
+ann_status ann_hub_features(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                            int32_t R, int32_t medoid, const int32_t *hub_ids, int32_t n_hubs,
+                            const int32_t *assign, const double *centroids, int32_t h,
+                            int32_t wcap, int32_t standardise, float *features,
+                            int32_t *walk_sizes, void *workspace, size_t ws_bytes,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

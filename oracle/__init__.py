@@ -59,6 +59,9 @@ def _declare(L):
     L.oracle_hub_graph.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
     L.oracle_hub_medoid.argtypes = [_P, ctypes.c_int, ctypes.c_int]
     L.oracle_hub_medoid.restype = _I32
+    L.oracle_hub_features.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _I32, _P,
+                                      ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _P, _P]
     L.oracle_entry_select.argtypes = [_P, _I64, _P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
                                       _P, _I32, ctypes.c_int, _F64, _I32, _P, _P, _P]
 
@@ -214,6 +217,24 @@ def entry_select(qemb, hemb, hg, hub_ids, Lh: int, theta: float, med: int,
                               _ptr(hub_ids), int(hub_entry), Lh, float(theta), int(med),
                               _ptr(ent), _ptr(sc), _ptr(bh))
     return ent, sc, bh
+
+
+def hub_features(base, graph, med: int, hub_ids, assign, centroids, h: int = 5,
+                 wcap: int = 4096, standardize: bool = True):
+    """32 topology features per hub from a guided walk (see oracle.c).
+    Returns (features nh x 32 float64, walk node counts per depth nh x 6)."""
+    base = _f32(base)
+    graph = _i32(graph)
+    hub_ids = _i32(hub_ids)
+    assign = _i32(assign)
+    centroids = np.ascontiguousarray(centroids, np.float64)
+    nh = hub_ids.shape[0]
+    f = np.empty((nh, 32), np.float64)
+    ws = np.empty((nh, 6), np.int32)
+    lib().oracle_hub_features(_ptr(base), base.shape[0], base.shape[1], _ptr(graph), graph.shape[1],
+                              int(med), _ptr(hub_ids), nh, _ptr(assign), _ptr(centroids), h, wcap,
+                              int(standardize), _ptr(f), _ptr(ws))
+    return f, ws
 
 
 def recall(found_ids, truth_ids, k: int) -> np.ndarray:

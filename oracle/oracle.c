@@ -596,3 +596,181 @@ void oracle_entry_select(const float *qemb, i64 nq, const float *hemb, int nh, i
         free(pool);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Topology features of the hub nodes (feature distillation section).       */
+/* The paper samples a subgraph around each hub by a guided walk and embeds   */
+/* it with Graph2Vec; here the walk is kept and the embedding is replaced by  */
+/* 32 plain statistics of the hub, its neighbourhood and the walk subgraph.   */
+/*                                                                            */
+/* Guided walk from hub v (max hop h): a FIFO over the subgraph's node list.  */
+/* A dequeued node u samples x = max(2, ceil(MinDeg * deg(u) / MaxDeg)) of its */
+/* neighbours: the ceil(x/2) nearest and the floor(x/2) farthest by (d2, id)  */
+/* (all of them when deg(u) <= x).  Each sampled edge counts; a sampled node  */
+/* not yet in the subgraph joins it (while it has fewer than wcap nodes) one  */
+/* hop deeper than u and is expanded later if its depth is below h.           */
+/* MinDeg / MaxDeg: smallest / largest out-degree over nodes with one.        */
+/*                                                                            */
+/* Features (nu = mean distance of a node to its first neighbour slot):       */
+/*  0 out-degree/R          1 in-degree/mean in-degree                         */
+/*  2-6 log2(1 + walk nodes at depth 1..5)   7 log2(1 + walk edges)            */
+/*  8-11 mean/min/max/std of dist(v, out-neighbour)/nu                         */
+/*  12-15 mean/min/max/std of dist(v, walk node)/nu                            */
+/*  16 cluster size/(n/n_h)  17 dist(v, centroid)/nu  18 dist(v, medoid)/nu     */
+/*  19 share of walk nodes in another cluster                                  */
+/*  20 mean out-degree/R and 21 mean in-degree/mean in-degree of walk nodes     */
+/*  22 mean walk-edge length/nu   23 deepest walk depth/h   24-31 zero         */
+/* Each column is then standardised across hubs (population std; 0 if none). */
+
+static int cmp_dkey(const void *a, const void *b)
+{
+    const double *x = (const double *)a, *y = (const double *)b;
+    if (x[0] < y[0]) return -1;
+    if (x[0] > y[0]) return 1;
+    return (x[1] < y[1]) ? -1 : (x[1] > y[1]);
+}
+
+static void stats4(const double *v, int m, double *out)
+{
+    if (m == 0) { out[0] = out[1] = out[2] = out[3] = 0.0; return; }
+    double s = 0.0, lo = v[0], hi = v[0];
+    for (int i = 0; i < m; ++i) { s += v[i]; if (v[i] < lo) lo = v[i]; if (v[i] > hi) hi = v[i]; }
+    double mean = s / m, q = 0.0;
+    for (int i = 0; i < m; ++i) q += (v[i] - mean) * (v[i] - mean);
+    out[0] = mean; out[1] = lo; out[2] = hi; out[3] = sqrt(q / m);
+}
+
+void oracle_hub_features(const float *base, i64 n, int d, const i32 *graph, int R, i32 medoid,
+                         const i32 *hub_ids, int nh, const i32 *assign, const double *centroids,
+                         int h, int wcap, int standardize, double *feat /* nh x 32 */,
+                         i32 *walk_sizes /* nh x 6 */)
+{
+    int *deg = (int *)calloc((size_t)n, sizeof(int));
+    i64 *indeg = (i64 *)calloc((size_t)n, sizeof(i64));
+    i64 *csize = (i64 *)calloc((size_t)nh, sizeof(i64));
+    int mindeg = 1 << 30, maxdeg = 0;
+    double nu = 0.0;
+    i64 nu_cnt = 0, edges = 0;
+    for (i64 v = 0; v < n; ++v) {
+        int c = 0;
+        i32 first = -1;
+        for (int s = 0; s < R; ++s) {
+            i32 w = graph[v * R + s];
+            if (w < 0) continue;
+            if (first < 0) first = w;
+            ++c;
+            indeg[w]++;
+        }
+        deg[v] = c;
+        edges += c;
+        if (c > 0) {
+            if (c < mindeg) mindeg = c;
+            if (c > maxdeg) maxdeg = c;
+            nu += sqrt(d2(base + v * d, base + (i64)first * d, d));
+            nu_cnt++;
+        }
+        csize[assign[v]]++;
+    }
+    nu /= (double)nu_cnt;
+    const double mean_in = (double)edges / (double)n;
+
+    i32 *S = (i32 *)malloc(sizeof(i32) * (size_t)wcap);
+    int *depth = (int *)malloc(sizeof(int) * (size_t)wcap);
+    unsigned char *in_s = (unsigned char *)calloc((size_t)n, 1);
+    double *buf = (double *)malloc(sizeof(double) * (size_t)(2 * (R > wcap ? R : wcap) + 2));
+    double *vals = (double *)malloc(sizeof(double) * (size_t)(wcap > R ? wcap : R));
+
+    for (int c = 0; c < nh; ++c) {
+        double *f = feat + (i64)c * 32;
+        for (int t = 0; t < 32; ++t) f[t] = 0.0;
+        const i32 v = hub_ids[c];
+        int ns = 0, head = 0;
+        i64 wedges = 0;
+        double wlen = 0.0;
+        S[ns] = v; depth[ns] = 0; ns++; in_s[v] = 1;
+        while (head < ns) {
+            int hu = head++;
+            if (depth[hu] >= h) continue;
+            i32 u = S[hu];
+            int du = deg[u];
+            int x = (int)(((i64)mindeg * du + maxdeg - 1) / maxdeg);
+            if (x < 2) x = 2;
+            int m = 0;
+            for (int s = 0; s < R; ++s) {
+                i32 w = graph[(i64)u * R + s];
+                if (w < 0) continue;
+                buf[2 * m] = d2(base + (i64)u * d, base + (i64)w * d, d);
+                buf[2 * m + 1] = (double)w;
+                ++m;
+            }
+            qsort(buf, (size_t)m, 2 * sizeof(double), cmp_dkey);
+            int lo_n = m <= x ? m : (x + 1) / 2;
+            int hi_n = m <= x ? 0 : x / 2;
+            for (int q = 0; q < lo_n + hi_n; ++q) {
+                int idx = q < lo_n ? q : m - hi_n + (q - lo_n);
+                i32 w = (i32)buf[2 * idx + 1];
+                wedges++;
+                wlen += sqrt(buf[2 * idx]);
+                if (!in_s[w] && ns < wcap) {
+                    in_s[w] = 1;
+                    S[ns] = w;
+                    depth[ns] = depth[hu] + 1;
+                    ns++;
+                }
+            }
+        }
+        int cnt_d[6] = {0, 0, 0, 0, 0, 0};
+        int maxd = 0;
+        for (int q = 0; q < ns; ++q) {
+            if (depth[q] <= 5) cnt_d[depth[q]]++;
+            if (depth[q] > maxd) maxd = depth[q];
+        }
+        if (walk_sizes) {
+            for (int t = 0; t < 6; ++t) walk_sizes[c * 6 + t] = cnt_d[t];
+        }
+        f[0] = (double)deg[v] / R;
+        f[1] = (double)indeg[v] / mean_in;
+        for (int t = 1; t <= 5; ++t) f[1 + t] = log2(1.0 + cnt_d[t]);
+        f[7] = log2(1.0 + (double)wedges);
+        int m = 0;
+        for (int s = 0; s < R; ++s) {
+            i32 w = graph[(i64)v * R + s];
+            if (w < 0) continue;
+            vals[m++] = sqrt(d2(base + (i64)v * d, base + (i64)w * d, d)) / nu;
+        }
+        stats4(vals, m, f + 8);
+        m = 0;
+        for (int q = 1; q < ns; ++q) vals[m++] = sqrt(d2(base + (i64)v * d, base + (i64)S[q] * d, d)) / nu;
+        stats4(vals, m, f + 12);
+        f[16] = (double)csize[c] / ((double)n / nh);
+        f[17] = sqrt(d2_mixed(base + (i64)v * d, centroids + (i64)c * d, d)) / nu;
+        f[18] = sqrt(d2(base + (i64)v * d, base + (i64)medoid * d, d)) / nu;
+        int other = 0;
+        double so = 0.0, si = 0.0;
+        for (int q = 0; q < ns; ++q) {
+            if (q > 0 && assign[S[q]] != c) other++;
+            so += deg[S[q]];
+            si += (double)indeg[S[q]];
+        }
+        f[19] = ns > 1 ? (double)other / (ns - 1) : 0.0;
+        f[20] = so / ns / R;
+        f[21] = si / ns / mean_in;
+        f[22] = wedges > 0 ? (wlen / (double)wedges) / nu : 0.0;
+        f[23] = (double)maxd / h;
+        for (int q = 0; q < ns; ++q) in_s[S[q]] = 0;
+    }
+    /* standardise columns */
+    for (int t = 0; t < 32 && standardize; ++t) {
+        double s = 0.0;
+        for (int c = 0; c < nh; ++c) s += feat[(i64)c * 32 + t];
+        double mean = s / nh, q = 0.0;
+        for (int c = 0; c < nh; ++c) {
+            double z = feat[(i64)c * 32 + t] - mean;
+            q += z * z;
+        }
+        double sd = sqrt(q / nh);
+        for (int c = 0; c < nh; ++c)
+            feat[(i64)c * 32 + t] = sd > 0 ? (feat[(i64)c * 32 + t] - mean) / sd : 0.0;
+    }
+    free(vals); free(buf); free(in_s); free(depth); free(S); free(csize); free(indeg); free(deg);
+}

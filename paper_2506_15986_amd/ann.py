@@ -70,6 +70,10 @@ _sig("ann_gt_knn", _I32, _P, _I64, _I32, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, 
 _sig("ann_medoid", _I32, _P, _I64, _I32, ctypes.POINTER(_I32), _P, _SZ, _P)
 _sig("ann_build_graph", _I32, _P, _I64, _I32, _I32, _I32, _F32, _P, ctypes.POINTER(_I32),
      ctypes.POINTER(_I32 * 2), _P, _SZ, _P)
+_sig("ann_select_hubs", _I32, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P, ctypes.POINTER(_I32),
+     _P, _SZ, _P)
+_sig("ann_hub_features", _I32, _P, _I64, _I32, _P, _I32, _I32, _P, _I32, _P, _P, _I32, _I32,
+     _I32, _P, _P, _P, _SZ, _P)
 
 
 def last_error() -> str:
@@ -201,3 +205,38 @@ def ann_build_graph(base: torch.Tensor, knn_k: int, R: int, alpha: float, stream
                                 _stream(stream)))
     del ws
     return graph, int(m.value), (int(br[0]), int(br[1]))
+
+
+def ann_select_hubs(base: torch.Tensor, n_hubs: int, iters: int, init_ids: torch.Tensor,
+                    stream=None):
+    """Lloyd k-means + Definition 3 hubs.  Returns (hub_ids int32, centroids
+    float64 [n_hubs, dim], assign int32 [n], steps)."""
+    _dev(base, torch.float32)
+    _dev(init_ids, torch.int32)
+    n, dim = base.shape
+    dev = base.device
+    hub = torch.empty(n_hubs, dtype=torch.int32, device=dev)
+    cen = torch.empty((n_hubs, dim), dtype=torch.float64, device=dev)
+    asg = torch.empty(n, dtype=torch.int32, device=dev)
+    steps = _I32(0)
+    ws = workspace("select_hubs", n, dim, n_hubs, 0, device=dev)
+    _check(_lib.ann_select_hubs(_ptr(base), n, dim, n_hubs, iters, _ptr(init_ids), _ptr(hub),
+                                _ptr(cen), _ptr(asg), ctypes.byref(steps), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    return hub, cen, asg, int(steps.value)
+
+
+def ann_hub_features(base, graph, medoid: int, hub_ids, assign, centroids, h: int = 5,
+                     wcap: int = 4096, standardise: bool = True, stream=None):
+    """Returns (features float32 [n_hubs, 32], walk sizes int32 [n_hubs, 6])."""
+    n, dim = base.shape
+    nh = hub_ids.shape[0]
+    R = graph.shape[1]
+    dev = base.device
+    f = torch.empty((nh, 32), dtype=torch.float32, device=dev)
+    wsz = torch.empty((nh, 6), dtype=torch.int32, device=dev)
+    ws = workspace("hub_features", n, dim, nh, R, device=dev)
+    _check(_lib.ann_hub_features(_ptr(base), n, dim, _ptr(graph), R, int(medoid), _ptr(hub_ids),
+                                 nh, _ptr(assign), _ptr(centroids), h, wcap, int(standardise),
+                                 _ptr(f), _ptr(wsz), _ptr(ws), ws.numel(), _stream(stream)))
+    return f, wsz

@@ -18,5 +18,7 @@ struct Carve {
 size_t knn_workspace(int64_t n, int64_t rows, int dim, int K);
 size_t build_graph_ws(int64_t n, int dim, int K, int R);
 size_t medoid_ws(int64_t n, int dim);
+size_t select_hubs_ws(int64_t n, int dim, int nh);
+size_t hub_features_ws(int64_t n, int nh);
 
 }  // namespace ann

@@ -1,0 +1,352 @@
+// Hub nodes (Definition 3) on Lloyd k-means clusters.
+//
+// Assignment: each point goes to argmin_c (d2(x, mu_c), c) where d2 is the
+// FP64 sum over dimensions in order, each term (x_j - mu_cj)^2 rounded
+// separately (no fused multiply-add) -- the same arithmetic as a plain
+// sequential loop, so every decision is reproducible bit for bit.  A block
+// stages 64 points in LDS and streams the centroids through LDS in chunks of
+// 32; wavefront w of the block scores centroids 8w..8w+7 of each chunk for
+// all 64 points.
+// Update: per-cluster FP64 sums by atomic adds (exact when the data sit on a
+// dyadic grid whose partial sums fit in 53 bits, so order does not matter),
+// mean = sum / count; an empty cluster keeps its centroid.  The loop stops
+// after an assignment step that changes nothing, or after `iters` steps.
+// Hub of a cluster: the member nearest its mean by (d2, id); an empty
+// cluster takes the nearest point that is not yet a hub (cluster order).
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+namespace ann {
+namespace {
+
+constexpr int KP = 64;    // points per block
+constexpr int KC = 32;    // centroids per LDS chunk
+constexpr int KD = 128;   // dims per LDS stage
+
+__device__ inline double term(float x, double m)
+{
+#pragma clang fp contract(off)
+    double t = (double)x - m;
+    return t * t;
+}
+
+__global__ void __launch_bounds__(256) assign_kernel(const float *base, int64_t n, int dim,
+                                                     const double *mu, int nh, int32_t *assign,
+                                                     int32_t *changed)
+{
+#pragma clang fp contract(off)
+    __shared__ float xs[KP][KD + 1];
+    __shared__ double ms[KC][KD];
+    __shared__ double bestv[4][KP];
+    __shared__ int bestc[4][KP];
+    const int t = threadIdx.x;
+    const int p = t & 63;          // point within the block
+    const int g = t >> 6;          // wave: centroids 8g..8g+7 of each chunk
+    const int64_t i = (int64_t)blockIdx.x * KP + p;
+    double bv = __longlong_as_double(0x7ff0000000000000ll);
+    int bc = 0x7fffffff;
+    for (int c0 = 0; c0 < nh; c0 += KC) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+        for (int d0 = 0; d0 < dim; d0 += KD) {
+            const int dd = dim - d0 < KD ? dim - d0 : KD;
+            __syncthreads();
+            for (int e = t; e < KP * KD; e += 256) {
+                int r = e / KD, j = e % KD;
+                int64_t g2 = (int64_t)blockIdx.x * KP + r;
+                xs[r][j] = (g2 < n && j < dd) ? base[g2 * dim + d0 + j] : 0.f;
+            }
+            for (int e = t; e < KC * KD; e += 256) {
+                int r = e / KD, j = e % KD;
+                ms[r][j] = (c0 + r < nh && j < dd) ? mu[(int64_t)(c0 + r) * dim + d0 + j] : 0.0;
+            }
+            __syncthreads();
+            for (int j = 0; j < dd; ++j) {
+                const float xv = xs[p][j];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[u] = acc[u] + term(xv, ms[8 * g + u][j]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int c = c0 + 8 * g + u;
+            if (c < nh && (acc[u] < bv || (acc[u] == bv && c < bc))) {
+                bv = acc[u];
+                bc = c;
+            }
+        }
+    }
+    bestv[g][p] = bv;
+    bestc[g][p] = bc;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        for (int q = 1; q < 4; ++q) {
+            double v = bestv[q][p];
+            int c = bestc[q][p];
+            if (v < bv || (v == bv && c < bc)) {
+                bv = v;
+                bc = c;
+            }
+        }
+        if (assign[i] != bc) {
+            assign[i] = bc;
+            *changed = 1;
+        }
+    }
+}
+
+__global__ void accumulate_kernel(const float *base, int64_t n, int dim, const int32_t *assign,
+                                  double *sums, int64_t *count)
+{
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int c = assign[i];
+    for (int j = lane; j < dim; j += 64)
+        atomicAdd(&sums[(int64_t)c * dim + j], (double)base[i * dim + j]);
+    if (lane == 0) atomicAdd((unsigned long long *)&count[c], 1ull);
+}
+
+__global__ void update_kernel(const double *sums, const int64_t *count, int nh, int dim, double *mu)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nh * dim) return;
+    const int64_t c = e / dim;
+    if (count[c] > 0) mu[e] = sums[e] / (double)count[c];
+}
+
+__device__ inline double d2_to(const float *x, const double *m, int dim)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int j = 0; j < dim; ++j) s = s + term(x[j], m[j]);
+    return s;
+}
+
+__global__ void hub_min_kernel(const float *base, int64_t n, int dim, const double *mu,
+                               const int32_t *assign, unsigned long long *best_bits)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = assign[i];
+    double v = d2_to(base + i * dim, mu + (int64_t)c * dim, dim);
+    atomicMin(&best_bits[c], (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void hub_id_kernel(const float *base, int64_t n, int dim, const double *mu,
+                              const int32_t *assign, const unsigned long long *best_bits,
+                              int32_t *hub)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = assign[i];
+    double v = d2_to(base + i * dim, mu + (int64_t)c * dim, dim);
+    if ((unsigned long long)__double_as_longlong(v) == best_bits[c]) atomicMin(&hub[c], (int32_t)i);
+}
+
+__global__ void init_mu_kernel(const float *base, int dim, const int32_t *init_ids, int nh,
+                               double *mu)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nh * dim) return;
+    const int64_t c = e / dim, j = e % dim;
+    mu[e] = (double)base[(int64_t)init_ids[c] * dim + j];
+}
+
+__global__ void fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u64(unsigned long long *p, int64_t n, unsigned long long v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_f64(double *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// nearest point to mu_c that is not flagged in `taken`; (d2, id) order
+struct Best {
+    double v;
+    int64_t id;
+};
+
+__global__ void __launch_bounds__(256) empty_scan_kernel(const float *base, int64_t n, int dim,
+                                                         const double *m, const int32_t *taken,
+                                                         Best *partial)
+{
+    __shared__ Best sh[256];
+    Best b{__longlong_as_double(0x7ff0000000000000ll), 0x7fffffffffffffffll};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (taken[i]) continue;
+        double v = d2_to(base + i * dim, m, dim);
+        if (v < b.v || (v == b.v && i < b.id)) b = Best{v, i};
+    }
+    sh[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            Best o = sh[threadIdx.x + s];
+            if (o.v < sh[threadIdx.x].v || (o.v == sh[threadIdx.x].v && o.id < sh[threadIdx.x].id))
+                sh[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void mark_taken_kernel(const int32_t *hub, int nh, int32_t *taken)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nh && hub[c] >= 0) taken[hub[c]] = 1;
+}
+
+inline int grid_for(int64_t n, int per = 256, int cap = 8192)
+{
+    int64_t b = (n + per - 1) / per;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+
+size_t select_hubs_ws(int64_t n, int dim, int nh)
+{
+    size_t b = round_up((size_t)nh * dim * 8, 256) * 2;       // mu, sums
+    b += round_up((size_t)nh * 8, 256) * 2;                   // count, best bits
+    b += round_up((size_t)n * 4, 256) * 2;                    // assign, taken
+    b += round_up(4096 * sizeof(Best), 256) + 1024;
+    return b;
+}
+
+ann_status select_hubs_run(const float *base, int64_t n, int dim, int nh, int iters,
+                           const int32_t *init_ids, int32_t *hub_ids, double *centroids_out,
+                           int32_t *assign_out, int32_t *steps_out, void *ws, hipStream_t st)
+{
+    Carve cv{static_cast<unsigned char *>(ws)};
+    double *mu = centroids_out ? centroids_out : cv.take<double>((size_t)nh * dim);
+    if (centroids_out) cv.take<double>((size_t)nh * dim);
+    double *sums = cv.take<double>((size_t)nh * dim);
+    int64_t *count = cv.take<int64_t>((size_t)nh);
+    unsigned long long *bits = cv.take<unsigned long long>((size_t)nh);
+    int32_t *assign = assign_out ? assign_out : cv.take<int32_t>((size_t)n);
+    if (assign_out) cv.take<int32_t>((size_t)n);
+    int32_t *taken = cv.take<int32_t>((size_t)n);
+    Best *partial = cv.take<Best>(4096);
+    int32_t *changed = cv.take<int32_t>(64);
+
+    const int64_t md = (int64_t)nh * dim;
+    hipLaunchKernelGGL(init_mu_kernel, dim3(grid_for(md, 256, 1 << 20)), dim3(256), 0, st, base, dim,
+                       init_ids, nh, mu);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(fill_i32, dim3(grid_for(n)), dim3(256), 0, st, assign, n, -1);
+    ANN_LAUNCHED();
+    int steps = 0;
+    for (int t = 0; t < iters; ++t) {
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, changed, 1, 0);
+        ANN_LAUNCHED();
+        hipLaunchKernelGGL(assign_kernel, dim3((unsigned)((n + KP - 1) / KP)), dim3(256), 0, st, base,
+                           n, dim, mu, nh, assign, changed);
+        ANN_LAUNCHED();
+        ++steps;
+        hipLaunchKernelGGL(fill_f64, dim3(grid_for(md)), dim3(256), 0, st, sums, md);
+        ANN_LAUNCHED();
+        hipLaunchKernelGGL(fill_u64, dim3(grid_for(nh)), dim3(256), 0, st,
+                           (unsigned long long *)count, (int64_t)nh, 0ull);
+        ANN_LAUNCHED();
+        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n,
+                           dim, assign, sums, count);
+        ANN_LAUNCHED();
+        hipLaunchKernelGGL(update_kernel, dim3(grid_for(md, 256, 1 << 20)), dim3(256), 0, st, sums,
+                           count, nh, dim, mu);
+        ANN_LAUNCHED();
+        int32_t h = 0;
+        ANN_HIP(hipMemcpyAsync(&h, changed, 4, hipMemcpyDeviceToHost, st));
+        ANN_HIP(hipStreamSynchronize(st));
+        if (!h) break;
+    }
+    // hubs
+    hipLaunchKernelGGL(fill_u64, dim3(grid_for(nh)), dim3(256), 0, st, bits, (int64_t)nh,
+                       0xFFFFFFFFFFFFFFFFull);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(fill_i32, dim3(grid_for(nh)), dim3(256), 0, st, hub_ids, (int64_t)nh,
+                       0x7fffffff);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(hub_min_kernel, dim3(grid_for(n, 256, 1 << 22)), dim3(256), 0, st, base, n, dim,
+                       mu, assign, bits);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(hub_id_kernel, dim3(grid_for(n, 256, 1 << 22)), dim3(256), 0, st, base, n, dim,
+                       mu, assign, bits, hub_ids);
+    ANN_LAUNCHED();
+    // empty clusters (no member): nearest point that is not yet a hub
+    std::vector<int32_t> hh((size_t)nh);
+    ANN_HIP(hipMemcpyAsync(hh.data(), hub_ids, sizeof(int32_t) * nh, hipMemcpyDeviceToHost, st));
+    ANN_HIP(hipStreamSynchronize(st));
+    bool any_empty = false;
+    for (int c = 0; c < nh; ++c) any_empty |= (hh[c] == 0x7fffffff);
+    if (any_empty) {
+        hipLaunchKernelGGL(fill_i32, dim3(grid_for(n)), dim3(256), 0, st, taken, n, 0);
+        ANN_LAUNCHED();
+        // flag the hubs of non-empty clusters
+        for (int c = 0; c < nh; ++c)
+            if (hh[c] == 0x7fffffff) hh[c] = -1;
+        ANN_HIP(hipMemcpyAsync(hub_ids, hh.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(mark_taken_kernel, dim3(grid_for(nh)), dim3(256), 0, st, hub_ids, nh, taken);
+        ANN_LAUNCHED();
+        const int blocks = grid_for(n, 256, 1024);
+        for (int c = 0; c < nh; ++c) {
+            if (hh[c] >= 0) continue;
+            hipLaunchKernelGGL(empty_scan_kernel, dim3(blocks), dim3(256), 0, st, base, n, dim,
+                               mu + (int64_t)c * dim, taken, partial);
+            ANN_LAUNCHED();
+            std::vector<Best> pb((size_t)blocks);
+            ANN_HIP(hipMemcpyAsync(pb.data(), partial, sizeof(Best) * blocks, hipMemcpyDeviceToHost, st));
+            ANN_HIP(hipStreamSynchronize(st));
+            Best b = pb[0];
+            for (int q = 1; q < blocks; ++q)
+                if (pb[q].v < b.v || (pb[q].v == b.v && pb[q].id < b.id)) b = pb[q];
+            hh[c] = (int32_t)b.id;
+            int32_t one = 1;
+            ANN_HIP(hipMemcpyAsync(taken + b.id, &one, 4, hipMemcpyHostToDevice, st));
+            ANN_HIP(hipStreamSynchronize(st));
+        }
+        ANN_HIP(hipMemcpyAsync(hub_ids, hh.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, st));
+        ANN_HIP(hipStreamSynchronize(st));
+    }
+    if (steps_out) *steps_out = steps;
+    return ANN_OK;
+}
+
+}  // namespace ann
+
+using namespace ann;
+
+extern "C" ann_status ann_select_hubs(const float *base, int64_t n, int32_t dim, int32_t n_hubs,
+                                      int32_t iters, const int32_t *init_ids, int32_t *hub_ids,
+                                      double *centroids, int32_t *assign, int32_t *steps,
+                                      void *workspace, size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(base && init_ids && hub_ids && workspace, "a required pointer is NULL");
+    ANN_REQUIRE(n >= 1 && n <= 0x7FFFFFFF, "n must be in [1, 2^31)");
+    ANN_REQUIRE(dim >= 1, "dim must be >= 1");
+    ANN_REQUIRE(n_hubs >= 1 && n_hubs <= n, "n_hubs must be in [1, n]");
+    ANN_REQUIRE(iters >= 1, "iters must be >= 1");
+    ANN_REQUIRE(ws_bytes >= ann_workspace_size(ANN_OP_SELECT_HUBS, n, dim, n_hubs, 0),
+                "workspace too small");
+    return select_hubs_run(base, n, dim, n_hubs, iters, init_ids, hub_ids, centroids, assign, steps,
+                           workspace, static_cast<hipStream_t>(stream));
+}

@@ -13,6 +13,10 @@ extern "C" size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t
         return build_graph_ws(n, dim, p0, p1);
     case ANN_OP_GT_KNN:
         return knn_workspace(n, p0, dim, p1);
+    case ANN_OP_SELECT_HUBS:
+        return select_hubs_ws(n, dim, p0);
+    case ANN_OP_HUB_FEATURES:
+        return hub_features_ws(n, p0);
     default:
         break;
     }

@@ -1,0 +1,69 @@
+"""GPU parity of hub selection (Lloyd k-means + Definition 3) and of the hub
+topology features against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_15986_amd import synth
+from tests.common import int_index, say, tiny_index
+
+pytestmark = pytest.mark.gpu
+
+
+def _ann():
+    from paper_2506_15986_amd import ann
+    return ann
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("which,nh", [("tiny", 64), ("int", 64), ("tiny", 7)])
+def test_select_hubs_bit_exact(which, nh):
+    ix = tiny_index() if which == "tiny" else int_index()
+    base = ix["base"]
+    init = synth.kmeans_init(ix["w"], base.shape[0], nh)
+    say("case: select_hubs %s nh=%d" % (which, nh))
+    ref = oracle.kmeans_hubs(base, nh, 20, init)
+    hub, cen, asg, steps = _ann().ann_select_hubs(_dev(base), nh, 20, _dev(init))
+    torch.cuda.synchronize()
+    assert steps == ref["steps"]
+    assert (asg.cpu().numpy() == ref["assign"]).all()
+    assert (cen.cpu().numpy() == ref["centroids"]).all()
+    assert (hub.cpu().numpy() == ref["hub_ids"]).all()
+
+
+def test_select_hubs_empty_cluster():
+    x = np.zeros((8, 4), np.float32)
+    x[:, 0] = [0, 0, 10, 11, 0, 0, 10, 11]
+    x[4:, 1] = 0.5
+    init = np.array([0, 1, 2], np.int32)
+    say("case: select_hubs empty cluster")
+    ref = oracle.kmeans_hubs(x, 3, 5, init)
+    hub, cen, asg, steps = _ann().ann_select_hubs(_dev(x), 3, 5, _dev(init))
+    torch.cuda.synchronize()
+    assert (asg.cpu().numpy() == ref["assign"]).all()
+    assert (hub.cpu().numpy() == ref["hub_ids"]).all()
+
+
+def test_hub_features_match_oracle():
+    ix = tiny_index()
+    base, g, med = ix["base"], ix["graph"], ix["medoid"]
+    nh = 64
+    init = synth.kmeans_init(ix["w"], base.shape[0], nh)
+    km = oracle.kmeans_hubs(base, nh, 20, init)
+    say("case: hub features tiny")
+    ref, ref_ws = oracle.hub_features(base, g, med, km["hub_ids"], km["assign"], km["centroids"])
+    raw, _ = oracle.hub_features(base, g, med, km["hub_ids"], km["assign"], km["centroids"],
+                                 standardize=False)
+    ann = _ann()
+    args = (_dev(base), _dev(g), med, _dev(km["hub_ids"]), _dev(km["assign"]),
+            _dev(km["centroids"]))
+    f, wsz = ann.ann_hub_features(*args)
+    fr, _ = ann.ann_hub_features(*args, standardise=False)
+    torch.cuda.synchronize()
+    assert (wsz.cpu().numpy() == ref_ws).all()
+    assert np.allclose(fr.cpu().numpy(), raw, rtol=1e-5, atol=1e-6)
+    assert np.allclose(f.cpu().numpy(), ref, rtol=0, atol=1e-4)

@@ -175,3 +175,75 @@ def test_adam_first_step_moves_by_lr_times_sign():
     p1, m, v = towers.adam_update(p, g, np.zeros(20), np.zeros(20), 1, 1e-3)
     # bias-corrected m = g and v = g^2 after one step
     assert np.allclose(p - p1, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- hub features
+def _path(n):
+    base = np.zeros((n, 4), np.float32)
+    base[:, 0] = np.arange(n)
+    g = -np.ones((n, 2), np.int32)
+    for m in range(n):
+        s = 0
+        if m > 0:
+            g[m, s] = m - 1
+            s += 1
+        if m < n - 1:
+            g[m, s] = m + 1
+    return base, g
+
+
+def test_hub_features_path_graph_closed_form():
+    # unit-spaced path: MinDeg 1, MaxDeg 2 -> x = 2 = deg, so the walk is a
+    # BFS: 2 new nodes per depth 1..5, 9 expanded nodes x 2 sampled edges
+    n = 40
+    base, g = _path(n)
+    assign = np.zeros(n, np.int32)
+    hubs = np.array([20], np.int32)
+    cen = base[hubs].astype(np.float64)
+    f, ws = oracle.hub_features(base, g, 0, hubs, assign, cen, h=5, standardize=False)
+    f = f[0]
+    assert ws[0].tolist() == [1, 2, 2, 2, 2, 2]
+    assert f[0] == 1.0                                 # out-degree 2 / R 2
+    assert abs(f[1] - 2.0 / (2 * (n - 1) / n)) < 1e-12  # in-degree 2 / mean in-degree
+    assert np.allclose(f[2:7], np.log2(3.0))
+    assert abs(f[7] - np.log2(19.0)) < 1e-12
+    assert np.allclose(f[8:12], [1, 1, 1, 0])          # nu = 1
+    assert np.allclose(f[12:16], [3, 1, 5, np.sqrt(2.0)])
+    assert abs(f[16] - 1.0) < 1e-12
+    assert abs(f[18] - 20.0) < 1e-12                   # medoid at position 0
+    assert f[19] == 0.0 and abs(f[20] - 1.0) < 1e-12
+    assert abs(f[22] - 1.0) < 1e-12 and f[23] == 1.0
+    assert (f[24:] == 0).all()
+
+
+def test_hub_features_nearest_and_farthest_sampling():
+    # node 0 at the origin links to 6 points at distances 1,2,3,4,5,6; every
+    # other node has degree 1 -> MinDeg 1, MaxDeg 6, x(0) = max(2, 1) = 2:
+    # one nearest (distance 1) and one farthest (distance 6) are sampled
+    base = np.zeros((7, 4), np.float32)
+    base[1:, 0] = [3, 1, 6, 2, 5, 4]
+    g = -np.ones((7, 6), np.int32)
+    g[0] = [1, 2, 3, 4, 5, 6]
+    for v in range(1, 7):
+        g[v, 0] = 0
+    assign = np.zeros(7, np.int32)
+    f, ws = oracle.hub_features(base, g, 0, np.array([0], np.int32), assign,
+                                base[:1].astype(np.float64), h=1, standardize=False)
+    assert ws[0].tolist() == [1, 2, 0, 0, 0, 0]
+    assert abs(f[0, 7] - np.log2(3.0)) < 1e-12         # two sampled edges
+    # walk nodes are ids 2 (distance 1) and 3 (distance 6); nu is the mean
+    # distance to the first neighbour slot: (3 + 3+1+6+2+5+4) / 7
+    nu = 24.0 / 7.0
+    assert np.allclose(f[0, 12:16], np.array([3.5, 1.0, 6.0, 2.5]) / nu)
+    assert abs(f[0, 22] - 3.5 / nu) < 1e-12
+
+
+def test_hub_features_standardised_columns():
+    base, g = _path(60)
+    assign = (np.arange(60) // 20).astype(np.int32)
+    hubs = np.array([10, 30, 50], np.int32)
+    cen = np.stack([base[assign == c].astype(np.float64).mean(0) for c in range(3)])
+    f, _ = oracle.hub_features(base, g, 30, hubs, assign, cen)
+    assert np.allclose(f.mean(0), 0, atol=1e-12)
+    sd = f.std(0)
+    assert np.all((np.abs(sd - 1) < 1e-9) | (sd == 0))
