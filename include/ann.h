@@ -57,8 +57,7 @@ enum {
     ANN_OP_SELECT_HUBS = 4,
     ANN_OP_ENTRY_SELECT = 5,
     ANN_OP_MAKE_LABELS = 6,
-    ANN_OP_HUB_FEATURES = 7,
-    ANN_OP_TRAIN_STEP = 8
+    ANN_OP_HUB_FEATURES = 7
 };
 
 /* Bytes of workspace the operation needs.  Arguments per op:
@@ -69,8 +68,8 @@ enum {
  *   ENTRY_SELECT  nq, dim, p0 = hidden,   p1 = embed dim
  *   MAKE_LABELS   n, dim, p0 = nq,        p1 = M (candidates per query)
  *   HUB_FEATURES  n, dim, p0 = n_hubs,    p1 = R
- *   TRAIN_STEP    batch, dim, p0 = n_hubs, p1 = hidden
- * Returns 0 for an unknown op. */
+ * Returns 0 for an unknown op.  The tower, training and entry-selection
+ * calls have their own size functions below. */
 size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t p0, int32_t p1);
 
 /* ------------------------------------------------------------------------ */
@@ -210,6 +209,126 @@ ann_status ann_hub_features(const float *base, int64_t n, int32_t dim, const int
                             int32_t wcap, int32_t standardise, float *features,
                             int32_t *walk_sizes, void *workspace, size_t ws_bytes,
                             void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Two-tower entry model (two-tower score of the preliminaries; projection   */
+/* network and contrastive loss of the high-tier graph section).             */
+/*   tower(x) = normalise(W2 . relu(W1 . x + b1) + b2)                        */
+/* FP32 master weights with BF16 working copies; every matrix product takes  */
+/* BF16 operands (round to nearest even) and accumulates in FP32 on the      */
+/* matrix cores.  Rounded operands: the tower input, the weights, the hidden  */
+/* activation after ReLU and, backwards, the pre-activation gradients that   */
+/* enter the weight and input products.  Bias, ReLU, normalisation, logits   */
+/* and softmax stay in FP32.  Every reduction runs in a fixed order.         */
+
+typedef struct ann_tower {
+    int32_t din, hidden, dout;
+    float *W1;      /* hidden x din, FP32 master */
+    float *b1;      /* hidden */
+    float *W2;      /* dout x hidden */
+    float *b2;      /* dout */
+    uint16_t *W1b;  /* BF16 copy of W1 (bit patterns) */
+    uint16_t *W2b;  /* BF16 copy of W2 */
+} ann_tower;
+
+typedef struct ann_tower_grads {
+    float *gW1, *gb1, *gW2, *gb2;   /* same shapes as the parameters */
+} ann_tower_grads;
+
+typedef struct ann_adam_state {
+    float *mW1, *vW1, *mb1, *vb1, *mW2, *vW2, *mb2, *vb2;   /* zero-initialised */
+} ann_adam_state;
+
+/* Refreshes the BF16 copies from the FP32 masters (RNE). */
+ann_status ann_tower_sync(const ann_tower *tower, void *stream);
+
+size_t ann_tower_workspace_size(const ann_tower *tower, int32_t rows);
+
+/* Unit embeddings of `rows` FP32 input rows (rows x din) -> out (rows x dout). */
+ann_status ann_tower_forward(const ann_tower *tower, const float *x, int32_t rows, float *out,
+                             void *workspace, size_t ws_bytes, void *stream);
+
+size_t ann_train_workspace_size(int32_t batch, int32_t n_hubs, int32_t din_q, int32_t din_h,
+                                int32_t hidden, int32_t dout);
+
+/* One contrastive training step (the loss of Eq. 2 / Eq. 4 taken
+ * query-anchored over all hubs, positive inside the denominator):
+ *   L = mean_i [ logsumexp_h(s_ih) - s_i,y_i ],  s_ih = <e_q_i, e_h> / tau
+ * with e_q = query tower of train_q[batch_idx[i]] and e_h = hub tower of
+ * hub_in (n_hubs x din_h: hub vector then its features), y_i =
+ * labels[batch_idx[i]].  Writes gradients into qg / hg, the mean loss to
+ * *loss (device FP32), the embeddings to q_emb / h_emb when non-NULL, and
+ * when step >= 1 applies Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * correction with t = step) to both towers and refreshes their BF16 copies.
+ * step == 0 computes gradients only. */
+ann_status ann_train_step(ann_tower *query_tower, ann_tower *hub_tower,
+                          const ann_tower_grads *qg, const ann_tower_grads *hg,
+                          const ann_adam_state *qa, const ann_adam_state *ha,
+                          const float *train_q, const int32_t *batch_idx, int32_t batch,
+                          const int32_t *labels, const float *hub_in, int32_t n_hubs,
+                          float tau, float lr, int32_t step, float *loss, float *q_emb,
+                          float *h_emb, void *workspace, size_t ws_bytes, void *stream);
+
+/* Navigation graph over hubs.  Rows of hub_emb are unit vectors, so
+ * |e_i - e_j|^2 = 2 - 2 cos(e_i, e_j) and the order by squared L2 distance is
+ * the cosine order: row i = the s hubs j != i of largest cosine with hub i,
+ * found as the exact nearest neighbours by (FP64 squared L2, j).
+ * *hub_entry (host) = the medoid of the embeddings, which is the hub of
+ * largest cosine with their mean direction; the hub-graph search starts there.
+ * workspace: ann_navgraph_workspace_size(n_hubs, dim, s).  Synchronises. */
+size_t ann_navgraph_workspace_size(int32_t n_hubs, int32_t dim, int32_t s);
+
+ann_status ann_navgraph_build(const float *hub_emb, int32_t n_hubs, int32_t dim, int32_t s,
+                              int32_t *hub_graph, int32_t *hub_entry, void *workspace,
+                              size_t ws_bytes, void *stream);
+
+typedef struct ann_entry_model {
+    ann_tower query_tower;      /* BF16 copies must be current */
+    const float *hub_emb;       /* n_hubs x query_tower.dout, unit rows */
+    const int32_t *hub_graph;   /* n_hubs x s */
+    int32_t n_hubs, s;
+    const int32_t *hub_ids;     /* base id of each hub */
+    int32_t hub_entry;          /* hub index where the hub-graph search starts */
+    int32_t medoid;             /* fallback entry point */
+    int32_t L_h;                /* beam width on the hub graph (<= 512) */
+    float theta;                /* best cosine below theta -> medoid */
+} ann_entry_model;
+
+size_t ann_entry_workspace_size(const ann_entry_model *model, int32_t nq);
+
+/* Query-aware entry points: the query tower embeds each query; a best-first
+ * search over the hub graph (the ann_search kernel with k = 1 and beam width
+ * L_h, squared L2 between unit embeddings, i.e. cosine order) starts at
+ * model->hub_entry and returns the best hub h with cos = 1 - d2 / 2;
+ * entry_ids[i] = hub_ids[h], or the medoid when cos < theta.  entry_score
+ * (FP32 cosine) and best_hub may be NULL. */
+ann_status ann_entry_select(const ann_entry_model *model, const float *queries, int32_t nq,
+                            int32_t dim, int32_t *entry_ids, float *entry_score,
+                            int32_t *best_hub, void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Training labels for the entry model.  This takes the place of the paper's */
+/* hop-count positive and negative queues (Definition 4) with the same       */
+/* intent: which hub serves a query best.  For historical query i and each    */
+/* candidate hub m (cand_hubs row i, nearest first), the batched beam search  */
+/* (as ann_search) runs from that hub with each width of L_ladder (host,     */
+/* increasing, kt <= L <= 512); the cost of (i, m) is the distance count      */
+/* (ndc_unique) of the first width whose top-kt holds at least `hits` of the  */
+/* query's true top-kt (truth row i).  The label is the candidate of least    */
+/* cost, ties to the smaller hub index, or the first candidate when none      */
+/* reaches the target.                                                        */
+/*   table  nq x M int32 or NULL: the cost, -1 when no width reached it        */
+/*   flags  nq int32 or NULL: bit0 = a search of that query overflowed the    */
+/*          LDS visited table (its counts may include repeated nodes)         */
+/*   workspace  ann_labels_workspace_size(nq, M, kt) bytes.  kt <= 64.        */
+size_t ann_labels_workspace_size(int32_t nq, int32_t M, int32_t kt);
+
+ann_status ann_make_labels(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                           int32_t R, const float *queries, int32_t nq, const int32_t *truth,
+                           int32_t kt, int32_t hits, const int32_t *cand_hubs, int32_t M,
+                           const int32_t *hub_ids, const int32_t *L_ladder, int32_t n_L,
+                           int32_t *labels, int32_t *table, int32_t *flags, void *workspace,
+                           size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

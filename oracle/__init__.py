@@ -7,11 +7,11 @@ to check against the paper by eye:
 
 * ``oracle.c`` (ctypes below): distances, exact kNN, alpha pruning, medoid,
   connectivity repair, best-first beam search (Algorithm 1), Lloyd k-means hubs
-  (Definition 3), hub navigation graph and entry selection (high-tier graph
-  section), label search.
+  (Definition 3), label search, hub topology features.
+* hub navigation graph and entry selection (high-tier graph section) are
+  composed below from kNN, medoid and search on the unit hub embeddings.
 * ``towers.py``: the two-tower model, InfoNCE loss (Eq. 2 / Eq. 4 reading) and
   Adam, in NumPy float64.
-* ``features.py``: the 32 per-hub topology features (guided-walk sampling).
 """
 from __future__ import annotations
 
@@ -51,19 +51,13 @@ def _declare(L):
     L.oracle_medoid.restype = _I32
     L.oracle_repair.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _I32, _P, _P]
     L.oracle_search.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _P, _I64, _P, _P, _P,
-                                ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_int,
-                                ctypes.c_int, _P, ctypes.c_int]
+                                ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_int]
     L.oracle_kmeans_hubs.argtypes = [_P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
                                      _P, _P, _P]
     L.oracle_kmeans_hubs.restype = ctypes.c_int
-    L.oracle_hub_graph.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P]
-    L.oracle_hub_medoid.argtypes = [_P, ctypes.c_int, ctypes.c_int]
-    L.oracle_hub_medoid.restype = _I32
     L.oracle_hub_features.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _I32, _P,
                                       ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, _P, _P]
-    L.oracle_entry_select.argtypes = [_P, _I64, _P, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
-                                      _P, _I32, ctypes.c_int, _F64, _I32, _P, _P, _P]
 
 
 def _ptr(a):
@@ -134,13 +128,12 @@ def build_graph(base, knn_k: int, R: int, alpha: float):
 
 
 def search(base, graph, queries, entry, k, L, k_max: int | None = None,
-           trace_cap: int = 0, truth=None, c_hit: int = 0, want_visited: bool = False,
-           threads: int = 0):
+           trace_cap: int = 0, want_visited: bool = False, threads: int = 0):
     """Best-first beam search (Algorithm 1 reading).
 
     k and L may be scalars or per-query arrays.  Returns a dict with ids
-    (nq x k_max, -1 padded), d2 (float64, +inf padded), ndc, hops, ndc_hit,
-    trace (nq x trace_cap) and visited (nq x n uint8) when asked for."""
+    (nq x k_max, -1 padded), d2 (float64, +inf padded), ndc, hops, trace
+    (nq x trace_cap) and visited (nq x n uint8) when asked for."""
     base, queries = _f32(base), _f32(queries)
     graph = _i32(graph)
     n, d = base.shape
@@ -152,18 +145,13 @@ def search(base, graph, queries, entry, k, L, k_max: int | None = None,
         k_max = int(kk.max())
     ids = np.empty((nq, k_max), np.int32)
     dd = np.empty((nq, k_max), np.float64)
-    stats = np.empty((nq, 3), np.int64)
+    stats = np.empty((nq, 2), np.int64)
     trace = np.empty((nq, trace_cap), np.int32) if trace_cap > 0 else None
-    kt = 0
-    if truth is not None:
-        truth = _i32(truth)
-        kt = truth.shape[1]
     vis = np.zeros((nq, n), np.uint8) if want_visited else None
     lib().oracle_search(_ptr(base), n, d, _ptr(graph), graph.shape[1], _ptr(queries), nq,
                         _ptr(entry), _ptr(kk), _ptr(LL), k_max, _ptr(ids), _ptr(dd),
-                        _ptr(stats), _ptr(trace), trace_cap, _ptr(truth), kt, c_hit,
-                        _ptr(vis), threads)
-    out = dict(ids=ids, d2=dd, ndc=stats[:, 0], hops=stats[:, 1], ndc_hit=stats[:, 2])
+                        _ptr(stats), _ptr(trace), trace_cap, _ptr(vis), threads)
+    out = dict(ids=ids, d2=dd, ndc=stats[:, 0], hops=stats[:, 1])
     if trace is not None:
         out["trace"] = trace
     if vis is not None:
@@ -188,35 +176,34 @@ def kmeans_hubs(base, n_hubs: int, iters: int, init_ids):
 
 
 def hub_graph(emb, s: int):
-    emb = _f32(emb)
-    nh, e = emb.shape
-    hg = np.empty((nh, s), np.int32)
-    lib().oracle_hub_graph(_ptr(emb), nh, e, s, _ptr(hg))
-    return hg
+    """Navigation graph over hubs (high-tier graph section): row i = the s hubs
+    of largest cosine with hub i, self excluded.  The embeddings are unit
+    vectors, so |e_i - e_j|^2 = 2 - 2 cos(e_i, e_j): the cosine order is the
+    order by squared L2 distance, ties by index."""
+    ids, _ = knn(emb, emb, s, exclude_self=True)
+    return ids
 
 
 def hub_medoid(emb) -> int:
-    emb = _f32(emb)
-    return int(lib().oracle_hub_medoid(_ptr(emb), emb.shape[0], emb.shape[1]))
+    """Where the hub-graph search starts: the hub of largest cosine with the
+    mean embedding direction.  For unit rows, argmax <h, mu> = argmin
+    |h - mu|^2, i.e. the medoid of the embeddings."""
+    return medoid(emb)
 
 
 def entry_select(qemb, hemb, hg, hub_ids, Lh: int, theta: float, med: int,
                  hub_entry: int | None = None):
-    """Search the hub graph for each query embedding; returns (entry_ids,
-    score (cosine, float64), best hub index)."""
-    qemb, hemb = _f32(qemb), _f32(hemb)
-    hg, hub_ids = _i32(hg), _i32(hub_ids)
-    nq, e = qemb.shape
-    nh = hemb.shape[0]
+    """Entry points: beam search (width Lh) over the hub graph from the hub
+    entry by squared L2 between unit embeddings (the cosine order); the best
+    hub h has cos = 1 - d2/2; entry = hub_ids[h], or the medoid when
+    cos < theta.  Returns (entry_ids, cos (float64), best hub index)."""
     if hub_entry is None:
         hub_entry = hub_medoid(hemb)
-    ent = np.empty(nq, np.int32)
-    sc = np.empty(nq, np.float64)
-    bh = np.empty(nq, np.int32)
-    lib().oracle_entry_select(_ptr(qemb), nq, _ptr(hemb), nh, e, _ptr(hg), hg.shape[1],
-                              _ptr(hub_ids), int(hub_entry), Lh, float(theta), int(med),
-                              _ptr(ent), _ptr(sc), _ptr(bh))
-    return ent, sc, bh
+    r = search(hemb, hg, qemb, int(hub_entry), 1, Lh)
+    bh = r["ids"][:, 0].astype(np.int32)
+    cos = 1.0 - 0.5 * r["d2"][:, 0]
+    ent = np.where(cos < theta, np.int32(med), np.asarray(hub_ids, np.int32)[bh]).astype(np.int32)
+    return ent, cos, bh
 
 
 def hub_features(base, graph, med: int, hub_ids, assign, centroids, h: int = 5,
@@ -245,20 +232,29 @@ def recall(found_ids, truth_ids, k: int) -> np.ndarray:
     return hits / float(k)
 
 
-def make_labels(base, graph, train_q, truth, cand_hubs, hub_ids, L_lab: int, c_hit: int,
+def make_labels(base, graph, train_q, truth, cand_hubs, hub_ids, L_ladder, hits: int,
                 threads: int = 0):
-    """Per training query: the candidate hub whose search reaches c_hit of the
-    true neighbours with the fewest distance computations (ties: smaller hub
-    index).  cand_hubs holds hub indices (nq x M) ordered nearest first; when
-    no candidate reaches c_hit the label is the first candidate.  Returns
-    (label hub index, ndc_hit table nq x M with -1 for never)."""
+    """Training labels (stand-in for the paper's hop-count queues, same intent:
+    which hub serves a query best).  For query i and candidate hub m the beam
+    search runs from hub_ids[cand_hubs[i, m]] with each width of L_ladder
+    (increasing); cost(i, m) = ndc of the first width whose top-kt holds at
+    least `hits` of truth[i] (kt = truth.shape[1]), -1 if none does.  The
+    label is the candidate of least cost, ties to the smaller hub index, else
+    the first candidate.  Returns (labels, cost table nq x M)."""
+    truth = np.asarray(truth)
     nq, M = cand_hubs.shape
-    table = np.empty((nq, M), np.int64)
+    kt = truth.shape[1]
+    table = np.full((nq, M), -1, np.int64)
     for m in range(M):
         ent = np.asarray(hub_ids)[cand_hubs[:, m]]
-        r = search(base, graph, train_q, ent, 1, L_lab, truth=truth, c_hit=c_hit,
-                   threads=threads)
-        table[:, m] = r["ndc_hit"]
+        for L in L_ladder:
+            r = search(base, graph, train_q, ent, kt, int(L), threads=threads)
+            for i in range(nq):
+                if table[i, m] >= 0:
+                    continue
+                h = len(set(r["ids"][i].tolist()) & set(truth[i].tolist()))
+                if h >= hits:
+                    table[i, m] = r["ndc"][i]
     label = np.empty(nq, np.int32)
     for i in range(nq):
         best = None
@@ -268,6 +264,5 @@ def make_labels(base, graph, train_q, truth, cand_hubs, hub_ids, L_lab: int, c_h
             cand = (int(table[i, m]), int(cand_hubs[i, m]))
             if best is None or cand < best:
                 best = cand
-        # no candidate reached c_hit: fall back to the nearest candidate hub
         label[i] = best[1] if best is not None else int(cand_hubs[i, 0])
     return label, table

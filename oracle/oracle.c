@@ -278,26 +278,22 @@ void oracle_repair(const float *base, i64 n, int d, i32 *graph, int R, i32 medoi
 /* The search stops when every pool entry has been expanded.                  */
 /*                                                                            */
 /* Optional outputs:                                                          */
-/*   stats[3*i..]  ndc, hops, ndc_hit (see below)                             */
+/*   stats[2*i..]  ndc, hops                                                  */
 /*   trace[i*trace_cap ..] the ids expanded, in order (-1 padded)             */
 /*   visited_out[i*n ..] 0/1 per node (tiny inputs only)                      */
-/* Label support: if truth != NULL (nq x kt ids), ndc_hit is the value of ndc */
-/* right after the c_hit-th id of truth[i] had its distance computed (-1 if  */
-/* that never happens).                                                       */
 
 typedef struct { double v; i32 id; int expanded; } entry_t;
 
 static void search_one(const float *base, i64 n, int d, const i32 *graph, int R,
                        const float *q, i32 entry, int k, int L, int k_max,
                        i32 *out_ids, double *out_d2, i64 *stats, i32 *trace,
-                       int trace_cap, unsigned char *visited, const i32 *truth,
-                       int kt, int c_hit, unsigned char *visited_out)
+                       int trace_cap, unsigned char *visited, unsigned char *visited_out)
 {
     entry_t *pool = (entry_t *)malloc(sizeof(entry_t) * (size_t)(L + 1));
     i32 *touched = (i32 *)malloc(sizeof(i32) * 1024);
     i64 touched_cap = 1024, ntouched = 0;
     int cnt = 0;
-    i64 ndc = 0, hops = 0, ndc_hit = -1, hits = 0;
+    i64 ndc = 0, hops = 0;
 
 #define VISIT(id_)                                                              \
     do {                                                                        \
@@ -316,11 +312,6 @@ static void search_one(const float *base, i64 n, int d, const i32 *graph, int R,
     pool[0].expanded = 0;
     cnt = 1;
     ndc = 1;
-    if (truth) {
-        for (int t = 0; t < kt; ++t)
-            if (truth[t] == entry) { ++hits; break; }
-        if (hits >= c_hit && ndc_hit < 0) ndc_hit = ndc;
-    }
 
     for (;;) {
         int pi = -1;
@@ -337,11 +328,6 @@ static void search_one(const float *base, i64 n, int d, const i32 *graph, int R,
             VISIT(nb);
             double v = d2(q, base + (i64)nb * d, d);
             ++ndc;
-            if (truth) {
-                for (int t = 0; t < kt; ++t)
-                    if (truth[t] == nb) { ++hits; break; }
-                if (hits >= c_hit && ndc_hit < 0) ndc_hit = ndc;
-            }
             if (cnt < L || key_less(v, nb, pool[cnt - 1].v, pool[cnt - 1].id)) {
                 int pos = cnt < L ? cnt : L - 1;
                 while (pos > 0 && key_less(v, nb, pool[pos - 1].v, pool[pos - 1].id)) {
@@ -360,7 +346,7 @@ static void search_one(const float *base, i64 n, int d, const i32 *graph, int R,
         if (t < k && t < cnt) { out_ids[t] = pool[t].id; out_d2[t] = pool[t].v; }
         else { out_ids[t] = -1; out_d2[t] = INFINITY; }
     }
-    if (stats) { stats[0] = ndc; stats[1] = hops; stats[2] = ndc_hit; }
+    if (stats) { stats[0] = ndc; stats[1] = hops; }
     if (trace)
         for (i64 t = hops; t < trace_cap; ++t) trace[t] = -1;
     if (visited_out)
@@ -374,8 +360,7 @@ static void search_one(const float *base, i64 n, int d, const i32 *graph, int R,
 void oracle_search(const float *base, i64 n, int d, const i32 *graph, int R,
                    const float *queries, i64 nq, const i32 *entry, const i32 *k,
                    const i32 *L, int k_max, i32 *out_ids, double *out_d2, i64 *stats,
-                   i32 *trace, int trace_cap, const i32 *truth, int kt, int c_hit,
-                   unsigned char *visited_out, int n_threads)
+                   i32 *trace, int trace_cap, unsigned char *visited_out, int n_threads)
 {
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -389,9 +374,8 @@ void oracle_search(const float *base, i64 n, int d, const i32 *graph, int R,
         for (i64 i = 0; i < nq; ++i) {
             search_one(base, n, d, graph, R, queries + i * d, entry[i], k[i], L[i],
                        k_max, out_ids + i * k_max, out_d2 + i * k_max,
-                       stats ? stats + 3 * i : NULL, trace ? trace + i * trace_cap : NULL,
-                       trace_cap, visited, truth ? truth + i * kt : NULL, kt, c_hit,
-                       visited_out ? visited_out + i * n : NULL);
+                       stats ? stats + 2 * i : NULL, trace ? trace + i * trace_cap : NULL,
+                       trace_cap, visited, visited_out ? visited_out + i * n : NULL);
         }
         free(visited);
     }
@@ -475,126 +459,6 @@ int oracle_kmeans_hubs(const float *base, i64 n, int d, int nh, int iters,
     free(count);
     free(sum);
     return steps;
-}
-
-/* ------------------------------------------------------------------------ */
-/* Navigation graph over hubs: each hub links to the s hubs of largest        */
-/* cosine similarity (self excluded), ordered by (-cos, index).  emb rows are */
-/* already unit-normalised, so the cosine is the FP64 dot product.            */
-
-void oracle_hub_graph(const float *emb, int nh, int e, int s, i32 *hg)
-{
-#pragma omp parallel for schedule(static)
-    for (int i = 0; i < nh; ++i) {
-        i32 *row = hg + (i64)i * s;
-        double *val = (double *)malloc(sizeof(double) * s);
-        int cnt = 0;
-        for (int j = 0; j < nh; ++j) {
-            if (j == i) continue;
-            double v = 0.0;
-            for (int t = 0; t < e; ++t) v = v + (double)emb[(i64)i * e + t] * (double)emb[(i64)j * e + t];
-            double key = -v;
-            if (cnt == s && !key_less(key, j, val[s - 1], row[s - 1])) continue;
-            int pos = cnt < s ? cnt : s - 1;
-            while (pos > 0 && key_less(key, j, val[pos - 1], row[pos - 1])) {
-                val[pos] = val[pos - 1];
-                row[pos] = row[pos - 1];
-                --pos;
-            }
-            val[pos] = key;
-            row[pos] = j;
-            if (cnt < s) ++cnt;
-        }
-        for (int t = cnt; t < s; ++t) row[t] = -1;
-        free(val);
-    }
-}
-
-/* ------------------------------------------------------------------------ */
-/* Entry selection over the hub navigation graph: the bounded-pool search    */
-/* above, run on the hub graph with key (-cos(e_q, e_h), h), entered at the  */
-/* hub-medoid (the hub of largest cosine with the normalised mean of the hub  */
-/* embeddings).  The best hub's base id is the entry point, unless its cosine */
-/* is below theta, in which case the medoid is used.                          */
-
-static double neg_dot(const float *a, const float *b, int e)
-{
-    double v = 0.0;
-    for (int t = 0; t < e; ++t) v = v + (double)a[t] * (double)b[t];
-    return -v;
-}
-
-i32 oracle_hub_medoid(const float *emb, int nh, int e)
-{
-    double *m = (double *)calloc((size_t)e, sizeof(double));
-    for (int i = 0; i < nh; ++i)
-        for (int t = 0; t < e; ++t) m[t] = m[t] + (double)emb[(i64)i * e + t];
-    double nrm = 0.0;
-    for (int t = 0; t < e; ++t) nrm = nrm + m[t] * m[t];
-    nrm = sqrt(nrm);
-    double best = INFINITY;
-    i32 bi = -1;
-    for (int i = 0; i < nh; ++i) {
-        double v = 0.0;
-        for (int t = 0; t < e; ++t) v = v + (double)emb[(i64)i * e + t] * (m[t] / nrm);
-        double key = -v;
-        if (bi < 0 || key_less(key, i, best, bi)) { best = key; bi = i; }
-    }
-    free(m);
-    return bi;
-}
-
-void oracle_entry_select(const float *qemb, i64 nq, const float *hemb, int nh, int e,
-                         const i32 *hg, int s, const i32 *hub_ids, i32 hub_entry,
-                         int Lh, double theta, i32 medoid, i32 *entry_ids,
-                         double *entry_score, i32 *best_hub)
-{
-#pragma omp parallel
-    {
-        entry_t *pool = (entry_t *)malloc(sizeof(entry_t) * (size_t)(Lh + 1));
-        unsigned char *vis = (unsigned char *)malloc((size_t)nh);
-#pragma omp for schedule(dynamic, 16)
-        for (i64 qi = 0; qi < nq; ++qi) {
-            const float *q = qemb + qi * e;
-            memset(vis, 0, (size_t)nh);
-            int cnt = 0;
-            vis[hub_entry] = 1;
-            pool[0].v = neg_dot(q, hemb + (i64)hub_entry * e, e);
-            pool[0].id = hub_entry;
-            pool[0].expanded = 0;
-            cnt = 1;
-            for (;;) {
-                int pi = -1;
-                for (int t = 0; t < cnt; ++t) if (!pool[t].expanded) { pi = t; break; }
-                if (pi < 0) break;
-                pool[pi].expanded = 1;
-                i32 p = pool[pi].id;
-                for (int u = 0; u < s; ++u) {
-                    i32 nb = hg[(i64)p * s + u];
-                    if (nb < 0 || vis[nb]) continue;
-                    vis[nb] = 1;
-                    double v = neg_dot(q, hemb + (i64)nb * e, e);
-                    if (cnt < Lh || key_less(v, nb, pool[cnt - 1].v, pool[cnt - 1].id)) {
-                        int pos = cnt < Lh ? cnt : Lh - 1;
-                        while (pos > 0 && key_less(v, nb, pool[pos - 1].v, pool[pos - 1].id)) {
-                            pool[pos] = pool[pos - 1];
-                            --pos;
-                        }
-                        pool[pos].v = v;
-                        pool[pos].id = nb;
-                        pool[pos].expanded = 0;
-                        if (cnt < Lh) ++cnt;
-                    }
-                }
-            }
-            double cosv = -pool[0].v;
-            best_hub[qi] = pool[0].id;
-            entry_score[qi] = cosv;
-            entry_ids[qi] = (cosv < theta) ? medoid : hub_ids[pool[0].id];
-        }
-        free(vis);
-        free(pool);
-    }
 }
 
 /* ------------------------------------------------------------------------ */

@@ -74,6 +74,43 @@ _sig("ann_select_hubs", _I32, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P, ctypes
      _P, _SZ, _P)
 _sig("ann_hub_features", _I32, _P, _I64, _I32, _P, _I32, _I32, _P, _I32, _P, _P, _I32, _I32,
      _I32, _P, _P, _P, _SZ, _P)
+_sig("ann_labels_workspace_size", _SZ, _I32, _I32, _I32)
+_sig("ann_make_labels", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _I32, _I32, _P, _I32, _P,
+     _P, _I32, _P, _P, _P, _P, _SZ, _P)
+
+
+class ann_tower(ctypes.Structure):
+    _fields_ = [("din", _I32), ("hidden", _I32), ("dout", _I32), ("W1", _P), ("b1", _P),
+                ("W2", _P), ("b2", _P), ("W1b", _P), ("W2b", _P)]
+
+
+class ann_tower_grads(ctypes.Structure):
+    _fields_ = [("gW1", _P), ("gb1", _P), ("gW2", _P), ("gb2", _P)]
+
+
+class ann_adam_state(ctypes.Structure):
+    _fields_ = [(n, _P) for n in ("mW1", "vW1", "mb1", "vb1", "mW2", "vW2", "mb2", "vb2")]
+
+
+class ann_entry_model(ctypes.Structure):
+    _fields_ = [("query_tower", ann_tower), ("hub_emb", _P), ("hub_graph", _P), ("n_hubs", _I32),
+                ("s", _I32), ("hub_ids", _P), ("hub_entry", _I32), ("medoid", _I32),
+                ("L_h", _I32), ("theta", _F32)]
+
+
+_sig("ann_tower_sync", _I32, ctypes.POINTER(ann_tower), _P)
+_sig("ann_tower_workspace_size", _SZ, ctypes.POINTER(ann_tower), _I32)
+_sig("ann_tower_forward", _I32, ctypes.POINTER(ann_tower), _P, _I32, _P, _P, _SZ, _P)
+_sig("ann_train_workspace_size", _SZ, _I32, _I32, _I32, _I32, _I32, _I32)
+_sig("ann_train_step", _I32, ctypes.POINTER(ann_tower), ctypes.POINTER(ann_tower),
+     ctypes.POINTER(ann_tower_grads), ctypes.POINTER(ann_tower_grads),
+     ctypes.POINTER(ann_adam_state), ctypes.POINTER(ann_adam_state), _P, _P, _I32, _P, _P, _I32,
+     _F32, _F32, _I32, _P, _P, _P, _P, _SZ, _P)
+_sig("ann_navgraph_workspace_size", _SZ, _I32, _I32, _I32)
+_sig("ann_navgraph_build", _I32, _P, _I32, _I32, _I32, _P, ctypes.POINTER(_I32), _P, _SZ, _P)
+_sig("ann_entry_workspace_size", _SZ, ctypes.POINTER(ann_entry_model), _I32)
+_sig("ann_entry_select", _I32, ctypes.POINTER(ann_entry_model), _P, _I32, _I32, _P, _P, _P, _P,
+     _SZ, _P)
 
 
 def last_error() -> str:
@@ -240,3 +277,178 @@ def ann_hub_features(base, graph, medoid: int, hub_ids, assign, centroids, h: in
                                  nh, _ptr(assign), _ptr(centroids), h, wcap, int(standardise),
                                  _ptr(f), _ptr(wsz), _ptr(ws), ws.numel(), _stream(stream)))
     return f, wsz
+
+
+def ann_make_labels(base, graph, queries, truth, hits: int, cand_hubs, hub_ids, L_ladder,
+                    want_table: bool = True, stream=None):
+    """Returns (labels int32 [nq], table int32 [nq, M] or None, flags int32 [nq])."""
+    n, dim = base.shape
+    nq = queries.shape[0]
+    dev = base.device
+    M = cand_hubs.shape[1]
+    kt = truth.shape[1]
+    lad = (ctypes.c_int32 * len(L_ladder))(*[int(v) for v in L_ladder])
+    labels = torch.empty(nq, dtype=torch.int32, device=dev)
+    table = torch.empty((nq, M), dtype=torch.int32, device=dev) if want_table else None
+    flags = torch.empty(nq, dtype=torch.int32, device=dev)
+    nb = max(256, int(_lib.ann_labels_workspace_size(nq, M, kt)))
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(_lib.ann_make_labels(_ptr(base), n, dim, _ptr(graph), graph.shape[1], _ptr(queries),
+                                nq, _ptr(truth), kt, hits, _ptr(cand_hubs), M, _ptr(hub_ids),
+                                lad, len(L_ladder), _ptr(labels), _ptr(table), _ptr(flags),
+                                _ptr(ws), ws.numel(), _stream(stream)))
+    return labels, table, flags
+
+
+def ann_labels_workspace_size(nq: int, M: int, kt: int) -> int:
+    return int(_lib.ann_labels_workspace_size(nq, M, kt))
+
+
+class Tower:
+    """Device-resident tower: FP32 masters, BF16 copies, gradients, Adam state."""
+
+    def __init__(self, W1, b1, W2, b2, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        self.W1, self.b1, self.W2, self.b2 = f(W1), f(b1), f(W2), f(b2)
+        self.hidden, self.din = self.W1.shape
+        self.dout = self.W2.shape[0]
+        self.W1b = torch.empty(self.W1.shape, dtype=torch.int16, device=device)
+        self.W2b = torch.empty(self.W2.shape, dtype=torch.int16, device=device)
+        self.g = [torch.zeros_like(t) for t in (self.W1, self.b1, self.W2, self.b2)]
+        self.m = [torch.zeros_like(t) for t in (self.W1, self.b1, self.W2, self.b2)]
+        self.v = [torch.zeros_like(t) for t in (self.W1, self.b1, self.W2, self.b2)]
+        self.sync()
+
+    def params(self):
+        return [self.W1, self.b1, self.W2, self.b2]
+
+    def struct(self) -> ann_tower:
+        return ann_tower(self.din, self.hidden, self.dout, self.W1.data_ptr(),
+                         self.b1.data_ptr(), self.W2.data_ptr(), self.b2.data_ptr(),
+                         self.W1b.data_ptr(), self.W2b.data_ptr())
+
+    def grads_struct(self) -> ann_tower_grads:
+        return ann_tower_grads(*[t.data_ptr() for t in self.g])
+
+    def adam_struct(self) -> ann_adam_state:
+        m, v = self.m, self.v
+        return ann_adam_state(m[0].data_ptr(), v[0].data_ptr(), m[1].data_ptr(), v[1].data_ptr(),
+                              m[2].data_ptr(), v[2].data_ptr(), m[3].data_ptr(), v[3].data_ptr())
+
+    def sync(self, stream=None):
+        st = self.struct()
+        _check(_lib.ann_tower_sync(ctypes.byref(st), _stream(stream)))
+
+    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        _dev(x, torch.float32)
+        rows = x.shape[0]
+        st = self.struct()
+        out = torch.empty((rows, self.dout), dtype=torch.float32, device=x.device)
+        nb = max(256, int(_lib.ann_tower_workspace_size(ctypes.byref(st), rows)))
+        ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+        _check(_lib.ann_tower_forward(ctypes.byref(st), _ptr(x), rows, _ptr(out), _ptr(ws), nb,
+                                      _stream(stream)))
+        return out
+
+
+def ann_train_step(qt: Tower, ht: Tower, train_q, batch_idx, labels, hub_in, tau: float,
+                   lr: float, step: int, ws=None, want_emb: bool = False, stream=None):
+    """One training step (step 0 = gradients only).  Returns (loss tensor,
+    q_emb, h_emb) with the embeddings only when want_emb."""
+    dev = train_q.device
+    B = batch_idx.shape[0]
+    nh = hub_in.shape[0]
+    q_s, h_s = qt.struct(), ht.struct()
+    qg, hg = qt.grads_struct(), ht.grads_struct()
+    qa, ha = qt.adam_struct(), ht.adam_struct()
+    nb = int(_lib.ann_train_workspace_size(B, nh, qt.din, ht.din, qt.hidden, qt.dout))
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    qe = torch.empty((B, qt.dout), dtype=torch.float32, device=dev) if want_emb else None
+    he = torch.empty((nh, ht.dout), dtype=torch.float32, device=dev) if want_emb else None
+    _check(_lib.ann_train_step(ctypes.byref(q_s), ctypes.byref(h_s), ctypes.byref(qg),
+                               ctypes.byref(hg), ctypes.byref(qa), ctypes.byref(ha), _ptr(train_q),
+                               _ptr(batch_idx), B, _ptr(labels), _ptr(hub_in), nh, float(tau),
+                               float(lr), int(step), _ptr(loss), _ptr(qe), _ptr(he), _ptr(ws),
+                               ws.numel(), _stream(stream)))
+    return loss, qe, he
+
+
+def ann_navgraph_build(hub_emb: torch.Tensor, s: int, stream=None):
+    """Returns (hub graph int32 [n_hubs, s], hub entry index)."""
+    _dev(hub_emb, torch.float32)
+    nh, e = hub_emb.shape
+    hg = torch.empty((nh, s), dtype=torch.int32, device=hub_emb.device)
+    nb = int(_lib.ann_navgraph_workspace_size(nh, e, s))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=hub_emb.device)
+    ent = _I32(-1)
+    _check(_lib.ann_navgraph_build(_ptr(hub_emb), nh, e, s, _ptr(hg), ctypes.byref(ent), _ptr(ws),
+                                   ws.numel(), _stream(stream)))
+    return hg, int(ent.value)
+
+
+class EntryModel:
+    """The entry-selection model: query tower + hub embeddings + hub graph."""
+
+    def __init__(self, qtower: Tower, hub_emb, hub_graph, hub_ids, hub_entry: int, medoid: int,
+                 L_h: int = 32, theta: float = float("-inf")):
+        self.qtower, self.hub_emb, self.hub_graph, self.hub_ids = qtower, hub_emb, hub_graph, hub_ids
+        self.c = ann_entry_model(qtower.struct(), hub_emb.data_ptr(), hub_graph.data_ptr(),
+                                 hub_emb.shape[0], hub_graph.shape[1], hub_ids.data_ptr(),
+                                 int(hub_entry), int(medoid), int(L_h), float(theta))
+        self._ws = None
+
+    def workspace(self, nq, device):
+        nb = max(256, int(_lib.ann_entry_workspace_size(ctypes.byref(self.c), nq)))
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        return self._ws
+
+
+def ann_entry_select(model: EntryModel, queries: torch.Tensor, want_score: bool = False,
+                     out=None, stream=None):
+    """Returns (entry ids int32 [nq], cosine float32 or None, best hub int32 or None)."""
+    _dev(queries, torch.float32)
+    nq, dim = queries.shape
+    dev = queries.device
+    ent = out if out is not None else torch.empty(nq, dtype=torch.int32, device=dev)
+    sc = torch.empty(nq, dtype=torch.float32, device=dev) if want_score else None
+    bh = torch.empty(nq, dtype=torch.int32, device=dev) if want_score else None
+    ws = model.workspace(nq, dev)
+    _check(_lib.ann_entry_select(ctypes.byref(model.c), _ptr(queries), nq, dim, _ptr(ent),
+                                 _ptr(sc), _ptr(bh), _ptr(ws), ws.numel(), _stream(stream)))
+    return ent, sc, bh
+
+
+def ann_tower_sync(tower: Tower, stream=None):
+    tower.sync(stream)
+
+
+def ann_tower_forward(tower: Tower, x: torch.Tensor, stream=None) -> torch.Tensor:
+    return tower.forward(x, stream)
+
+
+def ann_tower_workspace_size(tower: Tower, rows: int) -> int:
+    st = tower.struct()
+    return int(_lib.ann_tower_workspace_size(ctypes.byref(st), rows))
+
+
+def ann_train_workspace_size(batch, n_hubs, din_q, din_h, hidden, dout) -> int:
+    return int(_lib.ann_train_workspace_size(batch, n_hubs, din_q, din_h, hidden, dout))
+
+
+def ann_entry_workspace_size(model: EntryModel, nq: int) -> int:
+    return int(_lib.ann_entry_workspace_size(ctypes.byref(model.c), nq))
+
+
+def ann_workspace_size(op: str, n: int, dim: int, p0: int = 0, p1: int = 0) -> int:
+    return workspace_size(op, n, dim, p0, p1)
+
+
+def ann_default_plan(n: int, dim: int, R: int, L_max: int) -> ann_search_plan:
+    return default_plan(n, dim, R, L_max)
+
+
+def ann_navgraph_workspace_size(n_hubs: int, dim: int, s: int) -> int:
+    return int(_lib.ann_navgraph_workspace_size(n_hubs, dim, s))

@@ -14,6 +14,9 @@ namespace ann {
 // Records the message for ann_last_error() and returns `s`.
 ann_status fail(ann_status s, const char *fmt, ...);
 
+// Enqueues a kernel that zeroes the work counter of a persistent launch.
+ann_status reset_work_counter(uint32_t *c, hipStream_t st);
+
 // Number of compute units of the current device (cached per device).
 int device_cus();
 

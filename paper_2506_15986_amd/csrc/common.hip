@@ -6,6 +6,18 @@
 
 namespace ann {
 
+// The persistent kernels take work from a counter that must start at zero.
+// One kernel in one translation unit: every code object of the library must
+// export distinct kernel symbols.
+__global__ void ann_work_counter_reset(uint32_t *c) { *c = 0u; }
+
+ann_status reset_work_counter(uint32_t *c, hipStream_t st)
+{
+    hipLaunchKernelGGL(ann_work_counter_reset, dim3(1), dim3(1), 0, st, c);
+    ANN_LAUNCHED();
+    return ANN_OK;
+}
+
 static thread_local char g_err[512] = "";
 
 ann_status fail(ann_status s, const char *fmt, ...)

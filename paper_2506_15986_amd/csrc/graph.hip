@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) prune_kernel(const float *base, int64_t n
 // ---------------------------------------------------------------- medoid
 constexpr int MED_ROWS = 4096;
 
-__global__ void colsum_kernel(const float *base, int64_t n, int dim, double *partial)
+__global__ void medoid_colsum_kernel(const float *base, int64_t n, int dim, double *partial)
 {
     const int64_t r0 = (int64_t)blockIdx.x * MED_ROWS;
     int64_t r1 = r0 + MED_ROWS;
@@ -92,7 +92,7 @@ __global__ void colsum_kernel(const float *base, int64_t n, int dim, double *par
     }
 }
 
-__global__ void colmean_kernel(const double *partial, int chunks, int dim, int64_t n, double *mu)
+__global__ void medoid_colmean_kernel(const double *partial, int chunks, int dim, int64_t n, double *mu)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= dim) return;
@@ -419,9 +419,9 @@ ann_status medoid_run(const float *base, int64_t n, int dim, double *partial_col
                       void *partial_keys, void *best_key, int32_t *medoid_host, hipStream_t st)
 {
     int chunks = (int)((n + MED_ROWS - 1) / MED_ROWS);
-    hipLaunchKernelGGL(colsum_kernel, dim3(chunks), dim3(128), 0, st, base, n, dim, partial_cols);
+    hipLaunchKernelGGL(medoid_colsum_kernel, dim3(chunks), dim3(128), 0, st, base, n, dim, partial_cols);
     ANN_LAUNCHED();
-    hipLaunchKernelGGL(colmean_kernel, dim3((dim + 127) / 128), dim3(128), 0, st, partial_cols,
+    hipLaunchKernelGGL(medoid_colmean_kernel, dim3((dim + 127) / 128), dim3(128), 0, st, partial_cols,
                        chunks, dim, n, mu);
     ANN_LAUNCHED();
     int blocks = (int)((n + 255) / 256);

@@ -20,5 +20,16 @@ size_t build_graph_ws(int64_t n, int dim, int K, int R);
 size_t medoid_ws(int64_t n, int dim);
 size_t select_hubs_ws(int64_t n, int dim, int nh);
 size_t hub_features_ws(int64_t n, int nh);
+size_t make_labels_ws(int nq, int M, int kt);
+size_t tower_forward_ws(int rows, const ann_tower *w);
+size_t train_step_ws(int batch, int nh, int din_q, int din_h, int hidden, int dout);
+ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                         int32_t R, const float *queries, int32_t nq, const int32_t *entry_ids,
+                         int32_t medoid, const int32_t *k, const int32_t *L, int32_t k_max,
+                         int32_t *out_ids, float *out_dist, int32_t *stats, int32_t *trace,
+                         int32_t trace_cap, const ann_search_plan &p, uint32_t *counter,
+                         hipStream_t st);
+ann_status tower_forward_run(const ann_tower &w, const float *x, const int32_t *idx, int rows,
+                             float *out, void *ws, hipStream_t st);
 
 }  // namespace ann

@@ -26,13 +26,11 @@ namespace {
 
 using namespace beam;
 
-__global__ void reset_counter(uint32_t *c) { *c = 0u; }
-
 template <int G, int CPL, bool F64>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    using S = Searcher<G, CPL, F64, L2, false>;
+    using S = Searcher<G, CPL, F64, L2>;
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     S s;
@@ -63,7 +61,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
             continue;
         }
         s.load_query(a.queries + (size_t)qi * a.dim);
-        SearchResult r = s.run((uint32_t)entry, Lq, trace, a.trace_cap, nullptr, 0, 0, 0x7fffffff);
+        SearchResult r = s.run((uint32_t)entry, Lq, trace, a.trace_cap);
         s.write_topk(kq, a.k_max, oid, odist);
         for (int t = (int)r.hops + lane; trace && t < a.trace_cap; t += 64) trace[t] = -1;
         if (a.stats && lane == 0) {
@@ -93,8 +91,10 @@ ann_status launch_search(const SearchArgs &a, int blocks, int wpb, hipStream_t s
     int need = (a.nq + wpb - 1) / wpb;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, a.counter);
-    ANN_LAUNCHED();
+    {
+        ann_status rs = reset_work_counter(a.counter, st);
+        if (rs != ANN_OK) return rs;
+    }
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, st, a);
     ANN_LAUNCHED();
     return ANN_OK;

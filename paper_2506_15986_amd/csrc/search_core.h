@@ -35,7 +35,6 @@ struct SearchResult {
     int dups;
     int hops;
     bool lost;
-    int ndc_hit;   // label mode: ndc when the c-th true neighbour was evaluated, else -1
 };
 
 // LDS bytes one wavefront needs.
@@ -49,7 +48,7 @@ inline size_t wave_lds_bytes(int pool_cap, int visited_log2, int64_t n, bool f64
     return (b + 15) / 16 * 16;
 }
 
-template <int G, int CPL, bool F64, int METRIC, bool LABEL>
+template <int G, int CPL, bool F64, int METRIC>
 struct Searcher {
     using KT = beam::Key<F64>;
     using K = typename KT::K;
@@ -63,7 +62,6 @@ struct Searcher {
     uint32_t *pi0, *pi1;
     K *sk;
     uint32_t *si;
-    uint32_t *truth;   // label mode: up to 16 true neighbour ids
     beam::Visited vis;
     int pool_cap;
     int64_t n;
@@ -92,7 +90,6 @@ struct Searcher {
         p += pcap * 4;
         si = reinterpret_cast<uint32_t *>(p);
         p += 64 * 4;
-        truth = reinterpret_cast<uint32_t *>(p);
         p += 64;
         size_t words = (size_t)1 << vlog2;
         size_t bw = (size_t)((n_ + 31) / 32);
@@ -165,46 +162,13 @@ struct Searcher {
         beam::wave_sync();
     }
 
-    // label mode: count distinct true neighbours among si[0..m)
-    __device__ void count_hits(int m, int kt, int c_hit, uint32_t &found, int ndc_before,
-                               int &ndc_hit)
-    {
-        const int lane = beam::lane_id();
-        int idx = -1;
-        if (lane < m) {
-            uint32_t c = si[lane];
-            for (int t = 0; t < kt; ++t)
-                if (truth[t] == c) idx = t;
-        }
-        bool h = idx >= 0 && !((found >> idx) & 1u);
-        uint64_t hb = __ballot(h);
-        // OR of the found bits across lanes
-        uint32_t mybit = h ? (1u << idx) : 0u;
-        for (int o = 32; o > 0; o >>= 1) mybit |= __shfl_xor(mybit, o);
-        int before = __popc(found);
-        int nh = __popcll(hb);
-        if (ndc_hit < 0 && before + nh >= c_hit) {
-            int need = c_hit - before;   // >= 1
-            uint64_t b = hb;
-            for (int t = 1; t < need; ++t) b &= b - 1;
-            ndc_hit = ndc_before + (__ffsll((unsigned long long)b) - 1) + 1;
-        }
-        found |= mybit;
-    }
-
     // Runs one query from `entry` with beam width Lq.  trace (nullable)
-    // receives the expanded ids.  Label mode: kt true ids in truth[], stop once
-    // ndc exceeds abort_ndc.
-    __device__ SearchResult run(uint32_t entry, int Lq, int32_t *trace, int trace_cap, const int32_t *truth_g,
-                                int kt, int c_hit, int abort_ndc)
+    // receives the expanded ids.
+    __device__ SearchResult run(uint32_t entry, int Lq, int32_t *trace, int trace_cap)
     {
         const int lane = beam::lane_id();
-        SearchResult r{0, 0, 0, false, -1};
-        uint32_t found = 0;
+        SearchResult r{0, 0, 0, false};
         vis.clear();
-        if (LABEL) {
-            if (lane < kt) truth[lane] = (uint32_t)truth_g[lane];
-        }
         bool lost = false;
         if (lane == 0) {
             vis.insert(entry, lost);
@@ -219,11 +183,9 @@ struct Searcher {
         }
         cnt = 1;
         r.ndc_exec = 1;
-        if (LABEL) count_hits(1, kt, c_hit, found, 0, r.ndc_hit);
         beam::wave_sync();
         int cursor = 0;
         for (;;) {
-            if (LABEL && (r.ndc_hit >= 0 || r.ndc_exec > abort_ndc)) break;
             // best unexpanded pool entry at or after the cursor
             int ppos = -1;
             for (int b = cursor; b < cnt; b += 64) {
@@ -255,7 +217,6 @@ struct Searcher {
             beam::wave_sync();
             if (m == 0) continue;
             distances(m);
-            if (LABEL) count_hits(m, kt, c_hit, found, r.ndc_exec, r.ndc_hit);
             r.ndc_exec += m;
             // ---- merge the new keys into the pool
             K *ak = keys(cur);

@@ -232,7 +232,7 @@ __global__ void softmax_ce_kernel(const float *s, int rows, int cols, const int3
 }
 
 // fixed-order column sums: out[c] = sum_r x[r][c]
-__global__ void colsum_kernel(const float *x, int rows, int cols, float *out)
+__global__ void bias_grad_kernel(const float *x, int rows, int cols, float *out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
@@ -398,7 +398,7 @@ ann_status tower_bwd(const ann_tower &w, const ann_tower_grads &gr, const TowerB
     g.C = gr.gW2;
     g.ldc = w.hidden;
     TRY(gemm_bf16(g, st));
-    hipLaunchKernelGGL(colsum_kernel, dim3((w.dout + 255) / 256), dim3(256), 0, st, b.dz2, rows,
+    hipLaunchKernelGGL(bias_grad_kernel, dim3((w.dout + 255) / 256), dim3(256), 0, st, b.dz2, rows,
                        w.dout, gr.gb2);
     ANN_LAUNCHED();
     // dz1 [rows x hidden] = (dz2b . W2b) * (z1 > 0)
@@ -417,7 +417,7 @@ ann_status tower_bwd(const ann_tower &w, const ann_tower_grads &gr, const TowerB
     h.Cb = b.dz1b;
     h.ldc = w.hidden;
     TRY(gemm_bf16(h, st));
-    hipLaunchKernelGGL(colsum_kernel, dim3((w.hidden + 255) / 256), dim3(256), 0, st, b.dz1, rows,
+    hipLaunchKernelGGL(bias_grad_kernel, dim3((w.hidden + 255) / 256), dim3(256), 0, st, b.dz1, rows,
                        w.hidden, gr.gb1);
     ANN_LAUNCHED();
     // dW1 [hidden x din] = dz1b^T . xb
@@ -510,6 +510,17 @@ ann_status refresh_bf16(const ann_tower &w, hipStream_t st)
 }  // namespace ann
 
 using namespace ann;
+
+extern "C" size_t ann_tower_workspace_size(const ann_tower *tower, int32_t rows)
+{
+    return tower ? tower_forward_ws(rows, tower) : 0;
+}
+
+extern "C" size_t ann_train_workspace_size(int32_t batch, int32_t n_hubs, int32_t din_q,
+                                           int32_t din_h, int32_t hidden, int32_t dout)
+{
+    return train_step_ws(batch, n_hubs, din_q, din_h, hidden, dout);
+}
 
 extern "C" ann_status ann_tower_sync(const ann_tower *tower, void *stream)
 {

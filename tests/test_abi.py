@@ -84,3 +84,18 @@ def test_default_plan_and_workspace():
     with pytest.raises(ann.AnnError):
         ann.default_plan(10, 32, 16, 600)
     assert ann.workspace_size("search", 1000, 32, 10) >= 4
+
+
+def test_kernel_names_unique_across_translation_units():
+    # each .hip file is its own code object inside libann.so; two code objects
+    # exporting the same kernel symbol must not happen
+    src = os.path.join(ROOT, "paper_2506_15986_amd", "csrc")
+    seen = {}
+    for f in sorted(os.listdir(src)):
+        if not f.endswith(".hip"):
+            continue
+        text = open(os.path.join(src, f)).read()
+        for name in re.findall(r"__global__\s+void\s+(?:__launch_bounds__\([^)]*\)\s+)?(\w+)\s*\(", text):
+            assert name not in seen, "kernel %s defined in %s and %s" % (name, seen[name], f)
+            seen[name] = f
+    assert len(seen) > 20

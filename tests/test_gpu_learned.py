@@ -1,0 +1,260 @@
+"""GPU parity of the learned entry model: tower forward, training gradients
+(against the oracle's float64 two-tower model on the same BF16 operands),
+Adam, the hub navigation graph, entry selection and training labels."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import towers as T
+from paper_2506_15986_amd import synth
+from tests.common import int_index, say, tiny_index
+
+pytestmark = pytest.mark.gpu
+
+
+def _ann():
+    from paper_2506_15986_amd import ann
+    return ann
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _setup(nh=64, hidden=128, dout=64):
+    ix = tiny_index()
+    base, w = ix["base"], ix["w"]
+    d = base.shape[1]
+    init = synth.kmeans_init(w, base.shape[0], nh)
+    km = oracle.kmeans_hubs(base, nh, 20, init)
+    feat, _ = oracle.hub_features(base, ix["graph"], ix["medoid"], km["hub_ids"], km["assign"],
+                                  km["centroids"])
+    hub_in = np.concatenate([base[km["hub_ids"]], feat.astype(np.float32)], axis=1)
+    qp = synth.tower_init(w, [(hidden, d), (dout, hidden)])
+    hp = synth.tower_init(w, [(hidden, d + 32), (dout, hidden)])
+    return ix, km, hub_in, qp, hp
+
+
+def test_tower_forward_matches_oracle():
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    say("case: tower forward")
+    t = ann.Tower(*qp)
+    e = t.forward(_dev(ix["q"])).cpu().numpy()
+    ref, _ = T.tower_forward(qp, ix["q"].astype(np.float64), bf16=True)
+    assert np.abs(e - ref).max() < 2e-3
+    assert np.allclose(np.linalg.norm(e, axis=1), 1.0, atol=1e-5)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_train_step_gradients_match_oracle():
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    tq = synth.train_queries(ix["w"], 512)
+    r = np.random.default_rng(1)
+    labels = r.integers(0, hub_in.shape[0], size=tq.shape[0]).astype(np.int32)
+    idx = r.permutation(tq.shape[0])[:256].astype(np.int32)
+    say("case: train step gradients")
+    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    loss, qe, he = ann.ann_train_step(qt, ht, _dev(tq), _dev(idx), _dev(labels), _dev(hub_in), 0.07,
+                                      1e-3, 0, want_emb=True)
+    torch.cuda.synchronize()
+    ref_loss, gq, gh, eq, eh = T.train_step_grads(qp, hp, tq[idx].astype(np.float64),
+                                                  hub_in.astype(np.float64), labels[idx], 0.07,
+                                                  bf16=True)
+    assert abs(loss.item() - ref_loss) <= 1e-4 * abs(ref_loss)
+    for got, ref in zip([t.cpu().numpy() for t in qt.g + ht.g], list(gq) + list(gh)):
+        assert _rel(got, ref) <= 1e-3
+    # a second identical step gives identical bits (fixed-order reductions)
+    g1 = [t.clone() for t in qt.g + ht.g]
+    ann.ann_train_step(qt, ht, _dev(tq), _dev(idx), _dev(labels), _dev(hub_in), 0.07, 1e-3, 0)
+    torch.cuda.synchronize()
+    for a, b in zip(g1, qt.g + ht.g):
+        assert torch.equal(a, b)
+
+
+def test_adam_step_matches_oracle_update():
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    tq = synth.train_queries(ix["w"], 256)
+    labels = np.arange(256, dtype=np.int32) % hub_in.shape[0]
+    idx = np.arange(256, dtype=np.int32)
+    say("case: adam")
+    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    ann.ann_train_step(qt, ht, _dev(tq), _dev(idx), _dev(labels), _dev(hub_in), 0.07, 1e-3, 0)
+    grads = [t.cpu().numpy().astype(np.float64) for t in qt.g]
+    ann.ann_train_step(qt, ht, _dev(tq), _dev(idx), _dev(labels), _dev(hub_in), 0.07, 1e-3, 1)
+    torch.cuda.synchronize()
+    for p0, g, p1 in zip(qp, grads, [t.cpu().numpy() for t in qt.params()]):
+        want, _, _ = T.adam_update(np.asarray(p0, np.float64), g, 0 * g, 0 * g, 1, 1e-3)
+        assert np.allclose(p1, want, rtol=1e-6, atol=1e-7)
+    # BF16 copies follow the masters
+    w1b = qt.W1b.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    assert np.array_equal(w1b.view(np.float32),
+                          T.bf16_round(qt.W1.cpu().numpy().astype(np.float64)).astype(np.float32))
+
+
+def test_training_reduces_loss():
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    tq = synth.train_queries(ix["w"], 1000)
+    # label = nearest hub by L2 (a learnable target)
+    lab, _ = oracle.knn(ix["base"][km["hub_ids"]], tq, 1)
+    labels = lab[:, 0].astype(np.int32)
+    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    tq_d, lab_d, hub_d = _dev(tq), _dev(labels), _dev(hub_in)
+    say("case: training reduces loss")
+    losses = []
+    for step in range(1, 61):
+        idx = _dev(synth.batch_order(ix["w"], 1000, step)[:256].astype(np.int32))
+        loss, _, _ = ann.ann_train_step(qt, ht, tq_d, idx, lab_d, hub_d, 0.07, 3e-3, step)
+        losses.append(loss.item())
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:5])
+
+
+@pytest.mark.skip(reason="went silent on the GPU (killed after 180 s) in its first run with the "
+                         "first navgraph / hub-search kernels; no cause was found by reading, by CPU "
+                         "emulation of the search or in the assembly, so those kernels were taken "
+                         "out and this case is kept off the GPU")
+def test_navgraph_and_entry_select_match_oracle():
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    say("case: navgraph + entry select")
+    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    hemb = ht.forward(_dev(hub_in))
+    hg, hub_entry = ann.ann_navgraph_build(hemb, 16)
+    torch.cuda.synchronize()
+    he = hemb.cpu().numpy()
+    assert (hg.cpu().numpy() == oracle.hub_graph(he, 16)).all()
+    assert hub_entry == oracle.hub_medoid(he)
+    hub_ids = _dev(km["hub_ids"])
+    for Lh in (8, 32, 64):
+        model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, ix["medoid"], L_h=Lh)
+        ent, sc, bh = ann.ann_entry_select(model, _dev(ix["q"]), want_score=True)
+        qe = qt.forward(_dev(ix["q"])).cpu().numpy()
+        torch.cuda.synchronize()
+        ref_ent, ref_sc, ref_bh = oracle.entry_select(qe, he, hg.cpu().numpy(), km["hub_ids"], Lh,
+                                                      -math.inf, ix["medoid"], hub_entry)
+        got_bh = bh.cpu().numpy()
+        cos = qe.astype(np.float64) @ he.astype(np.float64).T
+        for i in range(len(got_bh)):
+            if got_bh[i] != ref_bh[i]:
+                # only a near tie between the two choices may differ
+                assert abs(cos[i, got_bh[i]] - cos[i, ref_bh[i]]) <= 1e-5
+        assert (got_bh == ref_bh).mean() >= 0.98
+        assert np.allclose(sc.cpu().numpy(), ref_sc, atol=1e-5)
+        if Lh >= 64:
+            assert (got_bh == np.argmax(cos, axis=1)).mean() >= 0.98
+    # theta above every cosine -> medoid everywhere
+    model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, ix["medoid"], L_h=16, theta=2.0)
+    ent, _, _ = ann.ann_entry_select(model, _dev(ix["q"]))
+    assert (ent.cpu().numpy() == ix["medoid"]).all()
+
+
+def test_hub_graph_and_entry_select_via_search_engines():
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    say("case: hub embeddings")
+    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    hemb = ht.forward(_dev(hub_in))
+    torch.cuda.synchronize()
+    he = hemb.cpu().numpy()
+    say("case: navigation graph")
+    hg, hub_entry = ann.ann_navgraph_build(hemb, 16)
+    torch.cuda.synchronize()
+    ref_hg = oracle.hub_graph(he, 16)
+    got_hg = hg.cpu().numpy()
+    d2 = ((he[:, None, :].astype(np.float64) - he[None, :, :]) ** 2).sum(-1)
+    for i in range(he.shape[0]):
+        for t in range(16):
+            if got_hg[i, t] != ref_hg[i, t]:   # only FP64 near-ties may swap
+                assert abs(d2[i, got_hg[i, t]] - d2[i, ref_hg[i, t]]) <= 1e-12
+    assert (got_hg == ref_hg).mean() >= 0.99
+    assert hub_entry == oracle.hub_medoid(he)
+    hub_ids = _dev(km["hub_ids"])
+    qe = qt.forward(_dev(ix["q"])).cpu().numpy()
+    cos = qe.astype(np.float64) @ he.astype(np.float64).T
+    for Lh in (8, 32, 64):
+        say("case: entry select L_h=%d" % Lh)
+        model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, ix["medoid"], L_h=Lh)
+        ent, sc, bh = ann.ann_entry_select(model, _dev(ix["q"]), want_score=True)
+        torch.cuda.synchronize()
+        ref_ent, ref_sc, ref_bh = oracle.entry_select(qe, he, ref_hg, km["hub_ids"], Lh,
+                                                      -math.inf, ix["medoid"], hub_entry)
+        got_bh = bh.cpu().numpy()
+        for i in range(len(got_bh)):
+            if got_bh[i] != ref_bh[i]:   # FP32 search vs FP64 oracle: near ties only
+                assert abs(cos[i, got_bh[i]] - cos[i, ref_bh[i]]) <= 1e-5
+        assert (got_bh == ref_bh).mean() >= 0.98
+        assert (ent.cpu().numpy() == km["hub_ids"][got_bh]).all()
+        assert np.allclose(sc.cpu().numpy(), cos[np.arange(len(got_bh)), got_bh], atol=1e-5)
+        if Lh >= 64:
+            assert (got_bh == np.argmax(cos, axis=1)).mean() >= 0.98
+    say("case: entry select theta fallback")
+    model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, ix["medoid"], L_h=16, theta=2.0)
+    ent, _, _ = ann.ann_entry_select(model, _dev(ix["q"]))
+    torch.cuda.synchronize()
+    assert (ent.cpu().numpy() == ix["medoid"]).all()
+
+
+@pytest.mark.skip(reason="its label-mode search kernel went silent on the GPU (killed after 180 s) "
+                         "twice, the second time after a fix for duplicated kernel symbols; the "
+                         "label-mode kernel was switched off and labels now come from the plain "
+                         "search kernel (test_ladder_labels_match_oracle); the old call signature "
+                         "no longer exists, so this case cannot run")
+@pytest.mark.parametrize("which", ["tiny", "int"])
+def test_labels_match_oracle(which):
+    ix = tiny_index() if which == "tiny" else int_index()
+    base, g, w = ix["base"], ix["graph"], ix["w"]
+    nh, M, L = 64, 8, 64
+    init = synth.kmeans_init(w, base.shape[0], nh)
+    km = oracle.kmeans_hubs(base, nh, 20, init)
+    tq = synth.train_queries(w, 300)
+    truth, _ = oracle.knn(base, tq, 10)
+    cand, _ = oracle.knn(base[km["hub_ids"]], tq, M)
+    say("case: labels %s" % which)
+    ref_lab, ref_tab = oracle.make_labels(base, g, tq, truth, cand, km["hub_ids"], L, 10)
+    lab, tab, flags = _ann().ann_make_labels(_dev(base), _dev(g), _dev(tq), _dev(truth), 10,
+                                             _dev(cand), _dev(km["hub_ids"]), L)
+    torch.cuda.synchronize()
+    lab, tab, flags = lab.cpu().numpy(), tab.cpu().numpy(), flags.cpu().numpy()
+    assert (flags == 0).all()
+    assert (lab == ref_lab).all()
+    hit = tab >= 0
+    assert (tab[hit] == ref_tab[hit]).all()
+    assert (ref_tab[tab == -1] == -1).all()
+    for i, m in zip(*np.where(tab == -2)):
+        best = min(v for v in tab[i] if v >= 0)
+        assert ref_tab[i, m] == -1 or ref_tab[i, m] > best
+
+
+@pytest.mark.parametrize("which", ["tiny", "int"])
+def test_ladder_labels_match_oracle(which):
+    ix = tiny_index() if which == "tiny" else int_index()
+    base, g, w = ix["base"], ix["graph"], ix["w"]
+    nh, M, ladder = 64, 6, [10, 16, 32, 64]
+    init = synth.kmeans_init(w, base.shape[0], nh)
+    km = oracle.kmeans_hubs(base, nh, 20, init)
+    tq = synth.train_queries(w, 200)
+    truth, _ = oracle.knn(base, tq, 10)
+    cand, _ = oracle.knn(base[km["hub_ids"]], tq, M)
+    say("case: ladder labels %s (oracle)" % which)
+    ref_lab, ref_tab = oracle.make_labels(base, g, tq, truth, cand, km["hub_ids"], ladder, 10)
+    say("case: ladder labels %s (gpu)" % which)
+    lab, tab, flags = _ann().ann_make_labels(_dev(base), _dev(g), _dev(tq), _dev(truth), 10,
+                                             _dev(cand), _dev(km["hub_ids"]), ladder)
+    torch.cuda.synchronize()
+    say("case: ladder labels %s (compare)" % which)
+    lab, tab, flags = lab.cpu().numpy(), tab.cpu().numpy(), flags.cpu().numpy()
+    assert (flags == 0).all()
+    if which == "int":      # FP32 distances are exact: identical trajectories
+        assert (tab == ref_tab).all() and (lab == ref_lab).all()
+    else:                   # FP32 vs FP64 near ties may move a cost
+        assert (tab == ref_tab).mean() >= 0.98
+        assert (lab == ref_lab).mean() >= 0.97
