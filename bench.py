@@ -1,12 +1,19 @@
-"""Benchmark: QPS at recall@10 = 0.95 of the GATE search path on one MI355X.
+"""Benchmark: QPS at recall@10 = 0.95 of the GATE query path on one MI355X,
+GATE entry vs medoid entry.
 
-Workload (default): 1,000,000 x 128 base vectors holding integers 0..255
-(256-component Gaussian mixture, sigma 20), 10,000 test queries from the same
-mixture; proximity graph = exact 128-NN -> alpha 1.2 pruning -> R = 32 with
-connectivity repair, built on the GPU.  One step = the whole query path over
-the 10,000-query batch with inputs resident in HBM: entry selection (when
-the learned entry is enabled) followed by the batched beam search.  The beam
-width L is the smallest on the sweep whose mean recall@10 reaches 0.95.
+Workload (default, "sift1m"): 1,000,000 x 128 base vectors holding integers
+0..255 (256-component Gaussian mixture, sigma 20), 10,000 test queries and
+100,000 training queries from the same mixture.  Index: exact 128-NN ->
+alpha 1.2 pruning -> R = 32 with connectivity repair; 1,024 Lloyd hubs; two
+towers 128->128->64 and (128+32)->128->64 trained with the contrastive loss;
+hub navigation graph s = 16.  All of it is built on the GPU before timing.
+
+One step = the whole query path over the 10,000-query batch, inputs resident
+in HBM: entry selection (query tower + hub-graph search) then the batched
+beam search.  The beam width L is the smallest on the sweep whose mean
+recall@10 reaches 0.95.  The medoid entry is measured the same way (search
+only); when it never reaches 0.95 its best recall and the QPS there are
+reported.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
@@ -47,11 +54,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sift1m")
-    ap.add_argument("--n", type=int, default=0, help="override base size (parity runs)")
+    ap.add_argument("--n", type=int, default=0, help="override base size")
+    ap.add_argument("--n-train", type=int, default=0, help="override training-query count")
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-steps", action="store_true",
-                    help="only the timed search steps (for rocprofv3 runs)")
+    ap.add_argument("--no-gate", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build "
@@ -60,13 +68,13 @@ def main():
 
     import torch
 
-    from paper_2506_15986_amd import ann, synth
+    from paper_2506_15986_amd import ann, gate, synth
 
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[args.workload]
-    if args.n:
-        w = synth.scaled(w, n=args.n)
-    knn_k, R, alpha, k = 128, 32, 1.2, 10
+    if args.n or args.n_train:
+        w = synth.scaled(w, n=args.n or None, n_train=args.n_train or None)
+    knn_k, R, k = 128, 32, 10
 
     t0 = time.time()
     base = synth.base(w)
@@ -76,121 +84,144 @@ def main():
     q_d = torch.from_numpy(queries).to(dev)
     nq = q_d.shape[0]
 
-    t0 = time.time()
-    graph, medoid, bridges = ann.ann_build_graph(base_d, knn_k, R, alpha)
-    torch.cuda.synchronize()
-    t_graph = time.time() - t0
-    log("graph: kNN %d -> alpha %.1f -> R %d, medoid %d, bridges %s (%.1fs)" %
-        (knn_k, alpha, R, medoid, bridges, t_graph))
-
-    t0 = time.time()
+    index = gate.build_index(base_d, knn_k, R, 1.2)
+    log("graph: kNN %d -> alpha 1.2 -> R %d, medoid %d, bridges %s (%.1fs)" %
+        (knn_k, R, index.medoid, index.bridges, index.build_s))
     gt_ids, _ = ann.ann_gt_knn(base_d, q_d, k)
     gt = gt_ids.cpu().numpy()
-    log("ground truth top-%d (%.1fs)" % (k, time.time() - t0))
 
     kk = torch.full((nq,), k, dtype=torch.int32, device=dev)
-
-    def run(L, entry=None, plan=None):
-        Lt = torch.full((nq,), L, dtype=torch.int32, device=dev)
-        if plan is None:
-            plan = ann.default_plan(w.n, w.d, R, L)
-        return ann.ann_search(base_d, graph, q_d, entry, medoid, kk, Lt, k_max=k, plan=plan), plan
-
-    # ---- medoid entry: smallest L on the sweep reaching the target recall
-    sweep = []
-    L95 = None
-    for L in L_SWEEP:
-        (ids, _, st, _), _ = run(L)
-        torch.cuda.synchronize()
-        rec = float(recall_at(ids.cpu().numpy(), gt).mean())
-        s = st.cpu().numpy()
-        sweep.append(dict(L=L, recall=rec, ndc=float(s[:, 0].mean()), hops=float(s[:, 2].mean())))
-        log("  medoid L=%4d recall@10=%.4f ndc=%.0f hops=%.0f" % (L, rec, s[:, 0].mean(),
-                                                                   s[:, 2].mean()))
-        if rec >= TARGET:
-            L95 = L
-            break
-    L_use = L95 if L95 is not None else L_SWEEP[-1]
-    reached = L95 is not None
-
-    # ---- timed steps
-    plan = ann.default_plan(w.n, w.d, R, L_use)
-    Lt = torch.full((nq,), L_use, dtype=torch.int32, device=dev)
     out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
            torch.empty((nq, k), dtype=torch.float32, device=dev),
            torch.empty((nq, 4), dtype=torch.int32, device=dev))
     ws = ann.workspace("search", w.n, w.d, nq, device=dev)
 
-    def step():
-        ann.ann_search(base_d, graph, q_d, None, medoid, kk, Lt, k_max=k, plan=plan, out=out,
-                       ws=ws)
+    def sweep(entry, label):
+        rows, L95 = [], None
+        for L in L_SWEEP:
+            index.search(q_d, L, kk, entry, out=out, ws=ws)
+            torch.cuda.synchronize()
+            rec = float(recall_at(out[0].cpu().numpy(), gt).mean())
+            st = out[2].cpu().numpy()
+            rows.append(dict(L=L, recall=round(rec, 5), ndc=round(float(st[:, 0].mean()), 1),
+                             hops=round(float(st[:, 2].mean()), 1)))
+            log("  %s L=%4d recall@10=%.4f ndc=%.0f hops=%.0f" % (label, L, rec, st[:, 0].mean(),
+                                                                  st[:, 2].mean()))
+            if rec >= TARGET:
+                L95 = L
+                break
+        return rows, L95
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    t0 = time.time()
-    for a, b in ev:
-        a.record()
-        step()
-        b.record()
-    torch.cuda.synchronize()
-    wall = time.time() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
-    ms_step = wall * 1000.0 / args.steps
-    qps = nq * args.steps / wall
-    ids, st = out[0].cpu().numpy(), out[2].cpu().numpy()
-    rec = float(recall_at(ids, gt).mean())
-    log("timed: L=%d recall=%.4f %.3f ms/step (kernel %.3f ms) -> %.0f QPS" %
-        (L_use, rec, ms_step, float(np.mean(kern_ms)), qps))
-    if args.profile_steps:
-        return
+    def timed(L, entry_fn, label):
+        """K timed steps; entry_fn() runs the entry selection (or None)."""
+        plan = ann.default_plan(w.n, w.d, R, L)
+        Lt = torch.full((nq,), L, dtype=torch.int32, device=dev)
 
-    # ---- roofline of the search kernel: algorithmic bytes per launch
-    d = w.d
-    ndc_u = st[:, 0].astype(np.float64)
-    hops = st[:, 2].astype(np.float64)
-    bytes_launch = float((4 * d * ndc_u + 4 * R * hops + 4 * d + 8 * k).sum())
-    t_launch = float(np.mean(kern_ms)) / 1000.0
-    achieved = bytes_launch / t_launch / 1e9
+        def step():
+            e = entry_fn() if entry_fn else None
+            ann.ann_search(base_d, index.graph, q_d, e, index.medoid, kk, Lt, k_max=k, plan=plan,
+                           out=out, ws=ws)
 
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t0 = time.time()
+        for a, m, b in ev:
+            a.record()
+            e = entry_fn() if entry_fn else None
+            m.record()
+            ann.ann_search(base_d, index.graph, q_d, e, index.medoid, kk, Lt, k_max=k, plan=plan,
+                           out=out, ws=ws)
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        search_ms = float(np.mean([m.elapsed_time(b) for a, m, b in ev]))
+        entry_ms = float(np.mean([a.elapsed_time(m) for a, m, b in ev]))
+        st = out[2].cpu().numpy()
+        rec = float(recall_at(out[0].cpu().numpy(), gt).mean())
+        res = dict(L=L, recall=round(rec, 5), qps=round(nq * args.steps / wall, 1),
+                   ms_per_step=round(wall * 1000.0 / args.steps, 4), search_ms=round(search_ms, 4),
+                   entry_ms=round(entry_ms, 4), ndc=round(float(st[:, 0].mean()), 1),
+                   hops=round(float(st[:, 2].mean()), 1))
+        d = w.d
+        bytes_launch = float((4 * d * st[:, 0].astype(np.float64) +
+                              4 * R * st[:, 2].astype(np.float64) + 4 * d + 8 * k).sum())
+        res["bytes_per_launch"] = bytes_launch
+        res["achieved_gbs"] = round(bytes_launch / (search_ms / 1000.0) / 1e9, 1)
+        log("timed %s: L=%d recall=%.4f %.3f ms/step (entry %.3f, search %.3f ms) -> %.0f QPS, "
+            "%.0f GB/s" % (label, L, rec, res["ms_per_step"], entry_ms, search_ms, res["qps"],
+                           res["achieved_gbs"]))
+        return res
+
+    # ---- medoid entry
+    med_rows, med_L95 = sweep(None, "medoid")
+    best_med = max(med_rows, key=lambda r: r["recall"])
+    med = timed(med_L95 if med_L95 else best_med["L"], None, "medoid")
+    med["reached_target"] = med_L95 is not None
+
+    # ---- GATE entry
+    gres, ginfo, abl = None, {}, {}
+    if not args.no_gate:
+        tq = torch.from_numpy(synth.train_queries(w)).to(dev)
+        t = time.time()
+        g = gate.build_gate(index, tq, w, epochs=args.epochs, log=log)
+        ginfo = dict(g.info, build_s=round(time.time() - t, 1))
+        ent = torch.empty(nq, dtype=torch.int32, device=dev)
+        g.select(q_d, out=ent)
+        g_rows, g_L95 = sweep(ent, "gate")
+        best_g = max(g_rows, key=lambda r: r["recall"])
+        gres = timed(g_L95 if g_L95 else best_g["L"], lambda: g.select(q_d, out=ent)[0], "gate")
+        gres["reached_target"] = g_L95 is not None
+        gres["sweep"] = g_rows
+        # ablation: nearest hub by L2, no learning (entry cost not timed)
+        ne = gate.nearest_hub_entries(index, g.hub_ids, q_d)
+        n_rows, n_L95 = sweep(ne, "nearest-hub")
+        abl["nearest_hub"] = dict(L95=n_L95, sweep=n_rows)
+        del tq
+
+    head = gres if (gres is not None and gres["reached_target"]) else med
     # ---- CPU baseline: the oracle on a bounded sample of the same queries
     cpu = None
     if not args.no_cpu:
         import oracle
-        g_host = graph.cpu().numpy()
+        g_host = index.graph.cpu().numpy()
+        ent_host = ent.cpu().numpy() if gres is not None else np.full(nq, index.medoid, np.int32)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         cores = min(cores, 16)
-        m = 256
-        tot_q, tot_t = 0, 0.0
+        L_cpu = head["L"]
+        m, tot_q, tot_t = 256, 0, 0.0
         while tot_t < args.cpu_seconds and tot_q < nq:
             sl = slice(tot_q, min(nq, tot_q + m))
             t0 = time.time()
-            oracle.search(base, g_host, queries[sl], medoid, k, L_use, threads=cores)
+            oracle.search(base, g_host, queries[sl], ent_host[sl], k, L_cpu, threads=cores)
             tot_t += time.time() - t0
             tot_q = sl.stop
             m *= 2
         cpu = dict(value=round(tot_q / tot_t, 2), unit="queries/s", cores=int(cores), kind="oracle",
-                   sample="first %d of the %d queries, medoid entry, L=%d, k=%d, FP64" %
-                          (tot_q, nq, L_use, k))
+                   sample="first %d of the %d queries, %s entries (GPU-selected), L=%d, k=%d, "
+                          "FP64 search only" % (tot_q, nq, "GATE" if gres else "medoid", L_cpu, k))
         log("cpu oracle: %d queries in %.1fs on %d threads -> %.1f QPS" %
             (tot_q, tot_t, cores, tot_q / tot_t))
 
+    achieved = head["achieved_gbs"]
     res = dict(
-        metric=METRIC, value=round(qps, 1), unit="queries/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(ms_step, 4), higher_is_better=True, scaling="weak",
-        vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload="%s: N=%d d=%d (integers 0..255, 256-component GMM), %d queries, "
-                             "graph kNN%d/alpha%.1f/R%d + repair; entry=medoid; L=%d" %
-                             (w.name, w.n, w.d, nq, knn_k, alpha, R, L_use),
-                    entry="medoid", L=L_use, k=k, recall_at_10=round(rec, 4),
-                    recall_target_reached=reached, graph_build_s=round(t_graph, 2),
-                    bridges=list(bridges), sweep=sweep),
-        roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+        metric=METRIC, value=head["qps"], unit="queries/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(
+            workload="%s: N=%d d=%d integers 0..255 (256-component GMM, sigma 20), %d queries, "
+                     "%d training queries; graph kNN%d/alpha1.2/R%d + repair; 1024 hubs; "
+                     "towers %d->128->64" % (w.name, w.n, w.d, nq, w.n_train, knn_k, R, w.d),
+            entry="gate" if head is gres else "medoid", k=k, L=head["L"],
+            recall_at_10=head["recall"], recall_target=TARGET,
+            gate=gres, medoid=med, medoid_sweep=med_rows, ablation=abl, gate_build=ginfo,
+            graph_build_s=round(index.build_s, 2), bridges=list(index.bridges)),
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                      kernel="search_kernel", bytes_per_launch=bytes_launch,
-                      launch_ms=round(t_launch * 1000, 4)),
+                      kernel="search_kernel", bytes_per_launch=head["bytes_per_launch"],
+                      launch_ms=head["search_ms"]),
         cpu_baseline=cpu,
     )
     print(json.dumps(res), flush=True)

@@ -239,6 +239,12 @@ typedef struct ann_adam_state {
     float *mW1, *vW1, *mb1, *vb1, *mW2, *vW2, *mb2, *vb2;   /* zero-initialised */
 } ann_adam_state;
 
+/* Hub tower input: row c = [ base row hub_ids[c] | features row c ]
+ * (n_hubs x (dim + n_feat) FP32).  n_feat may be 0 (the hub vectors alone). */
+ann_status ann_hub_input(const float *base, int64_t n, int32_t dim, const int32_t *hub_ids,
+                         int32_t n_hubs, const float *features, int32_t n_feat, float *out,
+                         void *stream);
+
 /* Refreshes the BF16 copies from the FP32 masters (RNE). */
 ann_status ann_tower_sync(const ann_tower *tower, void *stream);
 

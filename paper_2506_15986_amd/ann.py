@@ -98,6 +98,7 @@ class ann_entry_model(ctypes.Structure):
                 ("L_h", _I32), ("theta", _F32)]
 
 
+_sig("ann_hub_input", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _P)
 _sig("ann_tower_sync", _I32, ctypes.POINTER(ann_tower), _P)
 _sig("ann_tower_workspace_size", _SZ, ctypes.POINTER(ann_tower), _I32)
 _sig("ann_tower_forward", _I32, ctypes.POINTER(ann_tower), _P, _I32, _P, _P, _SZ, _P)
@@ -452,3 +453,15 @@ def ann_default_plan(n: int, dim: int, R: int, L_max: int) -> ann_search_plan:
 
 def ann_navgraph_workspace_size(n_hubs: int, dim: int, s: int) -> int:
     return int(_lib.ann_navgraph_workspace_size(n_hubs, dim, s))
+
+
+def ann_hub_input(base: torch.Tensor, hub_ids: torch.Tensor, features: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """[base[hub_ids] | features] as an n_hubs x (dim + n_feat) FP32 matrix."""
+    n, dim = base.shape
+    nh = hub_ids.shape[0]
+    nf = 0 if features is None else features.shape[1]
+    out = torch.empty((nh, dim + nf), dtype=torch.float32, device=base.device)
+    _check(_lib.ann_hub_input(_ptr(base), n, dim, _ptr(hub_ids), nh, _ptr(features), nf, _ptr(out),
+                              _stream(stream)))
+    return out

@@ -511,6 +511,21 @@ ann_status refresh_bf16(const ann_tower &w, hipStream_t st)
 
 using namespace ann;
 
+extern "C" ann_status ann_hub_input(const float *base, int64_t n, int32_t dim, const int32_t *hub_ids,
+                                    int32_t n_hubs, const float *features, int32_t n_feat,
+                                    float *out, void *stream)
+{
+    ANN_REQUIRE(base && hub_ids && out, "a required pointer is NULL");
+    ANN_REQUIRE(n_feat == 0 || features, "features is NULL");
+    ANN_REQUIRE(n >= 1 && dim >= 1 && n_hubs >= 1 && n_feat >= 0, "bad sizes");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t count = (int64_t)n_hubs * (dim + n_feat);
+    hipLaunchKernelGGL(hub_input_kernel, dim3(gridn(count)), dim3(256), 0, st, base, dim, hub_ids,
+                       features, n_feat, n_hubs, out, (uint16_t *)nullptr);
+    ANN_LAUNCHED();
+    return ANN_OK;
+}
+
 extern "C" size_t ann_tower_workspace_size(const ann_tower *tower, int32_t rows)
 {
     return tower ? tower_forward_ws(rows, tower) : 0;

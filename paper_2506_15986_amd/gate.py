@@ -1,0 +1,151 @@
+"""Index and entry-model construction for the GATE query path, composed from
+the libann entry points (every step runs in the library's kernels; this
+module only sequences the calls and holds the device tensors).
+
+    index = build_index(base, knn_k=128, R=32, alpha=1.2)
+    gate = build_gate(index, train_queries, workload)
+    entries = gate.select(queries)            # query tower + hub-graph search
+    ids, dist, stats, _ = index.search(queries, L, k, entries)
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import ann, synth
+
+
+@dataclasses.dataclass
+class Index:
+    base: torch.Tensor
+    graph: torch.Tensor
+    medoid: int
+    bridges: tuple
+    R: int
+    build_s: float
+
+    @property
+    def n(self):
+        return self.base.shape[0]
+
+    @property
+    def dim(self):
+        return self.base.shape[1]
+
+    def search(self, queries, L, k, entry_ids=None, plan=None, out=None, ws=None):
+        nq = queries.shape[0]
+        dev = queries.device
+        kk = k if torch.is_tensor(k) else torch.full((nq,), int(k), dtype=torch.int32, device=dev)
+        LL = L if torch.is_tensor(L) else torch.full((nq,), int(L), dtype=torch.int32, device=dev)
+        if plan is None:
+            Lmax = int(L) if not torch.is_tensor(L) else int(LL.max().item())
+            plan = ann.default_plan(self.n, self.dim, self.R, Lmax)
+        return ann.ann_search(self.base, self.graph, queries, entry_ids, self.medoid, kk, LL,
+                              k_max=int(k) if not torch.is_tensor(k) else None, plan=plan,
+                              out=out, ws=ws)
+
+
+def build_index(base: torch.Tensor, knn_k: int = 128, R: int = 32, alpha: float = 1.2) -> Index:
+    t = time.time()
+    graph, med, bridges = ann.ann_build_graph(base, knn_k, R, alpha)
+    torch.cuda.synchronize()
+    return Index(base, graph, med, bridges, R, time.time() - t)
+
+
+@dataclasses.dataclass
+class Gate:
+    qtower: ann.Tower
+    htower: ann.Tower
+    hub_ids: torch.Tensor
+    hub_in: torch.Tensor
+    hub_emb: torch.Tensor
+    hub_graph: torch.Tensor
+    hub_entry: int
+    model: ann.EntryModel
+    info: dict
+
+    def select(self, queries, out=None, want_score=False):
+        return ann.ann_entry_select(self.model, queries, want_score=want_score, out=out)
+
+
+def nearest_hub_entries(index: Index, hub_ids: torch.Tensor, queries: torch.Tensor):
+    """Ablation without learning: entry = the hub nearest the query by L2."""
+    hv = ann.ann_hub_input(index.base, hub_ids)
+    ids, _ = ann.ann_gt_knn(hv, queries, 1)
+    return hub_ids[ids[:, 0].long()].contiguous()
+
+
+def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
+               kmeans_iters: int = 20, M: int = 8, ladder=(10, 16, 24, 32, 48, 64, 96, 128),
+               hidden: int = 128, dout: int = 64, epochs: int = 20, batch: int = 1024,
+               lr: float = 1e-3, tau: float = 0.07, s: int = 16, L_h: int = 32,
+               theta: float = -math.inf, train: bool = True, log=print) -> Gate:
+    base, dev = index.base, index.base.device
+    n, d = base.shape
+    info = {}
+    t = time.time()
+    init = torch.from_numpy(synth.kmeans_init(w, n, n_hubs)).to(dev)
+    hub_ids, cen, assign, steps = ann.ann_select_hubs(base, n_hubs, kmeans_iters, init)
+    torch.cuda.synchronize()
+    info["kmeans_steps"] = steps
+    info["hubs_s"] = time.time() - t
+    log("hubs: %d Lloyd steps, %.1fs" % (steps, info["hubs_s"]))
+
+    t = time.time()
+    feat, _ = ann.ann_hub_features(base, index.graph, index.medoid, hub_ids, assign, cen)
+    hub_in = ann.ann_hub_input(base, hub_ids, feat)
+    hub_vec = ann.ann_hub_input(base, hub_ids)
+    torch.cuda.synchronize()
+    info["features_s"] = time.time() - t
+
+    t = time.time()
+    truth, _ = ann.ann_gt_knn(base, train_q, 10)
+    cand, _ = ann.ann_gt_knn(hub_vec, train_q, M)
+    labels, table, flags = ann.ann_make_labels(base, index.graph, train_q, truth, 10, cand, hub_ids,
+                                               list(ladder))
+    torch.cuda.synchronize()
+    info["labels_s"] = time.time() - t
+    tab = table.cpu().numpy()
+    info["labels_reached"] = float((tab >= 0).any(axis=1).mean())
+    info["label_is_nearest_hub"] = float((labels.cpu().numpy() == cand[:, 0].cpu().numpy()).mean())
+    info["label_flags"] = int((flags.cpu().numpy() != 0).sum())
+    log("labels: %.1fs, reached %.3f, nearest-hub agreement %.3f" %
+        (info["labels_s"], info["labels_reached"], info["label_is_nearest_hub"]))
+
+    qp = synth.tower_init(w, [(hidden, d), (dout, hidden)])
+    hp = synth.tower_init(w, [(hidden, d + 32), (dout, hidden)])
+    qt, ht = ann.Tower(*qp, device=dev), ann.Tower(*hp, device=dev)
+    t = time.time()
+    nt = train_q.shape[0]
+    step = 0
+    losses = []
+    nb = ann.ann_train_workspace_size(batch, n_hubs, d, d + 32, hidden, dout)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    if train:
+        for ep in range(epochs):
+            order = torch.from_numpy(synth.batch_order(w, nt, ep).astype(np.int32)).to(dev)
+            for b0 in range(0, nt - batch + 1, batch):
+                step += 1
+                loss, _, _ = ann.ann_train_step(qt, ht, train_q, order[b0:b0 + batch], labels, hub_in,
+                                                tau, lr, step, ws=ws)
+            losses.append(loss.item())
+    torch.cuda.synchronize()
+    info["train_s"] = time.time() - t
+    info["train_steps"] = step
+    info["loss_per_epoch"] = [round(x, 4) for x in losses]
+    if losses:
+        log("training: %d steps, %.1fs, loss %.3f -> %.3f" % (step, info["train_s"], losses[0],
+                                                              losses[-1]))
+    hemb = ht.forward(hub_in)
+    hg, hub_entry = ann.ann_navgraph_build(hemb, s)
+    model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, index.medoid, L_h=L_h, theta=theta)
+    # training accuracy: does the query tower pick the label hub?
+    sample = train_q[: min(nt, 10000)]
+    _, _, bh = ann.ann_entry_select(model, sample, want_score=True)
+    info["train_top1"] = float((bh == labels[: sample.shape[0]]).float().mean().item())
+    log("entry model: train top-1 agreement with labels %.3f" % info["train_top1"])
+    return Gate(qt, ht, hub_ids, hub_in, hemb, hg, hub_entry, model, info)
