@@ -49,6 +49,11 @@ const char *ann_last_error(void);
 /* ABI version (major * 100 + minor). */
 int32_t ann_version(void);
 
+/* *result (host) = max |x_i| over x[0..count).  workspace >= 4 bytes.
+ * Synchronises `stream`. */
+ann_status ann_max_abs(const float *x, int64_t count, float *result, void *workspace,
+                       size_t ws_bytes, void *stream);
+
 /* Operation codes for ann_workspace_size(). */
 enum {
     ANN_OP_SEARCH = 1,
@@ -223,6 +228,8 @@ ann_status ann_hub_features(const float *base, int64_t n, int32_t dim, const int
 
 typedef struct ann_tower {
     int32_t din, hidden, dout;
+    float in_scale; /* the input is multiplied by in_scale before the BF16 rounding
+                       (a power of two keeps it exact) */
     float *W1;      /* hidden x din, FP32 master */
     float *b1;      /* hidden */
     float *W2;      /* dout x hidden */
@@ -239,11 +246,11 @@ typedef struct ann_adam_state {
     float *mW1, *vW1, *mb1, *vb1, *mW2, *vW2, *mb2, *vb2;   /* zero-initialised */
 } ann_adam_state;
 
-/* Hub tower input: row c = [ base row hub_ids[c] | features row c ]
+/* Hub tower input: row c = [ base row hub_ids[c] * vec_scale | features row c ]
  * (n_hubs x (dim + n_feat) FP32).  n_feat may be 0 (the hub vectors alone). */
 ann_status ann_hub_input(const float *base, int64_t n, int32_t dim, const int32_t *hub_ids,
-                         int32_t n_hubs, const float *features, int32_t n_feat, float *out,
-                         void *stream);
+                         int32_t n_hubs, const float *features, int32_t n_feat, float vec_scale,
+                         float *out, void *stream);
 
 /* Refreshes the BF16 copies from the FP32 masters (RNE). */
 ann_status ann_tower_sync(const ann_tower *tower, void *stream);

@@ -48,13 +48,14 @@ def _rnd(x, bf16):
     return bf16_round(x) if bf16 else np.asarray(x, dtype=np.float64)
 
 
-def tower_forward(params, x, bf16=True):
-    """params = (W1 [h x din], b1 [h], W2 [e x h], b2 [e]) float32 masters.
+def tower_forward(params, x, bf16=True, in_scale=1.0):
+    """params = (W1 [h x din], b1 [h], W2 [e x h], b2 [e]) float32 masters;
+    the input is multiplied by in_scale (a power of two) before rounding.
 
     Returns (e_hat [n x e], cache)."""
     W1, b1, W2, b2 = [np.asarray(p, np.float64) for p in params]
     W1r, W2r = _rnd(W1, bf16), _rnd(W2, bf16)
-    xr = _rnd(x, bf16)
+    xr = _rnd(np.asarray(x, np.float64) * in_scale, bf16)
     z1 = xr @ W1r.T + b1
     a1 = np.maximum(z1, 0.0)
     a1r = _rnd(a1, bf16)
@@ -99,10 +100,10 @@ def infonce(eq, eh, labels, tau):
     return loss, deq, deh, ds
 
 
-def train_step_grads(qparams, hparams, xq, xh, labels, tau, bf16=True):
+def train_step_grads(qparams, hparams, xq, xh, labels, tau, bf16=True, q_scale=1.0):
     """Full forward/backward of one batch: returns (loss, q grads, h grads,
-    eq, eh)."""
-    eq, cq = tower_forward(qparams, xq, bf16)
+    eq, eh).  q_scale: the query tower's input scale."""
+    eq, cq = tower_forward(qparams, xq, bf16, q_scale)
     eh, ch = tower_forward(hparams, xh, bf16)
     loss, deq, deh, _ = infonce(eq, eh, labels, tau)
     gq = tower_backward(cq, deq, bf16)

@@ -61,6 +61,7 @@ def _sig(name, restype, *argtypes):
 _lib.ann_last_error.restype = ctypes.c_char_p
 _lib.ann_version.restype = _I32
 _sig("ann_workspace_size", _SZ, _I32, _I64, _I32, _I32, _I32)
+_sig("ann_max_abs", _I32, _P, _I64, ctypes.POINTER(_F32), _P, _SZ, _P)
 _sig("ann_default_plan", _I32, _I64, _I32, _I32, _I32, ctypes.POINTER(ann_search_plan))
 _sig("ann_search", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _I32, _P, _P, _I32, _P, _P, _P,
      _P, _I32, ctypes.POINTER(ann_search_plan), _P, _SZ, _P)
@@ -80,7 +81,8 @@ _sig("ann_make_labels", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _I32, _I32
 
 
 class ann_tower(ctypes.Structure):
-    _fields_ = [("din", _I32), ("hidden", _I32), ("dout", _I32), ("W1", _P), ("b1", _P),
+    _fields_ = [("din", _I32), ("hidden", _I32), ("dout", _I32), ("in_scale", _F32), ("W1", _P),
+                ("b1", _P),
                 ("W2", _P), ("b2", _P), ("W1b", _P), ("W2b", _P)]
 
 
@@ -98,7 +100,7 @@ class ann_entry_model(ctypes.Structure):
                 ("L_h", _I32), ("theta", _F32)]
 
 
-_sig("ann_hub_input", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _P)
+_sig("ann_hub_input", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _F32, _P, _P)
 _sig("ann_tower_sync", _I32, ctypes.POINTER(ann_tower), _P)
 _sig("ann_tower_workspace_size", _SZ, ctypes.POINTER(ann_tower), _I32)
 _sig("ann_tower_forward", _I32, ctypes.POINTER(ann_tower), _P, _I32, _P, _P, _SZ, _P)
@@ -308,8 +310,9 @@ def ann_labels_workspace_size(nq: int, M: int, kt: int) -> int:
 class Tower:
     """Device-resident tower: FP32 masters, BF16 copies, gradients, Adam state."""
 
-    def __init__(self, W1, b1, W2, b2, device="cuda"):
+    def __init__(self, W1, b1, W2, b2, device="cuda", in_scale: float = 1.0):
         f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        self.in_scale = float(in_scale)
         self.W1, self.b1, self.W2, self.b2 = f(W1), f(b1), f(W2), f(b2)
         self.hidden, self.din = self.W1.shape
         self.dout = self.W2.shape[0]
@@ -324,7 +327,7 @@ class Tower:
         return [self.W1, self.b1, self.W2, self.b2]
 
     def struct(self) -> ann_tower:
-        return ann_tower(self.din, self.hidden, self.dout, self.W1.data_ptr(),
+        return ann_tower(self.din, self.hidden, self.dout, self.in_scale, self.W1.data_ptr(),
                          self.b1.data_ptr(), self.W2.data_ptr(), self.b2.data_ptr(),
                          self.W1b.data_ptr(), self.W2b.data_ptr())
 
@@ -456,12 +459,29 @@ def ann_navgraph_workspace_size(n_hubs: int, dim: int, s: int) -> int:
 
 
 def ann_hub_input(base: torch.Tensor, hub_ids: torch.Tensor, features: torch.Tensor | None = None,
-                  stream=None) -> torch.Tensor:
-    """[base[hub_ids] | features] as an n_hubs x (dim + n_feat) FP32 matrix."""
+                  vec_scale: float = 1.0, stream=None) -> torch.Tensor:
+    """[base[hub_ids] * vec_scale | features] as an n_hubs x (dim + n_feat) FP32 matrix."""
     n, dim = base.shape
     nh = hub_ids.shape[0]
     nf = 0 if features is None else features.shape[1]
     out = torch.empty((nh, dim + nf), dtype=torch.float32, device=base.device)
-    _check(_lib.ann_hub_input(_ptr(base), n, dim, _ptr(hub_ids), nh, _ptr(features), nf, _ptr(out),
-                              _stream(stream)))
+    _check(_lib.ann_hub_input(_ptr(base), n, dim, _ptr(hub_ids), nh, _ptr(features), nf,
+                              float(vec_scale), _ptr(out), _stream(stream)))
     return out
+
+
+def ann_max_abs(x: torch.Tensor, stream=None) -> float:
+    _dev(x, torch.float32)
+    ws = torch.empty(256, dtype=torch.uint8, device=x.device)
+    r = _F32(0)
+    _check(_lib.ann_max_abs(_ptr(x), x.numel(), ctypes.byref(r), _ptr(ws), ws.numel(),
+                            _stream(stream)))
+    return float(r.value)
+
+
+def input_scale(max_abs: float) -> float:
+    """Power of two 2^-e with max_abs * 2^-e <= 1 (exact in BF16)."""
+    import math
+    if max_abs <= 0:
+        return 1.0
+    return 2.0 ** (-max(0, math.ceil(math.log2(max_abs))))

@@ -18,6 +18,20 @@ ann_status reset_work_counter(uint32_t *c, hipStream_t st)
     return ANN_OK;
 }
 
+// max |x| over an array; non-negative float bits order like unsigned ints
+__global__ void ann_max_abs_kernel(const float *x, int64_t count, unsigned int *out)
+{
+    unsigned int m = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned int b = __float_as_uint(fabsf(x[i]));
+        m = b > m ? b : m;
+    }
+    atomicMax(out, m);
+}
+
+__global__ void ann_zero_u32_kernel(unsigned int *p) { *p = 0u; }
+
 static thread_local char g_err[512] = "";
 
 ann_status fail(ann_status s, const char *fmt, ...)
@@ -49,3 +63,26 @@ int device_cus()
 extern "C" const char *ann_last_error(void) { return ann::g_err; }
 
 extern "C" int32_t ann_version(void) { return 100; }
+
+extern "C" ann_status ann_max_abs(const float *x, int64_t count, float *result, void *workspace,
+                                  size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(x && result && workspace, "a required pointer is NULL");
+    ANN_REQUIRE(count >= 1, "count must be >= 1");
+    ANN_REQUIRE(ws_bytes >= 4, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned int *d = static_cast<unsigned int *>(workspace);
+    hipLaunchKernelGGL(ann::ann_zero_u32_kernel, dim3(1), dim3(1), 0, st, d);
+    ANN_LAUNCHED();
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(ann::ann_max_abs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, count, d);
+    ANN_LAUNCHED();
+    unsigned int h = 0;
+    ANN_HIP(hipMemcpyAsync(&h, d, 4, hipMemcpyDeviceToHost, st));
+    ANN_HIP(hipStreamSynchronize(st));
+    float f;
+    memcpy(&f, &h, sizeof(f));
+    *result = f;
+    return ANN_OK;
+}

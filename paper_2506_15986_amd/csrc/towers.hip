@@ -151,28 +151,29 @@ __global__ void to_bf16_kernel(const float *x, int64_t count, uint16_t *out)
         out[i] = f2bf(x[i]);
 }
 
-// rows idx[i] of x (ld cols) -> bf16 rows i; idx NULL = identity
+// rows idx[i] of x (ld cols), times `scale`, -> bf16 rows i; idx NULL = identity
 __global__ void gather_bf16_kernel(const float *x, int cols, const int32_t *idx, int rows,
-                                   uint16_t *out)
+                                   float scale, uint16_t *out)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)rows * cols;
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = e / cols, c = e % cols;
         int64_t src = idx ? idx[r] : r;
-        out[e] = f2bf(x[src * cols + c]);
+        out[e] = f2bf(x[src * cols + c] * scale);
     }
 }
 
-// hub tower input [x_hub | features]: rows of base (hub ids) then 32 features
+// hub tower input [x_hub * vec_scale | features]: rows of base (hub ids) then the features
 __global__ void hub_input_kernel(const float *base, int dim, const int32_t *hub_ids,
-                                 const float *feat, int nfeat, int nh, float *out32,
-                                 uint16_t *outb)
+                                 const float *feat, int nfeat, int nh, float vec_scale,
+                                 float *out32, uint16_t *outb)
 {
     const int cols = dim + nfeat;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)nh * cols;
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = e / cols, c = e % cols;
-        float v = c < dim ? base[(int64_t)hub_ids[r] * dim + c] : feat[r * nfeat + (c - dim)];
+        float v = c < dim ? base[(int64_t)hub_ids[r] * dim + c] * vec_scale
+                          : feat[r * nfeat + (c - dim)];
         if (out32) out32[e] = v;
         if (outb) outb[e] = f2bf(v);
     }
@@ -464,6 +465,7 @@ ann_status check_tower(const ann_tower *w, const char *name)
     ANN_REQUIRE(w->W1 && w->b1 && w->W2 && w->b2 && w->W1b && w->W2b, "%s tower has a NULL pointer",
                 name);
     ANN_REQUIRE(w->din >= 1 && w->hidden >= 1 && w->dout >= 1, "%s tower has a bad shape", name);
+    ANN_REQUIRE(w->in_scale > 0.f, "%s tower in_scale must be > 0", name);
     ANN_SUPPORTED(w->dout <= 1024 && w->hidden <= 4096 && w->din <= 4096, "%s tower too large",
                   name);
     return ANN_OK;
@@ -492,7 +494,7 @@ ann_status tower_forward_run(const ann_tower &w, const float *x, const int32_t *
     TowerBufs b = carve_tower(cv, rows, w.din, w.hidden, w.dout);
     b.e = out;
     hipLaunchKernelGGL(gather_bf16_kernel, dim3(gridn((int64_t)rows * w.din)), dim3(256), 0, st, x,
-                       w.din, idx, rows, b.xb);
+                       w.din, idx, rows, w.in_scale, b.xb);
     ANN_LAUNCHED();
     return tower_fwd(w, b, rows, st);
 }
@@ -513,7 +515,7 @@ using namespace ann;
 
 extern "C" ann_status ann_hub_input(const float *base, int64_t n, int32_t dim, const int32_t *hub_ids,
                                     int32_t n_hubs, const float *features, int32_t n_feat,
-                                    float *out, void *stream)
+                                    float vec_scale, float *out, void *stream)
 {
     ANN_REQUIRE(base && hub_ids && out, "a required pointer is NULL");
     ANN_REQUIRE(n_feat == 0 || features, "features is NULL");
@@ -521,7 +523,7 @@ extern "C" ann_status ann_hub_input(const float *base, int64_t n, int32_t dim, c
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t count = (int64_t)n_hubs * (dim + n_feat);
     hipLaunchKernelGGL(hub_input_kernel, dim3(gridn(count)), dim3(256), 0, st, base, dim, hub_ids,
-                       features, n_feat, n_hubs, out, (uint16_t *)nullptr);
+                       features, n_feat, n_hubs, vec_scale, out, (uint16_t *)nullptr);
     ANN_LAUNCHED();
     return ANN_OK;
 }
@@ -594,11 +596,11 @@ extern "C" ann_status ann_train_step(ann_tower *qt, ann_tower *ht, const ann_tow
 
     // forward
     hipLaunchKernelGGL(gather_bf16_kernel, dim3(gridn((int64_t)batch * qt->din)), dim3(256), 0, st,
-                       train_q, qt->din, batch_idx, batch, bq.xb);
+                       train_q, qt->din, batch_idx, batch, qt->in_scale, bq.xb);
     ANN_LAUNCHED();
     TRY(tower_fwd(*qt, bq, batch, st));
     hipLaunchKernelGGL(gather_bf16_kernel, dim3(gridn((int64_t)n_hubs * ht->din)), dim3(256), 0, st,
-                       hub_in, ht->din, (const int32_t *)nullptr, n_hubs, bh.xb);
+                       hub_in, ht->din, (const int32_t *)nullptr, n_hubs, ht->in_scale, bh.xb);
     ANN_LAUNCHED();
     TRY(tower_fwd(*ht, bh, n_hubs, st));
     const int e = qt->dout;

@@ -80,7 +80,8 @@ def nearest_hub_entries(index: Index, hub_ids: torch.Tensor, queries: torch.Tens
 
 
 def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
-               kmeans_iters: int = 20, M: int = 8, ladder=(10, 16, 24, 32, 48, 64, 96, 128),
+               kmeans_iters: int = 20, M: int = 8,
+               ladder=(10, 16, 24, 32, 48, 64, 96, 128, 192, 256),
                hidden: int = 128, dout: int = 64, epochs: int = 20, batch: int = 1024,
                lr: float = 1e-3, tau: float = 0.07, s: int = 16, L_h: int = 32,
                theta: float = -math.inf, train: bool = True, log=print) -> Gate:
@@ -96,8 +97,11 @@ def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: i
     log("hubs: %d Lloyd steps, %.1fs" % (steps, info["hubs_s"]))
 
     t = time.time()
+    # inputs scaled by a power of two into [-1, 1] (exact in BF16)
+    scale = ann.input_scale(ann.ann_max_abs(base))
+    info["input_scale"] = scale
     feat, _ = ann.ann_hub_features(base, index.graph, index.medoid, hub_ids, assign, cen)
-    hub_in = ann.ann_hub_input(base, hub_ids, feat)
+    hub_in = ann.ann_hub_input(base, hub_ids, feat, vec_scale=scale)
     hub_vec = ann.ann_hub_input(base, hub_ids)
     torch.cuda.synchronize()
     info["features_s"] = time.time() - t
@@ -118,7 +122,7 @@ def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: i
 
     qp = synth.tower_init(w, [(hidden, d), (dout, hidden)])
     hp = synth.tower_init(w, [(hidden, d + 32), (dout, hidden)])
-    qt, ht = ann.Tower(*qp, device=dev), ann.Tower(*hp, device=dev)
+    qt, ht = ann.Tower(*qp, device=dev, in_scale=scale), ann.Tower(*hp, device=dev)
     t = time.time()
     nt = train_q.shape[0]
     step = 0

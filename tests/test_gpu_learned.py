@@ -53,21 +53,22 @@ def _rel(a, b):
     return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30)
 
 
-def test_train_step_gradients_match_oracle():
+@pytest.mark.parametrize("scale", [1.0, 0.0625])
+def test_train_step_gradients_match_oracle(scale):
     ix, km, hub_in, qp, hp = _setup()
     ann = _ann()
     tq = synth.train_queries(ix["w"], 512)
     r = np.random.default_rng(1)
     labels = r.integers(0, hub_in.shape[0], size=tq.shape[0]).astype(np.int32)
     idx = r.permutation(tq.shape[0])[:256].astype(np.int32)
-    say("case: train step gradients")
-    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    say("case: train step gradients, input scale %g" % scale)
+    qt, ht = ann.Tower(*qp, in_scale=scale), ann.Tower(*hp)
     loss, qe, he = ann.ann_train_step(qt, ht, _dev(tq), _dev(idx), _dev(labels), _dev(hub_in), 0.07,
                                       1e-3, 0, want_emb=True)
     torch.cuda.synchronize()
     ref_loss, gq, gh, eq, eh = T.train_step_grads(qp, hp, tq[idx].astype(np.float64),
                                                   hub_in.astype(np.float64), labels[idx], 0.07,
-                                                  bf16=True)
+                                                  bf16=True, q_scale=scale)
     assert abs(loss.item() - ref_loss) <= 1e-4 * abs(ref_loss)
     for got, ref in zip([t.cpu().numpy() for t in qt.g + ht.g], list(gq) + list(gh)):
         assert _rel(got, ref) <= 1e-3
