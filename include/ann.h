@@ -85,12 +85,25 @@ size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t p0, int32_
  * ann_autotune_search(); all fields are plain values. */
 typedef struct ann_search_plan {
     int32_t pool_cap;        /* largest beam width L the launch supports (<= 512) */
-    int32_t visited_log2;    /* LDS visited table = 2^visited_log2 id slots (8..14) */
+    int32_t visited_log2;    /* LDS visited filter = 2^visited_log2 slots (8..14) */
     int32_t group;           /* lanes that cooperate on one vector gather: 8 or 16 */
     int32_t waves_per_block; /* 1, 2 or 4 independent wavefronts per workgroup */
     int32_t blocks;          /* persistent grid size; 0 = as many as fit on the GPU */
     int32_t fp64;            /* 1 = FP64 distances (diagnostic mode), 0 = FP32 */
+    int32_t filter;          /* visited filter form, one of ANN_FILTER_* */
 } ann_search_plan;
+
+/* Visited filter forms (per wavefront, in LDS).  Every form answers "seen"
+ * only for ids it was given; the hash forms may forget an id, which costs a
+ * repeated distance computation but never changes the results.
+ *   AUTO   BITSET when n bits fit in the TAG16 table's bytes, else TAG16 when
+ *          its tags fit in 15 bits, else ID32
+ *   BITSET one bit per id (exact); needs ceil(n/32) <= 2^visited_log2 words
+ *   TAG16  4-way set-associative table of 16-bit tags, 2 bytes per slot; an
+ *          invertible hash makes (set, tag) name one id; needs
+ *          ceil(log2 n) - (visited_log2 - 2) <= 15
+ *   ID32   linear-probing table of 32-bit ids, 4 bytes per slot */
+enum { ANN_FILTER_AUTO = 0, ANN_FILTER_BITSET = 1, ANN_FILTER_TAG16 = 2, ANN_FILTER_ID32 = 3 };
 
 /* Fills *plan with the default plan for (n, dim, R, L_max).  host pointer. */
 ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_t L_max,
@@ -342,6 +355,97 @@ ann_status ann_make_labels(const float *base, int64_t n, int32_t dim, const int3
                            const int32_t *hub_ids, const int32_t *L_ladder, int32_t n_L,
                            int32_t *labels, int32_t *table, int32_t *flags, void *workspace,
                            size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batch driver: plan tuning, one-call query batches and HIP graphs.         */
+/* Thousands of queries with uneven k and L run in one persistent search     */
+/* launch; the plan (gather width, LDS filter size and form, waves per       */
+/* workgroup) is chosen by timing candidates on a sample batch.              */
+
+/* LDS bytes one wavefront of `plan` needs for n ids of dimension dim
+ * (host-only, no GPU work); 0 when the plan's filter form cannot hold n ids. */
+size_t ann_search_plan_lds(const ann_search_plan *plan, int64_t n, int32_t dim);
+
+/* Candidate plans for (n, dim, R, L_max): writes up to `cap` plans to the
+ * host array `plans` and returns how many there are (call with cap = 0 to
+ * count).  pool_cap is L_max rounded up to 16; the candidates vary the
+ * gather group, the filter size (visited_log2 10..13, form AUTO) and the
+ * waves per workgroup.  Host-only. */
+int32_t ann_autotune_candidates(int64_t n, int32_t dim, int32_t R, int32_t L_max,
+                                ann_search_plan *plans, int32_t cap);
+
+/* Times each of the n_cand plans (host array) on the given batch — one
+ * warm-up launch, then `reps` timed launches each, HIP events on `stream` —
+ * and writes the fastest to *best (host).  times_ms (host, n_cand floats or
+ * NULL) receives each plan's mean launch time.  Every candidate's ids and
+ * distances are compared with the first candidate's on the device; any
+ * difference returns ANN_EDEVICE (the plans must agree by construction).
+ * The outputs hold the last candidate's results.  Arguments as ann_search;
+ * workspace = ann_autotune_workspace_size(n, dim, nq, k_max) bytes.
+ * Synchronises `stream`. */
+size_t ann_autotune_workspace_size(int64_t n, int32_t dim, int32_t nq, int32_t k_max);
+
+ann_status ann_autotune_search(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                               int32_t R, const float *queries, int32_t nq,
+                               const int32_t *entry_ids, int32_t medoid, const int32_t *k,
+                               const int32_t *L, int32_t k_max, int32_t *out_ids,
+                               float *out_dist, int32_t *stats, const ann_search_plan *cands,
+                               int32_t n_cand, int32_t reps, ann_search_plan *best,
+                               float *times_ms, void *workspace, size_t ws_bytes,
+                               void *stream);
+
+/* One batch of the query path, described once: the index, the queries and
+ * their per-query k and L, the outputs, the plan and the workspaces.  All
+ * pointers are device pointers that must stay valid while the batch (or a
+ * graph made from it) is used.
+ *   entry_ids   nq int32: written by the entry stage, read by the search
+ *               stage; NULL (search stage only) = the medoid for every query
+ *   model       entry model (host struct, copied) or NULL when no entry stage
+ *   entry_ws    ann_entry_workspace_size(model, nq) bytes (entry stage)
+ *   search_ws   ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0) bytes */
+typedef struct ann_query_batch {
+    const float *base;
+    int64_t n;
+    int32_t dim;
+    const int32_t *graph;
+    int32_t R;
+    const float *queries;
+    int32_t nq;
+    int32_t *entry_ids;
+    int32_t medoid;
+    const int32_t *k;
+    const int32_t *L;
+    int32_t k_max;
+    int32_t *out_ids;
+    float *out_dist;
+    int32_t *stats;
+    ann_search_plan plan;
+    const ann_entry_model *model;
+    void *entry_ws;
+    size_t entry_ws_bytes;
+    void *search_ws;
+    size_t search_ws_bytes;
+} ann_query_batch;
+
+/* Stages of a batch. */
+enum { ANN_STAGE_ENTRY = 1, ANN_STAGE_SEARCH = 2, ANN_STAGE_ALL = 3 };
+
+/* Enqueues the chosen stages of the batch on `stream`: ENTRY =
+ * ann_entry_select(model, queries) -> entry_ids; SEARCH = ann_search from
+ * entry_ids (or the medoid). */
+ann_status ann_query_run(const ann_query_batch *batch, int32_t stages, void *stream);
+
+/* A HIP graph of the chosen stages of a batch (captured once on a private
+ * stream; the batch struct and model are copied, the buffers are not).  Each
+ * launch replays the same kernels on the buffers' current contents, so new
+ * queries written into the same buffers are served by the next launch.
+ * The graph holds no memset nodes. */
+typedef struct ann_query_graph ann_query_graph;
+
+ann_status ann_query_graph_create(const ann_query_batch *batch, int32_t stages,
+                                  ann_query_graph **out);
+ann_status ann_query_graph_launch(ann_query_graph *graph, void *stream);
+void ann_query_graph_destroy(ann_query_graph *graph);
 
 #ifdef __cplusplus
 }

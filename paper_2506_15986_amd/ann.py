@@ -21,6 +21,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 ANN_OK, ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE, ANN_ENOTSUP = 0, 1, 2, 3, 4
+ANN_FILTER_AUTO, ANN_FILTER_BITSET, ANN_FILTER_TAG16, ANN_FILTER_ID32 = 0, 1, 2, 3
 OP = dict(search=1, build_graph=2, gt_knn=3, select_hubs=4, entry_select=5, make_labels=6,
           hub_features=7, train_step=8)
 
@@ -34,7 +35,8 @@ class AnnError(RuntimeError):
 class ann_search_plan(ctypes.Structure):
     _fields_ = [("pool_cap", ctypes.c_int32), ("visited_log2", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("blocks", ctypes.c_int32), ("fp64", ctypes.c_int32)]
+                ("blocks", ctypes.c_int32), ("fp64", ctypes.c_int32),
+                ("filter", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -485,3 +487,159 @@ def input_scale(max_abs: float) -> float:
     if max_abs <= 0:
         return 1.0
     return 2.0 ** (-max(0, math.ceil(math.log2(max_abs))))
+
+
+# ------------------------------------------------------------------ batch driver
+
+class ann_query_batch(ctypes.Structure):
+    _fields_ = [("base", _P), ("n", _I64), ("dim", _I32), ("graph", _P), ("R", _I32),
+                ("queries", _P), ("nq", _I32), ("entry_ids", _P), ("medoid", _I32), ("k", _P),
+                ("L", _P), ("k_max", _I32), ("out_ids", _P), ("out_dist", _P), ("stats", _P),
+                ("plan", ann_search_plan), ("model", ctypes.POINTER(ann_entry_model)),
+                ("entry_ws", _P), ("entry_ws_bytes", _SZ), ("search_ws", _P),
+                ("search_ws_bytes", _SZ)]
+
+
+ANN_STAGE_ENTRY, ANN_STAGE_SEARCH, ANN_STAGE_ALL = 1, 2, 3
+
+_sig("ann_search_plan_lds", _SZ, ctypes.POINTER(ann_search_plan), _I64, _I32)
+_sig("ann_autotune_candidates", _I32, _I64, _I32, _I32, _I32, ctypes.POINTER(ann_search_plan),
+     _I32)
+_sig("ann_autotune_workspace_size", _SZ, _I64, _I32, _I32, _I32)
+_sig("ann_autotune_search", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _I32, _P, _P, _I32, _P,
+     _P, _P, ctypes.POINTER(ann_search_plan), _I32, _I32, ctypes.POINTER(ann_search_plan),
+     ctypes.POINTER(_F32), _P, _SZ, _P)
+_sig("ann_query_run", _I32, ctypes.POINTER(ann_query_batch), _I32, _P)
+_sig("ann_query_graph_create", _I32, ctypes.POINTER(ann_query_batch), _I32,
+     ctypes.POINTER(ctypes.c_void_p))
+_sig("ann_query_graph_launch", _I32, ctypes.c_void_p, _P)
+_lib.ann_query_graph_destroy.restype = None
+_lib.ann_query_graph_destroy.argtypes = [ctypes.c_void_p]
+
+
+def ann_search_plan_lds(plan: ann_search_plan, n: int, dim: int) -> int:
+    return int(_lib.ann_search_plan_lds(ctypes.byref(plan), n, dim))
+
+
+def ann_autotune_candidates(n: int, dim: int, R: int, L_max: int) -> list:
+    cnt = int(_lib.ann_autotune_candidates(n, dim, R, L_max, None, 0))
+    arr = (ann_search_plan * max(cnt, 1))()
+    _lib.ann_autotune_candidates(n, dim, R, L_max, arr, cnt)
+    return [arr[i] for i in range(cnt)]
+
+
+def ann_autotune_workspace_size(n: int, dim: int, nq: int, k_max: int) -> int:
+    return int(_lib.ann_autotune_workspace_size(n, dim, nq, k_max))
+
+
+def ann_autotune_search(base, graph, queries, entry_ids, medoid: int, k, L, k_max: int,
+                        L_max: int, cands=None, reps: int = 3, stream=None):
+    """Times the candidate plans on this batch; returns (best plan,
+    [(plan, mean ms per launch or -1 when the plan does not fit)])."""
+    n, dim = base.shape
+    nq, R = queries.shape[0], graph.shape[1]
+    dev = base.device
+    if not torch.is_tensor(k):
+        k = torch.full((nq,), int(k), dtype=torch.int32, device=dev)
+    if not torch.is_tensor(L):
+        L = torch.full((nq,), int(L), dtype=torch.int32, device=dev)
+    if cands is None:
+        cands = ann_autotune_candidates(n, dim, R, L_max)
+    arr = (ann_search_plan * len(cands))(*cands)
+    times = (_F32 * len(cands))()
+    best = ann_search_plan()
+    ids = torch.empty((nq, k_max), dtype=torch.int32, device=dev)
+    dist = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+    stats = torch.empty((nq, 4), dtype=torch.int32, device=dev)
+    ws = torch.empty(max(256, ann_autotune_workspace_size(n, dim, nq, k_max)), dtype=torch.uint8,
+                     device=dev)
+    _check(_lib.ann_autotune_search(_ptr(base), n, dim, _ptr(graph), R, _ptr(queries), nq,
+                                    _ptr(entry_ids), int(medoid), _ptr(k), _ptr(L), k_max,
+                                    _ptr(ids), _ptr(dist), _ptr(stats), arr, len(cands), reps,
+                                    ctypes.byref(best), times, _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return best, [(cands[i], float(times[i])) for i in range(len(cands))]
+
+
+class QueryBatch:
+    """Device buffers and the C description (ann_query_batch) of one batch of
+    the query path; the tensors are kept alive with it."""
+
+    def __init__(self, base, graph, medoid: int, queries, k, L, k_max: int, plan=None,
+                 model: EntryModel | None = None, entry_ids=None, want_stats: bool = True):
+        dev = base.device
+        n, dim = base.shape
+        nq, R = queries.shape[0], graph.shape[1]
+        if not torch.is_tensor(k):
+            k = torch.full((nq,), int(k), dtype=torch.int32, device=dev)
+        if not torch.is_tensor(L):
+            L = torch.full((nq,), int(L), dtype=torch.int32, device=dev)
+        if plan is None:
+            plan = default_plan(n, dim, R, int(L.max().item()) if nq else 1)
+        if entry_ids is None and model is not None:
+            entry_ids = torch.empty(nq, dtype=torch.int32, device=dev)
+        self.base, self.graph, self.queries, self.k, self.L = base, graph, queries, k, L
+        self.entry_ids, self.model, self.plan = entry_ids, model, plan
+        self.ids = torch.empty((nq, k_max), dtype=torch.int32, device=dev)
+        self.dist = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+        self.stats = torch.empty((nq, 4), dtype=torch.int32, device=dev) if want_stats else None
+        self.search_ws = workspace("search", n, dim, nq, device=dev)
+        self.entry_ws = None
+        self._model_c = None
+        if model is not None:
+            self._model_c = ann_entry_model.from_buffer_copy(model.c)
+            nb = max(256, int(_lib.ann_entry_workspace_size(ctypes.byref(self._model_c), nq)))
+            self.entry_ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.c = ann_query_batch(
+            _ptr(base), n, dim, _ptr(graph), R, _ptr(queries), nq, _ptr(entry_ids), int(medoid),
+            _ptr(k), _ptr(L), k_max, _ptr(self.ids), _ptr(self.dist), _ptr(self.stats), plan,
+            ctypes.pointer(self._model_c) if self._model_c is not None else None,
+            _ptr(self.entry_ws), self.entry_ws.numel() if self.entry_ws is not None else 0,
+            _ptr(self.search_ws), self.search_ws.numel())
+
+    def run(self, stages: int = ANN_STAGE_ALL, stream=None):
+        _check(_lib.ann_query_run(ctypes.byref(self.c), stages, _stream(stream)))
+        return self.ids, self.dist, self.stats
+
+    def graph_exec(self, stages: int = ANN_STAGE_ALL) -> "QueryGraph":
+        return QueryGraph(self, stages)
+
+
+class QueryGraph:
+    """A HIP graph of a QueryBatch's stages (ann_query_graph_*)."""
+
+    def __init__(self, batch: QueryBatch, stages: int = ANN_STAGE_ALL):
+        self.batch = batch
+        h = ctypes.c_void_p()
+        _check(_lib.ann_query_graph_create(ctypes.byref(batch.c), stages, ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(_lib.ann_query_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _lib.ann_query_graph_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ann_query_run(batch: QueryBatch, stages: int = ANN_STAGE_ALL, stream=None):
+    return batch.run(stages, stream)
+
+
+def ann_query_graph_create(batch: QueryBatch, stages: int = ANN_STAGE_ALL) -> QueryGraph:
+    return QueryGraph(batch, stages)
+
+
+def ann_query_graph_launch(graph: QueryGraph, stream=None):
+    graph.launch(stream)
+
+
+def ann_query_graph_destroy(graph: QueryGraph):
+    graph.close()

@@ -7,8 +7,8 @@
 //          sorted by (key, id); bit 31 of id marks "expanded"
 //   stage  64 entries for the candidates of the current hop
 //   vis    the visited filter: an exact bitset when the id range fits, else
-//          an open-addressing table of ids that may forget an id when a probe
-//          run is full but never reports an unseen id as seen
+//          a hash table (16-bit tags or 32-bit ids) that may forget an id but
+//          never reports an unseen id as seen
 // Keys are order-preserving integer images of the FP32 (or FP64) distance,
 // so comparisons are integer compares and ties fall to the smaller id.
 #pragma once
@@ -88,53 +88,91 @@ __device__ inline int lower_bound(const K *ak, const uint32_t *ai, int cnt, K k,
     return lo;
 }
 
-// ascending bitonic sort of one (key, id) per lane across the wavefront
-template <typename K>
-__device__ inline void wave_sort(K &k, uint32_t &id)
+// value of v in lane t (t uniform across the wavefront)
+__device__ inline uint32_t readlane(uint32_t v, int t)
 {
-    const int lane = lane_id();
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, t);
+}
+__device__ inline int readlane(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+__device__ inline uint64_t readlane(uint64_t v, int t)
+{
+    return ((uint64_t)readlane((uint32_t)(v >> 32), t) << 32) | readlane((uint32_t)v, t);
+}
+
+// Sum over aligned groups of G lanes (G = 8 or 16); every lane of a group
+// receives the group's sum.  FP32 uses DPP lane moves: swap neighbours, swap
+// pairs, then mirror within 8 lanes (and within 16 for G = 16); FP64 uses
+// xor shuffles.
+template <int CTRL>
+__device__ inline float dpp_move(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+template <int G>
+__device__ inline float group_sum(float v)
+{
+    static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+    v += dpp_move<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);    // row_half_mirror
+    if (G == 16) v += dpp_move<0x140>(v);   // row_mirror
+    return v;
+}
+
+template <int G>
+__device__ inline double group_sum(double v)
+{
 #pragma unroll
-    for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            K ok = __shfl_xor(k, stride);
-            uint32_t oi = __shfl_xor(id, stride);
-            bool up = (lane & size) == 0;
-            bool lower = (lane & stride) == 0;
-            bool mine_less = key_less(k, id, ok, oi);
-            bool keep = (lower == up) ? mine_less : !mine_less;
-            if (!keep) {
-                k = ok;
-                id = oi;
-            }
-        }
-    }
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
 // ---------------------------------------------------------------- visited
+//
+// Three forms, chosen per launch:
+//   kBitset  one bit per id in [0, n): exact.
+//   kTag16   4-way set-associative table of 16-bit tags.  An odd-constant
+//            multiply modulo 2^b (b = bits of n) is a bijection on [0, 2^b);
+//            its top bits pick the set and the rest is the tag, so (set, tag)
+//            names exactly one id and a tag match is never a false "seen".
+//            A full set evicts one way (the evicted id is forgotten).
+//   kId32    open-addressing table of 32-bit ids with bounded linear probing;
+//            an id that finds no free slot in the probe run is not recorded.
+// Forgetting is safe for the results (see the search kernel's header) and is
+// reported through `lost`.
+enum FilterKind { kBitset = 1, kTag16 = 2, kId32 = 3 };
+
+constexpr uint32_t kHashMul = 0x9E3779B1u;
+constexpr uint32_t kTagEmpty = 0xFFFFu;
+
 struct Visited {
     uint32_t *t;
-    int log2cap;
-    bool bitset;   // exact bitset over [0, n)
-    int words;     // slots to clear
+    int kind;
+    int words;          // 32-bit words to clear
+    int log2cap;        // kId32: slots; kTag16: slots (4 per set)
+    int tag_bits;       // kTag16: b - log2(sets), <= 15
+    uint32_t hmask;     // kTag16: 2^b - 1
 
     __device__ inline void clear() const
     {
-        for (int i = lane_id(); i < words; i += 64) t[i] = bitset ? 0u : kEmpty;
+        const uint32_t v = kind == kBitset ? 0u : kEmpty;
+        for (int i = lane_id(); i < words; i += 64) t[i] = v;
         wave_sync();
     }
 
-    // true if id was not seen before (and records it when there is room);
-    // `lost` is set when the id could not be recorded.
+    // true if id was not seen before (and records it when it can); `lost` is
+    // set when an id could not be recorded or another was evicted.
     __device__ inline bool insert(uint32_t id, bool &lost) const
     {
-        if (bitset) {
+        if (kind == kBitset) {
             uint32_t bit = 1u << (id & 31u);
             uint32_t old = atomicOr(&t[id >> 5], bit);
             return (old & bit) == 0;
         }
+        if (kind == kTag16) return insert_tag(id, lost);
         const uint32_t mask = (1u << log2cap) - 1u;
-        uint32_t h = (id * 2654435761u) >> (32 - log2cap);
+        uint32_t h = (id * kHashMul) >> (32 - log2cap);
         for (int p = 0; p < kMaxProbe; ++p) {
             uint32_t slot = (h + (uint32_t)p) & mask;
             uint32_t old = atomicCAS(&t[slot], kEmpty, id);
@@ -143,7 +181,91 @@ struct Visited {
         lost = true;
         return true;
     }
+
+    __device__ inline bool insert_tag(uint32_t id, bool &lost) const
+    {
+        const uint32_t h = (id * kHashMul) & hmask;
+        const uint32_t set = h >> tag_bits;
+        const uint32_t tag = h & ((1u << tag_bits) - 1u);
+        uint32_t *w = t + 2 * set;
+        for (int it = 0; it < 8; ++it) {
+            const uint32_t w0 = __atomic_load_n(&w[0], __ATOMIC_RELAXED);
+            const uint32_t w1 = __atomic_load_n(&w[1], __ATOMIC_RELAXED);
+            if ((w0 & 0xFFFFu) == tag || (w0 >> 16) == tag || (w1 & 0xFFFFu) == tag ||
+                (w1 >> 16) == tag)
+                return false;
+            // first free way, else evict the way picked by the tag's low bits
+            uint32_t *a;
+            uint32_t old, nw;
+            if ((w0 & 0xFFFFu) == kTagEmpty) {
+                a = &w[0]; old = w0; nw = (w0 & 0xFFFF0000u) | tag;
+            } else if ((w0 >> 16) == kTagEmpty) {
+                a = &w[0]; old = w0; nw = (w0 & 0xFFFFu) | (tag << 16);
+            } else if ((w1 & 0xFFFFu) == kTagEmpty) {
+                a = &w[1]; old = w1; nw = (w1 & 0xFFFF0000u) | tag;
+            } else if ((w1 >> 16) == kTagEmpty) {
+                a = &w[1]; old = w1; nw = (w1 & 0xFFFFu) | (tag << 16);
+            } else {
+                const uint32_t way = tag & 3u;
+                a = &w[way >> 1];
+                old = (way >> 1) ? w1 : w0;
+                nw = (way & 1u) ? ((old & 0xFFFFu) | (tag << 16)) : ((old & 0xFFFF0000u) | tag);
+                if (atomicCAS(a, old, nw) == old) {
+                    lost = true;
+                    return true;
+                }
+                continue;
+            }
+            if (atomicCAS(a, old, nw) == old) return true;
+        }
+        lost = true;
+        return true;
+    }
 };
+
+// Filter layout for a launch: kind, table words and tag width.  kind_req 0
+// picks the bitset when it is no larger than the table, else kTag16 when the
+// tag fits in 15 bits, else kId32.  Returns false for a form that cannot hold
+// n (a bitset larger than the table, or tags wider than 15 bits).
+struct FilterShape {
+    int kind, words, tag_bits;
+    uint32_t hmask;
+};
+
+__host__ __device__ inline int bits_for(int64_t n)
+{
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+__host__ __device__ inline bool filter_shape(int kind_req, int log2cap, int64_t n, FilterShape &f)
+{
+    const int64_t bitset_words = (n + 31) / 32;
+    const int sets_log2 = log2cap - 2;
+    int b = bits_for(n);
+    if (b < sets_log2) b = sets_log2;
+    const int tbits = b - sets_log2;
+    int kind = kind_req;
+    if (kind == 0)
+        kind = bitset_words <= ((int64_t)1 << log2cap) / 2 ? kBitset : (tbits <= 15 ? kTag16 : kId32);
+    f.kind = kind;
+    f.tag_bits = tbits;
+    f.hmask = b >= 32 ? 0xFFFFFFFFu : (uint32_t)(((uint64_t)1 << b) - 1u);
+    if (kind == kBitset) {
+        f.words = (int)bitset_words;
+        return bitset_words <= ((int64_t)1 << log2cap);
+    }
+    if (kind == kTag16) {
+        f.words = 1 << (log2cap - 1);
+        return tbits <= 15;
+    }
+    if (kind == kId32) {
+        f.words = 1 << log2cap;
+        return true;
+    }
+    return false;
+}
 
 }  // namespace beam
 }  // namespace ann

@@ -19,6 +19,7 @@ ann_status reset_work_counter(uint32_t *c, hipStream_t st);
 
 // Number of compute units of the current device (cached per device).
 int device_cus();
+int device_lds_bytes();   // LDS bytes one workgroup may allocate
 
 // True when p is aligned to `a` bytes.
 inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }

@@ -43,6 +43,22 @@ ann_status fail(ann_status s, const char *fmt, ...)
     return s;
 }
 
+int device_lds_bytes()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    if (cache[dev] == 0) {
+        int b = 0;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess ||
+            b <= 0)
+            b = 65536;
+        cache[dev] = b;
+    }
+    return cache[dev];
+}
+
 int device_cus()
 {
     static int cache[64] = {0};

@@ -397,7 +397,7 @@ ann_status run_argmin_scan(const float *base, int64_t n, int dim, const int32_t 
 size_t scan_temp_bytes(int64_t n)
 {
     size_t tmp = 0;
-    hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (int64_t *)nullptr, (int64_t *)nullptr,
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (int64_t *)nullptr, (int64_t *)nullptr,
                                      (int)(n + 1));
     return tmp;
 }

@@ -29,6 +29,16 @@ ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_
                          int32_t *out_ids, float *out_dist, int32_t *stats, int32_t *trace,
                          int32_t trace_cap, const ann_search_plan &p, uint32_t *counter,
                          hipStream_t st);
+ann_status validate_plan(const ann_search_plan &p);
+size_t search_wave_lds(const ann_search_plan &p, int64_t n, int dim);
+// host-side checks of ann_search's arguments; resolves a NULL plan to the
+// default one in `p`.  Enqueues nothing.
+ann_status search_check(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                        int32_t R, const float *queries, int32_t nq, const int32_t *entry_ids,
+                        int32_t medoid, const int32_t *k, const int32_t *L, int32_t k_max,
+                        int32_t *out_ids, float *out_dist, int32_t *trace, int32_t trace_cap,
+                        const ann_search_plan *plan, void *workspace, size_t ws_bytes,
+                        ann_search_plan &p);
 ann_status tower_forward_run(const ann_tower &w, const float *x, const int32_t *idx, int rows,
                              float *out, void *ws, hipStream_t st);
 

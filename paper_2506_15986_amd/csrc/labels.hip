@@ -148,9 +148,13 @@ extern "C" ann_status ann_make_labels(const float *base, int64_t n, int32_t dim,
             hipLaunchKernelGGL(gather_entries_kernel, dim3(nb), dim3(256), 0, st, cand_hubs, M, m,
                                hub_ids, nq, ent, kk, LL, kt, Lv);
             ANN_LAUNCHED();
+            // costs are distance counts, so the filter must not forget ids:
+            // 32-bit ids in 2^13 slots (load <= 0.4 up to L = 512)
             ann_search_plan p{};
             ann_status s = ann_default_plan(n, dim, R, Lv, &p);
             if (s != ANN_OK) return s;
+            p.filter = ANN_FILTER_ID32;
+            p.visited_log2 = 13;
             s = search_launch(base, n, dim, graph, R, queries, nq, ent, 0, kk, LL, kt, ids, dist,
                               stats, nullptr, 0, p, counter, st);
             if (s != ANN_OK) return s;

@@ -31,10 +31,10 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     using S = Searcher<G, CPL, F64, L2>;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     S s;
-    s.setup(smem + (size_t)wave * a.wave_lds, a.pool_cap, a.visited_log2, a.n, a.base,
+    s.setup(smem + (size_t)wave * a.wave_lds, a.pool_cap, a.visited_log2, a.filter, a.n, a.base,
             a.dim, a.graph, a.R);
     for (;;) {
         int qi = 0;
@@ -136,12 +136,24 @@ ann_status validate_plan(const ann_search_plan &p)
                 "plan.waves_per_block must be 1, 2 or 4");
     ANN_REQUIRE(p.blocks >= 0, "plan.blocks must be >= 0");
     ANN_REQUIRE(p.fp64 == 0 || p.fp64 == 1, "plan.fp64 must be 0 or 1");
+    ANN_REQUIRE(p.filter >= ANN_FILTER_AUTO && p.filter <= ANN_FILTER_ID32,
+                "plan.filter must be one of ANN_FILTER_*");
     return ANN_OK;
 }
 
-size_t search_wave_lds(const ann_search_plan &p, int64_t n)
+ann_status search_filter(const ann_search_plan &p, int64_t n, FilterShape &f)
 {
-    return wave_lds_bytes(p.pool_cap, p.visited_log2, n, p.fp64 != 0);
+    if (!filter_shape(p.filter, p.visited_log2, n, f))
+        return fail(ANN_ENOTSUP, "plan.filter %d cannot hold %lld ids with visited_log2 %d",
+                    p.filter, (long long)n, p.visited_log2);
+    return ANN_OK;
+}
+
+size_t search_wave_lds(const ann_search_plan &p, int64_t n, int dim)
+{
+    FilterShape f{};
+    if (!filter_shape(p.filter, p.visited_log2, n, f)) return 0;
+    return wave_lds_bytes(p.pool_cap, f, p.fp64 != 0, dim);
 }
 
 ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_t *graph,
@@ -172,7 +184,11 @@ ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_
     a.pool_cap = p.pool_cap;
     a.visited_log2 = p.visited_log2;
     a.counter = counter;
-    a.wave_lds = search_wave_lds(p, n);
+    {
+        ann_status fs = search_filter(p, n, a.filter);
+        if (fs != ANN_OK) return fs;
+    }
+    a.wave_lds = wave_lds_bytes(p.pool_cap, a.filter, p.fp64 != 0, dim);
     if (p.fp64) return dispatch<true>(a, p.group, p.blocks, p.waves_per_block, st);
     return dispatch<false>(a, p.group, p.blocks, p.waves_per_block, st);
 }
@@ -188,8 +204,9 @@ extern "C" ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_
     ANN_REQUIRE(n >= 1 && dim >= 1 && R >= 1 && L_max >= 1, "n, dim, R, L_max must be >= 1");
     ANN_SUPPORTED(L_max <= 512, "L_max %d exceeds 512", L_max);
     ann_search_plan p{};
-    p.pool_cap = L_max <= 64 ? 64 : (L_max <= 128 ? 128 : (L_max <= 256 ? 256 : 512));
+    p.pool_cap = (L_max + 15) / 16 * 16;
     p.visited_log2 = 12;
+    p.filter = ANN_FILTER_AUTO;
     p.group = dim <= 128 ? 8 : 16;
     p.waves_per_block = 1;
     p.blocks = 0;
@@ -199,13 +216,14 @@ extern "C" ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_
     return ANN_OK;
 }
 
-extern "C" ann_status ann_search(const float *base, int64_t n, int32_t dim, const int32_t *graph,
-                                 int32_t R, const float *queries, int32_t nq,
-                                 const int32_t *entry_ids, int32_t medoid, const int32_t *k,
-                                 const int32_t *L, int32_t k_max, int32_t *out_ids,
-                                 float *out_dist, int32_t *stats, int32_t *trace,
-                                 int32_t trace_cap, const ann_search_plan *plan, void *workspace,
-                                 size_t ws_bytes, void *stream)
+namespace ann {
+
+ann_status search_check(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                        int32_t R, const float *queries, int32_t nq, const int32_t *entry_ids,
+                        int32_t medoid, const int32_t *k, const int32_t *L, int32_t k_max,
+                        int32_t *out_ids, float *out_dist, int32_t *trace, int32_t trace_cap,
+                        const ann_search_plan *plan, void *workspace, size_t ws_bytes,
+                        ann_search_plan &p)
 {
     ANN_REQUIRE(base && graph && workspace, "a required pointer is NULL");
     ANN_REQUIRE(nq == 0 || (queries && k && L && out_ids && out_dist),
@@ -224,7 +242,6 @@ extern "C" ann_status ann_search(const float *base, int64_t n, int32_t dim, cons
     ANN_REQUIRE(trace == nullptr || trace_cap >= 1, "trace_cap must be >= 1 with a trace buffer");
     ANN_REQUIRE(ws_bytes >= ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0),
                 "workspace too small");
-    ann_search_plan p{};
     if (plan) {
         p = *plan;
     } else {
@@ -232,6 +249,37 @@ extern "C" ann_status ann_search(const float *base, int64_t n, int32_t dim, cons
         if (s != ANN_OK) return s;
     }
     ann_status s = validate_plan(p);
+    if (s != ANN_OK) return s;
+    FilterShape f{};
+    s = search_filter(p, n, f);
+    if (s != ANN_OK) return s;
+    const size_t lds = (size_t)p.waves_per_block * wave_lds_bytes(p.pool_cap, f, p.fp64 != 0, dim);
+    ANN_SUPPORTED(lds <= (size_t)device_lds_bytes(),
+                  "search plan needs %zu B of LDS per workgroup (the CU has %d)", lds,
+                  device_lds_bytes());
+    return ANN_OK;
+}
+
+}  // namespace ann
+
+extern "C" size_t ann_search_plan_lds(const ann_search_plan *plan, int64_t n, int32_t dim)
+{
+    if (!plan || validate_plan(*plan) != ANN_OK || n < 1 || dim < 1) return 0;
+    return search_wave_lds(*plan, n, dim);
+}
+
+extern "C" ann_status ann_search(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                                 int32_t R, const float *queries, int32_t nq,
+                                 const int32_t *entry_ids, int32_t medoid, const int32_t *k,
+                                 const int32_t *L, int32_t k_max, int32_t *out_ids,
+                                 float *out_dist, int32_t *stats, int32_t *trace,
+                                 int32_t trace_cap, const ann_search_plan *plan, void *workspace,
+                                 size_t ws_bytes, void *stream)
+{
+    ann_search_plan p{};
+    ann_status s = search_check(base, n, dim, graph, R, queries, nq, entry_ids, medoid, k, L,
+                                k_max, out_ids, out_dist, trace, trace_cap, plan, workspace,
+                                ws_bytes, p);
     if (s != ANN_OK) return s;
     if (nq == 0) return ANN_OK;
     return search_launch(base, n, dim, graph, R, queries, nq, entry_ids, medoid, k, L, k_max,

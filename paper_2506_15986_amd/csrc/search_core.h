@@ -26,6 +26,7 @@ struct SearchArgs {
     int trace_cap;
     int pool_cap;
     int visited_log2;
+    beam::FilterShape filter;
     uint32_t *counter;
     size_t wave_lds;
 };
@@ -37,14 +38,13 @@ struct SearchResult {
     bool lost;
 };
 
-// LDS bytes one wavefront needs.
-inline size_t wave_lds_bytes(int pool_cap, int visited_log2, int64_t n, bool f64)
+// LDS bytes one wavefront needs: the query vector, two pool buffers of
+// (key, id), the staging row of 64 (key, id) and the visited filter's words.
+inline size_t wave_lds_bytes(int pool_cap, const beam::FilterShape &f, bool f64, int dim)
 {
     size_t ks = f64 ? 8 : 4;
-    size_t words = (size_t)1 << visited_log2;
-    size_t bitset_words = (size_t)((n + 31) / 32);
-    if (bitset_words <= words) words = bitset_words;
-    size_t b = 2 * (size_t)pool_cap * ks + 64 * ks + 2 * (size_t)pool_cap * 4 + 64 * 4 + 64 + words * 4;
+    size_t b = ((size_t)dim * 4 + 15) / 16 * 16 + 2 * (size_t)pool_cap * ks + 64 * ks +
+               2 * (size_t)pool_cap * 4 + 64 * 4 + 64 + (size_t)f.words * 4;
     return (b + 15) / 16 * 16;
 }
 
@@ -54,7 +54,7 @@ struct Searcher {
     using K = typename KT::K;
     using D = typename KT::D;
     static constexpr int VPB = 64 / G;
-    static constexpr int U0 = 32 / VPB;
+    static constexpr int U0 = 16 / VPB;
     static constexpr int U1 = 16 / CPL;
     static constexpr int U = (U0 < U1 ? U0 : U1) < 1 ? 1 : (U0 < U1 ? U0 : U1);
 
@@ -69,15 +69,17 @@ struct Searcher {
     int chunks;
     const int32_t *graph;
     int R;
-    float4 q[CPL];
+    float4 *ql;   // the query vector, in LDS
     int cur;
     int cnt;
 
-    __device__ void setup(unsigned char *lds, int pcap, int vlog2, int64_t n_, const float *base,
-                          int dim, const int32_t *graph_, int R_)
+    __device__ void setup(unsigned char *lds, int pcap, int vlog2, const beam::FilterShape &fs,
+                          int64_t n_, const float *base, int dim, const int32_t *graph_, int R_)
     {
         const size_t ks = sizeof(K);
         unsigned char *p = lds;
+        ql = reinterpret_cast<float4 *>(p);
+        p += ((size_t)dim * 4 + 15) / 16 * 16;
         pk0 = reinterpret_cast<K *>(p);
         p += pcap * ks;
         pk1 = reinterpret_cast<K *>(p);
@@ -91,12 +93,12 @@ struct Searcher {
         si = reinterpret_cast<uint32_t *>(p);
         p += 64 * 4;
         p += 64;
-        size_t words = (size_t)1 << vlog2;
-        size_t bw = (size_t)((n_ + 31) / 32);
         vis.t = reinterpret_cast<uint32_t *>(p);
+        vis.kind = fs.kind;
+        vis.words = fs.words;
         vis.log2cap = vlog2;
-        vis.bitset = bw <= words;
-        vis.words = (int)(vis.bitset ? bw : words);
+        vis.tag_bits = fs.tag_bits;
+        vis.hmask = fs.hmask;
         pool_cap = pcap;
         n = n_;
         base4 = reinterpret_cast<const float4 *>(base);
@@ -107,13 +109,9 @@ struct Searcher {
 
     __device__ void load_query(const float *qp)
     {
-        const int gl = beam::lane_id() % G;
         const float4 *q4 = reinterpret_cast<const float4 *>(qp);
-#pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-            int ch = gl + G * t;
-            q[t] = ch < chunks ? q4[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+        for (int ch = beam::lane_id(); ch < chunks; ch += 64) ql[ch] = q4[ch];
+        beam::wave_sync();
     }
 
     __device__ inline K *keys(int c) const { return c ? pk1 : pk0; }
@@ -152,9 +150,11 @@ struct Searcher {
             for (int u = 0; u < U; ++u) {
                 D acc = 0;
 #pragma unroll
-                for (int t = 0; t < CPL; ++t) acc += partial(xv[u][t], q[t]);
-#pragma unroll
-                for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+                for (int t = 0; t < CPL; ++t) {
+                    const int ch = gl + G * t;
+                    if (ch < chunks) acc += partial(xv[u][t], ql[ch]);
+                }
+                acc = beam::group_sum<G>(acc);
                 int c = b0 + u * VPB + gi;
                 if (gl == 0 && c < m) sk[c] = KT::of(METRIC == beam::L2 ? acc : -acc);
             }
@@ -162,8 +162,29 @@ struct Searcher {
         beam::wave_sync();
     }
 
+    // first pool position at or after `from` whose entry is not expanded, or -1
+    __device__ int next_unexpanded(int from) const
+    {
+        const int lane = beam::lane_id();
+        const uint32_t *ai = ids(cur);
+        for (int b = from; b < cnt; b += 64) {
+            const int j = b + lane;
+            const bool un = j < cnt && !(ai[j] & beam::kExpanded);
+            const uint64_t bal = __ballot(un);
+            if (bal) return b + __ffsll((unsigned long long)bal) - 1;
+        }
+        return -1;
+    }
+
     // Runs one query from `entry` with beam width Lq.  trace (nullable)
     // receives the expanded ids.
+    //
+    // Latency hiding: the node expanded after p is either the old pool's next
+    // unexpanded entry or, when one beats it, the best new neighbour of p.
+    // The first one's adjacency row is loaded while p's neighbours are
+    // gathered; if a new neighbour wins, its row is loaded before the merge.
+    // A prefetched row is used only when its id is the node actually
+    // expanded, so the expansion order does not depend on the prediction.
     __device__ SearchResult run(uint32_t entry, int Lq, int32_t *trace, int trace_cap)
     {
         const int lane = beam::lane_id();
@@ -185,30 +206,35 @@ struct Searcher {
         r.ndc_exec = 1;
         beam::wave_sync();
         int cursor = 0;
+        uint32_t pf_id = beam::kEmpty;
+        int pf_nb = -1;
         for (;;) {
-            // best unexpanded pool entry at or after the cursor
-            int ppos = -1;
-            for (int b = cursor; b < cnt; b += 64) {
-                int j = b + lane;
-                bool un = j < cnt && !(ids(cur)[j] & beam::kExpanded);
-                uint64_t bal = __ballot(un);
-                if (bal) {
-                    ppos = b + __ffsll((unsigned long long)bal) - 1;
-                    break;
-                }
-            }
+            const int ppos = next_unexpanded(cursor);
             if (ppos < 0) break;
             cursor = ppos;
             const uint32_t p = ids(cur)[ppos] & beam::kIdMask;
+            int nb = -1;
+            if (p == pf_id)
+                nb = pf_nb;
+            else if (lane < R)
+                nb = graph[(size_t)p * R + lane];
+            const int npos = next_unexpanded(ppos + 1);
+            K nkey = KT::kMax;
+            uint32_t nid = beam::kEmpty;
+            pf_id = beam::kEmpty;
+            if (npos >= 0) {
+                nkey = keys(cur)[npos];
+                nid = ids(cur)[npos] & beam::kIdMask;
+                pf_id = nid;
+                pf_nb = lane < R ? graph[(size_t)nid * R + lane] : -1;
+            }
             beam::wave_sync();
             if (lane == 0) {
                 ids(cur)[ppos] = p | beam::kExpanded;
                 if (trace && r.hops < trace_cap) trace[r.hops] = (int32_t)p;
             }
             r.hops++;
-            // adjacency row, visited filter, compaction in slot order
-            int nb = -1;
-            if (lane < R) nb = graph[(size_t)p * R + lane];
+            // visited filter, compaction in slot order
             bool fresh = false;
             if (nb >= 0 && (int64_t)nb < n) fresh = vis.insert((uint32_t)nb, lost);
             uint64_t fb = __ballot(fresh);
@@ -218,7 +244,11 @@ struct Searcher {
             if (m == 0) continue;
             distances(m);
             r.ndc_exec += m;
-            // ---- merge the new keys into the pool
+            // ---- merge the new keys into the pool.  A new key's place is its
+            // insertion point in the old pool plus its rank among the new keys;
+            // an old entry moves down by the number of new keys inserted at or
+            // before it.  Both counts come from a scalar loop over the new keys
+            // (readlane), so no sort of the staging row is needed.
             K *ak = keys(cur);
             uint32_t *ai = ids(cur);
             K kk = KT::kMax;
@@ -229,47 +259,50 @@ struct Searcher {
                 ii = si[lane];
             }
             if (valid && cnt == Lq && !beam::key_less(kk, ii, ak[cnt - 1], ai[cnt - 1])) valid = false;
+            int pos = 0;
             bool dup = false;
             if (valid) {
-                int pos = beam::lower_bound(ak, ai, cnt, kk, ii);
+                pos = beam::lower_bound(ak, ai, cnt, kk, ii);
                 if (pos < cnt && ak[pos] == kk && (ai[pos] & beam::kIdMask) == ii) dup = true;
             }
             valid = valid && !dup;
             r.dups += __popcll(__ballot(dup));
-            const int mv = __popcll(__ballot(valid));
+            const uint64_t vmask = __ballot(valid);
+            const int mv = __popcll(vmask);
             if (mv == 0) continue;
-            if (!valid) {
-                kk = KT::kMax;
-                ii = beam::kEmpty;
+            int rank = 0;
+            for (uint64_t mm = vmask; mm; mm &= mm - 1) {
+                const int t = __ffsll((unsigned long long)mm) - 1;
+                if (beam::key_less(beam::readlane(kk, t), beam::readlane(ii, t), kk, ii)) ++rank;
             }
-            beam::wave_sort(kk, ii);
-            beam::wave_sync();
-            sk[lane] = kk;
-            si[lane] = ii;
-            beam::wave_sync();
+            // the smallest new key: expanded next if it beats the old pool's
+            // next unexpanded entry
+            const int l0 = __ffsll((unsigned long long)__ballot(valid && rank == 0)) - 1;
+            const K k0 = beam::readlane(kk, l0);
+            const uint32_t i0 = beam::readlane(ii, l0);
+            const int f0 = beam::readlane(pos, l0);
+            if (beam::key_less(k0, i0, nkey, nid)) {
+                pf_id = i0;
+                pf_nb = lane < R ? graph[(size_t)i0 * R + lane] : -1;
+            }
             K *bk = keys(cur ^ 1);
             uint32_t *bi = ids(cur ^ 1);
-            int f0 = 0x7fffffff;
-            if (lane < mv) {
-                int f = lane + beam::lower_bound(ak, ai, cnt, kk, ii);
-                if (f < Lq) {
-                    bk[f] = kk;
-                    bi[f] = ii;
-                }
-                f0 = f;
+            if (valid && pos + rank < Lq) {
+                bk[pos + rank] = kk;
+                bi[pos + rank] = ii;
             }
             for (int j = lane; j < cnt; j += 64) {
-                K kj = ak[j];
-                uint32_t ij = ai[j];
-                int f = j + beam::lower_bound(sk, si, mv, kj, ij);
+                int f = j;
+                for (uint64_t mm = vmask; mm; mm &= mm - 1)
+                    if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= j) ++f;
                 if (f < Lq) {
-                    bk[f] = kj;
-                    bi[f] = ij;
+                    bk[f] = ak[j];
+                    bi[f] = ai[j];
                 }
             }
-            f0 = __shfl(f0, 0);
-            int oc = cnt;
-            if (cursor < cnt) oc = cursor + beam::lower_bound(sk, si, mv, ak[cursor], ai[cursor]);
+            int oc = cursor;
+            for (uint64_t mm = vmask; mm; mm &= mm - 1)
+                if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= cursor) ++oc;
             cursor = f0 < oc ? f0 : oc;
             cnt = (cnt + mv < Lq) ? cnt + mv : Lq;
             cur ^= 1;

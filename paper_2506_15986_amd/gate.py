@@ -153,3 +153,46 @@ def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: i
     info["train_top1"] = float((bh == labels[: sample.shape[0]]).float().mean().item())
     log("entry model: train top-1 agreement with labels %.3f" % info["train_top1"])
     return Gate(qt, ht, hub_ids, hub_in, hemb, hg, hub_entry, model, info)
+
+
+def save_state(path: str, index: Index, gate: Gate | None, extra: dict) -> None:
+    """Writes the built index and entry model (arrays as .npy, scalars as
+    JSON) so that a later process can serve without rebuilding."""
+    import json
+    import os
+    os.makedirs(path, exist_ok=True)
+    np.save(os.path.join(path, "graph.npy"), index.graph.cpu().numpy())
+    meta = dict(extra, medoid=int(index.medoid), bridges=list(index.bridges), R=int(index.R),
+                build_s=float(index.build_s), gate=gate is not None)
+    if gate is not None:
+        qt = gate.qtower
+        for name, t in (("qW1", qt.W1), ("qb1", qt.b1), ("qW2", qt.W2), ("qb2", qt.b2),
+                        ("hub_ids", gate.hub_ids), ("hub_emb", gate.hub_emb),
+                        ("hub_graph", gate.hub_graph)):
+            np.save(os.path.join(path, name + ".npy"), t.cpu().numpy())
+        meta.update(in_scale=qt.in_scale, hub_entry=int(gate.hub_entry),
+                    L_h=int(gate.model.c.L_h), theta=float(gate.model.c.theta), info=gate.info)
+    with open(os.path.join(path, "meta.json"), "w") as f:
+        json.dump(meta, f)
+
+
+def load_state(path: str, base: torch.Tensor):
+    """Inverse of save_state: returns (index, gate or None, meta)."""
+    import json
+    import os
+    dev = base.device
+    with open(os.path.join(path, "meta.json")) as f:
+        meta = json.load(f)
+    ld = lambda name: torch.from_numpy(np.load(os.path.join(path, name + ".npy"))).to(dev)
+    index = Index(base, ld("graph").contiguous(), int(meta["medoid"]), tuple(meta["bridges"]),
+                  int(meta["R"]), float(meta["build_s"]))
+    gate = None
+    if meta["gate"]:
+        qt = ann.Tower(ld("qW1"), ld("qb1"), ld("qW2"), ld("qb2"), device=dev,
+                       in_scale=float(meta["in_scale"]))
+        hub_ids, hemb, hg = ld("hub_ids"), ld("hub_emb"), ld("hub_graph")
+        model = ann.EntryModel(qt, hemb, hg, hub_ids, int(meta["hub_entry"]), index.medoid,
+                               L_h=int(meta["L_h"]), theta=float(meta["theta"]))
+        gate = Gate(qt, None, hub_ids, None, hemb, hg, int(meta["hub_entry"]), model,
+                    dict(meta.get("info", {})))
+    return index, gate, meta

@@ -78,9 +78,10 @@ def test_search_rejects_bad_arguments_before_any_device_work(lib):
 def test_default_plan_and_workspace():
     from paper_2506_15986_amd import ann
     p = ann.default_plan(1_000_000, 128, 32, 200)
-    assert p.pool_cap == 256 and p.group == 8 and p.fp64 == 0
+    assert p.pool_cap == 208 and p.group == 8 and p.fp64 == 0 and p.filter == ann.ANN_FILTER_AUTO
     p = ann.default_plan(1_000_000, 960, 64, 400)
-    assert p.pool_cap == 512 and p.group == 16
+    assert p.pool_cap == 400 and p.group == 16
+    assert ann.default_plan(10, 32, 16, 1).pool_cap == 16
     with pytest.raises(ann.AnnError):
         ann.default_plan(10, 32, 16, 600)
     assert ann.workspace_size("search", 1000, 32, 10) >= 4
@@ -99,3 +100,65 @@ def test_kernel_names_unique_across_translation_units():
             assert name not in seen, "kernel %s defined in %s and %s" % (name, seen[name], f)
             seen[name] = f
     assert len(seen) > 20
+
+
+def _lds(pool_cap, filter_words, fp64=False, dim=128):
+    ks = 8 if fp64 else 4
+    b = (dim * 4 + 15) // 16 * 16 + 2 * pool_cap * ks + 64 * ks + 2 * pool_cap * 4 + 64 * 4 + 64 + \
+        filter_words * 4
+    return (b + 15) // 16 * 16
+
+
+def test_plan_lds_and_filter_forms():
+    from paper_2506_15986_amd import ann
+    P = lambda **kw: ann.make_plan(**dict(dict(pool_cap=64, visited_log2=12, group=8,
+                                               waves_per_block=1, blocks=0, fp64=0,
+                                               filter=ann.ANN_FILTER_AUTO), **kw))
+    lds = lambda p, n: ann.ann_search_plan_lds(p, n, 128)
+    # 10k ids: 313 bitset words fit in the 2048-word tag table -> bitset
+    assert lds(P(), 10_000) == _lds(64, 313)
+    # 1M ids: 31,250 bitset words do not -> 16-bit tags, 2 bytes per slot
+    assert lds(P(), 1_000_000) == _lds(64, 2048)
+    assert lds(P(visited_log2=10), 1_000_000) == _lds(64, 512)
+    assert lds(P(filter=ann.ANN_FILTER_ID32), 1_000_000) == _lds(64, 4096)
+    assert lds(P(filter=ann.ANN_FILTER_BITSET), 1_000_000) == 0        # cannot hold 1M bits
+    assert lds(P(filter=ann.ANN_FILTER_BITSET, visited_log2=14), 500_000) == _lds(64, 15625)
+    # tags of 2^30 ids with 2^10 sets need 20 bits: AUTO takes 32-bit ids
+    assert lds(P(), 1 << 30) == _lds(64, 4096)
+    assert lds(P(filter=ann.ANN_FILTER_TAG16), 1 << 30) == 0
+    # 2^25 ids with 2^10 sets: 15-bit tags still fit
+    assert lds(P(), 1 << 25) == _lds(64, 2048)
+    assert lds(P(fp64=1), 10_000) == _lds(64, 313, fp64=True)
+    assert lds(P(filter=7), 10_000) == 0                                  # invalid form
+
+
+def test_autotune_candidates():
+    from paper_2506_15986_amd import ann
+    c = ann.ann_autotune_candidates(1_000_000, 128, 32, 160)
+    d = ann.default_plan(1_000_000, 128, 32, 160)
+    assert c[0].as_dict() == d.as_dict()
+    assert len(c) == 24
+    assert len({tuple(p.as_dict().items()) for p in c}) == 24
+    assert all(p.pool_cap == 160 and p.blocks == 0 and p.fp64 == 0 for p in c)
+    assert {p.group for p in c} == {8, 16} and {p.visited_log2 for p in c} == {10, 11, 12, 13}
+    # wide vectors: group 16 only
+    c = ann.ann_autotune_candidates(1_000_000, 960, 64, 100)
+    assert len(c) == 12 and {p.group for p in c} == {16}
+    assert ann.ann_autotune_candidates(10, 32, 16, 600) == []
+
+
+def test_batch_driver_rejects_bad_arguments_without_gpu_work():
+    from paper_2506_15986_amd import ann
+    assert ann._lib.ann_query_run(None, 3, None) == ann.ANN_EINVAL
+    b = ann.ann_query_batch()
+    assert ann._lib.ann_query_run(ctypes.byref(b), 0, None) == ann.ANN_EINVAL
+    assert ann._lib.ann_query_run(ctypes.byref(b), 2, None) == ann.ANN_EINVAL     # null base
+    h = ctypes.c_void_p()
+    assert ann._lib.ann_query_graph_create(ctypes.byref(b), 4, ctypes.byref(h)) == ann.ANN_EINVAL
+    assert not h.value
+    assert ann._lib.ann_query_graph_launch(None, None) == ann.ANN_EINVAL
+    ann._lib.ann_query_graph_destroy(None)
+    best = ann.ann_search_plan()
+    assert ann._lib.ann_autotune_search(None, 10, 32, None, 16, None, 1, None, 0, None, None, 1,
+                                        None, None, None, None, 0, 1, ctypes.byref(best), None,
+                                        None, 0, None) == ann.ANN_EINVAL

@@ -1,0 +1,141 @@
+"""GPU tests of the batch driver: the autotuner, one-call query batches and
+their HIP graphs (C-ABI), against the separate entry points and the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_15986_amd import synth
+from tests.common import int_index, say, tiny_index
+
+pytestmark = pytest.mark.gpu
+
+
+def _ann():
+    from paper_2506_15986_amd import ann
+    return ann
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _model(ix, nh=64, L_h=16):
+    """An entry model on the tiny index with untrained towers (the driver's
+    results do not depend on what the towers learned)."""
+    ann = _ann()
+    base, w = ix["base"], ix["w"]
+    d = base.shape[1]
+    init = synth.kmeans_init(w, base.shape[0], nh)
+    hub_ids = np.sort(init).astype(np.int32)
+    qp = synth.tower_init(w, [(64, d), (32, 64)])
+    hp = synth.tower_init(w, [(64, d), (32, 64)])
+    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    hemb = ht.forward(_dev(base[hub_ids]))
+    hg, hub_entry = ann.ann_navgraph_build(hemb, 8)
+    torch.cuda.synchronize()
+    return ann.EntryModel(qt, hemb, hg, _dev(hub_ids), hub_entry, ix["medoid"], L_h=L_h)
+
+
+def test_autotune_returns_a_candidate_with_identical_results():
+    ann = _ann()
+    ix = int_index()
+    n, d = ix["base"].shape
+    R = ix["graph"].shape[1]
+    nq, L = ix["q"].shape[0], 64
+    say("case: autotune L=%d nq=%d" % (L, nq))
+    base, g, q = _dev(ix["base"]), _dev(ix["graph"]), _dev(ix["q"])
+    best, times = ann.ann_autotune_search(base, g, q, None, ix["medoid"], 10, L, 10, L, reps=2)
+    torch.cuda.synchronize()
+    cands = [p.as_dict() for p, _ in times]
+    assert best.as_dict() in cands
+    assert all(ms > 0 for _, ms in times)
+    assert min(ms for _, ms in times) == dict((tuple(p.as_dict().items()), ms)
+                                              for p, ms in times)[tuple(best.as_dict().items())]
+    say("case: autotuned plan vs oracle")
+    ids, dist, st, _ = ann.ann_search(base, g, q, None, ix["medoid"], 10, L, k_max=10, plan=best)
+    torch.cuda.synchronize()
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L)
+    assert (ids.cpu().numpy() == ref["ids"]).all()
+    assert (st.cpu().numpy()[:, 2] == ref["hops"]).all()
+
+
+def test_query_run_equals_separate_calls():
+    ann = _ann()
+    ix = tiny_index()
+    model = _model(ix)
+    base, g, q = _dev(ix["base"]), _dev(ix["graph"]), _dev(ix["q"])
+    nq = q.shape[0]
+    rng = np.random.default_rng(5)
+    ks = _dev(rng.integers(1, 11, nq).astype(np.int32))
+    Ls = _dev(rng.integers(10, 65, nq).astype(np.int32))
+    say("case: query_run ALL vs entry_select + search")
+    b = ann.QueryBatch(base, g, ix["medoid"], q, ks, Ls, 10, model=model)
+    ids, dist, st = b.run()
+    ent, _, _ = ann.ann_entry_select(model, q)
+    ids2, dist2, st2, _ = ann.ann_search(base, g, q, ent, ix["medoid"], ks, Ls, k_max=10,
+                                         plan=b.plan)
+    torch.cuda.synchronize()
+    assert (b.entry_ids.cpu().numpy() == ent.cpu().numpy()).all()
+    assert (ids.cpu().numpy() == ids2.cpu().numpy()).all()
+    assert (dist.cpu().numpy().view(np.uint32) == dist2.cpu().numpy().view(np.uint32)).all()
+    assert (st.cpu().numpy() == st2.cpu().numpy()).all()
+
+
+def test_query_graph_replays_match_eager():
+    ann = _ann()
+    ix = tiny_index()
+    model = _model(ix)
+    base, g = _dev(ix["base"]), _dev(ix["graph"])
+    q = _dev(ix["q"])
+    nq = q.shape[0]
+    b = ann.QueryBatch(base, g, ix["medoid"], q, 10, 32, 10, model=model)
+    say("case: eager reference")
+    ids_e, dist_e, _ = [t.clone() for t in b.run()]
+    torch.cuda.synchronize()
+    ref_ids, ref_dist = ids_e.cpu().numpy(), dist_e.cpu().numpy()
+    say("case: graph create")
+    gx = b.graph_exec(ann.ANN_STAGE_ALL)
+    for r in range(3):
+        say("case: replay %d" % r)
+        b.ids.fill_(-7)
+        b.dist.zero_()
+        b.entry_ids.fill_(-1)
+        torch.cuda.synchronize()
+        gx.launch()
+        torch.cuda.synchronize()
+        assert (b.ids.cpu().numpy() == ref_ids).all(), r
+        assert (b.dist.cpu().numpy().view(np.uint32) == ref_dist.view(np.uint32)).all(), r
+        # eager work between replays
+        ann.ann_search(base, g, q, None, ix["medoid"], 10, 16, k_max=10)
+        torch.cuda.synchronize()
+    say("case: replay on new query contents")
+    q2 = np.ascontiguousarray(ix["q"][::-1])
+    q.copy_(_dev(q2))
+    torch.cuda.synchronize()
+    gx.launch()
+    torch.cuda.synchronize()
+    ent, _, _ = ann.ann_entry_select(model, _dev(q2))
+    ids2, _, _, _ = ann.ann_search(base, g, _dev(q2), ent, ix["medoid"], 10, 32, k_max=10,
+                                   plan=b.plan)
+    torch.cuda.synchronize()
+    assert (b.ids.cpu().numpy() == ids2.cpu().numpy()).all()
+    assert (b.ids.cpu().numpy() == ref_ids[::-1]).all()
+    gx.close()
+
+
+def test_search_only_graph_from_the_medoid_matches_oracle():
+    ann = _ann()
+    ix = int_index()
+    base, g, q = _dev(ix["base"]), _dev(ix["graph"]), _dev(ix["q"])
+    say("case: search-only graph, medoid entry")
+    b = ann.QueryBatch(base, g, ix["medoid"], q, 10, 48, 10)
+    gx = b.graph_exec(ann.ANN_STAGE_SEARCH)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, 48)
+    for r in range(2):
+        b.ids.fill_(-7)
+        torch.cuda.synchronize()
+        gx.launch()
+        torch.cuda.synchronize()
+        assert (b.ids.cpu().numpy() == ref["ids"]).all(), r
+    gx.close()
