@@ -103,6 +103,10 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override base size")
     ap.add_argument("--n-train", type=int, default=0, help="override training-query count")
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--hidden", type=int, default=128)
+    ap.add_argument("--dout", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--tau", type=float, default=0.07)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--legs", default="medoid,gate,ablation,serve")
@@ -293,7 +297,9 @@ def main():
         if g is None:
             tq = torch.from_numpy(synth.train_queries(w)).to(dev)
             t = time.time()
-            g = gate.build_gate(index, tq, w, epochs=args.epochs, log=log)
+            gdata = gate.prepare_gate(index, tq, w, log=log)
+            g = gate.train_gate(index, gdata, tq, w, hidden=args.hidden, dout=args.dout,
+                                epochs=args.epochs, lr=args.lr, tau=args.tau, log=log)
             ginfo = dict(g.info, build_s=round(time.time() - t, 1))
         else:
             ginfo = dict(g.info)
@@ -314,7 +320,8 @@ def main():
             ne = gate.nearest_hub_entries(index, g.hub_ids, q_d)
             n_rows, n_L95 = sweep(ne, "nearest-hub")
             abl["nearest_hub"] = dict(L95=n_L95, sweep=n_rows)
-            g0 = gate.build_gate(index, tq, w, epochs=args.epochs, train=False, log=log)
+            g0 = gate.train_gate(index, gdata, tq, w, hidden=args.hidden, dout=args.dout,
+                                 train=False, log=log)
             e0, _, _ = g0.select(q_d)
             u_rows, u_L95 = sweep(e0, "untrained")
             abl["untrained_towers"] = dict(L95=u_L95, sweep=u_rows)

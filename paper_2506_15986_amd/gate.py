@@ -79,12 +79,24 @@ def nearest_hub_entries(index: Index, hub_ids: torch.Tensor, queries: torch.Tens
     return hub_ids[ids[:, 0].long()].contiguous()
 
 
-def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
-               kmeans_iters: int = 20, M: int = 8,
-               ladder=(10, 16, 24, 32, 48, 64, 96, 128, 192, 256),
-               hidden: int = 128, dout: int = 64, epochs: int = 20, batch: int = 1024,
-               lr: float = 1e-3, tau: float = 0.07, s: int = 16, L_h: int = 32,
-               theta: float = -math.inf, train: bool = True, log=print) -> Gate:
+@dataclasses.dataclass
+class GateData:
+    """Everything the entry model is trained from: hubs, hub-tower inputs and
+    the per-query labels (with the nearest-hub candidates they were chosen
+    among)."""
+    hub_ids: torch.Tensor
+    hub_in: torch.Tensor
+    labels: torch.Tensor
+    cand: torch.Tensor
+    scale: float
+    info: dict
+
+
+def prepare_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
+                 kmeans_iters: int = 20, M: int = 8,
+                 ladder=(10, 16, 24, 32, 48, 64, 96, 128, 192, 256), log=print) -> GateData:
+    """Hubs (Definition 3 on Lloyd k-means), hub topology features, hub-tower
+    inputs and the training labels."""
     base, dev = index.base, index.base.device
     n, d = base.shape
     info = {}
@@ -119,15 +131,33 @@ def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: i
     info["label_flags"] = int((flags.cpu().numpy() != 0).sum())
     log("labels: %.1fs, reached %.3f, nearest-hub agreement %.3f" %
         (info["labels_s"], info["labels_reached"], info["label_is_nearest_hub"]))
+    return GateData(hub_ids, hub_in, labels, cand, scale, info)
 
+
+def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Workload,
+               hidden: int = 128, dout: int = 64, epochs: int = 20, batch: int = 1024,
+               lr: float = 1e-3, tau: float = 0.07, s: int = 16, L_h: int = 32,
+               theta: float = -math.inf, train: bool = True, holdout: float = 0.1,
+               log=print) -> Gate:
+    """Trains the towers on the first (1 - holdout) of the training queries
+    (contrastive loss, Adam), embeds the hubs, builds the navigation graph and
+    reports top-1 label agreement on the trained and the held-out queries."""
+    dev = index.base.device
+    d = index.dim
+    n_hubs = data.hub_ids.shape[0]
+    info = dict(data.info)
+    hub_in, labels = data.hub_in, data.labels
     qp = synth.tower_init(w, [(hidden, d), (dout, hidden)])
-    hp = synth.tower_init(w, [(hidden, d + 32), (dout, hidden)])
-    qt, ht = ann.Tower(*qp, device=dev, in_scale=scale), ann.Tower(*hp, device=dev)
+    hp = synth.tower_init(w, [(hidden, hub_in.shape[1]), (dout, hidden)])
+    qt = ann.Tower(*qp, device=dev, in_scale=data.scale)
+    ht = ann.Tower(*hp, device=dev)
     t = time.time()
-    nt = train_q.shape[0]
+    nt_all = train_q.shape[0]
+    n_hold = int(round(holdout * nt_all))
+    nt = nt_all - n_hold
     step = 0
     losses = []
-    nb = ann.ann_train_workspace_size(batch, n_hubs, d, d + 32, hidden, dout)
+    nb = ann.ann_train_workspace_size(batch, n_hubs, d, hub_in.shape[1], hidden, dout)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
     if train:
         for ep in range(epochs):
@@ -138,21 +168,36 @@ def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: i
                                                 tau, lr, step, ws=ws)
             losses.append(loss.item())
     torch.cuda.synchronize()
-    info["train_s"] = time.time() - t
-    info["train_steps"] = step
-    info["loss_per_epoch"] = [round(x, 4) for x in losses]
+    info.update(train_s=time.time() - t, train_steps=step, hidden=hidden, dout=dout,
+                epochs=epochs, lr=lr, tau=tau, holdout=n_hold,
+                loss_per_epoch=[round(x, 4) for x in losses])
     if losses:
         log("training: %d steps, %.1fs, loss %.3f -> %.3f" % (step, info["train_s"], losses[0],
                                                               losses[-1]))
     hemb = ht.forward(hub_in)
     hg, hub_entry = ann.ann_navgraph_build(hemb, s)
-    model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, index.medoid, L_h=L_h, theta=theta)
-    # training accuracy: does the query tower pick the label hub?
-    sample = train_q[: min(nt, 10000)]
-    _, _, bh = ann.ann_entry_select(model, sample, want_score=True)
-    info["train_top1"] = float((bh == labels[: sample.shape[0]]).float().mean().item())
-    log("entry model: train top-1 agreement with labels %.3f" % info["train_top1"])
-    return Gate(qt, ht, hub_ids, hub_in, hemb, hg, hub_entry, model, info)
+    model = ann.EntryModel(qt, hemb, hg, data.hub_ids, hub_entry, index.medoid, L_h=L_h,
+                           theta=theta)
+    # label agreement: does the query tower pick the label hub?
+    m = min(nt, 10000)
+    _, _, bh = ann.ann_entry_select(model, train_q[:m], want_score=True)
+    info["train_top1"] = float((bh == labels[:m]).float().mean().item())
+    if n_hold:
+        _, _, bh = ann.ann_entry_select(model, train_q[nt:], want_score=True)
+        info["val_top1"] = float((bh == labels[nt:]).float().mean().item())
+        info["val_nearest_hub_top1"] = float((data.cand[nt:, 0] == labels[nt:]).float().mean().item())
+    log("entry model: top-1 agreement with labels: train %.3f, held-out %s" %
+        (info["train_top1"], "%.3f" % info["val_top1"] if n_hold else "-"))
+    return Gate(qt, ht, data.hub_ids, hub_in, hemb, hg, hub_entry, model, info)
+
+
+def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
+               kmeans_iters: int = 20, M: int = 8,
+               ladder=(10, 16, 24, 32, 48, 64, 96, 128, 192, 256), data: GateData | None = None,
+               log=print, **train_kw) -> Gate:
+    if data is None:
+        data = prepare_gate(index, train_q, w, n_hubs, kmeans_iters, M, ladder, log=log)
+    return train_gate(index, data, train_q, w, log=log, **train_kw)
 
 
 def save_state(path: str, index: Index, gate: Gate | None, extra: dict) -> None:

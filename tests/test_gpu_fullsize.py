@@ -1,0 +1,163 @@
+"""GPU parity at the full benchmark size (1M x 128 integers, 10,000 queries),
+in the launch configuration bench.py times: outputs the oracle can compute
+one by one are checked on seeded samples, the rest through properties that
+hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_15986_amd import synth
+from tests.common import say
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLE_ROWS = 16
+N_SAMPLE_QUERIES = 48
+L_BENCH = 152
+
+
+def _ann():
+    from paper_2506_15986_amd import ann
+    return ann
+
+
+@pytest.fixture(scope="module")
+def full():
+    ann = _ann()
+    from paper_2506_15986_amd import gate
+    w = synth.WORKLOADS["sift1m"]
+    say("case: sift1m data and graph build (1M x 128)")
+    base = synth.base(w)
+    q = synth.queries(w)
+    dev = torch.device("cuda:0")
+    bd, qd = torch.from_numpy(base).to(dev), torch.from_numpy(q).to(dev)
+    index = gate.build_index(bd, 128, 32, 1.2)
+    return dict(w=w, base=base, q=q, bd=bd, qd=qd, index=index,
+                graph=index.graph.cpu().numpy(), ann=ann)
+
+
+def test_graph_rows_medoid_and_connectivity_at_1m(full):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order
+    base, g, index = full["base"], full["graph"], full["index"]
+    n, R = g.shape
+    say("case: medoid at 1M")
+    assert index.medoid == oracle.medoid(base)
+    say("case: sampled rows: exact 128-NN then alpha 1.2 pruning")
+    rows = np.random.default_rng(11).choice(n, N_SAMPLE_ROWS, replace=False)
+    ids, d2 = oracle.knn(base, base[rows], 129)
+    for r, p in enumerate(rows):
+        keep = ids[r] != p                      # exclude self by id
+        cid, cd2 = ids[r][keep][:128], d2[r][keep][:128]
+        # prune p's candidates on a sub-base: row 0 stands for p, rows 1..K
+        # for its candidates in (d2, id) order
+        sub = np.concatenate([base[p:p + 1], base[cid]])
+        cand = np.full((sub.shape[0], 128), -1, np.int32)
+        cand[0] = np.arange(1, 129, dtype=np.int32)
+        dd = np.zeros((sub.shape[0], 128))
+        dd[0] = cd2
+        pr = oracle.alpha_prune(sub, cand, dd, R, 1.2)[0]
+        want = np.where(pr >= 0, cid[np.maximum(pr - 1, 0)], -1)
+        assert (g[p, :R - 2] == want[:R - 2]).all(), p
+    say("case: repair slots and connectivity")
+    assert index.bridges[0] >= 0 and index.bridges[1] >= 0
+    src = np.repeat(np.arange(n), R)
+    dst = g.reshape(-1)
+    ok = dst >= 0
+    A = sp.csr_matrix((np.ones(ok.sum(), np.int8), (src[ok], dst[ok])), shape=(n, n))
+    assert breadth_first_order(A, index.medoid, directed=True,
+                               return_predecessors=False).shape[0] == n
+    assert breadth_first_order(A.T.tocsr(), index.medoid, directed=True,
+                               return_predecessors=False).shape[0] == n
+    assert ((g >= -1) & (g < n)).all()
+    assert not (g == np.arange(n)[:, None]).any()            # no self loops
+
+
+def test_hubs_sampled_clusters_at_1m(full):
+    ann = full["ann"]
+    base, w = full["base"], full["w"]
+    n = base.shape[0]
+    say("case: Lloyd hubs at 1M, 1024 clusters")
+    init = torch.from_numpy(synth.kmeans_init(w, n, 1024)).to(full["bd"].device)
+    hub, cen, asg, steps = ann.ann_select_hubs(full["bd"], 1024, 20, init)
+    torch.cuda.synchronize()
+    hub, cen, asg = hub.cpu().numpy(), cen.cpu().numpy(), asg.cpu().numpy()
+    assert len(np.unique(hub)) == 1024
+    rng = np.random.default_rng(12)
+    for c in rng.choice(1024, 24, replace=False):
+        mem = np.flatnonzero(asg == c)
+        if len(mem) == 0:
+            continue
+        # the centroid is the exact member mean (integer sums are exact in FP64)
+        mu = base[mem].astype(np.float64).sum(0) / len(mem)
+        assert (cen[c] == mu).all(), c
+        # the hub is the member nearest the centroid by (d2 in dimension order, id)
+        acc = np.zeros(len(mem))
+        x = base[mem].astype(np.float64)
+        for j in range(base.shape[1]):
+            acc = acc + (x[:, j] - cen[c, j]) ** 2
+        best = mem[np.lexsort((mem, acc))[0]]
+        assert hub[c] == best, c
+    if steps < 20:
+        # converged: every sampled point sits in its nearest cluster
+        pts = rng.choice(n, 500, replace=False)
+        acc = np.zeros((len(pts), 1024))
+        x = base[pts].astype(np.float64)
+        for j in range(base.shape[1]):
+            acc = acc + (x[:, j:j + 1] - cen[None, :, j]) ** 2
+        assert (acc.argmin(1) == asg[pts]).all()
+
+
+def test_gate_search_in_the_bench_configuration_at_1m(full):
+    ann = full["ann"]
+    from paper_2506_15986_amd import gate
+    base, q, g = full["base"], full["q"], full["graph"]
+    bd, qd, index = full["bd"], full["qd"], full["index"]
+    nq = q.shape[0]
+    say("case: GATE build at 1M (hubs, features, labels, training)")
+    tq = torch.from_numpy(synth.train_queries(full["w"])).to(bd.device)
+    gm = gate.build_gate(index, tq, full["w"], log=say)
+    del tq
+    say("case: entry selection, sampled against the oracle on the GPU embeddings")
+    ent, sc, bh = ann.ann_entry_select(gm.model, qd, want_score=True)
+    torch.cuda.synchronize()
+    ent_h, bh_h = ent.cpu().numpy(), bh.cpu().numpy()
+    s = np.random.default_rng(13).choice(nq, N_SAMPLE_QUERIES, replace=False)
+    qe = gm.qtower.forward(qd[torch.from_numpy(s).to(bd.device)]).cpu().numpy()
+    he = gm.hub_emb.cpu().numpy()
+    ref_ent, ref_cos, ref_bh = oracle.entry_select(qe, he, gm.hub_graph.cpu().numpy(),
+                                                   gm.hub_ids.cpu().numpy(), 32, -np.inf,
+                                                   index.medoid, gm.hub_entry)
+    cos = qe.astype(np.float64) @ he.astype(np.float64).T
+    for i, qi in enumerate(s):
+        if bh_h[qi] != ref_bh[i]:
+            assert abs(cos[i, bh_h[qi]] - cos[i, ref_bh[i]]) <= 1e-5, qi
+    assert (bh_h[s] == ref_bh).mean() >= 0.95
+    say("case: autotuned plan and graph replay at L=%d" % L_BENCH)
+    kk = torch.full((nq,), 10, dtype=torch.int32, device=bd.device)
+    LL = torch.full((nq,), L_BENCH, dtype=torch.int32, device=bd.device)
+    plan, _ = ann.ann_autotune_search(bd, index.graph, qd, ent, index.medoid, kk, LL, 10, L_BENCH,
+                                      reps=1)
+    b = ann.QueryBatch(bd, index.graph, index.medoid, qd, kk, LL, 10, plan=plan, model=gm.model)
+    gx = b.graph_exec(ann.ANN_STAGE_ALL)
+    gx.launch()
+    torch.cuda.synchronize()
+    ids, dist = b.ids.cpu().numpy(), b.dist.cpu().numpy()
+    assert (b.entry_ids.cpu().numpy() == ent_h).all()
+    say("case: sampled queries against the oracle search (FP32 exact on integers)")
+    ref = oracle.search(base, g, q[s], ent_h[s], 10, L_BENCH)
+    assert (ids[s] == ref["ids"]).all()
+    assert (b.stats.cpu().numpy()[s, 2] == ref["hops"]).all()
+    say("case: whole-batch properties")
+    assert (ids >= 0).all() and (ids < base.shape[0]).all()
+    exact = ((base[ids.reshape(-1)].astype(np.float64) -
+              np.repeat(q, 10, axis=0).astype(np.float64)) ** 2).sum(1).reshape(nq, 10)
+    assert (dist.astype(np.float64) == exact).all()
+    assert ((dist[:, 1:] > dist[:, :-1]) |
+            ((dist[:, 1:] == dist[:, :-1]) & (ids[:, 1:] > ids[:, :-1]))).all()
+    gt, _ = ann.ann_gt_knn(bd, qd, 10)
+    rec = (ids[:, :, None] == gt.cpu().numpy()[:, None, :]).any(-1).mean()
+    say("recall@10 at L=%d: %.4f" % (L_BENCH, rec))
+    assert rec >= 0.94
+    gx.close()
