@@ -146,9 +146,12 @@ enum FilterKind { kBitset = 1, kTag16 = 2, kId32 = 3 };
 constexpr uint32_t kHashMul = 0x9E3779B1u;
 constexpr uint32_t kTagEmpty = 0xFFFFu;
 
+// KIND is the filter form, fixed at compile time so that one kernel holds
+// the code (and the registers) of one form only.
+template <int KIND>
 struct Visited {
+    static_assert(KIND == kBitset || KIND == kTag16 || KIND == kId32, "filter form");
     uint32_t *t;
-    int kind;
     int words;          // 32-bit words to clear
     int log2cap;        // kId32: slots; kTag16: slots (4 per set)
     int tag_bits;       // kTag16: b - log2(sets), <= 15
@@ -156,7 +159,7 @@ struct Visited {
 
     __device__ inline void clear() const
     {
-        const uint32_t v = kind == kBitset ? 0u : kEmpty;
+        const uint32_t v = KIND == kBitset ? 0u : kEmpty;
         for (int i = lane_id(); i < words; i += 64) t[i] = v;
         wave_sync();
     }
@@ -165,14 +168,15 @@ struct Visited {
     // set when an id could not be recorded or another was evicted.
     __device__ inline bool insert(uint32_t id, bool &lost) const
     {
-        if (kind == kBitset) {
+        if (KIND == kBitset) {
             uint32_t bit = 1u << (id & 31u);
             uint32_t old = atomicOr(&t[id >> 5], bit);
             return (old & bit) == 0;
         }
-        if (kind == kTag16) return insert_tag(id, lost);
+        if (KIND == kTag16) return insert_tag(id, lost);
         const uint32_t mask = (1u << log2cap) - 1u;
         uint32_t h = (id * kHashMul) >> (32 - log2cap);
+#pragma unroll 1
         for (int p = 0; p < kMaxProbe; ++p) {
             uint32_t slot = (h + (uint32_t)p) & mask;
             uint32_t old = atomicCAS(&t[slot], kEmpty, id);
@@ -188,6 +192,7 @@ struct Visited {
         const uint32_t set = h >> tag_bits;
         const uint32_t tag = h & ((1u << tag_bits) - 1u);
         uint32_t *w = t + 2 * set;
+#pragma unroll 1
         for (int it = 0; it < 8; ++it) {
             const uint32_t w0 = __atomic_load_n(&w[0], __ATOMIC_RELAXED);
             const uint32_t w1 = __atomic_load_n(&w[1], __ATOMIC_RELAXED);

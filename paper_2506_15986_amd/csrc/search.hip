@@ -26,11 +26,11 @@ namespace {
 
 using namespace beam;
 
-template <int G, int CPL, bool F64>
+template <int G, int CPL, bool F64, int FILT>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    using S = Searcher<G, CPL, F64, L2>;
+    using S = Searcher<G, CPL, F64, L2, FILT>;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     S s;
@@ -74,10 +74,10 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
     }
 }
 
-template <int G, int CPL, bool F64>
-ann_status launch_search(const SearchArgs &a, int blocks, int wpb, hipStream_t st)
+template <int G, int CPL, bool F64, int FILT>
+ann_status launch_one(const SearchArgs &a, int blocks, int wpb, hipStream_t st)
 {
-    auto kern = search_kernel<G, CPL, F64>;
+    auto kern = search_kernel<G, CPL, F64, FILT>;
     size_t lds = (size_t)wpb * a.wave_lds;
     if (lds > 65536) ANN_HIP(hipFuncSetAttribute((const void *)kern,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -98,6 +98,18 @@ ann_status launch_search(const SearchArgs &a, int blocks, int wpb, hipStream_t s
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, st, a);
     ANN_LAUNCHED();
     return ANN_OK;
+}
+
+template <int G, int CPL, bool F64>
+ann_status launch_search(const SearchArgs &a, int blocks, int wpb, hipStream_t st)
+{
+    switch (a.filter.kind) {
+    case kBitset: return launch_one<G, CPL, F64, kBitset>(a, blocks, wpb, st);
+    case kTag16: return launch_one<G, CPL, F64, kTag16>(a, blocks, wpb, st);
+    case kId32: return launch_one<G, CPL, F64, kId32>(a, blocks, wpb, st);
+    default: break;
+    }
+    return fail(ANN_ENOTSUP, "unknown filter form %d", a.filter.kind);
 }
 
 template <bool F64>

@@ -48,7 +48,7 @@ inline size_t wave_lds_bytes(int pool_cap, const beam::FilterShape &f, bool f64,
     return (b + 15) / 16 * 16;
 }
 
-template <int G, int CPL, bool F64, int METRIC>
+template <int G, int CPL, bool F64, int METRIC, int FILT>
 struct Searcher {
     using KT = beam::Key<F64>;
     using K = typename KT::K;
@@ -62,7 +62,7 @@ struct Searcher {
     uint32_t *pi0, *pi1;
     K *sk;
     uint32_t *si;
-    beam::Visited vis;
+    beam::Visited<FILT> vis;
     int pool_cap;
     int64_t n;
     const float4 *base4;
@@ -94,7 +94,6 @@ struct Searcher {
         p += 64 * 4;
         p += 64;
         vis.t = reinterpret_cast<uint32_t *>(p);
-        vis.kind = fs.kind;
         vis.words = fs.words;
         vis.log2cap = vlog2;
         vis.tag_bits = fs.tag_bits;
