@@ -46,6 +46,14 @@ TARGET = 0.95
 L_SWEEP = ([10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56] + list(range(64, 257, 8)) +
            [288, 320, 384, 448, 512])
 SEARCH_SOURCES = ("search.hip", "search_core.h", "beam.h")
+WORKLOAD_TEXT = {
+    "sift1m": "integers 0..255 (256-component GMM, sigma 20)",
+    "shift1m": "unit-normalised (512-component GMM); test and training queries from means shifted "
+               "by 0.3 sigma with Dirichlet(0.3) cluster weights",
+    "gist1m": "256-component GMM with LogNormal(0, 0.5) per-dimension scales; half the queries "
+              "mean-shifted",
+    "tiny": "16-component GMM, sigma 1",
+}
 COPY_BYTES = 1 << 30
 
 
@@ -113,12 +121,15 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
     ap.add_argument("--save-state", default="")
     ap.add_argument("--load-state", default="")
+    ap.add_argument("--targets", default="0.95",
+                    help="recall@10 targets to report (the headline is 0.95)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
+    targets = sorted(set([TARGET] + [float(x) for x in args.targets.split(",") if x]))
 
     import torch
 
@@ -168,10 +179,26 @@ def main():
                              hops=round(float(st[:, 2].mean()), 1)))
             log("  %s L=%4d recall@10=%.4f ndc=%.0f hops=%.0f" % (label, L, rec, st[:, 0].mean(),
                                                                   st[:, 2].mean()))
-            if rec >= TARGET:
+            if rec >= TARGET and L95 is None:
                 L95 = L
+            if rec >= max(targets):
                 break
         return rows, L95
+
+    def extra_targets(rows, model, entry, label):
+        """QPS at the other recall targets (their smallest L on the sweep)."""
+        out = []
+        for t in targets:
+            if t == TARGET:
+                continue
+            Lt = next((r["L"] for r in rows if r["recall"] >= t), None)
+            rec = dict(target=t, L=Lt)
+            if Lt is not None:
+                r = timed(Lt, model, entry, "%s@%g" % (label, t))
+                rec.update(recall=r["recall"], qps=r["qps"], search_ms=r["search_ms"],
+                           entry_ms=r["entry_ms"], ndc=r["ndc"])
+            out.append(rec)
+        return out
 
     def tune(L, entry, label):
         if state is not None and state.get("plan_%s" % label):
@@ -290,6 +317,8 @@ def main():
             L_med = L95 if med_hit else max(med_rows, key=lambda r: r["recall"])["L"]
         med = timed(L_med, None, None, "medoid")
         med["reached_target"] = med_hit
+        if state is None and len(targets) > 1:
+            med["targets"] = extra_targets(med_rows, None, None, "medoid")
 
     # ---- GATE entry
     if "gate" in legs:
@@ -313,6 +342,8 @@ def main():
         gres = timed(L_gate, g.model, ent, "gate")
         gres["reached_target"] = g_hit
         gres["sweep"] = g_rows
+        if state is None and len(targets) > 1:
+            gres["targets"] = extra_targets(g_rows, g.model, ent, "gate")
         if "serve" in legs:
             gres["serving"] = serving(g.model, L_gate, gres)
         if "ablation" in legs and tq is not None:
@@ -388,9 +419,11 @@ def main():
         warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(
-            workload="%s: N=%d d=%d integers 0..255 (256-component GMM, sigma 20), %d queries, "
-                     "%d training queries; graph kNN%d/alpha1.2/R%d + repair; 1024 hubs; "
-                     "towers %d->128->64" % (w.name, w.n, w.d, nq, w.n_train, knn_k, R, w.d),
+            workload="%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d/alpha1.2/R%d "
+                     "+ repair; 1024 hubs; towers %d->%d->%d" %
+                     (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k, R, w.d,
+                      args.hidden, args.dout),
+            recall_targets=targets,
             entry="gate" if head is gres else "medoid", k=k, L=head["L"],
             recall_at_10=head["recall"], recall_target=TARGET,
             gate=gres, medoid=med, medoid_sweep=med_rows, ablation=abl, gate_build=ginfo,

@@ -318,6 +318,8 @@ typedef struct ann_entry_model {
     int32_t medoid;             /* fallback entry point */
     int32_t L_h;                /* beam width on the hub graph (<= 512) */
     float theta;                /* best cosine below theta -> medoid */
+    ann_search_plan hub_plan;   /* plan of the hub-graph search; pool_cap 0 = the default
+                                   plan for (n_hubs, embed dim, s, L_h) */
 } ann_entry_model;
 
 size_t ann_entry_workspace_size(const ann_entry_model *model, int32_t nq);
@@ -378,8 +380,11 @@ int32_t ann_autotune_candidates(int64_t n, int32_t dim, int32_t R, int32_t L_max
  * warm-up launch, then `reps` timed launches each, HIP events on `stream` —
  * and writes the fastest to *best (host).  times_ms (host, n_cand floats or
  * NULL) receives each plan's mean launch time.  Every candidate's ids and
- * distances are compared with the first candidate's on the device; any
- * difference returns ANN_EDEVICE (the plans must agree by construction).
+ * distances are compared on the device with those of the first candidate of
+ * the same gather group (plans of one group sum each distance in the same
+ * order, so they must agree bit for bit; across groups FP32 sums may differ
+ * in the last place on data whose distances are not exact); any difference
+ * returns ANN_EDEVICE.
  * The outputs hold the last candidate's results.  Arguments as ann_search;
  * workspace = ann_autotune_workspace_size(n, dim, nq, k_max) bytes.
  * Synchronises `stream`. */

@@ -99,7 +99,7 @@ class ann_adam_state(ctypes.Structure):
 class ann_entry_model(ctypes.Structure):
     _fields_ = [("query_tower", ann_tower), ("hub_emb", _P), ("hub_graph", _P), ("n_hubs", _I32),
                 ("s", _I32), ("hub_ids", _P), ("hub_entry", _I32), ("medoid", _I32),
-                ("L_h", _I32), ("theta", _F32)]
+                ("L_h", _I32), ("theta", _F32), ("hub_plan", ann_search_plan)]
 
 
 _sig("ann_hub_input", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _F32, _P, _P)
@@ -398,12 +398,23 @@ class EntryModel:
     """The entry-selection model: query tower + hub embeddings + hub graph."""
 
     def __init__(self, qtower: Tower, hub_emb, hub_graph, hub_ids, hub_entry: int, medoid: int,
-                 L_h: int = 32, theta: float = float("-inf")):
+                 L_h: int = 32, theta: float = float("-inf"), hub_plan=None):
         self.qtower, self.hub_emb, self.hub_graph, self.hub_ids = qtower, hub_emb, hub_graph, hub_ids
         self.c = ann_entry_model(qtower.struct(), hub_emb.data_ptr(), hub_graph.data_ptr(),
                                  hub_emb.shape[0], hub_graph.shape[1], hub_ids.data_ptr(),
-                                 int(hub_entry), int(medoid), int(L_h), float(theta))
+                                 int(hub_entry), int(medoid), int(L_h), float(theta),
+                                 hub_plan if hub_plan is not None else ann_search_plan())
         self._ws = None
+
+    def tune_hub_plan(self, sample_queries, reps: int = 3):
+        """Autotunes the hub-graph search on the embeddings of sample queries
+        and keeps the fastest plan; returns it."""
+        qe = self.qtower.forward(sample_queries)
+        L = int(self.c.L_h)
+        best, _ = ann_autotune_search(self.hub_emb, self.hub_graph, qe, None, int(self.c.hub_entry),
+                                      1, L, 1, L, reps=reps)
+        self.c.hub_plan = best
+        return best
 
     def workspace(self, nq, device):
         nb = max(256, int(_lib.ann_entry_workspace_size(ctypes.byref(self.c), nq)))

@@ -43,10 +43,11 @@ __global__ void fill_kl_kernel(int32_t *k, int32_t *L, int nq, int kv, int Lv)
     L[i] = Lv;
 }
 
-ann_search_plan entry_plan(int nh, int e, int s, int Lh)
+ann_search_plan entry_plan(const ann_entry_model &m)
 {
+    if (m.hub_plan.pool_cap != 0) return m.hub_plan;
     ann_search_plan p{};
-    ann_default_plan(nh, e, s, Lh, &p);
+    ann_default_plan(m.n_hubs, m.query_tower.dout, m.s, m.L_h, &p);
     return p;
 }
 
@@ -119,6 +120,18 @@ extern "C" ann_status ann_entry_select(const ann_entry_model *m, const float *qu
     ANN_REQUIRE(nq >= 0, "nq must be >= 0");
     ANN_REQUIRE(nq == 0 || (queries && entry_ids && workspace), "a required pointer is NULL");
     ANN_REQUIRE(ws_bytes >= entry_select_ws(nq, &m->query_tower), "workspace too small");
+    const ann_search_plan plan = entry_plan(*m);
+    {
+        ann_status ps = validate_plan(plan);
+        if (ps != ANN_OK) return ps;
+        ANN_REQUIRE(plan.pool_cap >= m->L_h, "hub_plan.pool_cap %d < L_h %d", plan.pool_cap,
+                    m->L_h);
+        ANN_SUPPORTED(search_wave_lds(plan, m->n_hubs, m->query_tower.dout) != 0 &&
+                          (size_t)plan.waves_per_block *
+                                  search_wave_lds(plan, m->n_hubs, m->query_tower.dout) <=
+                              (size_t)device_lds_bytes(),
+                      "hub_plan does not fit the hub table on a CU");
+    }
     if (nq == 0) return ANN_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int e = m->query_tower.dout;
@@ -135,7 +148,6 @@ extern "C" ann_status ann_entry_select(const ann_entry_model *m, const float *qu
     const int blocks = (nq + 255) / 256;
     hipLaunchKernelGGL(fill_kl_kernel, dim3(blocks), dim3(256), 0, st, kk, LL, nq, 1, m->L_h);
     ANN_LAUNCHED();
-    ann_search_plan plan = entry_plan(m->n_hubs, e, m->s, m->L_h);
     s = search_launch(m->hub_emb, m->n_hubs, e, m->hub_graph, m->s, qemb, nq, nullptr,
                       m->hub_entry, kk, LL, 1, best, d2, nullptr, nullptr, 0, plan, counter, st);
     if (s != ANN_OK) return s;

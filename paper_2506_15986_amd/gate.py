@@ -178,6 +178,7 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     hg, hub_entry = ann.ann_navgraph_build(hemb, s)
     model = ann.EntryModel(qt, hemb, hg, data.hub_ids, hub_entry, index.medoid, L_h=L_h,
                            theta=theta)
+    info["hub_plan"] = model.tune_hub_plan(train_q[:min(nt, 10000)]).as_dict()
     # label agreement: does the query tower pick the label hub?
     m = min(nt, 10000)
     _, _, bh = ann.ann_entry_select(model, train_q[:m], want_score=True)
@@ -216,7 +217,8 @@ def save_state(path: str, index: Index, gate: Gate | None, extra: dict) -> None:
                         ("hub_graph", gate.hub_graph)):
             np.save(os.path.join(path, name + ".npy"), t.cpu().numpy())
         meta.update(in_scale=qt.in_scale, hub_entry=int(gate.hub_entry),
-                    L_h=int(gate.model.c.L_h), theta=float(gate.model.c.theta), info=gate.info)
+                    L_h=int(gate.model.c.L_h), theta=float(gate.model.c.theta), info=gate.info,
+                    hub_plan=gate.model.c.hub_plan.as_dict())
     with open(os.path.join(path, "meta.json"), "w") as f:
         json.dump(meta, f)
 
@@ -237,7 +239,9 @@ def load_state(path: str, base: torch.Tensor):
                        in_scale=float(meta["in_scale"]))
         hub_ids, hemb, hg = ld("hub_ids"), ld("hub_emb"), ld("hub_graph")
         model = ann.EntryModel(qt, hemb, hg, hub_ids, int(meta["hub_entry"]), index.medoid,
-                               L_h=int(meta["L_h"]), theta=float(meta["theta"]))
+                               L_h=int(meta["L_h"]), theta=float(meta["theta"]),
+                               hub_plan=ann.make_plan(**meta["hub_plan"]) if meta.get("hub_plan")
+                               else None)
         gate = Gate(qt, None, hub_ids, None, hemb, hg, int(meta["hub_entry"]), model,
                     dict(meta.get("info", {})))
     return index, gate, meta

@@ -139,3 +139,34 @@ def test_search_only_graph_from_the_medoid_matches_oracle():
         torch.cuda.synchronize()
         assert (b.ids.cpu().numpy() == ref["ids"]).all(), r
     gx.close()
+
+
+def test_autotune_on_float_data_and_a_tuned_hub_plan():
+    # grid data: FP32 distances are not exact, so plans of different gather
+    # groups may order near-ties differently; each group checks against its own
+    ann = _ann()
+    ix = tiny_index()
+    base, g, q = _dev(ix["base"]), _dev(ix["graph"]), _dev(ix["q"])
+    say("case: autotune on float data")
+    best, times = ann.ann_autotune_search(base, g, q, None, ix["medoid"], 10, 32, 10, 32, reps=1)
+    torch.cuda.synchronize()
+    assert {p.group for p, _ in times} == {8, 16}
+    ids, dist, _, _ = ann.ann_search(base, g, q, None, ix["medoid"], 10, 32, k_max=10, plan=best)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, 32)
+    d, rd = dist.cpu().numpy().astype(np.float64), ref["d2"]
+    assert np.abs(d - rd).max() <= 1e-5 * max(rd.max(), 1e-6)
+    assert (ids.cpu().numpy() == ref["ids"]).mean() >= 0.99
+    say("case: tuned hub-search plan")
+    model = _model(ix, L_h=24)
+    e0, _, b0 = ann.ann_entry_select(model, q, want_score=True)
+    plan = model.tune_hub_plan(q, reps=1)
+    assert plan.pool_cap >= 24
+    e1, _, b1 = ann.ann_entry_select(model, q, want_score=True)
+    torch.cuda.synchronize()
+    qe = model.qtower.forward(q).cpu().numpy().astype(np.float64)
+    he = model.hub_emb.cpu().numpy().astype(np.float64)
+    cos = qe @ he.T
+    b0, b1 = b0.cpu().numpy(), b1.cpu().numpy()
+    rows = np.arange(len(b0))
+    assert (np.abs(cos[rows, b0] - cos[rows, b1]) <= 1e-5).all()
+    assert (b0 == b1).mean() >= 0.98
