@@ -98,8 +98,11 @@ def recall_at(ids: np.ndarray, truth: np.ndarray, k: int = 10) -> np.ndarray:
 
 
 def recall_tie_aware(dist: np.ndarray, truth_dist: np.ndarray, k: int = 10) -> np.ndarray:
-    """A returned point counts when its distance is within the k-th true one."""
-    return (dist[:, :k] <= truth_dist[:, k - 1:k]).sum(1) / float(k)
+    """A returned point counts when its distance is within the k-th true one
+    (up to the 1e-5 relative tolerance between FP32 search distances and the
+    ground truth's)."""
+    lim = truth_dist[:, k - 1:k].astype(np.float64)
+    return (dist[:, :k].astype(np.float64) <= lim + 1e-5 * np.maximum(lim, 1e-6)).sum(1) / float(k)
 
 
 def main():
@@ -111,6 +114,9 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override base size")
     ap.add_argument("--n-train", type=int, default=0, help="override training-query count")
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--R", type=int, default=32, help="graph out-degree")
+    ap.add_argument("--knn-k", type=int, default=128, help="kNN candidates before pruning")
+    ap.add_argument("--hubs", type=int, default=1024)
     ap.add_argument("--hidden", type=int, default=128)
     ap.add_argument("--dout", type=int, default=64)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -139,7 +145,7 @@ def main():
     w = synth.WORKLOADS[args.workload]
     if args.n or args.n_train:
         w = synth.scaled(w, n=args.n or None, n_train=args.n_train or None)
-    knn_k, R, k = 128, 32, 10
+    knn_k, R, k = args.knn_k, args.R, 10
 
     t0 = time.time()
     base = synth.base(w)
@@ -326,7 +332,7 @@ def main():
         if g is None:
             tq = torch.from_numpy(synth.train_queries(w)).to(dev)
             t = time.time()
-            gdata = gate.prepare_gate(index, tq, w, log=log)
+            gdata = gate.prepare_gate(index, tq, w, n_hubs=args.hubs, log=log)
             g = gate.train_gate(index, gdata, tq, w, hidden=args.hidden, dout=args.dout,
                                 epochs=args.epochs, lr=args.lr, tau=args.tau, log=log)
             ginfo = dict(g.info, build_s=round(time.time() - t, 1))
@@ -420,9 +426,9 @@ def main():
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(
             workload="%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d/alpha1.2/R%d "
-                     "+ repair; 1024 hubs; towers %d->%d->%d" %
-                     (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k, R, w.d,
-                      args.hidden, args.dout),
+                     "+ repair; %d hubs; towers %d->%d->%d" %
+                     (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k, R,
+                      args.hubs, w.d, args.hidden, args.dout),
             recall_targets=targets,
             entry="gate" if head is gres else "medoid", k=k, L=head["L"],
             recall_at_10=head["recall"], recall_target=TARGET,

@@ -91,6 +91,9 @@ typedef struct ann_search_plan {
     int32_t blocks;          /* persistent grid size; 0 = as many as fit on the GPU */
     int32_t fp64;            /* 1 = FP64 distances (diagnostic mode), 0 = FP32 */
     int32_t filter;          /* visited filter form, one of ANN_FILTER_* */
+    int32_t waves_per_query; /* wavefronts that share one query: 1 (0 = 1), or 2 / 4 (FP32, group 16;
+                                the workgroup is then one query's waves, so
+                                waves_per_block must equal waves_per_query) */
 } ann_search_plan;
 
 /* Visited filter forms (per wavefront, in LDS).  Every form answers "seen"
@@ -371,8 +374,9 @@ size_t ann_search_plan_lds(const ann_search_plan *plan, int64_t n, int32_t dim);
 /* Candidate plans for (n, dim, R, L_max): writes up to `cap` plans to the
  * host array `plans` and returns how many there are (call with cap = 0 to
  * count).  pool_cap is L_max rounded up to 16; the candidates vary the
- * gather group, the filter size (visited_log2 10..13, form AUTO) and the
- * waves per workgroup.  Host-only. */
+ * gather group, the filter size (visited_log2 10..13, form AUTO), the waves
+ * per workgroup and, for group 16, the wavefronts per query (2, 4).
+ * Host-only. */
 int32_t ann_autotune_candidates(int64_t n, int32_t dim, int32_t R, int32_t L_max,
                                 ann_search_plan *plans, int32_t cap);
 

@@ -36,7 +36,7 @@ class ann_search_plan(ctypes.Structure):
     _fields_ = [("pool_cap", ctypes.c_int32), ("visited_log2", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("fp64", ctypes.c_int32),
-                ("filter", ctypes.c_int32)]
+                ("filter", ctypes.c_int32), ("waves_per_query", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -113,6 +113,16 @@ extern "C" int32_t ann_autotune_candidates(int64_t n, int32_t dim, int32_t R, in
                 if (search_wave_lds(p, n, dim) == 0) continue;
                 out.push_back(p);
             }
+            if (g != 16) continue;
+            for (int wq = 2; wq <= 4; wq *= 2) {
+                ann_search_plan p = base;
+                p.group = 16;
+                p.visited_log2 = vl;
+                p.waves_per_query = wq;
+                p.waves_per_block = wq;
+                if (search_wave_lds(p, n, dim) == 0) continue;
+                out.push_back(p);
+            }
         }
     }
     const int32_t total = (int32_t)out.size();

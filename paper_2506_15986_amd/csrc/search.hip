@@ -150,6 +150,12 @@ ann_status validate_plan(const ann_search_plan &p)
     ANN_REQUIRE(p.fp64 == 0 || p.fp64 == 1, "plan.fp64 must be 0 or 1");
     ANN_REQUIRE(p.filter >= ANN_FILTER_AUTO && p.filter <= ANN_FILTER_ID32,
                 "plan.filter must be one of ANN_FILTER_*");
+    ANN_REQUIRE(p.waves_per_query >= 0 && p.waves_per_query <= 4 && p.waves_per_query != 3,
+                "plan.waves_per_query must be 1, 2 or 4 (0 = 1)");
+    ANN_REQUIRE(p.waves_per_query <= 1 || p.waves_per_block == p.waves_per_query,
+                "plan.waves_per_block must equal waves_per_query when it is above 1");
+    ANN_SUPPORTED(p.waves_per_query <= 1 || (p.group == 16 && p.fp64 == 0),
+                  "several waves per query need group 16 and FP32");
     return ANN_OK;
 }
 
@@ -201,6 +207,7 @@ ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_
         if (fs != ANN_OK) return fs;
     }
     a.wave_lds = wave_lds_bytes(p.pool_cap, a.filter, p.fp64 != 0, dim);
+    if (p.waves_per_query > 1) return launch_search_mw(a, p.waves_per_query, p.blocks, st);
     if (p.fp64) return dispatch<true>(a, p.group, p.blocks, p.waves_per_block, st);
     return dispatch<false>(a, p.group, p.blocks, p.waves_per_block, st);
 }
@@ -219,6 +226,7 @@ extern "C" ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_
     p.pool_cap = (L_max + 15) / 16 * 16;
     p.visited_log2 = 12;
     p.filter = ANN_FILTER_AUTO;
+    p.waves_per_query = 1;
     p.group = dim <= 128 ? 8 : 16;
     p.waves_per_block = 1;
     p.blocks = 0;
@@ -265,7 +273,8 @@ ann_status search_check(const float *base, int64_t n, int32_t dim, const int32_t
     FilterShape f{};
     s = search_filter(p, n, f);
     if (s != ANN_OK) return s;
-    const size_t lds = (size_t)p.waves_per_block * wave_lds_bytes(p.pool_cap, f, p.fp64 != 0, dim);
+    const size_t lds = (size_t)(p.waves_per_query > 1 ? 1 : p.waves_per_block) *
+                       wave_lds_bytes(p.pool_cap, f, p.fp64 != 0, dim);
     ANN_SUPPORTED(lds <= (size_t)device_lds_bytes(),
                   "search plan needs %zu B of LDS per workgroup (the CU has %d)", lds,
                   device_lds_bytes());

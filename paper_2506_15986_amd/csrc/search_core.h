@@ -126,12 +126,14 @@ struct Searcher {
         }
     }
 
-    // keys of the m candidates si[0..m) into sk[0..m)
-    __device__ void distances(int m)
+    // keys of the m candidates si[0..m) into sk[0..m); with W waves sharing
+    // the work, wave w takes every W-th batch of VPB * U candidates
+    template <int W = 1>
+    __device__ void distances(int m, int w = 0)
     {
         const int lane = beam::lane_id();
         const int gi = lane / G, gl = lane % G;
-        for (int b0 = 0; b0 < m; b0 += VPB * U) {
+        for (int b0 = w * VPB * U; b0 < m; b0 += W * VPB * U) {
             float4 xv[U][CPL];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -173,6 +175,77 @@ struct Searcher {
             if (bal) return b + __ffsll((unsigned long long)bal) - 1;
         }
         return -1;
+    }
+
+    // Merges the m new keys (sk/si) into the pool.  Updates the cursor and,
+    // when the best new key will be expanded next, the prefetched row.
+    __device__ __forceinline__ void merge(int m, int Lq, int &cursor, uint32_t &pf_id, int &pf_nb,
+                                          K nkey, uint32_t nid, SearchResult &r)
+    {
+        const int lane = beam::lane_id();
+        // ---- merge the new keys into the pool.  A new key's place is its
+        // insertion point in the old pool plus its rank among the new keys;
+        // an old entry moves down by the number of new keys inserted at or
+        // before it.  Both counts come from a scalar loop over the new keys
+        // (readlane), so no sort of the staging row is needed.
+        K *ak = keys(cur);
+        uint32_t *ai = ids(cur);
+        K kk = KT::kMax;
+        uint32_t ii = beam::kEmpty;
+        bool valid = lane < m;
+        if (valid) {
+            kk = sk[lane];
+            ii = si[lane];
+        }
+        if (valid && cnt == Lq && !beam::key_less(kk, ii, ak[cnt - 1], ai[cnt - 1])) valid = false;
+        int pos = 0;
+        bool dup = false;
+        if (valid) {
+            pos = beam::lower_bound(ak, ai, cnt, kk, ii);
+            if (pos < cnt && ak[pos] == kk && (ai[pos] & beam::kIdMask) == ii) dup = true;
+        }
+        valid = valid && !dup;
+        r.dups += __popcll(__ballot(dup));
+        const uint64_t vmask = __ballot(valid);
+        const int mv = __popcll(vmask);
+        if (mv == 0) return;
+        int rank = 0;
+        for (uint64_t mm = vmask; mm; mm &= mm - 1) {
+            const int t = __ffsll((unsigned long long)mm) - 1;
+            if (beam::key_less(beam::readlane(kk, t), beam::readlane(ii, t), kk, ii)) ++rank;
+        }
+        // the smallest new key: expanded next if it beats the old pool's
+        // next unexpanded entry
+        const int l0 = __ffsll((unsigned long long)__ballot(valid && rank == 0)) - 1;
+        const K k0 = beam::readlane(kk, l0);
+        const uint32_t i0 = beam::readlane(ii, l0);
+        const int f0 = beam::readlane(pos, l0);
+        if (beam::key_less(k0, i0, nkey, nid)) {
+            pf_id = i0;
+            pf_nb = lane < R ? graph[(size_t)i0 * R + lane] : -1;
+        }
+        K *bk = keys(cur ^ 1);
+        uint32_t *bi = ids(cur ^ 1);
+        if (valid && pos + rank < Lq) {
+            bk[pos + rank] = kk;
+            bi[pos + rank] = ii;
+        }
+        for (int j = lane; j < cnt; j += 64) {
+            int f = j;
+            for (uint64_t mm = vmask; mm; mm &= mm - 1)
+                if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= j) ++f;
+            if (f < Lq) {
+                bk[f] = ak[j];
+                bi[f] = ai[j];
+            }
+        }
+        int oc = cursor;
+        for (uint64_t mm = vmask; mm; mm &= mm - 1)
+            if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= cursor) ++oc;
+        cursor = f0 < oc ? f0 : oc;
+        cnt = (cnt + mv < Lq) ? cnt + mv : Lq;
+        cur ^= 1;
+        beam::wave_sync();
     }
 
     // Runs one query from `entry` with beam width Lq.  trace (nullable)
@@ -243,69 +316,92 @@ struct Searcher {
             if (m == 0) continue;
             distances(m);
             r.ndc_exec += m;
-            // ---- merge the new keys into the pool.  A new key's place is its
-            // insertion point in the old pool plus its rank among the new keys;
-            // an old entry moves down by the number of new keys inserted at or
-            // before it.  Both counts come from a scalar loop over the new keys
-            // (readlane), so no sort of the staging row is needed.
-            K *ak = keys(cur);
-            uint32_t *ai = ids(cur);
-            K kk = KT::kMax;
-            uint32_t ii = beam::kEmpty;
-            bool valid = lane < m;
-            if (valid) {
-                kk = sk[lane];
-                ii = si[lane];
+            merge(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+        }
+        r.lost = __ballot(lost) != 0;
+        return r;
+    }
+
+    // The same search with W wavefronts of one workgroup per query.  Wave 0
+    // picks the node to expand, runs the visited filter and the merge; all W
+    // waves gather and reduce the new neighbours' distances (every W-th batch
+    // each).  ctrl (LDS, shared by the workgroup) carries the hop's count of
+    // new neighbours, -1 when the search is over.  Every wave of the group
+    // must call this with the same arguments; the barriers are workgroup-wide.
+    template <int W>
+    __device__ SearchResult run_multi(uint32_t entry, int Lq, int32_t *trace, int trace_cap, int w,
+                                      volatile int *ctrl)
+    {
+        const int lane = beam::lane_id();
+        SearchResult r{0, 0, 0, false};
+        bool lost = false;
+        int cursor = 0;
+        uint32_t pf_id = beam::kEmpty;
+        int pf_nb = -1;
+        K nkey = KT::kMax;
+        uint32_t nid = beam::kEmpty;
+        if (w == 0) {
+            vis.clear();
+            if (lane == 0) {
+                vis.insert(entry, lost);
+                si[0] = entry;
             }
-            if (valid && cnt == Lq && !beam::key_less(kk, ii, ak[cnt - 1], ai[cnt - 1])) valid = false;
-            int pos = 0;
-            bool dup = false;
-            if (valid) {
-                pos = beam::lower_bound(ak, ai, cnt, kk, ii);
-                if (pos < cnt && ak[pos] == kk && (ai[pos] & beam::kIdMask) == ii) dup = true;
-            }
-            valid = valid && !dup;
-            r.dups += __popcll(__ballot(dup));
-            const uint64_t vmask = __ballot(valid);
-            const int mv = __popcll(vmask);
-            if (mv == 0) continue;
-            int rank = 0;
-            for (uint64_t mm = vmask; mm; mm &= mm - 1) {
-                const int t = __ffsll((unsigned long long)mm) - 1;
-                if (beam::key_less(beam::readlane(kk, t), beam::readlane(ii, t), kk, ii)) ++rank;
-            }
-            // the smallest new key: expanded next if it beats the old pool's
-            // next unexpanded entry
-            const int l0 = __ffsll((unsigned long long)__ballot(valid && rank == 0)) - 1;
-            const K k0 = beam::readlane(kk, l0);
-            const uint32_t i0 = beam::readlane(ii, l0);
-            const int f0 = beam::readlane(pos, l0);
-            if (beam::key_less(k0, i0, nkey, nid)) {
-                pf_id = i0;
-                pf_nb = lane < R ? graph[(size_t)i0 * R + lane] : -1;
-            }
-            K *bk = keys(cur ^ 1);
-            uint32_t *bi = ids(cur ^ 1);
-            if (valid && pos + rank < Lq) {
-                bk[pos + rank] = kk;
-                bi[pos + rank] = ii;
-            }
-            for (int j = lane; j < cnt; j += 64) {
-                int f = j;
-                for (uint64_t mm = vmask; mm; mm &= mm - 1)
-                    if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= j) ++f;
-                if (f < Lq) {
-                    bk[f] = ak[j];
-                    bi[f] = ai[j];
-                }
-            }
-            int oc = cursor;
-            for (uint64_t mm = vmask; mm; mm &= mm - 1)
-                if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= cursor) ++oc;
-            cursor = f0 < oc ? f0 : oc;
-            cnt = (cnt + mv < Lq) ? cnt + mv : Lq;
-            cur ^= 1;
             beam::wave_sync();
+            distances(1);
+            cur = 0;
+            if (lane == 0) {
+                pk0[0] = sk[0];
+                pi0[0] = entry;
+            }
+            cnt = 1;
+            r.ndc_exec = 1;
+            beam::wave_sync();
+        }
+        for (;;) {
+            if (w == 0) {
+                int m = -1;
+                const int ppos = next_unexpanded(cursor);
+                if (ppos >= 0) {
+                    cursor = ppos;
+                    const uint32_t p = ids(cur)[ppos] & beam::kIdMask;
+                    int nb = -1;
+                    if (p == pf_id)
+                        nb = pf_nb;
+                    else if (lane < R)
+                        nb = graph[(size_t)p * R + lane];
+                    const int npos = next_unexpanded(ppos + 1);
+                    nkey = KT::kMax;
+                    nid = beam::kEmpty;
+                    pf_id = beam::kEmpty;
+                    if (npos >= 0) {
+                        nkey = keys(cur)[npos];
+                        nid = ids(cur)[npos] & beam::kIdMask;
+                        pf_id = nid;
+                        pf_nb = lane < R ? graph[(size_t)nid * R + lane] : -1;
+                    }
+                    beam::wave_sync();
+                    if (lane == 0) {
+                        ids(cur)[ppos] = p | beam::kExpanded;
+                        if (trace && r.hops < trace_cap) trace[r.hops] = (int32_t)p;
+                    }
+                    r.hops++;
+                    bool fresh = false;
+                    if (nb >= 0 && (int64_t)nb < n) fresh = vis.insert((uint32_t)nb, lost);
+                    const uint64_t fb = __ballot(fresh);
+                    m = __popcll(fb);
+                    if (fresh) si[__popcll(fb & ((1ull << lane) - 1ull))] = (uint32_t)nb;
+                }
+                if (lane == 0) ctrl[0] = m;
+            }
+            __syncthreads();
+            const int m = ctrl[0];
+            if (m < 0) break;
+            if (m > 0) distances<W>(m, w);
+            __syncthreads();
+            if (w == 0 && m > 0) {
+                r.ndc_exec += m;
+                merge(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            }
         }
         r.lost = __ballot(lost) != 0;
         return r;
@@ -329,5 +425,8 @@ struct Searcher {
         }
     }
 };
+
+// the several-wavefronts-per-query kernels (search_mw.hip)
+ann_status launch_search_mw(const SearchArgs &a, int waves_per_query, int blocks, hipStream_t st);
 
 }  // namespace ann

@@ -71,6 +71,12 @@ def test_search_rejects_bad_arguments_before_any_device_work(lib):
     assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
     bad.pool_cap, bad.group = 64, 12
     assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
+    bad.group, bad.waves_per_query, bad.waves_per_block = 8, 3, 1
+    assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
+    bad.waves_per_query = 2                      # needs waves_per_block == 2
+    assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
+    bad.waves_per_block = 2                      # group 8 cannot share a query
+    assert call(plan=ctypes.byref(bad)) == ann.ANN_ENOTSUP
     # nq == 0 is valid and enqueues nothing
     assert call(nq=0) == ann.ANN_OK
 
@@ -136,14 +142,19 @@ def test_autotune_candidates():
     from paper_2506_15986_amd import ann
     c = ann.ann_autotune_candidates(1_000_000, 128, 32, 160)
     d = ann.default_plan(1_000_000, 128, 32, 160)
-    assert c[0].as_dict() == d.as_dict()
-    assert len(c) == 24
-    assert len({tuple(p.as_dict().items()) for p in c}) == 24
+    assert c[0].as_dict() == d.as_dict() and d.waves_per_query == 1
+    # 2 groups x 4 filter sizes x 3 workgroup sizes, plus group 16 x 4 sizes x
+    # 2 and 4 waves per query
+    assert len(c) == 24 + 8
+    assert len({tuple(p.as_dict().items()) for p in c}) == 32
     assert all(p.pool_cap == 160 and p.blocks == 0 and p.fp64 == 0 for p in c)
     assert {p.group for p in c} == {8, 16} and {p.visited_log2 for p in c} == {10, 11, 12, 13}
+    mw = [p for p in c if p.waves_per_query > 1]
+    assert len(mw) == 8 and all(p.group == 16 and p.waves_per_block == p.waves_per_query
+                                for p in mw)
     # wide vectors: group 16 only
     c = ann.ann_autotune_candidates(1_000_000, 960, 64, 100)
-    assert len(c) == 12 and {p.group for p in c} == {16}
+    assert len(c) == 12 + 8 and {p.group for p in c} == {16}
     assert ann.ann_autotune_candidates(10, 32, 16, 600) == []
 
 

@@ -209,3 +209,56 @@ def test_every_filter_form_matches_oracle_exactly_when_large(filt):
     assert ok.mean() > 0.9
     assert (got["stats"][ok, 0] == ref["ndc"][ok]).all()
     assert (got["stats"][ok, 1] == ref["ndc"][ok]).all()
+
+
+@pytest.mark.parametrize("W", [2, 4])
+def test_several_waves_per_query_match(W):
+    ann = _ann()
+    ix = int_index()
+    nq, L = ix["q"].shape[0], 64
+    say("case: %d waves per query, integer data" % W)
+    plan = _plan(ix, L, group=16, waves_per_query=W, waves_per_block=W)
+    got = _run(ix, None, [10] * nq, [L] * nq, plan, trace_cap=2048)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L, trace_cap=2048)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["trace"] == ref["trace"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    assert (got["stats"][:, 1] == ref["ndc"]).all()
+    say("case: %d waves per query, uneven k, L and entries" % W)
+    rng = np.random.default_rng(7)
+    ks = rng.integers(1, 11, nq)
+    Ls = rng.integers(10, 129, nq)
+    ks = np.minimum(ks, Ls)
+    ent = rng.integers(0, ix["base"].shape[0], nq)
+    got = _run(ix, ent, ks, Ls, _plan(ix, 128, group=16, waves_per_query=W, waves_per_block=W),
+               k_max=10)
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ent, ks, Ls, k_max=10)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    say("case: %d waves per query, lossy filter" % W)
+    got = _run(ix, None, [10] * nq, [100] * nq,
+               _plan(ix, 100, group=16, waves_per_query=W, waves_per_block=W, visited_log2=8))
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, 100)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    say("case: %d waves per query, ragged batches" % W)
+    for m in (1, 3, 65):
+        sub = dict(ix, q=ix["q"][:m])
+        got = _run(sub, None, [10] * m, [32] * m,
+                   _plan(ix, 32, group=16, waves_per_query=W, waves_per_block=W))
+        ref = oracle.search(ix["base"], ix["graph"], ix["q"][:m], ix["medoid"], 10, 32)
+        assert (got["ids"] == ref["ids"]).all(), m
+
+
+@pytest.mark.parametrize("W", [2, 4])
+def test_several_waves_per_query_equal_one_wave_on_float_data(W):
+    ix = tiny_index()
+    nq, L = ix["q"].shape[0], 48
+    say("case: %d waves per query vs one, grid data" % W)
+    one = _run(ix, None, [10] * nq, [L] * nq, _plan(ix, L, group=16), trace_cap=512)
+    many = _run(ix, None, [10] * nq, [L] * nq,
+                _plan(ix, L, group=16, waves_per_query=W, waves_per_block=W), trace_cap=512)
+    assert (one["ids"] == many["ids"]).all()
+    assert (one["dist"].view(np.uint32) == many["dist"].view(np.uint32)).all()
+    assert (one["stats"] == many["stats"]).all()
+    assert (one["trace"] == many["trace"]).all()
