@@ -161,3 +161,112 @@ def test_gate_search_in_the_bench_configuration_at_1m(full):
     say("recall@10 at L=%d: %.4f" % (L_BENCH, rec))
     assert rec >= 0.94
     gx.close()
+
+
+# ---------------------------------------------------------------------------
+# 1M x 96 unit vectors, queries from shifted means (the distribution-shift
+# workload): FP64 graph build (exact on the 2^-22 grid), FP32 search checked
+# within tolerance with a near-tie certificate for every trajectory change.
+
+L_SHIFT = 96
+
+
+@pytest.fixture(scope="module")
+def shift():
+    ann = _ann()
+    from paper_2506_15986_amd import gate
+    w = synth.WORKLOADS["shift1m"]
+    say("case: shift1m data and graph build (1M x 96)")
+    base = synth.base(w)
+    q = synth.queries(w)
+    dev = torch.device("cuda:0")
+    bd, qd = torch.from_numpy(base).to(dev), torch.from_numpy(q).to(dev)
+    index = gate.build_index(bd, 128, 32, 1.2)
+    return dict(w=w, base=base, q=q, bd=bd, qd=qd, index=index,
+                graph=index.graph.cpu().numpy(), ann=ann)
+
+
+def test_shift1m_graph_rows_and_connectivity(shift):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order
+    base, g, index = shift["base"], shift["graph"], shift["index"]
+    n, R = g.shape
+    assert index.medoid == oracle.medoid(base)
+    rows = np.random.default_rng(21).choice(n, N_SAMPLE_ROWS, replace=False)
+    ids, d2 = oracle.knn(base, base[rows], 129)
+    for r, p in enumerate(rows):
+        keep = ids[r] != p
+        cid, cd2 = ids[r][keep][:128], d2[r][keep][:128]
+        sub = np.concatenate([base[p:p + 1], base[cid]])
+        cand = np.full((sub.shape[0], 128), -1, np.int32)
+        cand[0] = np.arange(1, 129, dtype=np.int32)
+        dd = np.zeros((sub.shape[0], 128))
+        dd[0] = cd2
+        pr = oracle.alpha_prune(sub, cand, dd, R, 1.2)[0]
+        want = np.where(pr >= 0, cid[np.maximum(pr - 1, 0)], -1)
+        assert (g[p, :R - 2] == want[:R - 2]).all(), p
+    src = np.repeat(np.arange(n), R)
+    dst = g.reshape(-1)
+    ok = dst >= 0
+    A = sp.csr_matrix((np.ones(ok.sum(), np.int8), (src[ok], dst[ok])), shape=(n, n))
+    assert breadth_first_order(A, index.medoid, return_predecessors=False).shape[0] == n
+    assert breadth_first_order(A.T.tocsr(), index.medoid, return_predecessors=False).shape[0] == n
+
+
+def test_shift1m_gate_search_in_the_bench_configuration(shift):
+    from tests.common import near_tie_certificate
+    ann = shift["ann"]
+    from paper_2506_15986_amd import gate
+    base, q, g = shift["base"], shift["q"], shift["graph"]
+    bd, qd, index = shift["bd"], shift["qd"], shift["index"]
+    nq = q.shape[0]
+    say("case: GATE build on the shifted training queries")
+    tq = torch.from_numpy(synth.train_queries(shift["w"])).to(bd.device)
+    gm = gate.build_gate(index, tq, shift["w"], log=say)
+    del tq
+    kk = torch.full((nq,), 10, dtype=torch.int32, device=bd.device)
+    LL = torch.full((nq,), L_SHIFT, dtype=torch.int32, device=bd.device)
+    ent = gm.select(qd)[0]
+    plan, _ = ann.ann_autotune_search(bd, index.graph, qd, ent, index.medoid, kk, LL, 10, L_SHIFT,
+                                      reps=1)
+    b = ann.QueryBatch(bd, index.graph, index.medoid, qd, kk, LL, 10, plan=plan, model=gm.model)
+    gx = b.graph_exec(ann.ANN_STAGE_ALL)
+    gx.launch()
+    torch.cuda.synchronize()
+    ids, dist = b.ids.cpu().numpy(), b.dist.cpu().numpy()
+    ent_h = b.entry_ids.cpu().numpy()
+    say("case: sampled queries: same plan with traces, against the oracle")
+    s = np.random.default_rng(22).choice(nq, N_SAMPLE_QUERIES, replace=False)
+    sd = torch.from_numpy(s).to(bd.device)
+    sids, sdist, _, str_ = ann.ann_search(bd, index.graph, qd[sd].contiguous(),
+                                          b.entry_ids[sd].contiguous(), index.medoid, 10, L_SHIFT,
+                                          k_max=10, plan=plan, trace_cap=1024)
+    torch.cuda.synchronize()
+    sids, sdist, str_ = sids.cpu().numpy(), sdist.cpu().numpy(), str_.cpu().numpy()
+    assert (sids == ids[s]).all()                 # a query's result does not depend on its batch
+    ref = oracle.search(base, g, q[s], ent_h[s], 10, L_SHIFT, trace_cap=1024)
+    uncertified = 0
+    for i in range(len(s)):
+        if (str_[i] == ref["trace"][i]).all():
+            rd = ref["d2"][i]
+            assert np.all(np.abs(sdist[i].astype(np.float64) - rd) <= 1e-5 * np.maximum(rd, 1e-6))
+            for t in range(10):
+                if sids[i, t] != ref["ids"][i, t]:
+                    row = list(ref["ids"][i])
+                    assert sids[i, t] in row
+                    assert abs(rd[row.index(sids[i, t])] - rd[t]) <= 1e-5 * rd[t]
+        elif not near_tie_certificate(base, g, q[s[i]], ent_h[s[i]], L_SHIFT, str_[i],
+                                      ref["trace"][i]):
+            uncertified += 1
+    assert uncertified == 0
+    say("case: whole-batch properties")
+    exact = ((base[ids.reshape(-1)].astype(np.float64) -
+              np.repeat(q, 10, axis=0).astype(np.float64)) ** 2).sum(1).reshape(nq, 10)
+    assert np.all(np.abs(dist - exact) <= 1e-5 * np.maximum(exact, 1e-6))
+    assert ((dist[:, 1:] > dist[:, :-1]) |
+            ((dist[:, 1:] == dist[:, :-1]) & (ids[:, 1:] > ids[:, :-1]))).all()
+    gt, _ = ann.ann_gt_knn(bd, qd, 10)
+    rec = (ids[:, :, None] == gt.cpu().numpy()[:, None, :]).any(-1).mean()
+    say("recall@10 at L=%d: %.4f" % (L_SHIFT, rec))
+    assert rec >= 0.94
+    gx.close()
