@@ -91,6 +91,19 @@ def measured_traffic(workload: str, L: int, nq: int, plan: dict):
     return None
 
 
+def host_cpu() -> dict:
+    """Host processor model and online core count (from /proc/cpuinfo)."""
+    model, n = "", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = model or line.split(":", 1)[1].strip()
+                n += 1
+    except OSError:
+        pass
+    return dict(model=model, logical_cpus=n or os.cpu_count())
+
+
 def recall_at(ids: np.ndarray, truth: np.ndarray, k: int = 10) -> np.ndarray:
     """Eq. 1 recall per query, ground truth ordered by (distance, id)."""
     hit = (ids[:, :k, None] == truth[:, None, :k]).any(-1)
@@ -259,7 +272,7 @@ def main():
         # exact distance and hop counts of the same searches: a filter large
         # enough not to forget (only the executed count depends on the filter)
         exact = ann.make_plan(**dict(plan.as_dict(), visited_log2=13, filter=ann.ANN_FILTER_ID32,
-                                     waves_per_block=1))
+                                     waves_per_block=1, waves_per_query=1))
         e = b.entry_ids if model is not None else entry
         if state is not None and state.get("exact_%s" % label):
             ex = state["exact_%s" % label]     # counted by the run that saved the state
@@ -410,7 +423,8 @@ def main():
                    sample="all %d queries x %d passes, %s entries (GPU-selected), L=%d, k=%d, "
                           "FP64 search only" % (nq, tot_q // nq, "GATE" if head is gres else
                                                 "medoid", L_cpu, k),
-                   one_thread=dict(value=round(m1 / t1, 2), sample="first %d queries" % m1))
+                   one_thread=dict(value=round(m1 / t1, 2), sample="first %d queries" % m1),
+                   host=host_cpu())
         log("cpu oracle: %d queries in %.1fs on %d threads -> %.1f QPS; 1 thread %.1f QPS" %
             (tot_q, tot_t, cores, tot_q / tot_t, m1 / t1))
 

@@ -186,42 +186,40 @@ struct Visited {
         return true;
     }
 
+    // 16-bit halves are tested two at a time (SWAR): a half of x is zero
+    // exactly when its bit 15 survives (x - 0x00010001) & ~x; a borrow into
+    // the upper half only arises when the lower half is zero, which is
+    // checked first.
+    __device__ static inline uint32_t zero_halves(uint32_t x)
+    {
+        return (x - 0x00010001u) & ~x & 0x80008000u;
+    }
+
     __device__ inline bool insert_tag(uint32_t id, bool &lost) const
     {
         const uint32_t h = (id * kHashMul) & hmask;
         const uint32_t set = h >> tag_bits;
         const uint32_t tag = h & ((1u << tag_bits) - 1u);
+        const uint32_t rep = tag * 0x00010001u;
         uint32_t *w = t + 2 * set;
 #pragma unroll 1
         for (int it = 0; it < 8; ++it) {
             const uint32_t w0 = __atomic_load_n(&w[0], __ATOMIC_RELAXED);
             const uint32_t w1 = __atomic_load_n(&w[1], __ATOMIC_RELAXED);
-            if ((w0 & 0xFFFFu) == tag || (w0 >> 16) == tag || (w1 & 0xFFFFu) == tag ||
-                (w1 >> 16) == tag)
-                return false;
-            // first free way, else evict the way picked by the tag's low bits
-            uint32_t *a;
-            uint32_t old, nw;
-            if ((w0 & 0xFFFFu) == kTagEmpty) {
-                a = &w[0]; old = w0; nw = (w0 & 0xFFFF0000u) | tag;
-            } else if ((w0 >> 16) == kTagEmpty) {
-                a = &w[0]; old = w0; nw = (w0 & 0xFFFFu) | (tag << 16);
-            } else if ((w1 & 0xFFFFu) == kTagEmpty) {
-                a = &w[1]; old = w1; nw = (w1 & 0xFFFF0000u) | tag;
-            } else if ((w1 >> 16) == kTagEmpty) {
-                a = &w[1]; old = w1; nw = (w1 & 0xFFFFu) | (tag << 16);
-            } else {
-                const uint32_t way = tag & 3u;
-                a = &w[way >> 1];
-                old = (way >> 1) ? w1 : w0;
-                nw = (way & 1u) ? ((old & 0xFFFFu) | (tag << 16)) : ((old & 0xFFFF0000u) | tag);
-                if (atomicCAS(a, old, nw) == old) {
-                    lost = true;
-                    return true;
-                }
-                continue;
+            if (zero_halves(w0 ^ rep) | zero_halves(w1 ^ rep)) return false;
+            // way: first empty half (an empty half holds 0xFFFF), else evict
+            // the way picked by the tag's low bits
+            const uint32_t e0 = zero_halves(~w0), e1 = zero_halves(~w1);
+            const uint32_t way = e0 ? ((e0 & 0x8000u) ? 0u : 1u)
+                                    : (e1 ? ((e1 & 0x8000u) ? 2u : 3u) : (tag & 3u));
+            const bool evict = (e0 | e1) == 0u;
+            const uint32_t old = (way & 2u) ? w1 : w0;
+            const uint32_t nw = (way & 1u) ? ((old & 0xFFFFu) | (tag << 16))
+                                           : ((old & 0xFFFF0000u) | tag);
+            if (atomicCAS(&w[way >> 1], old, nw) == old) {
+                if (evict) lost = true;
+                return true;
             }
-            if (atomicCAS(a, old, nw) == old) return true;
         }
         lost = true;
         return true;

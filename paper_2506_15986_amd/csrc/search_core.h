@@ -131,33 +131,52 @@ struct Searcher {
     template <int W = 1>
     __device__ void distances(int m, int w = 0)
     {
+        if (chunks == G * CPL)
+            distances_impl<W, true>(m, w);
+        else
+            distances_impl<W, false>(m, w);
+    }
+
+    // FULL: every lane's CPL chunks lie inside the vector (dim == 4 * G * CPL),
+    // so loads and sums need no per-lane bounds test.  A batch slot row whose
+    // candidates all lie past m is skipped (a uniform test); inside a partly
+    // valid row, lanes past m load the row's first candidate again and drop
+    // the result.
+    template <int W, bool FULL>
+    __device__ void distances_impl(int m, int w)
+    {
         const int lane = beam::lane_id();
         const int gi = lane / G, gl = lane % G;
         for (int b0 = w * VPB * U; b0 < m; b0 += W * VPB * U) {
             float4 xv[U][CPL];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                int c = b0 + u * VPB + gi;
-                bool ok = c < m;
-                uint32_t id = ok ? si[c] : 0u;
-                const float4 *row = base4 + (size_t)id * chunks;
+                const int cb = b0 + u * VPB;
+                if (cb < m) {
+                    const int c = cb + gi;
+                    const uint32_t id = si[c < m ? c : cb];
+                    const float4 *row = base4 + (size_t)id * chunks;
 #pragma unroll
-                for (int t = 0; t < CPL; ++t) {
-                    int ch = gl + G * t;
-                    xv[u][t] = (ok && ch < chunks) ? row[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    for (int t = 0; t < CPL; ++t) {
+                        const int ch = gl + G * t;
+                        xv[u][t] = (FULL || ch < chunks) ? row[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                D acc = 0;
+                const int cb = b0 + u * VPB;
+                if (cb < m) {
+                    D acc = 0;
 #pragma unroll
-                for (int t = 0; t < CPL; ++t) {
-                    const int ch = gl + G * t;
-                    if (ch < chunks) acc += partial(xv[u][t], ql[ch]);
+                    for (int t = 0; t < CPL; ++t) {
+                        const int ch = gl + G * t;
+                        if (FULL || ch < chunks) acc += partial(xv[u][t], ql[ch]);
+                    }
+                    acc = beam::group_sum<G>(acc);
+                    const int c = cb + gi;
+                    if (gl == 0 && c < m) sk[c] = KT::of(METRIC == beam::L2 ? acc : -acc);
                 }
-                acc = beam::group_sum<G>(acc);
-                int c = b0 + u * VPB + gi;
-                if (gl == 0 && c < m) sk[c] = KT::of(METRIC == beam::L2 ? acc : -acc);
             }
         }
         beam::wave_sync();
