@@ -138,7 +138,7 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
                hidden: int = 128, dout: int = 64, epochs: int = 20, batch: int = 1024,
                lr: float = 1e-3, tau: float = 0.07, s: int = 16, L_h: int = 32,
                theta: float = -math.inf, train: bool = True, holdout: float = 0.1,
-               log=print) -> Gate:
+               init: str = "random", log=print) -> Gate:
     """Trains the towers on the first (1 - holdout) of the training queries
     (contrastive loss, Adam), embeds the hubs, builds the navigation graph and
     reports top-1 label agreement on the trained and the held-out queries."""
@@ -149,6 +149,8 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     hub_in, labels = data.hub_in, data.labels
     qp = synth.tower_init(w, [(hidden, d), (dout, hidden)])
     hp = synth.tower_init(w, [(hidden, hub_in.shape[1]), (dout, hidden)])
+    if init == "tied":
+        qp, hp = tied_init(qp, hub_in.cpu().numpy(), d)
     qt = ann.Tower(*qp, device=dev, in_scale=data.scale)
     ht = ann.Tower(*hp, device=dev)
     t = time.time()
@@ -190,6 +192,20 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     log("entry model: top-1 agreement with labels: train %.3f, held-out %s" %
         (info["train_top1"], "%.3f" % info["val_top1"] if n_hold else "-"))
     return Gate(qt, ht, data.hub_ids, hub_in, hemb, hg, hub_entry, model, info)
+
+
+def tied_init(qp, hub_in: np.ndarray, d: int):
+    """Siamese start for the two towers: the hub tower's weights on the hub
+    vector equal the query tower's, its weights on the topology features start
+    at zero, and the first-layer bias centres the (scaled) inputs on the mean
+    hub vector.  A query and a hub vector then get the same embedding, so
+    cosine order starts from the geometry of the data and training adjusts
+    it.  qp: the query tower's (W1, b1, W2, b2) as drawn."""
+    W1, b1, W2, b2 = [np.asarray(a, np.float32) for a in qp]
+    centre = hub_in[:, :d].astype(np.float64).mean(0)
+    b1c = (b1.astype(np.float64) - W1.astype(np.float64) @ centre).astype(np.float32)
+    W1h = np.concatenate([W1, np.zeros((W1.shape[0], hub_in.shape[1] - d), np.float32)], 1)
+    return (W1, b1c, W2, b2), (W1h, b1c.copy(), W2.copy(), b2.copy())
 
 
 def build_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
