@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -405,6 +407,31 @@ class EntryModel:
                                  int(hub_entry), int(medoid), int(L_h), float(theta),
                                  hub_plan if hub_plan is not None else ann_search_plan())
         self._ws = None
+
+    def tune_L_h(self, sample_queries, agree: float = 0.995, ladder=(8, 12, 16, 24, 32, 48, 64)):
+        """Smallest hub-search width whose best hub matches the exact cosine
+        argmax over all hubs for at least `agree` of the sample queries (the
+        argmax is taken on the host from the embeddings the towers produce).
+        Sets and returns it."""
+        qe = self.qtower.forward(sample_queries).cpu().numpy().astype(np.float64)
+        he = self.hub_emb.cpu().numpy().astype(np.float64)
+        cos = qe @ he.T
+        best = cos.max(1)
+        rows = np.arange(qe.shape[0])
+        choice, rates = int(ladder[-1]), []
+        for L in ladder:
+            self.c.L_h = int(L)
+            self.c.hub_plan = ann_search_plan()
+            _, _, bh = ann_entry_select(self, sample_queries, want_score=True)
+            # a tie in cosine counts as agreement
+            ok = float((np.abs(cos[rows, bh.cpu().numpy()] - best) <= 1e-6).mean())
+            rates.append((int(L), round(ok, 5)))
+            if ok >= agree:
+                choice = int(L)
+                break
+        self.c.L_h = choice
+        self.L_h_rates = rates
+        return choice
 
     def tune_hub_plan(self, sample_queries, reps: int = 3):
         """Autotunes the hub-graph search on the embeddings of sample queries

@@ -88,6 +88,24 @@ __device__ inline int lower_bound(const K *ak, const uint32_t *ai, int cnt, K k,
     return lo;
 }
 
+// The same count with a step count that depends on cnt only (uniform across
+// the wavefront): steps of 2^t from the largest power of two <= cnt down to
+// 1, each adding its step when the entry ending that step is below the key.
+// Branch-free per lane (probes past cnt are clamped and ignored).
+template <typename K>
+__device__ inline int lower_bound_uniform(const K *ak, const uint32_t *ai, int cnt, K k, uint32_t id)
+{
+    int lo = 0;
+    if (cnt <= 0) return 0;
+    for (int step = 1 << (31 - __builtin_clz((unsigned)cnt)); step > 0; step >>= 1) {
+        const int probe = lo + step - 1;
+        const int j = probe < cnt ? probe : cnt - 1;
+        const bool below = probe < cnt && key_less(ak[j], ai[j], k, id);
+        lo += below ? step : 0;
+    }
+    return lo;
+}
+
 // value of v in lane t (t uniform across the wavefront)
 __device__ inline uint32_t readlane(uint32_t v, int t)
 {

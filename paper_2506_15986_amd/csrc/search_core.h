@@ -220,7 +220,7 @@ struct Searcher {
         int pos = 0;
         bool dup = false;
         if (valid) {
-            pos = beam::lower_bound(ak, ai, cnt, kk, ii);
+            pos = beam::lower_bound_uniform(ak, ai, cnt, kk, ii);
             if (pos < cnt && ak[pos] == kk && (ai[pos] & beam::kIdMask) == ii) dup = true;
         }
         valid = valid && !dup;

@@ -138,7 +138,7 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
                hidden: int = 128, dout: int = 64, epochs: int = 20, batch: int = 1024,
                lr: float = 1e-3, tau: float = 0.07, s: int = 16, L_h: int = 32,
                theta: float = -math.inf, train: bool = True, holdout: float = 0.1,
-               init: str = "random", log=print) -> Gate:
+               init: str = "random", tune_L_h: bool = True, log=print) -> Gate:
     """Trains the towers on the first (1 - holdout) of the training queries
     (contrastive loss, Adam), embeds the hubs, builds the navigation graph and
     reports top-1 label agreement on the trained and the held-out queries."""
@@ -180,6 +180,9 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     hg, hub_entry = ann.ann_navgraph_build(hemb, s)
     model = ann.EntryModel(qt, hemb, hg, data.hub_ids, hub_entry, index.medoid, L_h=L_h,
                            theta=theta)
+    if tune_L_h:
+        info["L_h"] = model.tune_L_h(train_q[:min(nt, 10000)])
+        info["L_h_agreement"] = model.L_h_rates
     info["hub_plan"] = model.tune_hub_plan(train_q[:min(nt, 10000)]).as_dict()
     # label agreement: does the query tower pick the label hub?
     m = min(nt, 10000)

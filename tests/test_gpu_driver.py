@@ -170,3 +170,22 @@ def test_autotune_on_float_data_and_a_tuned_hub_plan():
     rows = np.arange(len(b0))
     assert (np.abs(cos[rows, b0] - cos[rows, b1]) <= 1e-5).all()
     assert (b0 == b1).mean() >= 0.98
+
+
+def test_tune_hub_search_width():
+    # the chosen width's best hubs match the exact cosine argmax on the sample
+    ann = _ann()
+    ix = tiny_index()
+    model = _model(ix, L_h=32)
+    q = _dev(ix["q"])
+    say("case: hub-search width tuning")
+    L = model.tune_L_h(q, agree=0.99, ladder=(4, 8, 16, 32, 64))
+    assert L in (4, 8, 16, 32, 64) and model.c.L_h == L
+    rates = dict(model.L_h_rates)
+    assert rates[L] >= 0.99 or L == 64
+    assert all(r < 0.99 for l, r in rates.items() if l < L)
+    _, _, bh = ann.ann_entry_select(model, q, want_score=True)
+    qe = model.qtower.forward(q).cpu().numpy().astype(np.float64)
+    cos = qe @ model.hub_emb.cpu().numpy().astype(np.float64).T
+    hit = np.abs(cos[np.arange(len(qe)), bh.cpu().numpy()] - cos.max(1)) <= 1e-6
+    assert hit.mean() >= 0.99 or L == 64
