@@ -182,18 +182,27 @@ struct Searcher {
         beam::wave_sync();
     }
 
-    // first pool position at or after `from` whose entry is not expanded, or -1
-    __device__ int next_unexpanded(int from) const
+    // first two pool positions at or after `from` whose entries are not
+    // expanded (-1 when missing): one ballot usually yields both
+    __device__ void next_two_unexpanded(int from, int &first, int &second) const
     {
         const int lane = beam::lane_id();
         const uint32_t *ai = ids(cur);
+        first = -1;
+        second = -1;
         for (int b = from; b < cnt; b += 64) {
             const int j = b + lane;
             const bool un = j < cnt && !(ai[j] & beam::kExpanded);
-            const uint64_t bal = __ballot(un);
-            if (bal) return b + __ffsll((unsigned long long)bal) - 1;
+            uint64_t bal = __ballot(un);
+            if (!bal) continue;
+            if (first < 0) {
+                first = b + __ffsll((unsigned long long)bal) - 1;
+                bal &= bal - 1;
+                if (!bal) continue;
+            }
+            second = b + __ffsll((unsigned long long)bal) - 1;
+            return;
         }
-        return -1;
     }
 
     // Merges the m new keys (sk/si) into the pool.  Updates the cursor and,
@@ -300,7 +309,8 @@ struct Searcher {
         uint32_t pf_id = beam::kEmpty;
         int pf_nb = -1;
         for (;;) {
-            const int ppos = next_unexpanded(cursor);
+            int ppos, npos;
+            next_two_unexpanded(cursor, ppos, npos);
             if (ppos < 0) break;
             cursor = ppos;
             const uint32_t p = ids(cur)[ppos] & beam::kIdMask;
@@ -309,7 +319,6 @@ struct Searcher {
                 nb = pf_nb;
             else if (lane < R)
                 nb = graph[(size_t)p * R + lane];
-            const int npos = next_unexpanded(ppos + 1);
             K nkey = KT::kMax;
             uint32_t nid = beam::kEmpty;
             pf_id = beam::kEmpty;
@@ -379,7 +388,8 @@ struct Searcher {
         for (;;) {
             if (w == 0) {
                 int m = -1;
-                const int ppos = next_unexpanded(cursor);
+                int ppos, npos;
+                next_two_unexpanded(cursor, ppos, npos);
                 if (ppos >= 0) {
                     cursor = ppos;
                     const uint32_t p = ids(cur)[ppos] & beam::kIdMask;
@@ -388,7 +398,6 @@ struct Searcher {
                         nb = pf_nb;
                     else if (lane < R)
                         nb = graph[(size_t)p * R + lane];
-                    const int npos = next_unexpanded(ppos + 1);
                     nkey = KT::kMax;
                     nid = beam::kEmpty;
                     pf_id = beam::kEmpty;
