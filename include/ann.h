@@ -184,6 +184,33 @@ ann_status ann_build_graph(const float *base, int64_t n, int32_t dim, int32_t kn
                            float alpha, int32_t *graph, int32_t *medoid, int32_t *bridges,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* The same pipeline with candidate lists drawn from overlapping groups, for
+ * indexes too large for an all-pairs kNN (not a step of the paper, which
+ * assumes a built proximity graph: a construction shortcut for the 10M-point
+ * workload).  groups is n x n_member int32 (device): row i lists the groups
+ * of point i, column 0 its home group in [0, n_groups), further columns
+ * other groups or -1 (a repeated label counts once).  The candidates of
+ * point i are the exact knn_k nearest, by (squared L2, id), among the points
+ * whose row lists i's home group, i excluded; fewer (then -1 / +inf padded)
+ * when that set is smaller.  Then alpha pruning, the medoid and the
+ * connectivity repair as ann_build_graph; the repair's bridge to an
+ * unreached point is always the argmin over all eligible points (a full
+ * scan), since the candidate lists are not the global neighbours.  Cost:
+ * the sum over groups of (home points x members).  The labels are read on
+ * the host (the call synchronises).
+ *   workspace  ann_build_graph_partitioned_workspace_size(n, dim, knn_k, R,
+ *              largest member set, largest home set) bytes
+ * Errors: EINVAL for a home label outside [0, n_groups), another label
+ * outside [-1, n_groups), n_member < 1, or a workspace that is too small. */
+size_t ann_build_graph_partitioned_workspace_size(int64_t n, int32_t dim, int32_t knn_k, int32_t R,
+                                                  int64_t max_members, int64_t max_home);
+
+ann_status ann_build_graph_partitioned(const float *base, int64_t n, int32_t dim, int32_t knn_k,
+                                       int32_t R, float alpha, const int32_t *groups,
+                                       int32_t n_member, int32_t n_groups, int32_t *graph,
+                                       int32_t *medoid, int32_t *bridges, void *workspace,
+                                       size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Hub nodes and their topology features (hub extraction and feature         */
 /* distillation sections).                                                   */

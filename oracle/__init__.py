@@ -127,6 +127,41 @@ def build_graph(base, knn_k: int, R: int, alpha: float):
     return g, m, nf, nr, cand, cd2
 
 
+def knn_in_home_group(base, groups, k: int):
+    """Candidate lists restricted to overlapping groups (a construction
+    shortcut for large indexes; the paper assumes the proximity graph is
+    given).  groups is n x m: row p lists p's groups, column 0 its home
+    group, -1 = none.  The list of p holds the k nearest by (d2, id) among
+    the points q != p whose row lists p's home group; -1 / +inf padded.
+    Returns (ids int32, d2 float64)."""
+    base = _f32(base)
+    groups = np.asarray(groups).reshape(base.shape[0], -1)
+    n = base.shape[0]
+    ids = np.full((n, k), -1, np.int32)
+    dd = np.full((n, k), np.inf)
+    for g in np.unique(groups[:, 0]):
+        mem = np.flatnonzero((groups == g).any(axis=1)).astype(np.int32)
+        home = np.flatnonzero(groups[:, 0] == g)
+        kk = min(k + 1, len(mem))
+        li, ld = knn(base[mem], base[home], kk)
+        for r, p in enumerate(home):
+            keep = mem[li[r]] != p
+            got = mem[li[r][keep]][:k]
+            ids[p, :len(got)] = got
+            dd[p, :len(got)] = ld[r][keep][:k]
+    return ids, dd
+
+
+def build_graph_grouped(base, groups, knn_k: int, R: int, alpha: float):
+    """build_graph with the candidate lists of knn_in_home_group.
+    Returns (graph, medoid, n_forward, n_reverse, cand_ids, cand_d2)."""
+    cand, cd2 = knn_in_home_group(base, groups, knn_k)
+    g = alpha_prune(base, cand, cd2, R, alpha)
+    m = medoid(base)
+    g, nf, nr = repair(base, g, m)
+    return g, m, nf, nr, cand, cd2
+
+
 def search(base, graph, queries, entry, k, L, k_max: int | None = None,
            trace_cap: int = 0, want_visited: bool = False, threads: int = 0):
     """Best-first beam search (Algorithm 1 reading).

@@ -251,6 +251,55 @@ def ann_build_graph(base: torch.Tensor, knn_k: int, R: int, alpha: float, stream
     return graph, int(m.value), (int(br[0]), int(br[1]))
 
 
+_sig("ann_build_graph_partitioned_workspace_size", _SZ, _I64, _I32, _I32, _I32, _I64, _I64)
+_sig("ann_build_graph_partitioned", _I32, _P, _I64, _I32, _I32, _I32, _F32, _P, _I32, _I32, _P,
+     ctypes.POINTER(_I32), ctypes.POINTER(_I32 * 2), _P, _SZ, _P)
+
+
+def ann_build_graph_partitioned_workspace_size(n: int, dim: int, knn_k: int, R: int,
+                                               max_members: int, max_home: int) -> int:
+    return int(_lib.ann_build_graph_partitioned_workspace_size(n, dim, knn_k, R, max_members,
+                                                               max_home))
+
+
+def group_sizes(groups: np.ndarray, n_groups: int):
+    """(members per group, home points per group) of an n x n_member label
+    table (column 0 the home group, -1 = none, a repeated label counts once)."""
+    g = np.asarray(groups).reshape(groups.shape[0], -1)
+    home = np.bincount(g[:, 0], minlength=n_groups)
+    first = np.ones(g.shape, bool)
+    for c in range(1, g.shape[1]):
+        first[:, c] = (g[:, c] >= 0) & (g[:, :c] != g[:, c:c + 1]).all(axis=1)
+    mem = np.bincount(g[first], minlength=n_groups)
+    return mem, home
+
+
+def ann_build_graph_partitioned(base: torch.Tensor, knn_k: int, R: int, alpha: float,
+                                groups: torch.Tensor, n_groups: int, stream=None):
+    """kNN of each point among the members of its home group -> alpha prune
+    -> medoid -> repair.  groups: n x n_member int32 (column 0 the home
+    group).  Returns (graph int32 [n,R], medoid, (forward, reverse bridges))."""
+    _dev(base, torch.float32)
+    _dev(groups, torch.int32)
+    n, dim = base.shape
+    if groups.dim() == 1:
+        groups = groups.reshape(n, 1)
+    n_member = groups.shape[1]
+    mem, home = group_sizes(groups.cpu().numpy(), n_groups)
+    graph = torch.empty((n, R), dtype=torch.int32, device=base.device)
+    nb = max(256, ann_build_graph_partitioned_workspace_size(n, dim, knn_k, R, int(mem.max()),
+                                                             int(home.max())))
+    ws = torch.empty(nb, dtype=torch.uint8, device=base.device)
+    m = _I32(-1)
+    br = (_I32 * 2)()
+    _check(_lib.ann_build_graph_partitioned(_ptr(base), n, dim, knn_k, R, float(alpha),
+                                            _ptr(groups), int(n_member), int(n_groups),
+                                            _ptr(graph), ctypes.byref(m), ctypes.byref(br),
+                                            _ptr(ws), ws.numel(), _stream(stream)))
+    del ws
+    return graph, int(m.value), (int(br[0]), int(br[1]))
+
+
 def ann_select_hubs(base: torch.Tensor, n_hubs: int, iters: int, init_ids: torch.Tensor,
                     stream=None):
     """Lloyd k-means + Definition 3 hubs.  Returns (hub_ids int32, centroids

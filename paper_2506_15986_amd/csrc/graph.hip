@@ -24,6 +24,9 @@
 
 #include "common.h"
 #include "internal.h"
+
+#include <algorithm>
+#include <vector>
 #include "knn.h"
 
 namespace ann {
@@ -402,18 +405,6 @@ size_t scan_temp_bytes(int64_t n)
     return tmp;
 }
 
-size_t build_graph_ws(int64_t n, int dim, int K, int R)
-{
-    size_t b = knn_workspace(n, n, dim, K);
-    b += round_up((size_t)n * K * 4, 256) + round_up((size_t)n * K * 8, 256);  // cand ids, d2
-    b += round_up((size_t)n * 4, 256) * 2;                                    // mark, queue
-    b += round_up((size_t)(n + 1) * 8, 256) * 3;                              // cnt, off, fill
-    b += round_up((size_t)n * R * 4, 256);                                    // reverse adj
-    b += round_up(scan_temp_bytes(n) + 256, 256);
-    b += round_up((size_t)dim * 8, 256) + round_up(4096 * sizeof(DKey), 256) * 2;
-    b += 4096;
-    return b;
-}
 
 ann_status medoid_run(const float *base, int64_t n, int dim, double *partial_cols, double *mu,
                       void *partial_keys, void *best_key, int32_t *medoid_host, hipStream_t st)
@@ -450,6 +441,177 @@ size_t medoid_ws(int64_t n, int dim)
 
 using namespace ann;
 
+namespace ann {
+namespace {
+
+// Buffers of the steps after the candidate lists: pruning, medoid, repair.
+struct TailBufs {
+    int32_t *mark, *queue;
+    int64_t *cnt, *off, *fill;
+    int32_t *radj;
+    void *tmp;
+    size_t tmp_bytes;
+    double *mu;
+    DKey *partial, *best;
+    RepairState *rst;
+    double *med_cols;    // MED_ROWS-chunk column sums for the medoid
+};
+
+size_t tail_ws(int64_t n, int dim, int R)
+{
+    size_t b = round_up((size_t)n * 4, 256) * 2;                                    // mark, queue
+    b += round_up((size_t)(n + 1) * 8, 256) * 3;                                    // cnt, off, fill
+    b += round_up((size_t)n * R * 4, 256);                                          // reverse adj
+    b += round_up(scan_temp_bytes(n) + 256, 256);
+    b += round_up((size_t)dim * 8, 256) + round_up(4096 * sizeof(DKey), 256) * 2;
+    b += round_up(sizeof(RepairState), 256);
+    b += round_up((size_t)((n + MED_ROWS - 1) / MED_ROWS) * dim * 8, 256);
+    return b + 1024;
+}
+
+TailBufs take_tail(Carve &cv, int64_t n, int dim, int R)
+{
+    TailBufs t{};
+    t.mark = cv.take<int32_t>((size_t)n);
+    t.queue = cv.take<int32_t>((size_t)n);
+    t.cnt = cv.take<int64_t>((size_t)n + 1);
+    t.off = cv.take<int64_t>((size_t)n + 1);
+    t.fill = cv.take<int64_t>((size_t)n + 1);
+    t.radj = cv.take<int32_t>((size_t)n * R);
+    t.tmp_bytes = scan_temp_bytes(n) + 256;
+    t.tmp = cv.take<unsigned char>(t.tmp_bytes);
+    t.mu = cv.take<double>((size_t)dim);
+    t.partial = cv.take<DKey>(4096);
+    t.best = cv.take<DKey>(4096);
+    t.rst = cv.take<RepairState>(1);
+    t.med_cols = cv.take<double>((size_t)((n + MED_ROWS - 1) / MED_ROWS) * dim);
+    return t;
+}
+
+// alpha pruning of the candidate lists, medoid, connectivity repair.
+// cand_global: the lists are each point's global nearest neighbours, so the
+// first eligible entry of an unreached point's list is its bridge; otherwise
+// every bridge comes from a full scan.
+ann_status graph_tail(const float *base, int64_t n, int dim, int32_t *cand, double *cd2, int K,
+                      int R, float alpha, int32_t *graph, int32_t *medoid, int32_t *bridges,
+                      const TailBufs &t, hipStream_t st, bool cand_global)
+{
+    const double a2 = (double)alpha * (double)alpha;
+    hipLaunchKernelGGL(prune_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, dim,
+                       cand, cd2, K, R, a2, graph);
+    ANN_LAUNCHED();
+    int32_t med = -1;
+    ann_status s = medoid_run(base, n, dim, t.med_cols, t.mu, t.partial, t.best, &med, st);
+    if (s != ANN_OK) return s;
+    int32_t nb[2] = {0, 0};
+    for (int phase = 0; phase < 2; ++phase) {
+        if (phase == 1) {
+            ANN_HIP(hipMemsetAsync(t.cnt, 0, sizeof(int64_t) * (n + 1), st));
+            ANN_HIP(hipMemsetAsync(t.fill, 0, sizeof(int64_t) * (n + 1), st));
+            int eb = (int)((n * R + 255) / 256);
+            if (eb > 8192) eb = 8192;
+            hipLaunchKernelGGL(indeg_kernel, dim3(eb), dim3(256), 0, st, graph, n, R, t.cnt);
+            ANN_LAUNCHED();
+            size_t tb = t.tmp_bytes;
+            ANN_HIP(hipcub::DeviceScan::ExclusiveSum(t.tmp, tb, t.cnt, t.off, (int)(n + 1), st));
+            hipLaunchKernelGGL(rfill_kernel, dim3(eb), dim3(256), 0, st, graph, n, R, t.off, t.fill,
+                               t.radj);
+            ANN_LAUNCHED();
+        }
+        int ib = (int)((n + 255) / 256);
+        if (ib > 4096) ib = 4096;
+        hipLaunchKernelGGL(init_repair_kernel, dim3(ib), dim3(256), 0, st, t.mark, n, t.queue, med,
+                           t.rst, phase, 1);
+        ANN_LAUNCHED();
+        for (;;) {
+            hipLaunchKernelGGL(repair_driver, dim3(1), dim3(DRV), 0, st, graph, n, R, cand,
+                               cand_global ? K : 0, t.mark,
+                               t.queue, t.off, t.radj, t.rst, phase);
+            ANN_LAUNCHED();
+            RepairState h{};
+            ANN_HIP(hipMemcpyAsync(&h, t.rst, sizeof(h), hipMemcpyDeviceToHost, st));
+            ANN_HIP(hipStreamSynchronize(st));
+            if (h.status == 0) {
+                nb[phase] = h.bridges;
+                break;
+            }
+            // full scan for rst->pending
+            int32_t *u_ptr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(t.rst) +
+                                                         offsetof(RepairState, pending));
+            s = run_argmin_scan(base, n, dim, graph, R, t.mark, phase == 0 ? R - 2 : -1, u_ptr,
+                                t.partial, t.best, st);
+            if (s != ANN_OK) return s;
+            hipLaunchKernelGGL(apply_bridge_kernel, dim3(1), dim3(1), 0, st, graph, R, t.mark,
+                               t.queue, t.best, t.rst, phase);
+            ANN_LAUNCHED();
+        }
+    }
+    *medoid = med;
+    if (bridges) {
+        bridges[0] = nb[0];
+        bridges[1] = nb[1];
+    }
+    return ANN_OK;
+}
+
+// rows[members[r]] -> out row r
+__global__ void gather_rows_kernel(const float *base, int dim, const int32_t *members, int64_t m,
+                                   float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m * dim) return;
+    const int64_t r = i / dim;
+    out[i] = base[(int64_t)members[r] * dim + (i - r * dim)];
+}
+
+// candidate lists of one group's home points (local member indices) -> the
+// global lists, -1 / +inf padded
+__global__ void scatter_cand_kernel(const int32_t *loc_ids, const double *loc_d2, int Kg,
+                                    const int32_t *members, const int32_t *home, int64_t m, int K,
+                                    int32_t *cand, double *cd2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m * K) return;
+    const int64_t r = i / K;
+    const int j = (int)(i - r * K);
+    const int64_t dst = (int64_t)home[r] * K + j;
+    int32_t id = -1;
+    double d = __longlong_as_double(0x7ff0000000000000ll);
+    if (j < Kg) {
+        const int32_t l = loc_ids[r * Kg + j];
+        if (l >= 0) {
+            id = members[l];
+            d = loc_d2[r * Kg + j];
+        }
+    }
+    cand[dst] = id;
+    cd2[dst] = d;
+}
+
+}  // namespace
+
+size_t build_graph_ws(int64_t n, int dim, int K, int R)
+{
+    size_t b = knn_workspace(n, n, dim, K);
+    b += round_up((size_t)n * K * 4, 256) + round_up((size_t)n * K * 8, 256);  // cand ids, d2
+    return b + tail_ws(n, dim, R);
+}
+
+size_t build_partitioned_ws(int64_t n, int dim, int K, int R, int64_t max_mem, int64_t max_home)
+{
+    size_t b = round_up((size_t)n * K * 4, 256) + round_up((size_t)n * K * 8, 256);  // cand, d2
+    b += tail_ws(n, dim, R);
+    b += knn_workspace(max_mem, max_home, dim, K);
+    b += round_up((size_t)max_mem * dim * 4, 256) + round_up((size_t)max_home * dim * 4, 256);
+    b += round_up((size_t)max_mem * 4, 256) + round_up((size_t)max_home * 4, 256) * 2;
+    b += round_up((size_t)max_home * K * 4, 256) + round_up((size_t)max_home * K * 8, 256);
+    return b + 1024;
+}
+
+}  // namespace ann
+
+using namespace ann;
+
 extern "C" ann_status ann_build_graph(const float *base, int64_t n, int32_t dim, int32_t knn_k,
                                       int32_t R, float alpha, int32_t *graph, int32_t *medoid,
                                       int32_t *bridges, void *workspace, size_t ws_bytes,
@@ -473,84 +635,134 @@ extern "C" ann_status ann_build_graph(const float *base, int64_t n, int32_t dim,
     void *knn_ws = cv.take<unsigned char>(kws);
     int32_t *cand = cv.take<int32_t>((size_t)n * K);
     double *cd2 = cv.take<double>((size_t)n * K);
-    int32_t *mark = cv.take<int32_t>((size_t)n);
-    int32_t *queue = cv.take<int32_t>((size_t)n);
-    int64_t *cnt = cv.take<int64_t>((size_t)n + 1);
-    int64_t *off = cv.take<int64_t>((size_t)n + 1);
-    int64_t *fill = cv.take<int64_t>((size_t)n + 1);
-    int32_t *radj = cv.take<int32_t>((size_t)n * R);
-    size_t tmp_bytes = scan_temp_bytes(n) + 256;
-    void *tmp = cv.take<unsigned char>(tmp_bytes);
-    double *mu = cv.take<double>((size_t)dim);
-    DKey *partial = cv.take<DKey>(4096);
-    DKey *best = cv.take<DKey>(4096);
-    RepairState *rst = cv.take<RepairState>(1);
-
-    // 1. exact kNN candidates (self excluded)
+    TailBufs t = take_tail(cv, n, dim, R);
+    // exact kNN candidates (self excluded), then pruning, medoid, repair
     ann_status s = knn_run(base, n, dim, base, n, K, true, cand, nullptr, cd2, knn_ws, kws, st, 0);
     if (s != ANN_OK) return s;
-    // 2. alpha pruning
-    const double a2 = (double)alpha * (double)alpha;
-    hipLaunchKernelGGL(prune_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, dim,
-                       cand, cd2, K, R, a2, graph);
-    ANN_LAUNCHED();
-    // 3. medoid (its scratch reuses the kNN workspace, free again)
-    int32_t med = -1;
+    return graph_tail(base, n, dim, cand, cd2, K, R, alpha, graph, medoid, bridges, t, st, true);
+}
+
+extern "C" size_t ann_build_graph_partitioned_workspace_size(int64_t n, int32_t dim,
+                                                             int32_t knn_k, int32_t R,
+                                                             int64_t max_members, int64_t max_home)
+{
+    if (n < 2 || dim < 1 || knn_k < 1 || R < 3 || max_members < 1 || max_home < 1) return 0;
+    return build_partitioned_ws(n, dim, knn_k, R, max_members, max_home);
+}
+
+extern "C" ann_status ann_build_graph_partitioned(const float *base, int64_t n, int32_t dim,
+                                                  int32_t knn_k, int32_t R, float alpha,
+                                                  const int32_t *groups, int32_t n_member,
+                                                  int32_t n_groups, int32_t *graph,
+                                                  int32_t *medoid, int32_t *bridges,
+                                                  void *workspace, size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(base && groups && graph && medoid && workspace, "a required pointer is NULL");
+    ANN_REQUIRE(n >= 2 && n <= 0x7FFFFFFF, "n must be in [2, 2^31)");
+    ANN_REQUIRE(dim >= 1, "dim must be >= 1");
+    ANN_REQUIRE(R >= 3, "R must be >= 3");
+    ANN_SUPPORTED(R <= 64, "R must be <= 64");
+    ANN_REQUIRE(knn_k >= R - 2 && knn_k <= 1024, "knn_k must be in [R-2, 1024]");
+    ANN_REQUIRE(n_member >= 1, "n_member must be >= 1");
+    ANN_REQUIRE(n_groups >= 1, "n_groups must be >= 1");
+    ANN_REQUIRE(alpha >= 1.0f, "alpha must be >= 1");
+    ANN_REQUIRE(aligned(base, 16), "base must be 16-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t nm = (size_t)n_member;
+    std::vector<int32_t> lab((size_t)n * nm);
+    ANN_HIP(hipMemcpyAsync(lab.data(), groups, sizeof(int32_t) * lab.size(), hipMemcpyDeviceToHost,
+                           st));
+    ANN_HIP(hipStreamSynchronize(st));
+    // member and home lists of every group, each in id order (counting sort)
+    std::vector<int64_t> ms((size_t)n_groups + 1, 0), hs((size_t)n_groups + 1, 0);
+    auto listed_before = [&](int64_t i, size_t c) {
+        for (size_t e = 0; e < c; ++e)
+            if (lab[(size_t)i * nm + e] == lab[(size_t)i * nm + c]) return true;
+        return false;
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t h = lab[(size_t)i * nm];
+        ANN_REQUIRE(h >= 0 && h < n_groups, "home group of point %lld out of range", (long long)i);
+        hs[(size_t)h + 1]++;
+        for (size_t c = 0; c < nm; ++c) {
+            const int32_t g = lab[(size_t)i * nm + c];
+            ANN_REQUIRE(g >= -1 && g < n_groups, "group label of point %lld out of range",
+                        (long long)i);
+            if (g >= 0 && !listed_before(i, c)) ms[(size_t)g + 1]++;
+        }
+    }
+    int64_t max_mem = 1, max_home = 1;
+    for (int g = 0; g < n_groups; ++g) {
+        max_mem = std::max<int64_t>(max_mem, ms[(size_t)g + 1]);
+        max_home = std::max<int64_t>(max_home, hs[(size_t)g + 1]);
+        ms[(size_t)g + 1] += ms[(size_t)g];
+        hs[(size_t)g + 1] += hs[(size_t)g];
+    }
+    ANN_REQUIRE(ws_bytes >= build_partitioned_ws(n, dim, knn_k, R, max_mem, max_home),
+                "workspace too small (largest member set %lld, largest home set %lld)",
+                (long long)max_mem, (long long)max_home);
+    std::vector<int32_t> members((size_t)ms[(size_t)n_groups]), homes((size_t)n);
     {
-        Carve mc{static_cast<unsigned char *>(knn_ws)};
-        int chunks = (int)((n + MED_ROWS - 1) / MED_ROWS);
-        double *pc = mc.take<double>((size_t)chunks * dim);
-        s = medoid_run(base, n, dim, pc, mu, partial, best, &med, st);
-        if (s != ANN_OK) return s;
-    }
-    // 4. repair: forward then reverse
-    int32_t nb[2] = {0, 0};
-    for (int phase = 0; phase < 2; ++phase) {
-        if (phase == 1) {
-            ANN_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (n + 1), st));
-            ANN_HIP(hipMemsetAsync(fill, 0, sizeof(int64_t) * (n + 1), st));
-            int eb = (int)((n * R + 255) / 256);
-            if (eb > 8192) eb = 8192;
-            hipLaunchKernelGGL(indeg_kernel, dim3(eb), dim3(256), 0, st, graph, n, R, cnt);
-            ANN_LAUNCHED();
-            size_t tb = tmp_bytes;
-            ANN_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, off, (int)(n + 1), st));
-            hipLaunchKernelGGL(rfill_kernel, dim3(eb), dim3(256), 0, st, graph, n, R, off, fill, radj);
-            ANN_LAUNCHED();
-        }
-        int ib = (int)((n + 255) / 256);
-        if (ib > 4096) ib = 4096;
-        hipLaunchKernelGGL(init_repair_kernel, dim3(ib), dim3(256), 0, st, mark, n, queue, med, rst,
-                           phase, 1);
-        ANN_LAUNCHED();
-        for (;;) {
-            hipLaunchKernelGGL(repair_driver, dim3(1), dim3(DRV), 0, st, graph, n, R, cand, K, mark,
-                               queue, off, radj, rst, phase);
-            ANN_LAUNCHED();
-            RepairState h{};
-            ANN_HIP(hipMemcpyAsync(&h, rst, sizeof(h), hipMemcpyDeviceToHost, st));
-            ANN_HIP(hipStreamSynchronize(st));
-            if (h.status == 0) {
-                nb[phase] = h.bridges;
-                break;
+        std::vector<int64_t> mp(ms.begin(), ms.end() - 1), hp(hs.begin(), hs.end() - 1);
+        for (int64_t i = 0; i < n; ++i) {
+            homes[(size_t)hp[(size_t)lab[(size_t)i * nm]]++] = (int32_t)i;
+            for (size_t c = 0; c < nm; ++c) {
+                const int32_t g = lab[(size_t)i * nm + c];
+                if (g >= 0 && !listed_before(i, c)) members[(size_t)mp[(size_t)g]++] = (int32_t)i;
             }
-            // full scan for rst->pending
-            int32_t *u_ptr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(rst) +
-                                                         offsetof(RepairState, pending));
-            s = run_argmin_scan(base, n, dim, graph, R, mark, phase == 0 ? R - 2 : -1, u_ptr,
-                                partial, best, st);
-            if (s != ANN_OK) return s;
-            hipLaunchKernelGGL(apply_bridge_kernel, dim3(1), dim3(1), 0, st, graph, R, mark, queue,
-                               best, rst, phase);
-            ANN_LAUNCHED();
         }
     }
-    *medoid = med;
-    if (bridges) {
-        bridges[0] = nb[0];
-        bridges[1] = nb[1];
+    const int K = knn_k;
+    Carve cv{static_cast<unsigned char *>(workspace)};
+    int32_t *cand = cv.take<int32_t>((size_t)n * K);
+    double *cd2 = cv.take<double>((size_t)n * K);
+    TailBufs t = take_tail(cv, n, dim, R);
+    const size_t kws = knn_workspace(max_mem, max_home, dim, K);
+    void *knn_ws = cv.take<unsigned char>(kws);
+    float *mrows = cv.take<float>((size_t)max_mem * dim);
+    float *hrows = cv.take<float>((size_t)max_home * dim);
+    int32_t *mem_d = cv.take<int32_t>((size_t)max_mem);
+    int32_t *home_d = cv.take<int32_t>((size_t)max_home);
+    int32_t *self_d = cv.take<int32_t>((size_t)max_home);
+    int32_t *loc_ids = cv.take<int32_t>((size_t)max_home * K);
+    double *loc_d2 = cv.take<double>((size_t)max_home * K);
+    std::vector<int32_t> selfc((size_t)max_home);
+    // exact kNN of each group's home points among its members (self excluded),
+    // mapped to global ids
+    for (int g = 0; g < n_groups; ++g) {
+        const int64_t m = ms[(size_t)g + 1] - ms[(size_t)g];
+        const int64_t h = hs[(size_t)g + 1] - hs[(size_t)g];
+        if (h == 0) continue;
+        const int32_t *mem = members.data() + ms[(size_t)g];
+        const int32_t *hom = homes.data() + hs[(size_t)g];
+        // position of each home point in the member list (both in id order)
+        for (int64_t r = 0, e = 0; r < h; ++r) {
+            while (mem[e] != hom[r]) ++e;
+            selfc[(size_t)r] = (int32_t)e;
+        }
+        ANN_HIP(hipMemcpyAsync(mem_d, mem, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, st));
+        ANN_HIP(hipMemcpyAsync(home_d, hom, sizeof(int32_t) * (size_t)h, hipMemcpyHostToDevice, st));
+        ANN_HIP(hipMemcpyAsync(self_d, selfc.data(), sizeof(int32_t) * (size_t)h,
+                               hipMemcpyHostToDevice, st));
+        const int Kg = (int)std::min<int64_t>(K, m - 1);
+        if (Kg >= 1) {
+            hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((m * dim + 255) / 256)),
+                               dim3(256), 0, st, base, dim, mem_d, m, mrows);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((h * dim + 255) / 256)),
+                               dim3(256), 0, st, base, dim, home_d, h, hrows);
+            ANN_LAUNCHED();
+            ann_status s = knn_run(mrows, m, dim, hrows, h, Kg, true, loc_ids, nullptr, loc_d2,
+                                   knn_ws, kws, st, 0, self_d);
+            if (s != ANN_OK) return s;
+        }
+        hipLaunchKernelGGL(scatter_cand_kernel, dim3((unsigned)((h * K + 255) / 256)), dim3(256),
+                           0, st, loc_ids, loc_d2, Kg, mem_d, home_d, h, K, cand, cd2);
+        ANN_LAUNCHED();
+        // the staging buffers are rewritten by the next group's copies
+        ANN_HIP(hipStreamSynchronize(st));
     }
-    return ANN_OK;
+    return graph_tail(base, n, dim, cand, cd2, K, R, alpha, graph, medoid, bridges, t, st, false);
 }
 
 extern "C" ann_status ann_medoid(const float *base, int64_t n, int32_t dim, int32_t *medoid,

@@ -113,6 +113,13 @@ __device__ inline void write_rows(const RowState &rs, const Ent *buf, int64_t ro
     }
 }
 
+// base column that query row g must skip (-1: none)
+__device__ inline int64_t self_column(const KnnArgs &a, int64_t g)
+{
+    if (!a.exclude_self || g >= a.rows) return -1;
+    return a.self_col ? (int64_t)a.self_col[g] : g;
+}
+
 // ---------------------------------------------------------------- FP64 engine
 constexpr int F_BN = 64;    // columns per tile
 constexpr int F_DK = 32;    // dims per LDS stage
@@ -133,6 +140,9 @@ __global__ void __launch_bounds__(256) knn_f64_kernel(KnnArgs a)
         rs.thr[t] = knn::ent_max();
         rs.cnt[t] = 0;
     }
+    int64_t selfc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) selfc[i] = self_column(a, row0 + r0 + i);
     __syncthreads();
     for (int64_t col0 = 0; col0 < a.n; col0 += F_BN) {
         double acc[4][4];
@@ -176,7 +186,7 @@ __global__ void __launch_bounds__(256) knn_f64_kernel(KnnArgs a)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 int64_t col = col0 + c0 + k;
-                if (col >= a.n || (a.exclude_self && col == g)) continue;
+                if (col >= a.n || col == selfc[i]) continue;
                 offer(rs, a.buf, g, r0 + i, a.cap, knn::key_of(acc[i][k]), (uint32_t)col);
             }
         }
@@ -225,9 +235,11 @@ __global__ void __launch_bounds__(256) knn_i8_kernel(KnnArgs a)
         areg[s] = v;
     }
     int32_t anorm[4];
+    int64_t selfc[4];
     for (int i = 0; i < 4; ++i) {
         int64_t g = row0 + 16 * w + 4 * (lane >> 4) + i;
         anorm[i] = g < a.rows ? a.qnorm[g] : 0;
+        selfc[i] = self_column(a, g);
     }
     __syncthreads();
     const int chunks16 = a.dim / 16;
@@ -259,7 +271,7 @@ __global__ void __launch_bounds__(256) knn_i8_kernel(KnnArgs a)
                 for (int i = 0; i < 4; ++i) {
                     int lr = 16 * w + 4 * (lane >> 4) + i;
                     int64_t g = row0 + lr;
-                    if (g >= a.rows || (a.exclude_self && col == g)) continue;
+                    if (g >= a.rows || col == selfc[i]) continue;
                     int32_t d2 = anorm[i] + bn - 2 * acc[i];
                     offer(rs, a.buf, g, lr, a.cap, (uint64_t)(uint32_t)d2, (uint32_t)col);
                 }
@@ -312,7 +324,8 @@ ann_status data_is_uint8(const float *x, int64_t count, int *flag_dev, bool *res
 // to out_ids and out_f (float) and/or out_d (double).  Synchronises.
 ann_status knn_run(const float *base, int64_t n, int dim, const float *queries, int64_t rows,
                    int K, bool exclude_self, int32_t *out_ids, float *out_f, double *out_d,
-                   void *ws, size_t ws_bytes, hipStream_t st, int force_engine)
+                   void *ws, size_t ws_bytes, hipStream_t st, int force_engine,
+                   const int32_t *self_col)
 {
     ANN_REQUIRE(ws_bytes >= knn_workspace(n, rows, dim, K), "kNN workspace too small");
     unsigned char *p = static_cast<unsigned char *>(ws);
@@ -350,6 +363,7 @@ ann_status knn_run(const float *base, int64_t n, int dim, const float *queries, 
     a.rows = rows;
     a.K = K;
     a.exclude_self = exclude_self ? 1 : 0;
+    a.self_col = self_col;
     a.buf = buf;
     a.out_ids = out_ids;
     a.out_f = out_f;

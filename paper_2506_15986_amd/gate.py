@@ -49,9 +49,29 @@ class Index:
                               out=out, ws=ws)
 
 
-def build_index(base: torch.Tensor, knn_k: int = 128, R: int = 32, alpha: float = 1.2) -> Index:
+def build_index(base: torch.Tensor, knn_k: int = 128, R: int = 32, alpha: float = 1.2,
+                partitions: int = 0, overlap: int = 2, w: synth.Workload | None = None) -> Index:
+    """The proximity graph: all-pairs exact kNN candidates, or with
+    partitions > 0 candidates from overlapping groups: Lloyd k-means
+    (`partitions` clusters, 10 steps, seeded from the workload) gives the
+    hubs; each point lists its `overlap` nearest hubs, the first being its
+    home group, and its candidates are the exact knn_k nearest among the
+    points that list its home group.  Then alpha pruning, medoid, repair."""
     t = time.time()
-    graph, med, bridges = ann.ann_build_graph(base, knn_k, R, alpha)
+    if partitions > 0:
+        n = base.shape[0]
+        init = torch.from_numpy(synth.kmeans_init(w, n, partitions)).to(base.device)
+        hub_ids, _, _, _ = ann.ann_select_hubs(base, partitions, 10, init)
+        hubs = base[hub_ids.long()].contiguous()
+        groups = torch.empty((n, overlap), dtype=torch.int32, device=base.device)
+        step = 1 << 20
+        for s in range(0, n, step):
+            ids, _ = ann.ann_gt_knn(hubs, base[s:s + step], overlap)
+            groups[s:s + step] = ids
+        graph, med, bridges = ann.ann_build_graph_partitioned(base, knn_k, R, alpha, groups,
+                                                              partitions)
+    else:
+        graph, med, bridges = ann.ann_build_graph(base, knn_k, R, alpha)
     torch.cuda.synchronize()
     return Index(base, graph, med, bridges, R, time.time() - t)
 

@@ -270,3 +270,66 @@ def test_shift1m_gate_search_in_the_bench_configuration(shift):
     say("recall@10 at L=%d: %.4f" % (L_SHIFT, rec))
     assert rec >= 0.94
     gx.close()
+
+
+# ---------------------------------------------------------------------------
+# 1M x 960 (wide vectors, R = 64 from 256-NN): FP64 graph build on the 2^-14
+# grid, then the search kernel in its autotuned plan (several waves per query
+# are among the candidates) against the oracle on sampled queries.
+
+def test_gist1m_graph_rows_and_search_with_tuned_plan():
+    from tests.common import near_tie_certificate
+    ann = _ann()
+    from paper_2506_15986_amd import gate
+    w = synth.WORKLOADS["gist1m"]
+    say("case: gist1m data and graph build (1M x 960, 256-NN, R 64)")
+    base = synth.base(w)
+    q = synth.queries(w)
+    dev = torch.device("cuda:0")
+    bd, qd = torch.from_numpy(base).to(dev), torch.from_numpy(q).to(dev)
+    index = gate.build_index(bd, 256, 64, 1.2)
+    g = index.graph.cpu().numpy()
+    n, R = g.shape
+    say("case: sampled graph rows")
+    assert index.medoid == oracle.medoid(base)
+    rows = np.random.default_rng(31).choice(n, 8, replace=False)
+    ids, d2 = oracle.knn(base, base[rows], 257)
+    for r, p in enumerate(rows):
+        keep = ids[r] != p
+        cid, cd2 = ids[r][keep][:256], d2[r][keep][:256]
+        sub = np.concatenate([base[p:p + 1], base[cid]])
+        cand = np.full((sub.shape[0], 256), -1, np.int32)
+        cand[0] = np.arange(1, 257, dtype=np.int32)
+        dd = np.zeros((sub.shape[0], 256))
+        dd[0] = cd2
+        pr = oracle.alpha_prune(sub, cand, dd, R, 1.2)[0]
+        want = np.where(pr >= 0, cid[np.maximum(pr - 1, 0)], -1)
+        assert (g[p, :R - 2] == want[:R - 2]).all(), p
+    say("case: search with the tuned plan, medoid and random entries")
+    nq, L = q.shape[0], 128
+    ent = np.random.default_rng(32).integers(0, n, nq).astype(np.int32)
+    ent[: nq // 2] = index.medoid
+    ed = torch.from_numpy(ent).to(dev)
+    plan, times = ann.ann_autotune_search(bd, index.graph, qd, ed, index.medoid, 10, L, 10, L, reps=1)
+    say("tuned plan: %s" % plan)
+    assert any(p.waves_per_query > 1 for p, _ in times)
+    s = np.random.default_rng(33).choice(nq, 24, replace=False)
+    sd = torch.from_numpy(s).to(dev)
+    sids, sdist, _, st = ann.ann_search(bd, index.graph, qd[sd].contiguous(), ed[sd].contiguous(),
+                                        index.medoid, 10, L, k_max=10, plan=plan, trace_cap=1024)
+    torch.cuda.synchronize()
+    sids, sdist, st = sids.cpu().numpy(), sdist.cpu().numpy(), st.cpu().numpy()
+    ref = oracle.search(base, g, q[s], ent[s], 10, L, trace_cap=1024)
+    uncertified = 0
+    for i in range(len(s)):
+        if (st[i] == ref["trace"][i]).all():
+            rd = ref["d2"][i]
+            assert np.all(np.abs(sdist[i].astype(np.float64) - rd) <= 1e-5 * np.maximum(rd, 1e-6))
+            for t in range(10):
+                if sids[i, t] != ref["ids"][i, t]:
+                    row = list(ref["ids"][i])
+                    assert sids[i, t] in row
+                    assert abs(rd[row.index(sids[i, t])] - rd[t]) <= 1e-5 * rd[t]
+        elif not near_tie_certificate(base, g, q[s[i]], ent[s[i]], L, st[i], ref["trace"][i]):
+            uncertified += 1
+    assert uncertified == 0

@@ -105,3 +105,32 @@ def test_build_graph_small_alpha_variants():
         torch.cuda.synchronize()
         assert gm == med and (gf, gr) == (nf, nr)
         assert (g.cpu().numpy() == ref).all()
+
+
+def test_build_graph_partitioned_bit_exact():
+    # candidates among the members of each point's home group (k-means
+    # clusters, a second group for a third of the points, repeats, a home
+    # group of one point, a small group), then prune / medoid / full-scan
+    # repair; bit-exact against the oracle composition
+    ann = _ann()
+    ix = int_index()
+    base = ix["base"]
+    n = base.shape[0]
+    K, R = 64, 32
+    say("case: partitioned graph build, n=%d K=%d R=%d" % (n, K, R))
+    km = oracle.kmeans_hubs(base, 4, 10, synth.kmeans_init(ix["w"], n, 4))
+    groups = np.full((n, 2), -1, np.int32)
+    groups[:, 0] = km["assign"]
+    r = np.random.default_rng(3)
+    sel = r.random(n) < 0.33
+    groups[sel, 1] = r.integers(0, 4, int(sel.sum()))
+    groups[7] = [4, -1]
+    groups[100:110, 0] = 5
+    groups[200:300, 1] = 5
+    G = 6
+    ref, med, nf, nr, _, _ = oracle.build_graph_grouped(base, groups, K, R, 1.2)
+    g, m, br = ann.ann_build_graph_partitioned(_dev(base), K, R, 1.2, _dev(groups), G)
+    torch.cuda.synchronize()
+    assert m == med
+    assert br == (nf, nr)
+    assert (g.cpu().numpy() == ref).all()

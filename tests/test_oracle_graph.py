@@ -201,3 +201,48 @@ def test_build_graph_strongly_connected_tiny():
         kept = [c for c in g[p, :14] if c >= 0]
         order = cand[p].tolist()
         assert [order.index(c) for c in kept] == sorted(order.index(c) for c in kept)
+
+
+# ---------------------------------------------------------------- grouped candidate lists
+def test_knn_in_home_group_matches_masked_bruteforce():
+    # independent brute force: the full exact distance matrix (rationals on
+    # the grid are exact in FP64), a mask of the allowed pairs, a stable sort
+    # by (d2, id)
+    n, k = 90, 7
+    base = grid_data(n, 6, 11)
+    r = np.random.default_rng(5)
+    groups = np.full((n, 3), -1, np.int32)
+    groups[:, 0] = r.integers(0, 5, n)
+    groups[:, 1] = r.integers(0, 5, n)            # sometimes a repeat of column 0
+    groups[::4, 2] = r.integers(0, 5, (n + 3) // 4)
+    groups[13] = [4, -1, -1]                      # no other column
+    ids, dd = oracle.knn_in_home_group(base, groups, k)
+    b = base.astype(np.float64)
+    d2 = ((b[:, None, :] - b[None, :, :]) ** 2).sum(-1)
+    for p in range(n):
+        ok = [q for q in range(n) if q != p and groups[p, 0] in groups[q].tolist()]
+        ok.sort(key=lambda q: (d2[p, q], q))
+        want = ok[:k]
+        assert ids[p, :len(want)].tolist() == want
+        assert (ids[p, len(want):] == -1).all() and np.isinf(dd[p, len(want):]).all()
+        assert dd[p, :len(want)].tolist() == [d2[p, q] for q in want]
+
+
+def test_knn_in_home_group_one_group_is_plain_knn():
+    base = grid_data(200, 8, 12)
+    ids, dd = oracle.knn_in_home_group(base, np.zeros((200, 1), np.int32), 12)
+    ref, rd = oracle.knn(base, base, 12, exclude_self=True)
+    assert (ids == ref).all() and (dd == rd).all()
+
+
+def test_knn_in_home_group_singleton_and_duplicates():
+    # a group whose only member is its home point gets an empty list; exact
+    # duplicates of the home point come first, by id, and the point itself
+    # never appears
+    base = np.zeros((5, 2), np.float32)
+    base[3] = [3.0, 4.0]
+    groups = np.array([[0], [0], [0], [1], [0]], np.int32)
+    ids, dd = oracle.knn_in_home_group(base, groups, 3)
+    assert ids[3].tolist() == [-1, -1, -1]
+    assert ids[2].tolist() == [0, 1, 4] and dd[2].tolist() == [0.0, 0.0, 0.0]
+    assert ids[0].tolist() == [1, 2, 4]
