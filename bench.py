@@ -57,6 +57,7 @@ WORKLOAD_TEXT = {
     "gist1m": "256-component GMM with LogNormal(0, 0.5) per-dimension scales; half the queries "
               "mean-shifted",
     "tiny": "16-component GMM, sigma 1",
+    "sift10m": "integers 0..255 (256-component GMM, sigma 20); 30% of the queries mean-shifted",
 }
 COPY_BYTES = 1 << 30
 
@@ -133,6 +134,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--R", type=int, default=32, help="graph out-degree")
     ap.add_argument("--knn-k", type=int, default=128, help="kNN candidates before pruning")
+    ap.add_argument("--partitions", type=int, default=-1,
+                    help="candidate lists from this many overlapping k-means groups "
+                         "(-1: 0 up to N = 2M, else one group per 312,500 points)")
+    ap.add_argument("--overlap", type=int, default=2, help="groups listed per point")
     ap.add_argument("--hubs", type=int, default=1024)
     ap.add_argument("--hidden", type=int, default=128)
     ap.add_argument("--dout", type=int, default=64)
@@ -163,6 +168,8 @@ def main():
     if args.n or args.n_train:
         w = synth.scaled(w, n=args.n or None, n_train=args.n_train or None)
     knn_k, R, k = args.knn_k, args.R, 10
+    parts = args.partitions if args.partitions >= 0 else (0 if w.n <= 2_000_000 else
+                                                          w.n // 312_500)
 
     t0 = time.time()
     base = synth.base(w)
@@ -178,10 +185,12 @@ def main():
         log("state loaded from %s: medoid %d, L gate %s, L medoid %s" %
             (args.load_state, index.medoid, state.get("L_gate"), state.get("L_medoid")))
     else:
-        index = gate.build_index(base_d, knn_k, R, 1.2)
+        index = gate.build_index(base_d, knn_k, R, 1.2, partitions=parts, overlap=args.overlap,
+                                 w=w, log=log)
         g = None
-    log("graph: kNN %d -> alpha 1.2 -> R %d, medoid %d, bridges %s (%.1fs)" %
-        (knn_k, R, index.medoid, index.bridges, index.build_s))
+    log("graph: kNN %d%s -> alpha 1.2 -> R %d, medoid %d, bridges %s (%.1fs)" %
+        (knn_k, " in %d groups x %d" % (parts, args.overlap) if parts else "", R, index.medoid,
+         index.bridges, index.build_s))
     gt_ids, gt_dist = ann.ann_gt_knn(base_d, q_d, k)
     gt, gtd = gt_ids.cpu().numpy(), gt_dist.cpu().numpy()
 
@@ -192,8 +201,12 @@ def main():
     ws = ann.workspace("search", w.n, w.d, nq, device=dev)
 
     def sweep(entry, label):
+        """recall@10 over the L grid until the largest target is reached; the
+        first grid width that reaches the headline target is refined in
+        steps of 8 from the grid width below it."""
         rows, L95 = [], None
-        for L in L_SWEEP:
+
+        def measure(L):
             index.search(q_d, L, kk, entry, out=out, ws=ws)
             torch.cuda.synchronize()
             rec = float(recall_at(out[0].cpu().numpy(), gt).mean())
@@ -202,10 +215,22 @@ def main():
                              hops=round(float(st[:, 2].mean()), 1)))
             log("  %s L=%4d recall@10=%.4f ndc=%.0f hops=%.0f" % (label, L, rec, st[:, 0].mean(),
                                                                   st[:, 2].mean()))
+            return rec
+
+        prev = None
+        for L in L_SWEEP:
+            rec = measure(L)
             if rec >= TARGET and L95 is None:
-                L95 = L
+                for Lr in range(prev + 8, L, 8) if prev is not None else ():
+                    if measure(Lr) >= TARGET:
+                        L95 = Lr
+                        break
+                if L95 is None:
+                    L95 = L
             if rec >= max(targets):
                 break
+            prev = L
+        rows.sort(key=lambda r: r["L"])
         return rows, L95
 
     def extra_targets(rows, model, entry, label):
@@ -239,29 +264,35 @@ def main():
         return best, rows
 
     def pipelined(b, g_entry, g_search, L, plan, model):
-        """The same K steps with the entry stage of batch i+1 running on its own
-        stream while batch i is searched (two sets of entry/result buffers,
-        events order each buffer's entry stage after its previous search)."""
+        """The same K steps with two batches in flight: the entry stage runs
+        on its own stream, and the searches of consecutive batches on two
+        streams (one per buffer set), so the next batch's search fills the
+        compute units that the current one's last queries leave idle.  Events
+        order each buffer's entry stage after its previous search and each
+        search after its entry stage."""
         b2 = ann.QueryBatch(base_d, index.graph, index.medoid, q_d, kk,
                             torch.full((nq,), L, dtype=torch.int32, device=dev), k, plan=plan,
-                            model=model)
-        pairs = [(g_entry, g_search), (b2.graph_exec(ann.ANN_STAGE_ENTRY),
-                                       b2.graph_exec(ann.ANN_STAGE_SEARCH))]
-        s_e, s_s = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+                            model=model, entry_ids=None if model is not None else b.entry_ids)
+        pairs = [(g_entry, g_search),
+                 (b2.graph_exec(ann.ANN_STAGE_ENTRY) if model is not None else None,
+                  b2.graph_exec(ann.ANN_STAGE_SEARCH))]
+        s_e = torch.cuda.Stream(device=dev)
+        s_s = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
         ready = [torch.cuda.Event(), torch.cuda.Event()]
         done = [torch.cuda.Event(), torch.cuda.Event()]
-        for x in done:
-            x.record(s_s)
+        for x in range(2):
+            done[x].record(s_s[x])
 
         def pstep(i):
             x = i & 1
             ge, gs = pairs[x]
-            s_e.wait_event(done[x])
-            ge.launch(stream=s_e)
-            ready[x].record(s_e)
-            s_s.wait_event(ready[x])
-            gs.launch(stream=s_s)
-            done[x].record(s_s)
+            if ge is not None:
+                s_e.wait_event(done[x])
+                ge.launch(stream=s_e)
+                ready[x].record(s_e)
+                s_s[x].wait_event(ready[x])
+            gs.launch(stream=s_s[x])
+            done[x].record(s_s[x])
 
         for i in range(args.warmup):
             pstep(i)
@@ -272,11 +303,12 @@ def main():
         torch.cuda.synchronize()
         wall = time.time() - t0
         same = bool((b2.ids.cpu().numpy() == b.ids.cpu().numpy()).all())
-        pairs[1][0].close()
-        pairs[1][1].close()
+        for gx in pairs[1]:
+            if gx is not None:
+                gx.close()
         res = dict(qps=round(nq * args.steps / wall, 1),
                    ms_per_step=round(wall * 1000.0 / args.steps, 4), results_equal=same)
-        log("pipelined steps: %.3f ms/step -> %.0f QPS (results equal: %s)" %
+        log("pipelined steps (two batches in flight): %.3f ms/step -> %.0f QPS (results equal: %s)" %
             (res["ms_per_step"], res["qps"], same))
         return res
 
@@ -311,8 +343,7 @@ def main():
         wall = time.time() - t0
         search_ms = [e[1].elapsed_time(e[2]) for e in evs]
         entry_ms = [e[0].elapsed_time(e[1]) for e in evs]
-        pipe = (pipelined(b, g_entry, g_search, L, plan, model)
-                if model is not None and state is None else None)
+        pipe = pipelined(b, g_entry, g_search, L, plan, model) if state is None else None
         ids, dist = b.ids.cpu().numpy(), b.dist.cpu().numpy()
         rec = float(recall_at(ids, gt).mean())
         rec_t = float(recall_tie_aware(dist, gtd).mean())
@@ -422,6 +453,14 @@ def main():
                 hit += int((r.ids[:, :, None] == tr[:, None, :]).any(-1).sum())
                 tot += r.ids.size
             st["served_recall"] = round(hit / max(tot, 1), 5)
+            # recall@10 of every request (the first 10 ids of k = 100 ones)
+            h10 = t10 = 0
+            for r in srv.finished:
+                t0 = starts[r.rid]
+                tr = truth[t0:t0 + r.queries.shape[0], :10]
+                h10 += int((r.ids[:, :10, None] == tr[:, None, :]).any(-1).sum())
+                t10 += tr.size
+            st["served_recall_at_10"] = round(h10 / max(t10, 1), 5)
             st["offered_qps"] = round(frac * sat["qps"], 1)
             out["loads"].append(st)
             log("serving at %.0f%% of capacity: %s" % (100 * frac, st))
@@ -543,10 +582,11 @@ def main():
         warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(
-            workload="%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d/alpha1.2/R%d "
+            workload="%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d%s/alpha1.2/R%d "
                      "+ repair; %d hubs; towers %d->%d->%d" %
-                     (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k, R,
-                      args.hubs, w.d, args.hidden, args.dout),
+                     (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k,
+                      " within %d overlapping groups (x%d)" % (parts, args.overlap) if parts else "",
+                      R, args.hubs, w.d, args.hidden, args.dout),
             recall_targets=targets,
             entry="gate" if head is gres else "medoid", k=k, L=head["L"],
             recall_at_10=head["recall"], recall_target=TARGET,

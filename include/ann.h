@@ -192,12 +192,9 @@ ann_status ann_build_graph(const float *base, int64_t n, int32_t dim, int32_t kn
  * other groups or -1 (a repeated label counts once).  The candidates of
  * point i are the exact knn_k nearest, by (squared L2, id), among the points
  * whose row lists i's home group, i excluded; fewer (then -1 / +inf padded)
- * when that set is smaller.  Then alpha pruning, the medoid and the
- * connectivity repair as ann_build_graph; the repair's bridge to an
- * unreached point is always the argmin over all eligible points (a full
- * scan), since the candidate lists are not the global neighbours.  Cost:
- * the sum over groups of (home points x members).  The labels are read on
- * the host (the call synchronises).
+ * when that set is smaller.  Then ann_graph_from_candidates.  Cost: the sum
+ * over groups of (home points x members).  The labels are read on the host
+ * (the call synchronises).
  *   workspace  ann_build_graph_partitioned_workspace_size(n, dim, knn_k, R,
  *              largest member set, largest home set) bytes
  * Errors: EINVAL for a home label outside [0, n_groups), another label
@@ -210,6 +207,38 @@ ann_status ann_build_graph_partitioned(const float *base, int64_t n, int32_t dim
                                        int32_t n_member, int32_t n_groups, int32_t *graph,
                                        int32_t *medoid, int32_t *bridges, void *workspace,
                                        size_t ws_bytes, void *stream);
+
+/* The first step of ann_build_graph_partitioned for the home points of
+ * groups [g_begin, g_end) only, so that a caller can split the work:
+ * writes their rows of cand (n x knn_k int32, device) and cand_d2 (n x knn_k
+ * float64 squared distances, device); other rows are left untouched.
+ *   workspace  ann_group_candidates_workspace_size(dim, knn_k, largest
+ *              member set, largest home set) bytes (over all groups)
+ * Errors as ann_build_graph_partitioned, and EINVAL unless
+ * 0 <= g_begin <= g_end <= n_groups.  Synchronises. */
+size_t ann_group_candidates_workspace_size(int32_t dim, int32_t knn_k, int64_t max_members,
+                                           int64_t max_home);
+
+ann_status ann_group_candidates(const float *base, int64_t n, int32_t dim, int32_t knn_k,
+                                const int32_t *groups, int32_t n_member, int32_t n_groups,
+                                int32_t g_begin, int32_t g_end, int32_t *cand, double *cand_d2,
+                                void *workspace, size_t ws_bytes, void *stream);
+
+/* Graph from given candidate lists (rows sorted by (squared L2, id), -1 /
+ * +inf padded; cand_d2 the FP64 squared distances): alpha pruning, the
+ * medoid and the connectivity repair of ann_build_graph.  A repair bridge is
+ * the first eligible entry of the unreached point's list when there is one,
+ * else the argmin over all eligible points; for the exact global kNN lists
+ * of ann_build_graph the two rules pick the same node.
+ *   workspace  ann_graph_from_candidates_workspace_size(n, dim, R) bytes
+ * Requires 3 <= R <= 64, R-2 <= knn_k <= 1024, alpha >= 1.  Synchronises. */
+size_t ann_graph_from_candidates_workspace_size(int64_t n, int32_t dim, int32_t R);
+
+ann_status ann_graph_from_candidates(const float *base, int64_t n, int32_t dim,
+                                     const int32_t *cand, const double *cand_d2, int32_t knn_k,
+                                     int32_t R, float alpha, int32_t *graph, int32_t *medoid,
+                                     int32_t *bridges, void *workspace, size_t ws_bytes,
+                                     void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Hub nodes and their topology features (hub extraction and feature         */

@@ -49,7 +49,8 @@ def _declare(L):
     L.oracle_alpha_prune.argtypes = [_P, _I64, ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_int, _F32, _P]
     L.oracle_medoid.argtypes = [_P, _I64, ctypes.c_int]
     L.oracle_medoid.restype = _I32
-    L.oracle_repair.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _I32, _P, _P]
+    L.oracle_repair.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _I32, _P, ctypes.c_int,
+                                _P, _P]
     L.oracle_search.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _P, _I64, _P, _P, _P,
                                 ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P, ctypes.c_int]
     L.oracle_kmeans_hubs.argtypes = [_P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
@@ -105,14 +106,19 @@ def medoid(base) -> int:
     return int(lib().oracle_medoid(_ptr(base), base.shape[0], base.shape[1]))
 
 
-def repair(base, graph, med: int):
-    """Returns (repaired copy of graph, n_forward, n_reverse)."""
+def repair(base, graph, med: int, cand=None):
+    """Returns (repaired copy of graph, n_forward, n_reverse).  With candidate
+    lists, each bridge is the first eligible entry of the unreached point's
+    list when there is one (the same node as the argmin when the lists are
+    the global nearest neighbours)."""
     base = _f32(base)
     g = _i32(graph).copy()
     nf = _I32(0)
     nr = _I32(0)
+    c = None if cand is None else _i32(cand)
     lib().oracle_repair(_ptr(base), base.shape[0], base.shape[1], _ptr(g), g.shape[1],
-                        int(med), ctypes.byref(nf), ctypes.byref(nr))
+                        int(med), _ptr(c), 0 if c is None else c.shape[1], ctypes.byref(nf),
+                        ctypes.byref(nr))
     return g, nf.value, nr.value
 
 
@@ -153,12 +159,13 @@ def knn_in_home_group(base, groups, k: int):
 
 
 def build_graph_grouped(base, groups, knn_k: int, R: int, alpha: float):
-    """build_graph with the candidate lists of knn_in_home_group.
+    """build_graph with the candidate lists of knn_in_home_group; repair
+    bridges from those lists first (full argmin only when none is eligible).
     Returns (graph, medoid, n_forward, n_reverse, cand_ids, cand_d2)."""
     cand, cd2 = knn_in_home_group(base, groups, knn_k)
     g = alpha_prune(base, cand, cd2, R, alpha)
     m = medoid(base)
-    g, nf, nr = repair(base, g, m)
+    g, nf, nr = repair(base, g, m, cand)
     return g, m, nf, nr, cand, cd2
 
 

@@ -161,6 +161,10 @@ i32 oracle_medoid(const float *base, i64 n, int d)
 /*  reverse: BFS over reversed edges from the medoid; while a node w cannot   */
 /*           reach the medoid (smallest id first), link w -> t where t        */
 /*           minimises (d2(w,t), t) over the nodes that can reach it.          */
+/* With candidate lists (cand, K per row, -1 ends a row) the bridge of u is   */
+/* the first eligible entry of u's list, and the argmin above only when no    */
+/* entry is eligible.  For lists that hold u's global nearest neighbours by   */
+/* (d2, id) the two rules pick the same node.                                 */
 /* Returns the number of forward and reverse bridges through the pointers.    */
 
 static void bfs_from(const i32 *graph, i64 n, int R, i32 src, unsigned char *mark,
@@ -219,8 +223,21 @@ static void rbfs_from(const i64 *off, const i32 *adj, i32 src, unsigned char *ma
     }
 }
 
+/* first entry of row u of the candidate lists that passes the test, or -1 */
+static i32 first_listed(const i32 *cand, int K, i64 u, const unsigned char *mark,
+                        const i32 *graph, int R, int need_free_slot)
+{
+    if (!cand) return -1;
+    for (int q = 0; q < K; ++q) {
+        i32 v = cand[u * K + q];
+        if (v < 0) break;
+        if (mark[v] && (!need_free_slot || graph[(i64)v * R + (R - 2)] < 0)) return v;
+    }
+    return -1;
+}
+
 void oracle_repair(const float *base, i64 n, int d, i32 *graph, int R, i32 medoid,
-                   i32 *n_forward, i32 *n_reverse)
+                   const i32 *cand, int K, i32 *n_forward, i32 *n_reverse)
 {
     unsigned char *mark = (unsigned char *)calloc((size_t)n, 1);
     i32 *queue = (i32 *)malloc(sizeof(i32) * (size_t)n);
@@ -229,12 +246,14 @@ void oracle_repair(const float *base, i64 n, int d, i32 *graph, int R, i32 medoi
     bfs_from(graph, n, R, medoid, mark, queue);
     for (i64 u = 0; u < n; ++u) {
         if (mark[u]) continue;
-        double best = INFINITY;
-        i32 bv = -1;
-        for (i64 v = 0; v < n; ++v) {
-            if (!mark[v] || graph[v * R + (R - 2)] >= 0) continue;
-            double t = d2(base + u * d, base + v * d, d);
-            if (bv < 0 || key_less(t, (i32)v, best, bv)) { best = t; bv = (i32)v; }
+        i32 bv = first_listed(cand, K, u, mark, graph, R, 1);
+        if (bv < 0) {
+            double best = INFINITY;
+            for (i64 v = 0; v < n; ++v) {
+                if (!mark[v] || graph[v * R + (R - 2)] >= 0) continue;
+                double t = d2(base + u * d, base + v * d, d);
+                if (bv < 0 || key_less(t, (i32)v, best, bv)) { best = t; bv = (i32)v; }
+            }
         }
         graph[(i64)bv * R + (R - 2)] = (i32)u;
         ++nf;
@@ -248,12 +267,14 @@ void oracle_repair(const float *base, i64 n, int d, i32 *graph, int R, i32 medoi
     rbfs_from(off, adj, medoid, mark, queue);
     for (i64 w = 0; w < n; ++w) {
         if (mark[w]) continue;
-        double best = INFINITY;
-        i32 bt = -1;
-        for (i64 t = 0; t < n; ++t) {
-            if (!mark[t]) continue;
-            double v = d2(base + w * d, base + t * d, d);
-            if (bt < 0 || key_less(v, (i32)t, best, bt)) { best = v; bt = (i32)t; }
+        i32 bt = first_listed(cand, K, w, mark, graph, R, 0);
+        if (bt < 0) {
+            double best = INFINITY;
+            for (i64 t = 0; t < n; ++t) {
+                if (!mark[t]) continue;
+                double v = d2(base + w * d, base + t * d, d);
+                if (bt < 0 || key_less(v, (i32)t, best, bt)) { best = v; bt = (i32)t; }
+            }
         }
         graph[w * R + (R - 1)] = bt;
         ++nr;

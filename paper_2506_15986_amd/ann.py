@@ -262,6 +262,14 @@ def ann_build_graph_partitioned_workspace_size(n: int, dim: int, knn_k: int, R: 
                                                                max_home))
 
 
+_sig("ann_group_candidates_workspace_size", _SZ, _I32, _I32, _I64, _I64)
+_sig("ann_group_candidates", _I32, _P, _I64, _I32, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
+     _SZ, _P)
+_sig("ann_graph_from_candidates_workspace_size", _SZ, _I64, _I32, _I32)
+_sig("ann_graph_from_candidates", _I32, _P, _I64, _I32, _P, _P, _I32, _I32, _F32, _P,
+     ctypes.POINTER(_I32), ctypes.POINTER(_I32 * 2), _P, _SZ, _P)
+
+
 def group_sizes(groups: np.ndarray, n_groups: int):
     """(members per group, home points per group) of an n x n_member label
     table (column 0 the home group, -1 = none, a repeated label counts once)."""
@@ -296,6 +304,59 @@ def ann_build_graph_partitioned(base: torch.Tensor, knn_k: int, R: int, alpha: f
                                             _ptr(groups), int(n_member), int(n_groups),
                                             _ptr(graph), ctypes.byref(m), ctypes.byref(br),
                                             _ptr(ws), ws.numel(), _stream(stream)))
+    del ws
+    return graph, int(m.value), (int(br[0]), int(br[1]))
+
+
+def ann_group_candidates_workspace_size(dim: int, knn_k: int, max_members: int,
+                                        max_home: int) -> int:
+    return int(_lib.ann_group_candidates_workspace_size(dim, knn_k, max_members, max_home))
+
+
+def ann_graph_from_candidates_workspace_size(n: int, dim: int, R: int) -> int:
+    return int(_lib.ann_graph_from_candidates_workspace_size(n, dim, R))
+
+
+def ann_group_candidates(base: torch.Tensor, knn_k: int, groups: torch.Tensor, n_groups: int,
+                         g_begin: int, g_end: int, cand: torch.Tensor, cand_d2: torch.Tensor,
+                         stream=None, sizes=None):
+    """Candidate lists of the home points of groups [g_begin, g_end) written
+    into cand (n x knn_k int32) / cand_d2 (n x knn_k float64).  sizes: the
+    (members, homes) counts of group_sizes, when the caller has them."""
+    _dev(base, torch.float32)
+    _dev(groups, torch.int32)
+    _dev(cand, torch.int32)
+    _dev(cand_d2, torch.float64)
+    n, dim = base.shape
+    if groups.dim() == 1:
+        groups = groups.reshape(n, 1)
+    mem, home = sizes if sizes is not None else group_sizes(groups.cpu().numpy(), n_groups)
+    nb = max(256, int(_lib.ann_group_candidates_workspace_size(dim, knn_k, int(mem.max()),
+                                                               int(home.max()))))
+    ws = torch.empty(nb, dtype=torch.uint8, device=base.device)
+    _check(_lib.ann_group_candidates(_ptr(base), n, dim, knn_k, _ptr(groups), groups.shape[1],
+                                     int(n_groups), int(g_begin), int(g_end), _ptr(cand),
+                                     _ptr(cand_d2), _ptr(ws), ws.numel(), _stream(stream)))
+    del ws
+
+
+def ann_graph_from_candidates(base: torch.Tensor, cand: torch.Tensor, cand_d2: torch.Tensor,
+                              R: int, alpha: float, stream=None):
+    """alpha prune -> medoid -> repair of given candidate lists.  Returns
+    (graph int32 [n,R], medoid, (forward, reverse bridges))."""
+    _dev(base, torch.float32)
+    _dev(cand, torch.int32)
+    _dev(cand_d2, torch.float64)
+    n, dim = base.shape
+    graph = torch.empty((n, R), dtype=torch.int32, device=base.device)
+    nb = max(256, int(_lib.ann_graph_from_candidates_workspace_size(n, dim, R)))
+    ws = torch.empty(nb, dtype=torch.uint8, device=base.device)
+    m = _I32(-1)
+    br = (_I32 * 2)()
+    _check(_lib.ann_graph_from_candidates(_ptr(base), n, dim, _ptr(cand), _ptr(cand_d2),
+                                          cand.shape[1], R, float(alpha), _ptr(graph),
+                                          ctypes.byref(m), ctypes.byref(br), _ptr(ws), ws.numel(),
+                                          _stream(stream)))
     del ws
     return graph, int(m.value), (int(br[0]), int(br[1]))
 

@@ -488,13 +488,13 @@ TailBufs take_tail(Carve &cv, int64_t n, int dim, int R)
     return t;
 }
 
-// alpha pruning of the candidate lists, medoid, connectivity repair.
-// cand_global: the lists are each point's global nearest neighbours, so the
-// first eligible entry of an unreached point's list is its bridge; otherwise
-// every bridge comes from a full scan.
-ann_status graph_tail(const float *base, int64_t n, int dim, int32_t *cand, double *cd2, int K,
-                      int R, float alpha, int32_t *graph, int32_t *medoid, int32_t *bridges,
-                      const TailBufs &t, hipStream_t st, bool cand_global)
+// alpha pruning of the candidate lists, medoid, connectivity repair.  Each
+// repair bridge is the first eligible entry of the unreached point's
+// candidate list, else the argmin over all eligible points (a full scan);
+// for lists of global nearest neighbours the two are the same node.
+ann_status graph_tail(const float *base, int64_t n, int dim, const int32_t *cand,
+                      const double *cd2, int K, int R, float alpha, int32_t *graph,
+                      int32_t *medoid, int32_t *bridges, const TailBufs &t, hipStream_t st)
 {
     const double a2 = (double)alpha * (double)alpha;
     hipLaunchKernelGGL(prune_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, dim,
@@ -524,8 +524,8 @@ ann_status graph_tail(const float *base, int64_t n, int dim, int32_t *cand, doub
                            t.rst, phase, 1);
         ANN_LAUNCHED();
         for (;;) {
-            hipLaunchKernelGGL(repair_driver, dim3(1), dim3(DRV), 0, st, graph, n, R, cand,
-                               cand_global ? K : 0, t.mark,
+            hipLaunchKernelGGL(repair_driver, dim3(1), dim3(DRV), 0, st, graph, n, R, cand, K,
+                               t.mark,
                                t.queue, t.off, t.radj, t.rst, phase);
             ANN_LAUNCHED();
             RepairState h{};
@@ -597,11 +597,9 @@ size_t build_graph_ws(int64_t n, int dim, int K, int R)
     return b + tail_ws(n, dim, R);
 }
 
-size_t build_partitioned_ws(int64_t n, int dim, int K, int R, int64_t max_mem, int64_t max_home)
+size_t group_cand_ws(int dim, int K, int64_t max_mem, int64_t max_home)
 {
-    size_t b = round_up((size_t)n * K * 4, 256) + round_up((size_t)n * K * 8, 256);  // cand, d2
-    b += tail_ws(n, dim, R);
-    b += knn_workspace(max_mem, max_home, dim, K);
+    size_t b = knn_workspace(max_mem, max_home, dim, K);
     b += round_up((size_t)max_mem * dim * 4, 256) + round_up((size_t)max_home * dim * 4, 256);
     b += round_up((size_t)max_mem * 4, 256) + round_up((size_t)max_home * 4, 256) * 2;
     b += round_up((size_t)max_home * K * 4, 256) + round_up((size_t)max_home * K * 8, 256);
@@ -639,102 +637,83 @@ extern "C" ann_status ann_build_graph(const float *base, int64_t n, int32_t dim,
     // exact kNN candidates (self excluded), then pruning, medoid, repair
     ann_status s = knn_run(base, n, dim, base, n, K, true, cand, nullptr, cd2, knn_ws, kws, st, 0);
     if (s != ANN_OK) return s;
-    return graph_tail(base, n, dim, cand, cd2, K, R, alpha, graph, medoid, bridges, t, st, true);
+    return graph_tail(base, n, dim, cand, cd2, K, R, alpha, graph, medoid, bridges, t, st);
 }
 
-extern "C" size_t ann_build_graph_partitioned_workspace_size(int64_t n, int32_t dim,
-                                                             int32_t knn_k, int32_t R,
-                                                             int64_t max_members, int64_t max_home)
-{
-    if (n < 2 || dim < 1 || knn_k < 1 || R < 3 || max_members < 1 || max_home < 1) return 0;
-    return build_partitioned_ws(n, dim, knn_k, R, max_members, max_home);
-}
+namespace {
 
-extern "C" ann_status ann_build_graph_partitioned(const float *base, int64_t n, int32_t dim,
-                                                  int32_t knn_k, int32_t R, float alpha,
-                                                  const int32_t *groups, int32_t n_member,
-                                                  int32_t n_groups, int32_t *graph,
-                                                  int32_t *medoid, int32_t *bridges,
-                                                  void *workspace, size_t ws_bytes, void *stream)
+// Members and home points of every group, each list in id order.
+struct GroupLists {
+    std::vector<int64_t> ms, hs;          // offsets (n_groups + 1)
+    std::vector<int32_t> members, homes;
+    int64_t max_mem = 1, max_home = 1;
+};
+
+ann_status group_lists(const int32_t *groups_dev, int64_t n, int32_t n_member, int32_t n_groups,
+                       hipStream_t st, GroupLists &L)
 {
-    ANN_REQUIRE(base && groups && graph && medoid && workspace, "a required pointer is NULL");
-    ANN_REQUIRE(n >= 2 && n <= 0x7FFFFFFF, "n must be in [2, 2^31)");
-    ANN_REQUIRE(dim >= 1, "dim must be >= 1");
-    ANN_REQUIRE(R >= 3, "R must be >= 3");
-    ANN_SUPPORTED(R <= 64, "R must be <= 64");
-    ANN_REQUIRE(knn_k >= R - 2 && knn_k <= 1024, "knn_k must be in [R-2, 1024]");
-    ANN_REQUIRE(n_member >= 1, "n_member must be >= 1");
-    ANN_REQUIRE(n_groups >= 1, "n_groups must be >= 1");
-    ANN_REQUIRE(alpha >= 1.0f, "alpha must be >= 1");
-    ANN_REQUIRE(aligned(base, 16), "base must be 16-byte aligned");
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t nm = (size_t)n_member;
     std::vector<int32_t> lab((size_t)n * nm);
-    ANN_HIP(hipMemcpyAsync(lab.data(), groups, sizeof(int32_t) * lab.size(), hipMemcpyDeviceToHost,
-                           st));
+    ANN_HIP(hipMemcpyAsync(lab.data(), groups_dev, sizeof(int32_t) * lab.size(),
+                           hipMemcpyDeviceToHost, st));
     ANN_HIP(hipStreamSynchronize(st));
-    // member and home lists of every group, each in id order (counting sort)
-    std::vector<int64_t> ms((size_t)n_groups + 1, 0), hs((size_t)n_groups + 1, 0);
     auto listed_before = [&](int64_t i, size_t c) {
         for (size_t e = 0; e < c; ++e)
             if (lab[(size_t)i * nm + e] == lab[(size_t)i * nm + c]) return true;
         return false;
     };
+    L.ms.assign((size_t)n_groups + 1, 0);
+    L.hs.assign((size_t)n_groups + 1, 0);
     for (int64_t i = 0; i < n; ++i) {
         const int32_t h = lab[(size_t)i * nm];
         ANN_REQUIRE(h >= 0 && h < n_groups, "home group of point %lld out of range", (long long)i);
-        hs[(size_t)h + 1]++;
+        L.hs[(size_t)h + 1]++;
         for (size_t c = 0; c < nm; ++c) {
             const int32_t g = lab[(size_t)i * nm + c];
             ANN_REQUIRE(g >= -1 && g < n_groups, "group label of point %lld out of range",
                         (long long)i);
-            if (g >= 0 && !listed_before(i, c)) ms[(size_t)g + 1]++;
+            if (g >= 0 && !listed_before(i, c)) L.ms[(size_t)g + 1]++;
         }
     }
-    int64_t max_mem = 1, max_home = 1;
     for (int g = 0; g < n_groups; ++g) {
-        max_mem = std::max<int64_t>(max_mem, ms[(size_t)g + 1]);
-        max_home = std::max<int64_t>(max_home, hs[(size_t)g + 1]);
-        ms[(size_t)g + 1] += ms[(size_t)g];
-        hs[(size_t)g + 1] += hs[(size_t)g];
+        L.max_mem = std::max<int64_t>(L.max_mem, L.ms[(size_t)g + 1]);
+        L.max_home = std::max<int64_t>(L.max_home, L.hs[(size_t)g + 1]);
+        L.ms[(size_t)g + 1] += L.ms[(size_t)g];
+        L.hs[(size_t)g + 1] += L.hs[(size_t)g];
     }
-    ANN_REQUIRE(ws_bytes >= build_partitioned_ws(n, dim, knn_k, R, max_mem, max_home),
-                "workspace too small (largest member set %lld, largest home set %lld)",
-                (long long)max_mem, (long long)max_home);
-    std::vector<int32_t> members((size_t)ms[(size_t)n_groups]), homes((size_t)n);
-    {
-        std::vector<int64_t> mp(ms.begin(), ms.end() - 1), hp(hs.begin(), hs.end() - 1);
-        for (int64_t i = 0; i < n; ++i) {
-            homes[(size_t)hp[(size_t)lab[(size_t)i * nm]]++] = (int32_t)i;
-            for (size_t c = 0; c < nm; ++c) {
-                const int32_t g = lab[(size_t)i * nm + c];
-                if (g >= 0 && !listed_before(i, c)) members[(size_t)mp[(size_t)g]++] = (int32_t)i;
-            }
+    L.members.resize((size_t)L.ms[(size_t)n_groups]);
+    L.homes.resize((size_t)n);
+    std::vector<int64_t> mp(L.ms.begin(), L.ms.end() - 1), hp(L.hs.begin(), L.hs.end() - 1);
+    for (int64_t i = 0; i < n; ++i) {
+        L.homes[(size_t)hp[(size_t)lab[(size_t)i * nm]]++] = (int32_t)i;
+        for (size_t c = 0; c < nm; ++c) {
+            const int32_t g = lab[(size_t)i * nm + c];
+            if (g >= 0 && !listed_before(i, c)) L.members[(size_t)mp[(size_t)g]++] = (int32_t)i;
         }
     }
-    const int K = knn_k;
-    Carve cv{static_cast<unsigned char *>(workspace)};
-    int32_t *cand = cv.take<int32_t>((size_t)n * K);
-    double *cd2 = cv.take<double>((size_t)n * K);
-    TailBufs t = take_tail(cv, n, dim, R);
-    const size_t kws = knn_workspace(max_mem, max_home, dim, K);
+    return ANN_OK;
+}
+
+// candidate lists of the home points of groups [g0, g1)
+ann_status group_candidates(const float *base, int dim, int K, const GroupLists &L, int g0, int g1,
+                            int32_t *cand, double *cd2, Carve &cv, hipStream_t st)
+{
+    const size_t kws = knn_workspace(L.max_mem, L.max_home, dim, K);
     void *knn_ws = cv.take<unsigned char>(kws);
-    float *mrows = cv.take<float>((size_t)max_mem * dim);
-    float *hrows = cv.take<float>((size_t)max_home * dim);
-    int32_t *mem_d = cv.take<int32_t>((size_t)max_mem);
-    int32_t *home_d = cv.take<int32_t>((size_t)max_home);
-    int32_t *self_d = cv.take<int32_t>((size_t)max_home);
-    int32_t *loc_ids = cv.take<int32_t>((size_t)max_home * K);
-    double *loc_d2 = cv.take<double>((size_t)max_home * K);
-    std::vector<int32_t> selfc((size_t)max_home);
-    // exact kNN of each group's home points among its members (self excluded),
-    // mapped to global ids
-    for (int g = 0; g < n_groups; ++g) {
-        const int64_t m = ms[(size_t)g + 1] - ms[(size_t)g];
-        const int64_t h = hs[(size_t)g + 1] - hs[(size_t)g];
+    float *mrows = cv.take<float>((size_t)L.max_mem * dim);
+    float *hrows = cv.take<float>((size_t)L.max_home * dim);
+    int32_t *mem_d = cv.take<int32_t>((size_t)L.max_mem);
+    int32_t *home_d = cv.take<int32_t>((size_t)L.max_home);
+    int32_t *self_d = cv.take<int32_t>((size_t)L.max_home);
+    int32_t *loc_ids = cv.take<int32_t>((size_t)L.max_home * K);
+    double *loc_d2 = cv.take<double>((size_t)L.max_home * K);
+    std::vector<int32_t> selfc((size_t)L.max_home);
+    for (int g = g0; g < g1; ++g) {
+        const int64_t m = L.ms[(size_t)g + 1] - L.ms[(size_t)g];
+        const int64_t h = L.hs[(size_t)g + 1] - L.hs[(size_t)g];
         if (h == 0) continue;
-        const int32_t *mem = members.data() + ms[(size_t)g];
-        const int32_t *hom = homes.data() + hs[(size_t)g];
+        const int32_t *mem = L.members.data() + L.ms[(size_t)g];
+        const int32_t *hom = L.homes.data() + L.hs[(size_t)g];
         // position of each home point in the member list (both in id order)
         for (int64_t r = 0, e = 0; r < h; ++r) {
             while (mem[e] != hom[r]) ++e;
@@ -762,7 +741,115 @@ extern "C" ann_status ann_build_graph_partitioned(const float *base, int64_t n, 
         // the staging buffers are rewritten by the next group's copies
         ANN_HIP(hipStreamSynchronize(st));
     }
-    return graph_tail(base, n, dim, cand, cd2, K, R, alpha, graph, medoid, bridges, t, st, false);
+    return ANN_OK;
+}
+
+}  // namespace
+
+#define GROUP_ARGS_OK()                                                                      \
+    ANN_REQUIRE(n >= 2 && n <= 0x7FFFFFFF, "n must be in [2, 2^31)");                         \
+    ANN_REQUIRE(dim >= 1, "dim must be >= 1");                                                \
+    ANN_REQUIRE(knn_k >= 1 && knn_k <= 1024, "knn_k must be in [1, 1024]");                   \
+    ANN_REQUIRE(n_member >= 1, "n_member must be >= 1");                                      \
+    ANN_REQUIRE(n_groups >= 1, "n_groups must be >= 1");                                      \
+    ANN_REQUIRE(aligned(base, 16), "base must be 16-byte aligned")
+
+extern "C" size_t ann_group_candidates_workspace_size(int32_t dim, int32_t knn_k,
+                                                      int64_t max_members, int64_t max_home)
+{
+    if (dim < 1 || knn_k < 1 || max_members < 1 || max_home < 1) return 0;
+    return group_cand_ws(dim, knn_k, max_members, max_home);
+}
+
+extern "C" ann_status ann_group_candidates(const float *base, int64_t n, int32_t dim, int32_t knn_k,
+                                           const int32_t *groups, int32_t n_member,
+                                           int32_t n_groups, int32_t g_begin, int32_t g_end,
+                                           int32_t *cand, double *cand_d2, void *workspace,
+                                           size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(base && groups && cand && cand_d2 && workspace, "a required pointer is NULL");
+    GROUP_ARGS_OK();
+    ANN_REQUIRE(g_begin >= 0 && g_begin <= g_end && g_end <= n_groups,
+                "group range must satisfy 0 <= g_begin <= g_end <= n_groups");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    GroupLists L;
+    ann_status s = group_lists(groups, n, n_member, n_groups, st, L);
+    if (s != ANN_OK) return s;
+    ANN_REQUIRE(ws_bytes >= group_cand_ws(dim, knn_k, L.max_mem, L.max_home),
+                "workspace too small (largest member set %lld, largest home set %lld)",
+                (long long)L.max_mem, (long long)L.max_home);
+    Carve cv{static_cast<unsigned char *>(workspace)};
+    return group_candidates(base, dim, knn_k, L, g_begin, g_end, cand, cand_d2, cv, st);
+}
+
+extern "C" size_t ann_graph_from_candidates_workspace_size(int64_t n, int32_t dim, int32_t R)
+{
+    if (n < 2 || dim < 1 || R < 3) return 0;
+    return tail_ws(n, dim, R);
+}
+
+extern "C" ann_status ann_graph_from_candidates(const float *base, int64_t n, int32_t dim,
+                                                const int32_t *cand, const double *cand_d2,
+                                                int32_t knn_k, int32_t R, float alpha,
+                                                int32_t *graph, int32_t *medoid,
+                                                int32_t *bridges, void *workspace,
+                                                size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(base && cand && cand_d2 && graph && medoid && workspace,
+                "a required pointer is NULL");
+    ANN_REQUIRE(n >= 2 && n <= 0x7FFFFFFF, "n must be in [2, 2^31)");
+    ANN_REQUIRE(dim >= 1, "dim must be >= 1");
+    ANN_REQUIRE(R >= 3, "R must be >= 3");
+    ANN_SUPPORTED(R <= 64, "R must be <= 64");
+    ANN_REQUIRE(knn_k >= R - 2 && knn_k <= 1024, "knn_k must be in [R-2, 1024]");
+    ANN_REQUIRE(alpha >= 1.0f, "alpha must be >= 1");
+    ANN_REQUIRE(aligned(base, 16), "base must be 16-byte aligned");
+    ANN_REQUIRE(ws_bytes >= tail_ws(n, dim, R), "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carve cv{static_cast<unsigned char *>(workspace)};
+    TailBufs t = take_tail(cv, n, dim, R);
+    return graph_tail(base, n, dim, cand, cand_d2, knn_k, R, alpha, graph, medoid, bridges, t, st);
+}
+
+extern "C" size_t ann_build_graph_partitioned_workspace_size(int64_t n, int32_t dim,
+                                                             int32_t knn_k, int32_t R,
+                                                             int64_t max_members, int64_t max_home)
+{
+    if (n < 2 || dim < 1 || knn_k < 1 || R < 3 || max_members < 1 || max_home < 1) return 0;
+    return round_up((size_t)n * knn_k * 4, 256) + round_up((size_t)n * knn_k * 8, 256) +
+           std::max(tail_ws(n, dim, R), group_cand_ws(dim, knn_k, max_members, max_home));
+}
+
+extern "C" ann_status ann_build_graph_partitioned(const float *base, int64_t n, int32_t dim,
+                                                  int32_t knn_k, int32_t R, float alpha,
+                                                  const int32_t *groups, int32_t n_member,
+                                                  int32_t n_groups, int32_t *graph,
+                                                  int32_t *medoid, int32_t *bridges,
+                                                  void *workspace, size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(base && groups && graph && medoid && workspace, "a required pointer is NULL");
+    GROUP_ARGS_OK();
+    ANN_REQUIRE(R >= 3, "R must be >= 3");
+    ANN_SUPPORTED(R <= 64, "R must be <= 64");
+    ANN_REQUIRE(knn_k >= R - 2, "knn_k must be >= R-2");
+    ANN_REQUIRE(alpha >= 1.0f, "alpha must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    GroupLists L;
+    ann_status s = group_lists(groups, n, n_member, n_groups, st, L);
+    if (s != ANN_OK) return s;
+    ANN_REQUIRE(ws_bytes >= ann_build_graph_partitioned_workspace_size(n, dim, knn_k, R, L.max_mem,
+                                                                        L.max_home),
+                "workspace too small (largest member set %lld, largest home set %lld)",
+                (long long)L.max_mem, (long long)L.max_home);
+    const int K = knn_k;
+    Carve cv{static_cast<unsigned char *>(workspace)};
+    int32_t *cand = cv.take<int32_t>((size_t)n * K);
+    double *cd2 = cv.take<double>((size_t)n * K);
+    Carve rest = cv;     // the kNN staging and the tail's buffers share what is left
+    s = group_candidates(base, dim, K, L, 0, n_groups, cand, cd2, cv, st);
+    if (s != ANN_OK) return s;
+    TailBufs t = take_tail(rest, n, dim, R);
+    return graph_tail(base, n, dim, cand, cd2, K, R, alpha, graph, medoid, bridges, t, st);
 }
 
 extern "C" ann_status ann_medoid(const float *base, int64_t n, int32_t dim, int32_t *medoid,

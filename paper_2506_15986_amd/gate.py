@@ -50,13 +50,15 @@ class Index:
 
 
 def build_index(base: torch.Tensor, knn_k: int = 128, R: int = 32, alpha: float = 1.2,
-                partitions: int = 0, overlap: int = 2, w: synth.Workload | None = None) -> Index:
+                partitions: int = 0, overlap: int = 2, w: synth.Workload | None = None,
+                log=None) -> Index:
     """The proximity graph: all-pairs exact kNN candidates, or with
     partitions > 0 candidates from overlapping groups: Lloyd k-means
     (`partitions` clusters, 10 steps, seeded from the workload) gives the
     hubs; each point lists its `overlap` nearest hubs, the first being its
     home group, and its candidates are the exact knn_k nearest among the
-    points that list its home group.  Then alpha pruning, medoid, repair."""
+    points that list its home group (computed a few groups per call, with a
+    `log` line after each).  Then alpha pruning, medoid, repair."""
     t = time.time()
     if partitions > 0:
         n = base.shape[0]
@@ -68,8 +70,18 @@ def build_index(base: torch.Tensor, knn_k: int = 128, R: int = 32, alpha: float 
         for s in range(0, n, step):
             ids, _ = ann.ann_gt_knn(hubs, base[s:s + step], overlap)
             groups[s:s + step] = ids
-        graph, med, bridges = ann.ann_build_graph_partitioned(base, knn_k, R, alpha, groups,
-                                                              partitions)
+        sizes = ann.group_sizes(groups.cpu().numpy(), partitions)
+        cand = torch.empty((n, knn_k), dtype=torch.int32, device=base.device)
+        cd2 = torch.empty((n, knn_k), dtype=torch.float64, device=base.device)
+        step = 4
+        for g0 in range(0, partitions, step):
+            ann.ann_group_candidates(base, knn_k, groups, partitions, g0,
+                                     min(partitions, g0 + step), cand, cd2, sizes=sizes)
+            if log:
+                log("  candidate lists: groups %d..%d of %d done (%.1fs)" %
+                    (g0, min(partitions, g0 + step) - 1, partitions, time.time() - t))
+        graph, med, bridges = ann.ann_graph_from_candidates(base, cand, cd2, R, alpha)
+        del cand, cd2
     else:
         graph, med, bridges = ann.ann_build_graph(base, knn_k, R, alpha)
     torch.cuda.synchronize()

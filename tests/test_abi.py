@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -173,3 +174,43 @@ def test_batch_driver_rejects_bad_arguments_without_gpu_work():
     assert ann._lib.ann_autotune_search(None, 10, 32, None, 16, None, 1, None, 0, None, None, 1,
                                         None, None, None, None, 0, 1, ctypes.byref(best), None,
                                         None, 0, None) == ann.ANN_EINVAL
+
+
+def test_grouped_build_rejects_bad_arguments_without_gpu_work():
+    from paper_2506_15986_amd import ann
+    base = np.zeros((64, 8), np.float32)
+    lab = np.zeros((64, 2), np.int32)
+    cand = np.zeros((64, 8), np.int32)
+    cd2 = np.zeros((64, 8), np.float64)
+    ws = np.zeros(256, np.uint8)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
+
+    def gc(g0=0, g1=1, n_member=2, n_groups=1, k=8, b=base):
+        return ann._lib.ann_group_candidates(P(b), 64, 8, k, P(lab), n_member, n_groups, g0, g1,
+                                             P(cand), P(cd2), P(ws), ws.nbytes, None)
+
+    assert gc(g0=1, g1=0) == ann.ANN_EINVAL
+    assert gc(g1=2) == ann.ANN_EINVAL                 # past n_groups
+    assert gc(n_member=0) == ann.ANN_EINVAL
+    assert gc(n_groups=0) == ann.ANN_EINVAL
+    assert gc(k=0) == ann.ANN_EINVAL
+    raw = np.zeros(64 * 8 * 4 + 16, np.uint8)
+    assert gc(b=raw[4:4 + 64 * 8 * 4].view(np.float32)) == ann.ANN_EINVAL     # misaligned
+    g = np.zeros((64, 4), np.int32)
+    m, br = ctypes.c_int32(), (ctypes.c_int32 * 2)()
+    # R - 2 <= knn_k, alpha >= 1, R <= 64 (ENOTSUP), workspace size
+    assert ann._lib.ann_graph_from_candidates(P(base), 64, 8, P(cand), P(cd2), 1, 4, 1.2, P(g),
+                                              ctypes.byref(m), ctypes.byref(br), P(ws), ws.nbytes,
+                                              None) == ann.ANN_EINVAL
+    assert ann._lib.ann_graph_from_candidates(P(base), 64, 8, P(cand), P(cd2), 8, 4, 0.5, P(g),
+                                              ctypes.byref(m), ctypes.byref(br), P(ws), ws.nbytes,
+                                              None) == ann.ANN_EINVAL
+    assert ann._lib.ann_graph_from_candidates(P(base), 64, 8, P(cand), P(cd2), 8, 65, 1.2, P(g),
+                                              ctypes.byref(m), ctypes.byref(br), P(ws), ws.nbytes,
+                                              None) == ann.ANN_ENOTSUP
+    assert ann._lib.ann_graph_from_candidates(P(base), 64, 8, P(cand), P(cd2), 8, 4, 1.2, P(g),
+                                              ctypes.byref(m), ctypes.byref(br), P(ws), ws.nbytes,
+                                              None) == ann.ANN_EINVAL      # workspace too small
+    assert ann.ann_graph_from_candidates_workspace_size(64, 8, 4) > ws.nbytes
+    assert ann.ann_group_candidates_workspace_size(8, 8, 64, 32) > 0
+    assert ann.ann_group_candidates_workspace_size(8, 0, 64, 32) == 0

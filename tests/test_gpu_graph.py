@@ -134,3 +134,18 @@ def test_build_graph_partitioned_bit_exact():
     assert m == med
     assert br == (nf, nr)
     assert (g.cpu().numpy() == ref).all()
+    # the same build through the split entry points, a few groups per call
+    say("case: group candidates in chunks + graph from candidates")
+    bd, gd = _dev(base), _dev(groups)
+    cand = torch.full((n, K), -7, dtype=torch.int32, device=bd.device)
+    cd2 = torch.zeros((n, K), dtype=torch.float64, device=bd.device)
+    for g0, g1 in ((0, 2), (2, 2), (2, 5), (5, 6)):
+        ann.ann_group_candidates(bd, K, gd, G, g0, g1, cand, cd2)
+    rc, rd = oracle.knn_in_home_group(base, groups, K)
+    torch.cuda.synchronize()
+    assert (cand.cpu().numpy() == rc).all()
+    assert (cd2.cpu().numpy() == rd).all()
+    g2, m2, br2 = ann.ann_graph_from_candidates(bd, cand, cd2, R, 1.2)
+    torch.cuda.synchronize()
+    assert m2 == med and br2 == (nf, nr)
+    assert (g2.cpu().numpy() == ref).all()

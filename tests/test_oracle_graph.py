@@ -189,6 +189,37 @@ def test_repair_two_cycles_by_hand():
     assert (rg[mask] == g[mask]).all()
 
 
+def test_repair_listed_bridges_by_hand():
+    # the two cycles above; 3's list names 2 (not its nearest reached node 1)
+    # and 0, and 3's reverse bridge also comes from its list
+    base = np.array([[0, 0], [1, 0], [0, 1], [100, 0], [101, 0], [100, 1]], np.float32)
+    g = -np.ones((6, 4), np.int32)
+    g[0, 0], g[1, 0], g[2, 0] = 1, 2, 0
+    g[3, 0], g[4, 0], g[5, 0] = 4, 5, 3
+    cand = -np.ones((6, 3), np.int32)
+    cand[3] = [4, 2, 0]          # 4 is unreached: skipped; 2 is the first eligible
+    rg, nf, nr = oracle.repair(base, g, 0, cand)
+    assert nf == 1 and rg[2, 2] == 3 and rg[1, 2] == -1
+    assert nr == 1 and rg[3, 3] == 2
+    # an empty list falls back to the argmin
+    rg2, _, _ = oracle.repair(base, g, 0, -np.ones((6, 3), np.int32))
+    assert rg2[1, 2] == 3 and rg2[3, 3] == 1
+
+
+def test_repair_from_global_lists_equals_argmin_rule():
+    # with each point's exact global nearest neighbours as lists, the first
+    # eligible entry is the argmin over all eligible points
+    w = synth.scaled(synth.WORKLOADS["tiny"], n=1500)
+    base = synth.base(w)
+    cand, cd2 = oracle.knn(base, base, 64, exclude_self=True)
+    g = oracle.alpha_prune(base, cand, cd2, 16, 1.2)
+    m = oracle.medoid(base)
+    a = oracle.repair(base, g, m)
+    b = oracle.repair(base, g, m, cand)
+    assert a[1] > 0 and a[2] > 0
+    assert (a[0] == b[0]).all() and a[1:] == b[1:]
+
+
 def test_build_graph_strongly_connected_tiny():
     w = synth.scaled(synth.WORKLOADS["tiny"], n=1500)
     base = synth.base(w)
