@@ -23,10 +23,6 @@ struct KnnArgs {
     int32_t *out_ids;
     float *out_f;
     double *out_d;
-    const int8_t *b8;
-    const int32_t *bnorm;
-    const int8_t *q8;
-    const int32_t *qnorm;
 };
 
 // Workspace bytes for knn_run.

@@ -198,111 +198,390 @@ __global__ void __launch_bounds__(256) knn_f64_kernel(KnnArgs a)
 }
 
 // ---------------------------------------------------------------- int8 MFMA engine
-// Tile: 64 rows x 128 columns, k-steps of 32 bytes.  Wave w computes rows
-// [16w, 16w+16) against all 128 columns as 8 output blocks of 16x16.
-// v_mfma_i32_16x16x32_i8 operands: lane l supplies 8 bytes of row (l % 16)
-// of A (resp. column (l % 16) of B) at k offset 8 * (l / 16); the int32
+// Values are integers in [0, 255], shifted by -128 into int8; d2 = |x'|^2 +
+// |y'|^2 - 2 x'.y' is exact in int32 (below 2^24 for dim <= 256).
+//
+// A workgroup of 4 waves owns 256 query rows and one slice of the base
+// columns.  Wave w owns rows [64w, 64w + 64) as 4 blocks of 16 whose int8
+// operands stay in registers for the whole slice; the slice streams through
+// LDS in tiles of 64 columns (two buffers: the next tile is fetched while the
+// current one is multiplied), and each B fragment read from LDS feeds the
+// 4 row blocks.  v_mfma_i32_16x16x32_i8: lane l supplies 8 bytes of row
+// (l % 16) of A (resp. column (l % 16) of B) at k offset 8 * (l / 16); the
 // result element i of lane l is C[4 * (l / 16) + i][l % 16].
-constexpr int I_BN = 128;
-constexpr int I_MAXD = 256;
+//
+// Selection.  A slice is visited in increasing column order, so a column can
+// enter a row's best Kp only if its d2 is strictly below the Kp-th best d2
+// seen so far (an equal d2 loses the tie to the smaller id already held).
+// With t = |x'|^2 - thr per row, the test d2 < thr is 2 x'.y' - |y'|^2 > t:
+// one shift-add and one compare per distance, and a wave ballot skips the
+// append path when no lane passes.  Passing columns are appended to the
+// row's buffer (global memory, cap entries of (d2 << 32 | column)); before a
+// tile could overflow it, the owning wave sorts the buffer in LDS, keeps the
+// best Kp and tightens thr.  A second kernel merges the slices of each row,
+// drops the row's own column when asked, and writes the K best.
+namespace i8 {
+
+constexpr int kRowsWG = 256;
+constexpr int kCols = 64;
+constexpr int kMaxD = 256;
+constexpr int32_t kInf = 1 << 24;       // above every d2 of the data
+constexpr int32_t kPadNorm = 1 << 28;   // |y'|^2 of padding columns: never passes
+constexpr int kMaxMerged = 4096;        // slices x Kp entries merged per row
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) knn_i8_kernel(KnnArgs a)
-{
-    __shared__ __align__(16) int8_t Bs[I_BN][I_MAXD + 16];
-    __shared__ int32_t Bn[I_BN];
-    __shared__ RowState rs;
-    extern __shared__ __align__(16) unsigned char dyn[];
-    Ent *scratch = reinterpret_cast<Ent *>(dyn) + (threadIdx.x >> 6) * a.cap;
+struct Args {
+    const int8_t *b8;
+    const int32_t *bn;
+    int64_t n;
+    const int8_t *q8;
+    const int32_t *qn;
+    int64_t rows;
+    int Kp;               // entries kept per (row, slice)
+    int cap;              // buffer entries per (row, slice): power of two >= Kp + kCols
+    int slices;
+    int64_t slice_len;    // multiple of kCols
+    uint64_t *buf;        // rows x slices x cap
+    int32_t *cnt;         // rows x slices
+};
 
+__host__ __device__ inline size_t stride_for(int ks) { return (size_t)ks * 32 + 8; }
+
+__host__ inline size_t tile_lds(int ks, int cap)
+{
+    return round_up(2 * kCols * stride_for(ks), 16) + 2 * kCols * 4 + 3 * kRowsWG * 4 +
+           4 * (size_t)cap * 8;
+}
+
+// One wave: sort the c entries of g through LDS scratch s, keep the best Kp
+// in g (sorted); returns the kept count and sets thr to the Kp-th d2 (kInf
+// while fewer are held).
+__device__ inline int sort_keep(uint64_t *g, int c, int Kp, uint64_t *s, int32_t &thr)
+{
+    const int lane = __lane_id();
+    int P = 64;
+    while (P < c) P <<= 1;
+    for (int t = lane; t < P; t += 64) s[t] = t < c ? g[t] : ~0ull;
+    knn::wsync();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = lane; t < P / 2; t += 64) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t x = s[lo], y = s[hi];
+                if (up ? (y < x) : (x < y)) {
+                    s[lo] = y;
+                    s[hi] = x;
+                }
+            }
+            knn::wsync();
+        }
+    }
+    const int keep = c < Kp ? c : Kp;
+    for (int t = lane; t < keep; t += 64) g[t] = s[t];
+    thr = keep == Kp ? (int32_t)(s[Kp - 1] >> 32) : kInf;
+    knn::wsync();
+    return keep;
+}
+
+template <int KS>
+__global__ void __launch_bounds__(256) tiles_kernel(Args a)
+{
+    constexpr int STRIDE = KS * 32 + 8;
+    constexpr int CHUNKS = kCols * KS * 4;          // 8-byte chunks per tile
+    constexpr int PER_T = (CHUNKS + 255) / 256;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    int8_t *Bs = reinterpret_cast<int8_t *>(dyn);
+    int32_t *Bn = reinterpret_cast<int32_t *>(dyn + (2 * kCols * STRIDE + 15) / 16 * 16);
+    int32_t *r_an = Bn + 2 * kCols;
+    int32_t *r_thr = r_an + kRowsWG;
+    int32_t *r_cnt = r_thr + kRowsWG;
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = t & 63;
-    const int64_t row0 = (int64_t)blockIdx.x * knn::kRows;
-    const int ksteps = a.dim / 32;
-    if (t < knn::kRows) {
-        rs.thr[t] = knn::ent_max();
-        rs.cnt[t] = 0;
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(r_cnt + kRowsWG) + (size_t)w * a.cap;
+    const int64_t row0 = (int64_t)blockIdx.x * kRowsWG;
+    const int slice = blockIdx.y;
+    const int64_t c_begin = (int64_t)slice * a.slice_len;
+    int64_t c_end = c_begin + a.slice_len;
+    if (c_end > a.n) c_end = a.n;
+    const int ntiles = c_end > c_begin ? (int)((c_end - c_begin + kCols - 1) / kCols) : 0;
+    const int dim = KS * 32;
+
+    {
+        const int64_t g = row0 + t;
+        r_an[t] = g < a.rows ? a.qn[g] : 0;
+        r_thr[t] = kInf;
+        r_cnt[t] = 0;
     }
-    // A operand for all k-steps: row (16w + l%16), bytes 8*(l/16) + 32*s
-    long long areg[I_MAXD / 32];
-    const int64_t arow = row0 + 16 * w + (lane & 15);
-    for (int s = 0; s < I_MAXD / 32; ++s) {
-        long long v = 0;
-        if (s < ksteps && arow < a.rows)
-            v = *reinterpret_cast<const long long *>(a.q8 + arow * a.dim + 32 * s + 8 * (lane >> 4));
-        areg[s] = v;
+    // A operands: row block rb, k-step ks
+    long long areg[4][KS];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t g = row0 + 64 * w + 16 * rb + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            areg[rb][ks] = g < a.rows ? *reinterpret_cast<const long long *>(
+                                            a.q8 + g * dim + 32 * ks + 8 * (lane >> 4))
+                                      : 0ll;
     }
-    int32_t anorm[4];
-    int64_t selfc[4];
-    for (int i = 0; i < 4; ++i) {
-        int64_t g = row0 + 16 * w + 4 * (lane >> 4) + i;
-        anorm[i] = g < a.rows ? a.qnorm[g] : 0;
-        selfc[i] = self_column(a, g);
+    // t = |x'|^2 - thr of the 16 rows whose results this lane holds
+    int32_t tv[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t g = row0 + 64 * w + 16 * rb + 4 * (lane >> 4) + i;
+            tv[rb][i] = g < a.rows ? a.qn[g] - kInf : 0x7fffffff;
+        }
+
+    long long stage[PER_T];
+    int32_t stage_n = 0;
+    auto fetch = [&](int it) {
+        const int64_t c0 = c_begin + (int64_t)it * kCols;
+#pragma unroll
+        for (int e = 0; e < PER_T; ++e) {
+            const int ch = t + 256 * e;
+            long long v = 0;
+            if (ch < CHUNKS) {
+                const int c = ch / (KS * 4), j = ch % (KS * 4);
+                if (c0 + c < c_end)
+                    v = *reinterpret_cast<const long long *>(a.b8 + (c0 + c) * dim + 8 * j);
+            }
+            stage[e] = v;
+        }
+        if (t < kCols) stage_n = c0 + t < c_end ? a.bn[c0 + t] : kPadNorm;
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < PER_T; ++e) {
+            const int ch = t + 256 * e;
+            if (ch < CHUNKS) {
+                const int c = ch / (KS * 4), j = ch % (KS * 4);
+                *reinterpret_cast<long long *>(Bs + (size_t)(buf * kCols + c) * STRIDE + 8 * j) =
+                    stage[e];
+            }
+        }
+        if (t < kCols) Bn[buf * kCols + t] = stage_n;
+    };
+
+    if (ntiles > 0) {
+        fetch(0);
+        store(0);
     }
     __syncthreads();
-    const int chunks16 = a.dim / 16;
-    for (int64_t col0 = 0; col0 < a.n; col0 += I_BN) {
-        for (int e = t; e < I_BN * chunks16; e += 256) {
-            int c = e / chunks16, j = e % chunks16;
-            int64_t g = col0 + c;
-            v4i v = {0, 0, 0, 0};
-            if (g < a.n) v = *reinterpret_cast<const v4i *>(a.b8 + g * a.dim + 16 * j);
-            *reinterpret_cast<v4i *>(&Bs[c][16 * j]) = v;
-        }
-        for (int c = t; c < I_BN; c += 256) {
-            int64_t g = col0 + c;
-            Bn[c] = g < a.n ? a.bnorm[g] : 0;
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int blk = 0; blk < I_BN / 16; ++blk) {
-            v4i acc = {0, 0, 0, 0};
-            const int bc = 16 * blk + (lane & 15);
-            for (int s = 0; s < ksteps; ++s) {
-                long long bv = *reinterpret_cast<const long long *>(&Bs[bc][32 * s + 8 * (lane >> 4)]);
-                acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(areg[s], bv, acc, 0, 0, 0);
-            }
-            const int64_t col = col0 + bc;
-            if (col < a.n) {
-                const int32_t bn = Bn[bc];
+    for (int it = 0; it < ntiles; ++it) {
+        const int cur = it & 1;
+        if (it + 1 < ntiles) fetch(it + 1);
+        const int64_t c0 = c_begin + (int64_t)it * kCols;
+#pragma unroll 1
+        for (int cb = 0; cb < 4; ++cb) {
+            const int cl = 16 * cb + (lane & 15);
+            long long bf[KS];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    int lr = 16 * w + 4 * (lane >> 4) + i;
-                    int64_t g = row0 + lr;
-                    if (g >= a.rows || col == selfc[i]) continue;
-                    int32_t d2 = anorm[i] + bn - 2 * acc[i];
-                    offer(rs, a.buf, g, lr, a.cap, (uint64_t)(uint32_t)d2, (uint32_t)col);
+            for (int ks = 0; ks < KS; ++ks)
+                bf[ks] = *reinterpret_cast<const long long *>(
+                    Bs + (size_t)(cur * kCols + cl) * STRIDE + 32 * ks + 8 * (lane >> 4));
+            const int32_t bnc = Bn[cur * kCols + cl];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                v4i acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(areg[rb][ks], bf[ks], acc, 0, 0, 0);
+                bool p[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) p[i] = 2 * acc[i] - bnc > tv[rb][i];
+                if (__builtin_amdgcn_ballot_w64(p[0] | p[1] | p[2] | p[3])) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (!p[i]) continue;
+                        const int rl = 64 * w + 16 * rb + 4 * (lane >> 4) + i;
+                        const int32_t d2 = r_an[rl] + bnc - 2 * acc[i];
+                        const int slot = atomicAdd(&r_cnt[rl], 1);
+                        a.buf[((row0 + rl) * a.slices + slice) * (int64_t)a.cap + slot] =
+                            ((uint64_t)(uint32_t)d2 << 32) | (uint32_t)(c0 + cl);
+                    }
                 }
             }
         }
+        // sort the rows whose buffers could not take another tile
         knn::wsync();
-        merge_full_rows(rs, a.buf, row0, a.rows, a.cap, a.K, I_BN, scratch, false);
+        const int my = 64 * w + lane;
+        uint64_t full = __builtin_amdgcn_ballot_w64(r_cnt[my] > a.cap - kCols);
+        if (full) {
+            while (full) {
+                const int r = 64 * w + (int)__builtin_ctzll(full);
+                full &= full - 1;
+                int32_t thr;
+                uint64_t *g = a.buf + ((row0 + r) * a.slices + slice) * (int64_t)a.cap;
+                const int keep = sort_keep(g, r_cnt[r], a.Kp, scratch, thr);
+                if (lane == 0) {
+                    r_cnt[r] = keep;
+                    r_thr[r] = thr;
+                }
+                knn::wsync();
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int rl = 64 * w + 16 * rb + 4 * (lane >> 4) + i;
+                    if (row0 + rl < a.rows) tv[rb][i] = r_an[rl] - r_thr[rl];
+                }
+        }
+        if (it + 1 < ntiles) store(cur ^ 1);
         __syncthreads();
     }
-    merge_full_rows(rs, a.buf, row0, a.rows, a.cap, a.K, I_BN, scratch, true);
-    write_rows(rs, a.buf, row0, a.rows, a.cap, a.K, true, a.out_ids, a.out_f, a.out_d);
+    // final sort of every row of this wave; counts out
+    for (int r = 64 * w; r < 64 * w + 64; ++r) {
+        if (row0 + r >= a.rows) break;
+        int c = r_cnt[r];
+        if (c > 0) {
+            int32_t thr;
+            c = sort_keep(a.buf + ((row0 + r) * a.slices + slice) * (int64_t)a.cap, c, a.Kp,
+                          scratch, thr);
+        }
+        if (lane == 0) a.cnt[(row0 + r) * a.slices + slice] = c;
+    }
 }
+
+// One wave per row: the best Kp over the row's slices, the row's own column
+// dropped when asked, the first K written (-1 / +inf padded).
+__global__ void __launch_bounds__(64) select_kernel(const uint64_t *buf, const int32_t *cnt,
+                                                    int64_t rows, int slices, int cap, int Kp,
+                                                    int K, int exclude, const int32_t *self_col,
+                                                    int32_t *out_ids, float *out_f, double *out_d)
+{
+    extern __shared__ __align__(16) unsigned char dyn[];
+    uint64_t *s = reinterpret_cast<uint64_t *>(dyn);
+    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (g >= rows) return;
+    const uint64_t *list = buf + g * slices * (int64_t)cap;
+    int total;
+    if (slices == 1) {
+        total = cnt[g];
+    } else {
+        // concatenate the sorted slice lists, then sort (bitonic) through LDS
+        int c = 0;
+        for (int sl = 0; sl < slices; ++sl) {
+            const int m = cnt[g * slices + sl];
+            for (int t = lane; t < m; t += 64) s[c + t] = list[(int64_t)sl * cap + t];
+            c += m;
+        }
+        int P = 64;
+        while (P < c) P <<= 1;
+        for (int t = c + lane; t < P; t += 64) s[t] = ~0ull;
+        knn::wsync();
+        for (int size = 2; size <= P; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = lane; t < P / 2; t += 64) {
+                    const int lo = 2 * t - (t & (stride - 1));
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t x = s[lo], y = s[hi];
+                    if (up ? (y < x) : (x < y)) {
+                        s[lo] = y;
+                        s[hi] = x;
+                    }
+                }
+                knn::wsync();
+            }
+        total = c < Kp ? c : Kp;
+        list = s;
+    }
+    if (total > Kp) total = Kp;
+    // position of the row's own column among the first `total` entries
+    int self_at = total;
+    if (exclude) {
+        const uint32_t me = (uint32_t)(self_col ? self_col[g] : g);
+        for (int t = lane; t < total; t += 64)
+            if ((uint32_t)list[t] == me) self_at = t;
+        for (int o = 32; o > 0; o >>= 1) {
+            const int other = __shfl_xor(self_at, o);
+            self_at = other < self_at ? other : self_at;
+        }
+    }
+    const int have = total - (self_at < total ? 1 : 0);
+    for (int o = lane; o < K; o += 64) {
+        int32_t id = -1;
+        double v = __longlong_as_double(0x7ff0000000000000ll);
+        if (o < have) {
+            const uint64_t e = list[o < self_at ? o : o + 1];
+            id = (int32_t)(uint32_t)e;
+            v = (double)(int32_t)(e >> 32);
+        }
+        out_ids[g * K + o] = id;
+        if (out_f) out_f[g * K + o] = (float)v;
+        if (out_d) out_d[g * K + o] = v;
+    }
+}
+
+struct Plan {
+    int Kp, cap, slices;
+    int64_t slice_len;
+};
+
+Plan plan(int64_t n, int64_t rows, int K)
+{
+    Plan p{};
+    p.Kp = K + 1;          // room for the row's own column
+    p.cap = 64;
+    while (p.cap < p.Kp + kCols) p.cap <<= 1;
+    const int64_t blocks = (rows + kRowsWG - 1) / kRowsWG;
+    int64_t s = (2048 + blocks - 1) / (blocks > 0 ? blocks : 1);
+    const int64_t by_len = n / 4096 > 1 ? n / 4096 : 1;
+    const int64_t by_merge = kMaxMerged / p.Kp > 1 ? kMaxMerged / p.Kp : 1;
+    if (s > by_len) s = by_len;
+    if (s > by_merge) s = by_merge;
+    if (s < 1) s = 1;
+    p.slice_len = ((n + s - 1) / s + kCols - 1) / kCols * kCols;
+    p.slices = (int)((n + p.slice_len - 1) / p.slice_len);
+    if (p.slices < 1) p.slices = 1;
+    return p;
+}
+
+size_t workspace(int64_t n, int64_t rows, int dim, int K)
+{
+    const Plan p = plan(n, rows, K);
+    size_t b = round_up((size_t)rows * p.slices * p.cap * 8, 256);
+    b += round_up((size_t)rows * p.slices * 4, 256);
+    b += round_up((size_t)n * dim, 256) + round_up((size_t)n * 4, 256);
+    b += round_up((size_t)rows * dim, 256) + round_up((size_t)rows * 4, 256);
+    return b + 256;
+}
+
+template <int KS>
+ann_status launch_tiles(const Args &a, hipStream_t st)
+{
+    const size_t lds = tile_lds(KS, a.cap);
+    ANN_HIP(hipFuncSetAttribute((const void *)tiles_kernel<KS>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    dim3 grid((unsigned)((a.rows + kRowsWG - 1) / kRowsWG), (unsigned)a.slices);
+    hipLaunchKernelGGL(tiles_kernel<KS>, grid, dim3(256), lds, st, a);
+    ANN_LAUNCHED();
+    return ANN_OK;
+}
+
+}  // namespace i8
 
 }  // namespace
 
-size_t knn_cap(int K, bool int_engine)
+size_t knn_cap(int K)
 {
-    int tile = int_engine ? I_BN : F_BN;
     size_t c = 2;
-    while (c < (size_t)(K + tile)) c <<= 1;
+    while (c < (size_t)(K + F_BN)) c <<= 1;
     return c;
 }
 
 size_t knn_workspace(int64_t n, int64_t rows, int dim, int K)
 {
-    size_t cap = knn_cap(K, true) > knn_cap(K, false) ? knn_cap(K, true) : knn_cap(K, false);
-    size_t b = round_up((size_t)rows * cap * sizeof(Ent), 256);
-    b += round_up((size_t)n * dim, 256) + round_up((size_t)n * 4, 256);        // base int8 + norms
-    b += round_up((size_t)rows * dim, 256) + round_up((size_t)rows * 4, 256);  // query int8 + norms
-    b += 256;
-    return b;
+    const size_t f64 = round_up((size_t)rows * knn_cap(K) * sizeof(Ent), 256) + 256;
+    const size_t i8b = i8::workspace(n, rows, dim, K);
+    return (f64 > i8b ? f64 : i8b) + 256;
 }
 
 ann_status data_is_uint8(const float *x, int64_t count, int *flag_dev, bool *result, hipStream_t st)
@@ -328,23 +607,12 @@ ann_status knn_run(const float *base, int64_t n, int dim, const float *queries, 
                    const int32_t *self_col)
 {
     ANN_REQUIRE(ws_bytes >= knn_workspace(n, rows, dim, K), "kNN workspace too small");
+    if (rows == 0) return ANN_OK;
     unsigned char *p = static_cast<unsigned char *>(ws);
-    size_t cap_i = knn_cap(K, true), cap_f = knn_cap(K, false);
-    size_t cap = cap_i > cap_f ? cap_i : cap_f;
-    Ent *buf = reinterpret_cast<Ent *>(p);
-    p += round_up((size_t)rows * cap * sizeof(Ent), 256);
-    int8_t *b8 = reinterpret_cast<int8_t *>(p);
-    p += round_up((size_t)n * dim, 256);
-    int32_t *bn = reinterpret_cast<int32_t *>(p);
-    p += round_up((size_t)n * 4, 256);
-    int8_t *q8 = reinterpret_cast<int8_t *>(p);
-    p += round_up((size_t)rows * dim, 256);
-    int32_t *qn = reinterpret_cast<int32_t *>(p);
-    p += round_up((size_t)rows * 4, 256);
     int *flag = reinterpret_cast<int *>(p);
-
+    p += 256;
     bool use_int = false;
-    if (force_engine != 2 && dim % 32 == 0 && dim <= I_MAXD) {
+    if (force_engine != 2 && dim % 32 == 0 && dim <= i8::kMaxD) {
         bool bu = false, qu = false;
         ann_status s = data_is_uint8(base, n * dim, flag, &bu, st);
         if (s != ANN_OK) return s;
@@ -355,39 +623,72 @@ ann_status knn_run(const float *base, int64_t n, int dim, const float *queries, 
         use_int = bu && qu;
     }
     if (force_engine == 1 && !use_int) return fail(ANN_EINVAL, "int8 engine needs integer data in [0,255]");
-    KnnArgs a{};
-    a.base = base;
-    a.n = n;
-    a.dim = dim;
-    a.queries = queries;
-    a.rows = rows;
-    a.K = K;
-    a.exclude_self = exclude_self ? 1 : 0;
-    a.self_col = self_col;
-    a.buf = buf;
-    a.out_ids = out_ids;
-    a.out_f = out_f;
-    a.out_d = out_d;
-    const int blocks = (int)((rows + knn::kRows - 1) / knn::kRows);
     if (use_int) {
-        a.cap = (int)cap_i;
-        hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n, dim,
-                           b8, bn);
+        const i8::Plan pl = i8::plan(n, rows, K);
+        i8::Args a{};
+        a.buf = reinterpret_cast<uint64_t *>(p);
+        p += round_up((size_t)rows * pl.slices * pl.cap * 8, 256);
+        a.cnt = reinterpret_cast<int32_t *>(p);
+        p += round_up((size_t)rows * pl.slices * 4, 256);
+        int8_t *b8 = reinterpret_cast<int8_t *>(p);
+        p += round_up((size_t)n * dim, 256);
+        int32_t *bn = reinterpret_cast<int32_t *>(p);
+        p += round_up((size_t)n * 4, 256);
+        int8_t *q8 = reinterpret_cast<int8_t *>(p);
+        p += round_up((size_t)rows * dim, 256);
+        int32_t *qn = reinterpret_cast<int32_t *>(p);
+        hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n,
+                           dim, b8, bn);
         ANN_LAUNCHED();
-        hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, queries,
-                           rows, dim, q8, qn);
+        hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st,
+                           queries, rows, dim, q8, qn);
         ANN_LAUNCHED();
         a.b8 = b8;
-        a.bnorm = bn;
+        a.bn = bn;
+        a.n = n;
         a.q8 = q8;
-        a.qnorm = qn;
-        size_t lds = 4 * (size_t)a.cap * sizeof(Ent);
-        ANN_HIP(hipFuncSetAttribute((const void *)knn_i8_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(knn_i8_kernel, dim3(blocks), dim3(256), lds, st, a);
+        a.qn = qn;
+        a.rows = rows;
+        a.Kp = pl.Kp;
+        a.cap = pl.cap;
+        a.slices = pl.slices;
+        a.slice_len = pl.slice_len;
+        ann_status s = ANN_OK;
+        switch (dim / 32) {
+        case 1: s = i8::launch_tiles<1>(a, st); break;
+        case 2: s = i8::launch_tiles<2>(a, st); break;
+        case 3: s = i8::launch_tiles<3>(a, st); break;
+        case 4: s = i8::launch_tiles<4>(a, st); break;
+        case 5: s = i8::launch_tiles<5>(a, st); break;
+        case 6: s = i8::launch_tiles<6>(a, st); break;
+        case 7: s = i8::launch_tiles<7>(a, st); break;
+        default: s = i8::launch_tiles<8>(a, st); break;
+        }
+        if (s != ANN_OK) return s;
+        const size_t lds = pl.slices > 1 ? (size_t)i8::kMaxMerged * 8 : 0;
+        if (lds)
+            ANN_HIP(hipFuncSetAttribute((const void *)i8::select_kernel,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(i8::select_kernel, dim3((unsigned)rows), dim3(64), lds, st, a.buf, a.cnt,
+                           rows, pl.slices, pl.cap, pl.Kp, K, exclude_self ? 1 : 0, self_col,
+                           out_ids, out_f, out_d);
         ANN_LAUNCHED();
     } else {
-        a.cap = (int)cap_f;
+        KnnArgs a{};
+        a.base = base;
+        a.n = n;
+        a.dim = dim;
+        a.queries = queries;
+        a.rows = rows;
+        a.K = K;
+        a.exclude_self = exclude_self ? 1 : 0;
+        a.self_col = self_col;
+        a.buf = reinterpret_cast<Ent *>(p);
+        a.out_ids = out_ids;
+        a.out_f = out_f;
+        a.out_d = out_d;
+        a.cap = (int)knn_cap(K);
+        const int blocks = (int)((rows + knn::kRows - 1) / knn::kRows);
         size_t lds = 4 * (size_t)a.cap * sizeof(Ent);
         ANN_HIP(hipFuncSetAttribute((const void *)knn_f64_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

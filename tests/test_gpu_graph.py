@@ -56,6 +56,42 @@ def test_gt_knn_ragged_shapes(n, nq, d, k, ints):
     assert (dist.cpu().numpy()[ref_ids >= 0] == ref_d2[ref_ids >= 0].astype(np.float32)).all()
 
 
+@pytest.mark.parametrize("n,nq,d,k,vmax", [
+    (70_000, 300, 32, 10, 255),      # 17 column slices merged per row
+    (20_000, 50, 256, 100, 255),     # widest rows, 4 slices
+    (9_000, 700, 96, 300, 255),      # 2 slices of 301 kept entries
+    (130, 600, 64, 200, 255),        # k above n: -1 padded
+    (5_000, 3, 128, 1024, 255),      # largest k
+    (20_000, 64, 160, 50, 3),        # values 0..3: long runs of equal distances
+])
+def test_int8_engine_slices_and_ties(n, nq, d, k, vmax):
+    r = np.random.default_rng(n + d)
+    base = r.integers(0, vmax + 1, size=(n, d)).astype(np.float32)
+    q = r.integers(0, vmax + 1, size=(nq, d)).astype(np.float32)
+    say("case: int8 kNN n=%d nq=%d d=%d k=%d values 0..%d" % (n, nq, d, k, vmax))
+    ids, dist = _ann().ann_gt_knn(_dev(base), _dev(q), k)
+    torch.cuda.synchronize()
+    ref_ids, ref_d2 = oracle.knn(base, q, k)
+    assert (ids.cpu().numpy() == ref_ids).all()
+    ok = ref_ids >= 0
+    assert (dist.cpu().numpy()[ok] == ref_d2[ok].astype(np.float32)).all()
+    assert np.isinf(dist.cpu().numpy()[~ok]).all()
+
+
+def test_int8_engine_exclude_self_with_duplicates():
+    # rows repeated several times: the row's own column is dropped, its
+    # duplicates stay (distance 0, by id)
+    r = np.random.default_rng(11)
+    base = r.integers(0, 256, size=(3000, 64)).astype(np.float32)
+    base[1000:1040] = base[5]
+    say("case: int8 kNN exclude_self with 41 copies of one row")
+    ids, dist = _ann().ann_gt_knn(_dev(base), _dev(base), 60, exclude_self=True)
+    torch.cuda.synchronize()
+    ref_ids, ref_d2 = oracle.knn(base, base, 60, exclude_self=True)
+    assert (ids.cpu().numpy() == ref_ids).all()
+    assert (dist.cpu().numpy() == ref_d2.astype(np.float32)).all()
+
+
 def test_gt_knn_duplicates_tie_by_id_and_exclude_self():
     r = np.random.default_rng(3)
     base = r.integers(0, 4, size=(500, 32)).astype(np.float32)   # many exact ties
