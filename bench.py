@@ -134,9 +134,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--R", type=int, default=32, help="graph out-degree")
     ap.add_argument("--knn-k", type=int, default=128, help="kNN candidates before pruning")
-    ap.add_argument("--partitions", type=int, default=-1,
-                    help="candidate lists from this many overlapping k-means groups "
-                         "(-1: 0 up to N = 2M, else one group per 312,500 points)")
+    ap.add_argument("--partitions", type=int, default=0,
+                    help="candidate lists from this many overlapping k-means groups instead of "
+                         "the all-pairs kNN (0: all pairs)")
     ap.add_argument("--overlap", type=int, default=2, help="groups listed per point")
     ap.add_argument("--hubs", type=int, default=1024)
     ap.add_argument("--hidden", type=int, default=128)
@@ -168,8 +168,7 @@ def main():
     if args.n or args.n_train:
         w = synth.scaled(w, n=args.n or None, n_train=args.n_train or None)
     knn_k, R, k = args.knn_k, args.R, 10
-    parts = args.partitions if args.partitions >= 0 else (0 if w.n <= 2_000_000 else
-                                                          w.n // 312_500)
+    parts = args.partitions
 
     t0 = time.time()
     base = synth.base(w)

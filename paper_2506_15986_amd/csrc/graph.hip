@@ -221,6 +221,7 @@ __global__ void __launch_bounds__(DRV) repair_driver(int32_t *graph, int64_t n, 
     __shared__ int64_t s_head, s_tail, s_cursor;
     __shared__ int32_t s_found;
     __shared__ int32_t s_u;
+    __shared__ int32_t s_pos;
     const int t = threadIdx.x;
     if (t == 0) {
         s_head = st->head;
@@ -283,19 +284,20 @@ __global__ void __launch_bounds__(DRV) repair_driver(int32_t *graph, int64_t n, 
             return;
         }
         const int32_t u = s_u;
+        // first eligible entry of u's candidate list: each thread tests one
+        // position, the smallest eligible position wins (lists end in -1)
         if (t == 0) {
             s_cursor = u;
-            s_found = -1;
-            // first eligible node on u's exact kNN list
-            for (int q = 0; q < K; ++q) {
-                int32_t v = cand[(int64_t)u * K + q];
-                if (v < 0) break;
-                if (ld_mark(&mark[v]) && (phase == 1 || graph[(int64_t)v * R + slot] < 0)) {
-                    s_found = v;
-                    break;
-                }
-            }
+            s_pos = kNone;
         }
+        __syncthreads();
+        for (int q = t; q < K; q += DRV) {
+            const int32_t v = cand[(int64_t)u * K + q];
+            if (v >= 0 && ld_mark(&mark[v]) && (phase == 1 || graph[(int64_t)v * R + slot] < 0))
+                atomicMin(&s_pos, q);
+        }
+        __syncthreads();
+        if (t == 0) s_found = s_pos != kNone ? cand[(int64_t)u * K + s_pos] : -1;
         __syncthreads();
         if (s_found < 0) {
             if (t == 0) {
