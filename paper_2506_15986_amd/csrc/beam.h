@@ -106,6 +106,20 @@ __device__ inline int lower_bound_uniform(const K *ak, const uint32_t *ai, int c
     return lo;
 }
 
+// number of entries <= x in the non-decreasing a[0..cnt), by fixed steps
+// (the same number for every lane when cnt is uniform)
+__device__ inline int count_at_most(const int32_t *a, int cnt, int x)
+{
+    int lo = 0;
+    if (cnt <= 0) return 0;
+    for (int step = 1 << (31 - __builtin_clz((unsigned)cnt)); step > 0; step >>= 1) {
+        const int probe = lo + step - 1;
+        const bool in = probe < cnt && a[probe < cnt ? probe : cnt - 1] <= x;
+        lo += in ? step : 0;
+    }
+    return lo;
+}
+
 // value of v in lane t (t uniform across the wavefront)
 __device__ inline uint32_t readlane(uint32_t v, int t)
 {

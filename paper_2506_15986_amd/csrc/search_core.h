@@ -212,10 +212,11 @@ struct Searcher {
     {
         const int lane = beam::lane_id();
         // ---- merge the new keys into the pool.  A new key's place is its
-        // insertion point in the old pool plus its rank among the new keys;
-        // an old entry moves down by the number of new keys inserted at or
-        // before it.  Both counts come from a scalar loop over the new keys
-        // (readlane), so no sort of the staging row is needed.
+        // insertion point in the old pool plus its rank among the new keys
+        // (a scalar loop over the new keys, readlane); an old entry moves
+        // down by the number of new keys inserted at or before it.  The
+        // insertion points, stored by rank, are non-decreasing, so that
+        // number is a binary search over them.
         K *ak = keys(cur);
         uint32_t *ai = ids(cur);
         K kk = KT::kMax;
@@ -258,18 +259,18 @@ struct Searcher {
             bk[pos + rank] = kk;
             bi[pos + rank] = ii;
         }
+        // insertion points by rank (the staging ids are in registers now)
+        int32_t *sp = reinterpret_cast<int32_t *>(si);
+        if (valid) sp[rank] = pos;
+        beam::wave_sync();
         for (int j = lane; j < cnt; j += 64) {
-            int f = j;
-            for (uint64_t mm = vmask; mm; mm &= mm - 1)
-                if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= j) ++f;
+            const int f = j + beam::count_at_most(sp, mv, j);
             if (f < Lq) {
                 bk[f] = ak[j];
                 bi[f] = ai[j];
             }
         }
-        int oc = cursor;
-        for (uint64_t mm = vmask; mm; mm &= mm - 1)
-            if (beam::readlane(pos, __ffsll((unsigned long long)mm) - 1) <= cursor) ++oc;
+        const int oc = cursor + beam::count_at_most(sp, mv, cursor);
         cursor = f0 < oc ? f0 : oc;
         cnt = (cnt + mv < Lq) ? cnt + mv : Lq;
         cur ^= 1;
