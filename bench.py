@@ -79,19 +79,22 @@ def search_source_hash() -> str:
 def measured_traffic(workload: str, L: int, nq: int, plan: dict):
     """HBM bytes per search launch (reads, writes) from the committed counter
     summary, when it was taken on this kernel version, workload, L, batch and
-    plan."""
+    plan.  The plan must agree in gather group, filter form and size; the
+    wavefronts per workgroup only change how waves are packed, not what a
+    query reads, so they are not compared."""
     path = os.path.join(ROOT, "profiles", "search_kernel_%s.md" % workload)
     if not os.path.exists(path):
         return None
-    want = dict(kernel_hash=search_source_hash(), L=str(L), nq=str(nq),
-                plan="%d/%d/%d/%d" % (plan["group"], plan["visited_log2"], plan["waves_per_block"],
-                                      plan["filter"]))
+    want = dict(kernel_hash=search_source_hash(), L=str(L), nq=str(nq))
     for line in open(path):
         m = re.match(r"^traffic:\s*(.*)$", line.strip())
         if not m:
             continue
         kv = dict(p.split("=", 1) for p in m.group(1).split() if "=" in p)
-        if all(kv.get(a) == b for a, b in want.items()):
+        pl = kv.get("plan", "").split("/")
+        if (all(kv.get(a) == b for a, b in want.items()) and len(pl) == 4 and
+                pl[0] == str(plan["group"]) and pl[1] == str(plan["visited_log2"]) and
+                pl[3] == str(plan["filter"]) and plan.get("waves_per_query", 1) in (0, 1)):
             return float(kv["read_bytes"]), float(kv["write_bytes"])
     return None
 
