@@ -144,10 +144,10 @@ __device__ inline float dpp_move(float x)
 template <int G>
 __device__ inline float group_sum(float v)
 {
-    static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+    static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
     v += dpp_move<0xB1>(v);     // quad_perm [1,0,3,2]
     v += dpp_move<0x4E>(v);     // quad_perm [2,3,0,1]
-    v += dpp_move<0x141>(v);    // row_half_mirror
+    if (G >= 8) v += dpp_move<0x141>(v);    // row_half_mirror
     if (G == 16) v += dpp_move<0x140>(v);   // row_mirror
     return v;
 }

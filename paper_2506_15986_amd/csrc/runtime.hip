@@ -45,11 +45,11 @@ struct EventPair {
 
 }  // namespace
 
-// one reference result per gather group (8, 16)
+// one reference result per gather group (4, 8, 16)
 size_t autotune_ws(int64_t n, int dim, int nq, int k_max)
 {
     size_t b = round_up(ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0), 256);
-    b += round_up((size_t)nq * k_max * 4, 256) * 4;
+    b += round_up((size_t)nq * k_max * 4, 256) * 6;
     b += 256;
     return b;
 }
@@ -98,8 +98,9 @@ extern "C" int32_t ann_autotune_candidates(int64_t n, int32_t dim, int32_t R, in
     if (ann_default_plan(n, dim, R, L_max, &base) != ANN_OK) return 0;
     std::vector<ann_search_plan> out;
     out.push_back(base);    // the default plan first: the reference for the result check
-    const int groups[2] = {8, 16};
+    const int groups[3] = {4, 8, 16};
     for (int g : groups) {
+        if (g == 4 && dim > 64) continue;
         if (g == 8 && dim > 128) continue;
         for (int vl = 10; vl <= 13; ++vl) {
             for (int wpb = 1; wpb <= 4; wpb *= 2) {
@@ -155,9 +156,9 @@ extern "C" ann_status ann_autotune_search(const float *base, int64_t n, int32_t 
     const size_t sws = ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0);
     void *search_ws = cv.take<unsigned char>(sws);
     const int64_t cells = (int64_t)nq * k_max;
-    int32_t *ref_ids[2];
-    float *ref_dist[2];
-    for (int r = 0; r < 2; ++r) {
+    int32_t *ref_ids[3];
+    float *ref_dist[3];
+    for (int r = 0; r < 3; ++r) {
         ref_ids[r] = cv.take<int32_t>((size_t)cells);
         ref_dist[r] = cv.take<float>((size_t)cells);
     }
@@ -183,7 +184,7 @@ extern "C" ann_status ann_autotune_search(const float *base, int64_t n, int32_t 
     // plans with the same gather group sum every distance in the same order,
     // so their results must agree bit for bit; across groups the FP32 order
     // differs (exact data aside), so each group is checked against its first
-    int first[2] = {-1, -1}, bestc = -1;
+    int first[3] = {-1, -1, -1}, bestc = -1;
     float best_ms = 0.0f;
     for (int c = 0; c < n_cand; ++c) {
         if (!runs[c]) continue;
@@ -204,7 +205,7 @@ extern "C" ann_status ann_autotune_search(const float *base, int64_t n, int32_t 
         ANN_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         ms /= (float)reps;
         if (times_ms) times_ms[c] = ms;
-        const int gi = plans[c].group == 8 ? 0 : 1;
+        const int gi = plans[c].group == 4 ? 2 : plans[c].group == 8 ? 0 : 1;
         if (first[gi] < 0) {
             first[gi] = c;
             hipLaunchKernelGGL(tune_copy_kernel, dim3(grid_for(cells)), dim3(256), 0, st, out_ids,

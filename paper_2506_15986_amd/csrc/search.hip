@@ -116,6 +116,13 @@ template <bool F64>
 ann_status dispatch(const SearchArgs &a, int group, int blocks, int wpb, hipStream_t st)
 {
     const int chunks = a.dim / 4;
+    if (group == 4) {
+        int cpl = (chunks + 3) / 4;
+        if (cpl <= 1) return launch_search<4, 1, F64>(a, blocks, wpb, st);
+        if (cpl <= 2) return launch_search<4, 2, F64>(a, blocks, wpb, st);
+        if (cpl <= 4) return launch_search<4, 4, F64>(a, blocks, wpb, st);
+        return fail(ANN_ENOTSUP, "group 4 supports dim <= 64 (got %d)", a.dim);
+    }
     if (group == 8) {
         int cpl = (chunks + 7) / 8;
         switch (cpl) {
@@ -143,7 +150,7 @@ ann_status validate_plan(const ann_search_plan &p)
 {
     ANN_REQUIRE(p.pool_cap >= 1 && p.pool_cap <= 512, "plan.pool_cap must be in [1,512]");
     ANN_REQUIRE(p.visited_log2 >= 8 && p.visited_log2 <= 14, "plan.visited_log2 must be in [8,14]");
-    ANN_REQUIRE(p.group == 8 || p.group == 16, "plan.group must be 8 or 16");
+    ANN_REQUIRE(p.group == 4 || p.group == 8 || p.group == 16, "plan.group must be 4, 8 or 16");
     ANN_REQUIRE(p.waves_per_block == 1 || p.waves_per_block == 2 || p.waves_per_block == 4,
                 "plan.waves_per_block must be 1, 2 or 4");
     ANN_REQUIRE(p.blocks >= 0, "plan.blocks must be >= 0");
@@ -270,6 +277,8 @@ ann_status search_check(const float *base, int64_t n, int32_t dim, const int32_t
     }
     ann_status s = validate_plan(p);
     if (s != ANN_OK) return s;
+    ANN_SUPPORTED(p.group != 4 || dim <= 64, "group 4 supports dim <= 64 (got %d)", dim);
+    ANN_SUPPORTED(p.group != 8 || dim <= 128, "group 8 supports dim <= 128 (got %d)", dim);
     FilterShape f{};
     s = search_filter(p, n, f);
     if (s != ANN_OK) return s;

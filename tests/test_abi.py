@@ -78,6 +78,12 @@ def test_search_rejects_bad_arguments_before_any_device_work(lib):
     assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
     bad.waves_per_block = 2                      # group 8 cannot share a query
     assert call(plan=ctypes.byref(bad)) == ann.ANN_ENOTSUP
+    bad.waves_per_query, bad.waves_per_block, bad.group = 1, 1, 4
+    assert call(plan=ctypes.byref(bad), dim=68) == ann.ANN_ENOTSUP   # group 4: dim <= 64
+    bad.group = 8
+    assert call(plan=ctypes.byref(bad), dim=132) == ann.ANN_ENOTSUP  # group 8: dim <= 128
+    bad.group = 12
+    assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
     # nq == 0 is valid and enqueues nothing
     assert call(nq=0) == ann.ANN_OK
 

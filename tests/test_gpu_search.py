@@ -262,3 +262,26 @@ def test_several_waves_per_query_equal_one_wave_on_float_data(W):
     assert (one["dist"].view(np.uint32) == many["dist"].view(np.uint32)).all()
     assert (one["stats"] == many["stats"]).all()
     assert (one["trace"] == many["trace"]).all()
+
+
+@pytest.mark.parametrize("d", [16, 32, 48, 64])
+def test_group4_matches_oracle(d):
+    # four lanes per vector (one quad), up to 64 dimensions: FP64 mode gives
+    # the oracle's ids, distances, counts and expansion order bit for bit on
+    # 16..64-dimensional integer data (d = 48 leaves the last chunk slot of
+    # each lane empty)
+    r = np.random.default_rng(d)
+    n, nq, L = 3000, 64, 40
+    base = r.integers(0, 256, size=(n, d)).astype(np.float32)
+    q = r.integers(0, 256, size=(nq, d)).astype(np.float32)
+    g, med, *_ = oracle.build_graph(base, knn_k=32, R=16, alpha=1.2)
+    ix = dict(base=base, graph=g, q=q, medoid=med)
+    say("case: group 4, d=%d" % d)
+    ref = oracle.search(base, g, q, med, 10, L, trace_cap=256)
+    for fp64 in (1, 0):
+        got = _run(ix, None, [10] * nq, [L] * nq, _plan(ix, L, group=4, fp64=fp64), trace_cap=256)
+        assert (got["ids"] == ref["ids"]).all(), fp64
+        assert (got["stats"][:, 1] == ref["ndc"]).all(), fp64
+        assert (got["stats"][:, 2] == ref["hops"]).all(), fp64
+        assert (got["trace"] == ref["trace"]).all(), fp64
+        assert (got["dist"] == ref["d2"].astype(np.float32)).all(), fp64
