@@ -413,7 +413,7 @@ def main():
         nqm = qm.shape[0]
         Lk = {}
         for kq, grid in ((10, [L] + [x for x in L_SWEEP if x > L]),
-                         (100, [x for x in L_SWEEP if x >= 100])):
+                         (100, [x for x in L_SWEEP if x >= 100] + [640, 768, 896, 1024])):
             kt = torch.full((nqm,), kq, dtype=torch.int32, device=dev)
             Lk[kq] = None
             for Lx in grid:

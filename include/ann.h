@@ -84,7 +84,7 @@ size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t p0, int32_
  * defaults from ann_default_plan() or tuned values from
  * ann_autotune_search(); all fields are plain values. */
 typedef struct ann_search_plan {
-    int32_t pool_cap;        /* largest beam width L the launch supports (<= 512) */
+    int32_t pool_cap;        /* largest beam width L the launch supports (<= 1024) */
     int32_t visited_log2;    /* LDS visited filter = 2^visited_log2 slots (8..14) */
     int32_t group;           /* lanes that cooperate on one vector gather: 4 (dim <= 64), 8 (dim <= 128) or 16 */
     int32_t waves_per_block; /* 1, 2 or 4 independent wavefronts per workgroup */

@@ -93,7 +93,7 @@ struct ann_query_graph {
 extern "C" int32_t ann_autotune_candidates(int64_t n, int32_t dim, int32_t R, int32_t L_max,
                                            ann_search_plan *plans, int32_t cap)
 {
-    if (n < 1 || dim < 1 || R < 1 || L_max < 1 || L_max > 512) return 0;
+    if (n < 1 || dim < 1 || R < 1 || L_max < 1 || L_max > 1024) return 0;
     ann_search_plan base{};
     if (ann_default_plan(n, dim, R, L_max, &base) != ANN_OK) return 0;
     std::vector<ann_search_plan> out;

@@ -148,7 +148,7 @@ ann_status dispatch(const SearchArgs &a, int group, int blocks, int wpb, hipStre
 
 ann_status validate_plan(const ann_search_plan &p)
 {
-    ANN_REQUIRE(p.pool_cap >= 1 && p.pool_cap <= 512, "plan.pool_cap must be in [1,512]");
+    ANN_REQUIRE(p.pool_cap >= 1 && p.pool_cap <= 1024, "plan.pool_cap must be in [1,1024]");
     ANN_REQUIRE(p.visited_log2 >= 8 && p.visited_log2 <= 14, "plan.visited_log2 must be in [8,14]");
     ANN_REQUIRE(p.group == 4 || p.group == 8 || p.group == 16, "plan.group must be 4, 8 or 16");
     ANN_REQUIRE(p.waves_per_block == 1 || p.waves_per_block == 2 || p.waves_per_block == 4,
@@ -228,7 +228,7 @@ extern "C" ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_
 {
     ANN_REQUIRE(plan != nullptr, "plan is NULL");
     ANN_REQUIRE(n >= 1 && dim >= 1 && R >= 1 && L_max >= 1, "n, dim, R, L_max must be >= 1");
-    ANN_SUPPORTED(L_max <= 512, "L_max %d exceeds 512", L_max);
+    ANN_SUPPORTED(L_max <= 1024, "L_max %d exceeds 1024", L_max);
     ann_search_plan p{};
     p.pool_cap = (L_max + 15) / 16 * 16;
     p.visited_log2 = 12;

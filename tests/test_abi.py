@@ -67,7 +67,7 @@ def test_search_rejects_bad_arguments_before_any_device_work(lib):
     assert call(base=odd) == ann.ANN_EINVAL
     assert call(wsb=16) == ann.ANN_EINVAL
     assert call(k_max=0) == ann.ANN_EINVAL
-    bad = ann.ann_search_plan(pool_cap=1024, visited_log2=12, group=8, waves_per_block=1,
+    bad = ann.ann_search_plan(pool_cap=1040, visited_log2=12, group=8, waves_per_block=1,
                               blocks=0, fp64=0)
     assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
     bad.pool_cap, bad.group = 64, 12
@@ -95,8 +95,9 @@ def test_default_plan_and_workspace():
     p = ann.default_plan(1_000_000, 960, 64, 400)
     assert p.pool_cap == 400 and p.group == 16
     assert ann.default_plan(10, 32, 16, 1).pool_cap == 16
+    assert ann.default_plan(10, 32, 16, 600).pool_cap == 608
     with pytest.raises(ann.AnnError):
-        ann.default_plan(10, 32, 16, 600)
+        ann.default_plan(10, 32, 16, 1025)
     assert ann.workspace_size("search", 1000, 32, 10) >= 4
 
 
@@ -162,7 +163,7 @@ def test_autotune_candidates():
     # wide vectors: group 16 only
     c = ann.ann_autotune_candidates(1_000_000, 960, 64, 100)
     assert len(c) == 12 + 8 and {p.group for p in c} == {16}
-    assert ann.ann_autotune_candidates(10, 32, 16, 600) == []
+    assert ann.ann_autotune_candidates(10, 32, 16, 1025) == []
 
 
 def test_batch_driver_rejects_bad_arguments_without_gpu_work():

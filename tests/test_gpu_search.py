@@ -285,3 +285,18 @@ def test_group4_matches_oracle(d):
         assert (got["stats"][:, 2] == ref["hops"]).all(), fp64
         assert (got["trace"] == ref["trace"]).all(), fp64
         assert (got["dist"] == ref["d2"].astype(np.float32)).all(), fp64
+
+
+def test_pool_wider_than_512_matches_oracle():
+    # beam widths up to the 1024-entry pool (k = 100 at 10M points needs them)
+    ix = int_index()
+    nq = 24
+    q = ix["q"][:nq]
+    sub = dict(ix, q=q)
+    say("case: L = 700 and 1024, k = 100")
+    for L in (700, 1024):
+        ref = oracle.search(ix["base"], ix["graph"], q, ix["medoid"], 100, L)
+        got = _run(sub, None, [100] * nq, [L] * nq, _plan(ix, L))
+        assert (got["ids"] == ref["ids"]).all(), L
+        assert (got["stats"][:, 2] == ref["hops"]).all(), L
+        assert (got["dist"] == ref["d2"].astype(np.float32)).all(), L
