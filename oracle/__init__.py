@@ -56,6 +56,8 @@ def _declare(L):
     L.oracle_kmeans_hubs.argtypes = [_P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
                                      _P, _P, _P]
     L.oracle_kmeans_hubs.restype = ctypes.c_int
+    L.oracle_hbkm.argtypes = [_P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F64,
+                              ctypes.c_int, _P, _P, _P]
     L.oracle_hub_features.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _I32, _P,
                                       ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, _P, _P]
@@ -215,6 +217,21 @@ def kmeans_hubs(base, n_hubs: int, iters: int, init_ids):
     steps = lib().oracle_kmeans_hubs(_ptr(base), n, d, n_hubs, iters, _ptr(init_ids),
                                      _ptr(hub), _ptr(cen), _ptr(asg), _ptr(obj))
     return dict(hub_ids=hub, centroids=cen, assign=asg, steps=steps, objective=obj[:steps])
+
+
+def hbkm_hubs(base, k: int, levels: int, lam: float, iters: int):
+    """Hierarchical balanced k-means (Algorithm 2) into k^levels clusters,
+    then Definition 3 hubs.  Returns dict(hub_ids, centroids (float64),
+    assign)."""
+    base = _f32(base)
+    n, d = base.shape
+    nc = k ** levels
+    hub = np.empty(nc, np.int32)
+    cen = np.empty((nc, d), np.float64)
+    asg = np.empty(n, np.int32)
+    lib().oracle_hbkm(_ptr(base), n, d, k, levels, float(lam), iters, _ptr(asg), _ptr(cen),
+                      _ptr(hub))
+    return dict(hub_ids=hub, centroids=cen, assign=asg)
 
 
 def hub_graph(emb, s: int):

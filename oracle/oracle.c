@@ -412,6 +412,38 @@ void oracle_search(const float *base, i64 n, int d, const i32 *graph, int R,
 /* cluster takes the nearest point that is not yet a hub (cluster order).    */
 /* Returns the number of assignment steps run.                               */
 
+/* Definition 3 hubs of given clusters: the member nearest the cluster mean   */
+/* by (d2, id); an empty cluster takes the nearest point that is not yet a   */
+/* hub (clusters in index order).                                            */
+static void hubs_of_clusters(const float *base, i64 n, int d, int nh, const i32 *assign,
+                             const double *mu, i32 *hub_ids)
+{
+    if (n <= 0 || nh <= 0) return;
+    double *best = (double *)malloc(sizeof(double) * nh);
+    for (int c = 0; c < nh; ++c) { hub_ids[c] = -1; best[c] = INFINITY; }
+    for (i64 i = 0; i < n; ++i) {
+        int c = assign[i];
+        double v = d2_mixed(base + i * d, mu + (i64)c * d, d);
+        if (hub_ids[c] < 0 || key_less(v, (i32)i, best[c], hub_ids[c])) { best[c] = v; hub_ids[c] = (i32)i; }
+    }
+    unsigned char *is_hub = (unsigned char *)calloc((size_t)n, 1);
+    for (int c = 0; c < nh; ++c) if (hub_ids[c] >= 0) is_hub[hub_ids[c]] = 1;
+    for (int c = 0; c < nh; ++c) {
+        if (hub_ids[c] >= 0) continue;
+        double bv = INFINITY;
+        i32 bi = -1;
+        for (i64 i = 0; i < n; ++i) {
+            if (is_hub[i]) continue;
+            double v = d2_mixed(base + i * d, mu + (i64)c * d, d);
+            if (bi < 0 || key_less(v, (i32)i, bv, bi)) { bv = v; bi = (i32)i; }
+        }
+        hub_ids[c] = bi;
+        is_hub[bi] = 1;
+    }
+    free(is_hub);
+    free(best);
+}
+
 int oracle_kmeans_hubs(const float *base, i64 n, int d, int nh, int iters,
                        const i32 *init_ids, i32 *hub_ids, double *centroids,
                        i32 *assign, double *objective)
@@ -453,30 +485,7 @@ int oracle_kmeans_hubs(const float *base, i64 n, int d, int nh, int iters,
                 for (int j = 0; j < d; ++j) mu[(i64)c * d + j] = sum[(i64)c * d + j] / (double)count[c];
         if (!changed) break;
     }
-    /* hubs */
-    double *best = (double *)malloc(sizeof(double) * nh);
-    for (int c = 0; c < nh; ++c) { hub_ids[c] = -1; best[c] = INFINITY; }
-    for (i64 i = 0; i < n; ++i) {
-        int c = assign[i];
-        double v = d2_mixed(base + i * d, mu + (i64)c * d, d);
-        if (hub_ids[c] < 0 || key_less(v, (i32)i, best[c], hub_ids[c])) { best[c] = v; hub_ids[c] = (i32)i; }
-    }
-    unsigned char *is_hub = (unsigned char *)calloc((size_t)n, 1);
-    for (int c = 0; c < nh; ++c) if (hub_ids[c] >= 0) is_hub[hub_ids[c]] = 1;
-    for (int c = 0; c < nh; ++c) {
-        if (hub_ids[c] >= 0) continue;
-        double bv = INFINITY;
-        i32 bi = -1;
-        for (i64 i = 0; i < n; ++i) {
-            if (is_hub[i]) continue;
-            double v = d2_mixed(base + i * d, mu + (i64)c * d, d);
-            if (bi < 0 || key_less(v, (i32)i, bv, bi)) { bv = v; bi = (i32)i; }
-        }
-        hub_ids[c] = bi;
-        is_hub[bi] = 1;
-    }
-    free(is_hub);
-    free(best);
+    hubs_of_clusters(base, n, d, nh, assign, mu, hub_ids);
     free(count);
     free(sum);
     return steps;
@@ -658,4 +667,101 @@ void oracle_hub_features(const float *base, i64 n, int d, const i32 *graph, int 
             feat[(i64)c * 32 + t] = sd > 0 ? (feat[(i64)c * 32 + t] - mean) / sd : 0.0;
     }
     free(vals); free(buf); free(in_s); free(depth); free(S); free(csize); free(indeg); free(deg);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchical balanced k-means hubs (Algorithm 2, Definitions 2 and 3).    */
+/* levels = ceil(log_k n_c) with n_c = k^levels exactly.  At each level every */
+/* cluster of the previous level (a parent with m members, in id order) is   */
+/* split into k children by `iters` iterations of:                           */
+/*   - empty children; visit the members in id order, each joining the child */
+/*     j minimising d2(x, mu_j) + lambda * (2 (s_j - m/k) + 1), s_j the size  */
+/*     child j has reached so far in this pass: the size term of the balance  */
+/*     objective of Definition 2 after x joins (the other children's terms    */
+/*     are common to every j); ties go to the smaller j;                      */
+/*   - mu_j = mean of child j's members (rows in id order); an empty child    */
+/*     keeps its centroid.                                                    */
+/* Child j starts at the member at position floor((2j + 1) m / (2k)) of the  */
+/* parent (a parent without members passes its own centroid on).  Cluster    */
+/* p*k + j of a level is child j of cluster p of the level before.  The      */
+/* final clusters' hubs follow Definition 3 (hubs_of_clusters).              */
+
+void oracle_hbkm(const float *base, i64 n, int d, int k, int levels, double lambda, int iters,
+                 i32 *assign, double *centroids, i32 *hub_ids)
+{
+    i64 np = 1;                          /* parents at the current level */
+    double *pmu = (double *)calloc((size_t)d, sizeof(double));
+    i32 *cur = (i32 *)calloc((size_t)n, sizeof(i32));
+    i32 *child = (i32 *)malloc(sizeof(i32) * (size_t)n);
+    i64 *start = NULL;
+    i32 *members = (i32 *)malloc(sizeof(i32) * (size_t)n);
+    double *dist = (double *)malloc(sizeof(double) * (size_t)n * k);
+    double *mu = NULL;
+    for (int l = 1; l <= levels; ++l) {
+        const i64 nc = np * k;
+        free(start);
+        start = (i64 *)calloc((size_t)np + 1, sizeof(i64));
+        for (i64 i = 0; i < n; ++i) start[cur[i] + 1]++;
+        for (i64 p = 0; p < np; ++p) start[p + 1] += start[p];
+        {
+            i64 *fill = (i64 *)malloc(sizeof(i64) * (size_t)np);
+            for (i64 p = 0; p < np; ++p) fill[p] = start[p];
+            for (i64 i = 0; i < n; ++i) members[fill[cur[i]]++] = (i32)i;
+            free(fill);
+        }
+        mu = (double *)malloc(sizeof(double) * (size_t)nc * d);
+        i64 *cnt = (i64 *)malloc(sizeof(i64) * (size_t)k);
+        for (i64 p = 0; p < np; ++p) {
+            const i32 *M = members + start[p];
+            const i64 m = start[p + 1] - start[p];
+            double *cm = mu + p * k * d;
+            for (int j = 0; j < k; ++j)
+                for (int c = 0; c < d; ++c)
+                    cm[(i64)j * d + c] = m > 0 ? (double)base[(i64)M[(2 * j + 1) * m / (2 * k)] * d + c]
+                                               : pmu[p * d + c];
+            const double target = (double)m / (double)k;
+            for (int t = 0; t < iters; ++t) {
+#pragma omp parallel for schedule(static)
+                for (i64 r = 0; r < m; ++r)
+                    for (int j = 0; j < k; ++j)
+                        dist[r * k + j] = d2_mixed(base + (i64)M[r] * d, cm + (i64)j * d, d);
+                for (int j = 0; j < k; ++j) cnt[j] = 0;
+                for (i64 r = 0; r < m; ++r) {
+                    int bj = -1;
+                    double bv = INFINITY;
+                    for (int j = 0; j < k; ++j) {
+                        const double dev = (double)cnt[j] - target;
+                        const double pen = lambda * (2.0 * dev + 1.0);
+                        const double v = dist[r * k + j] + pen;
+                        if (bj < 0 || v < bv) { bv = v; bj = j; }
+                    }
+                    child[M[r]] = bj;
+                    cnt[bj]++;
+                }
+                for (int j = 0; j < k; ++j) {
+                    if (cnt[j] == 0) continue;
+                    double *mj = cm + (i64)j * d;
+                    for (int c = 0; c < d; ++c) mj[c] = 0.0;
+                    for (i64 r = 0; r < m; ++r)
+                        if (child[M[r]] == j)
+                            for (int c = 0; c < d; ++c) mj[c] = mj[c] + (double)base[(i64)M[r] * d + c];
+                    for (int c = 0; c < d; ++c) mj[c] = mj[c] / (double)cnt[j];
+                }
+            }
+            for (i64 r = 0; r < m; ++r) cur[M[r]] = (i32)(p * k + child[M[r]]);
+        }
+        free(cnt);
+        free(pmu);
+        pmu = mu;
+        np = nc;
+    }
+    for (i64 i = 0; i < n; ++i) assign[i] = cur[i];
+    memcpy(centroids, pmu, sizeof(double) * (size_t)np * d);
+    hubs_of_clusters(base, n, d, (int)np, assign, pmu, hub_ids);
+    free(pmu);
+    free(cur);
+    free(child);
+    free(start);
+    free(members);
+    free(dist);
 }

@@ -247,3 +247,60 @@ def test_hub_features_standardised_columns():
     assert np.allclose(f.mean(0), 0, atol=1e-12)
     sd = f.std(0)
     assert np.all((np.abs(sd - 1) < 1e-9) | (sd == 0))
+
+
+# ---------------------------------------------------------------- HBKM (Algorithm 2)
+def test_hbkm_one_pass_by_hand():
+    # 1-D points 0, 1, 2, 10, 11, 12; k = 2, one level, one iteration,
+    # lambda = 100.  Children start at members floor(1.5) = 1 (x = 1) and
+    # floor(4.5) = 4 (x = 11); target m/k = 3; the penalty of child j is
+    # lambda * (2 (s_j - 3) + 1) with s_j its size so far:
+    #   x=0:  v = (1 - 500, 121 - 500)        -> 0, sizes (1, 0)
+    #   x=1:  v = (0 - 300, 100 - 500)        -> 1, sizes (1, 1)
+    #   x=2:  v = (1 - 300, 81 - 300)         -> 0, sizes (2, 1)
+    #   x=10: v = (81 - 100, 1 - 300)         -> 1, sizes (2, 2)
+    #   x=11: v = (100 - 100, 0 - 100)        -> 1, sizes (2, 3)
+    #   x=12: v = (121 - 100, 1 + 100)        -> 0, sizes (3, 3)
+    x = np.array([[0], [1], [2], [10], [11], [12]], np.float32)
+    h = oracle.hbkm_hubs(x, 2, 1, 100.0, 1)
+    assert h["assign"].tolist() == [0, 1, 0, 1, 1, 0]
+    assert h["centroids"][:, 0].tolist() == [14.0 / 3.0, 22.0 / 3.0]
+    # hubs: members nearest the means, (0, 2, 12) -> 2 and (1, 10, 11) -> 10
+    assert h["hub_ids"].tolist() == [2, 3]      # ids of x = 2 and x = 10
+    # without the penalty the two groups of the line separate
+    h0 = oracle.hbkm_hubs(x, 2, 1, 0.0, 3)
+    assert h0["assign"].tolist() == [0, 0, 0, 1, 1, 1]
+
+
+def test_hbkm_without_penalty_is_lloyd():
+    # lambda = 0, one level: the pass is the nearest-centroid assignment, so
+    # the result is Lloyd's from the same starting members
+    w = synth.scaled(synth.WORKLOADS["tiny"], n=3000)
+    base = synth.base(w)
+    k = 12
+    init = np.array([(2 * j + 1) * 3000 // (2 * k) for j in range(k)], np.int32)
+    ref = oracle.kmeans_hubs(base, k, 40, init)
+    assert ref["steps"] < 40                     # Lloyd converged, so extra passes change nothing
+    h = oracle.hbkm_hubs(base, k, 1, 0.0, 40)
+    assert (h["assign"] == ref["assign"]).all()
+    assert (h["centroids"] == ref["centroids"]).all()
+    assert (h["hub_ids"] == ref["hub_ids"]).all()
+
+
+def test_hbkm_dominant_penalty_balances_exactly_and_levels_nest():
+    r = np.random.default_rng(4)
+    base = (np.rint(r.normal(0, 3, size=(4096, 16)) * 2 ** 10) / 2 ** 10).astype(np.float32)
+    # a penalty far above any distance: each point joins the smallest child
+    h = oracle.hbkm_hubs(base, 4, 3, 1e9, 3)
+    sizes = np.bincount(h["assign"], minlength=64)
+    assert (sizes == 64).all()
+    # a moderate penalty: level 2's clusters refine level 1's, and the hubs
+    # are members of their clusters
+    h2 = oracle.hbkm_hubs(base, 4, 2, 5.0, 4)
+    h1 = oracle.hbkm_hubs(base, 4, 1, 5.0, 4)
+    assert (h2["assign"] // 4 == h1["assign"]).all()
+    assert (h2["assign"][h2["hub_ids"]] == np.arange(16)).all()
+    # balance improves with the penalty
+    s0 = np.bincount(oracle.hbkm_hubs(base, 4, 2, 0.0, 4)["assign"], minlength=16)
+    s5 = np.bincount(h2["assign"], minlength=16)
+    assert ((s5 - 256) ** 2).sum() < ((s0 - 256) ** 2).sum()
