@@ -261,6 +261,33 @@ ann_status ann_select_hubs(const float *base, int64_t n, int32_t dim, int32_t n_
                            double *centroids, int32_t *assign, int32_t *steps,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* Hub nodes (Definition 3) on hierarchical balanced k-means clusters
+ * (Algorithm 2): levels rounds split every cluster into k children, giving
+ * n_c = k^levels clusters (cluster p*k + j of a round is child j of cluster p
+ * of the round before).  A split runs `iters` passes over the parent's
+ * members in id order; each pass starts from empty children and puts each
+ * member into the child j of smallest d2(x, mu_j) + lambda * (2 (s_j - m/k)
+ * + 1), where s_j is the size child j has reached so far in the pass and m
+ * the parent's size: the change in the balance objective of Definition 2
+ * when x joins child j (the printed size term read as that change; the other
+ * children's terms are common to every j).  Ties go to the smaller j; d2 and
+ * the penalty are FP64 without fused multiply-add.  After each pass mu_j is
+ * the FP64 mean of its members (an empty child keeps its centroid).  Child j
+ * starts at the parent's member at position floor((2j + 1) m / (2k)) (a
+ * parent without members passes its centroid on).  Hubs as ann_select_hubs.
+ *   k          2..64; k^levels <= min(n, 2^20)
+ *   lambda     >= 0 (0: hierarchical k-means without the size term)
+ *   hub_ids    n_c int32 output; centroids n_c x dim FP64 output or NULL;
+ *   assign     n int32 output (final cluster of every point)
+ *   workspace  ann_select_hubs_hbkm_workspace_size(n, dim, k, levels) bytes
+ * Synchronises `stream`. */
+size_t ann_select_hubs_hbkm_workspace_size(int64_t n, int32_t dim, int32_t k, int32_t levels);
+
+ann_status ann_select_hubs_hbkm(const float *base, int64_t n, int32_t dim, int32_t k,
+                                int32_t levels, double lambda, int32_t iters, int32_t *hub_ids,
+                                double *centroids, int32_t *assign, void *workspace,
+                                size_t ws_bytes, void *stream);
+
 /* 32 topology features per hub, standardised per column across hubs
  * (population std; a constant column becomes 0) unless standardise == 0.
  * A guided walk of at most h hops and wcap nodes samples, at each node u,

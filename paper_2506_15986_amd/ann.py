@@ -361,6 +361,35 @@ def ann_graph_from_candidates(base: torch.Tensor, cand: torch.Tensor, cand_d2: t
     return graph, int(m.value), (int(br[0]), int(br[1]))
 
 
+_sig("ann_select_hubs_hbkm_workspace_size", _SZ, _I64, _I32, _I32, _I32)
+_sig("ann_select_hubs_hbkm", _I32, _P, _I64, _I32, _I32, _I32, ctypes.c_double, _I32, _P, _P, _P,
+     _P, _SZ, _P)
+
+
+def ann_select_hubs_hbkm_workspace_size(n: int, dim: int, k: int, levels: int) -> int:
+    return int(_lib.ann_select_hubs_hbkm_workspace_size(n, dim, k, levels))
+
+
+def ann_select_hubs_hbkm(base: torch.Tensor, k: int, levels: int, lam: float, iters: int,
+                         stream=None):
+    """Hierarchical balanced k-means (Algorithm 2) into k^levels clusters and
+    their Definition 3 hubs.  Returns (hub_ids int32, centroids float64
+    [k^levels, dim], assign int32 [n])."""
+    _dev(base, torch.float32)
+    n, dim = base.shape
+    dev = base.device
+    nc = k ** levels
+    hub = torch.empty(nc, dtype=torch.int32, device=dev)
+    cen = torch.empty((nc, dim), dtype=torch.float64, device=dev)
+    asg = torch.empty(n, dtype=torch.int32, device=dev)
+    nb = max(256, ann_select_hubs_hbkm_workspace_size(n, dim, k, levels))
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(_lib.ann_select_hubs_hbkm(_ptr(base), n, dim, k, levels, float(lam), iters, _ptr(hub),
+                                     _ptr(cen), _ptr(asg), _ptr(ws), ws.numel(), _stream(stream)))
+    del ws
+    return hub, cen, asg
+
+
 def ann_select_hubs(base: torch.Tensor, n_hubs: int, iters: int, init_ids: torch.Tensor,
                     stream=None):
     """Lloyd k-means + Definition 3 hubs.  Returns (hub_ids int32, centroids

@@ -222,6 +222,148 @@ inline int grid_for(int64_t n, int per = 256, int cap = 8192)
     return (int)b;
 }
 
+// ---------------------------------------------------------------- HBKM
+// distance of every point to the k children of its cluster (the same FP64
+// arithmetic as the assignment above)
+__global__ void child_dist_kernel(const float *base, int64_t n, int dim, const int32_t *parent,
+                                  const double *mu, int k, double *D)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * k) return;
+    const int64_t i = e / k;
+    const int j = (int)(e - i * k);
+    D[e] = d2_to(base + i * dim, mu + ((int64_t)parent[i] * k + j) * dim, dim);
+}
+
+// Child j of cluster c starts at point init_ids[c * k + j], or at the
+// parent's centroid when the parent has no member (init id -1).
+__global__ void init_children_kernel(const float *base, int dim, const int32_t *init_ids, int64_t nc,
+                                     int k, const double *parent_mu, double *mu)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nc * dim) return;
+    const int64_t c = e / dim, j = e % dim;
+    const int32_t id = init_ids[c];
+    mu[e] = id >= 0 ? (double)base[(int64_t)id * dim + j] : parent_mu[(c / k) * dim + j];
+}
+
+// One wavefront per parent cluster: its members (id order) join children in
+// turn, each the child j of smallest d2(x, mu_j) + lambda * (2 (s_j - m/k) + 1)
+// with s_j child j's size so far (ties to the smaller j).  Lane j keeps s_j;
+// the distances of 64 members at a time are staged in LDS, so the sequential
+// chain only waits on LDS and shuffles.
+constexpr int HB_CHUNK = 64;
+
+__global__ void __launch_bounds__(64) balanced_pass_kernel(const int32_t *members,
+                                                           const int64_t *start, int64_t np,
+                                                           const double *D, int k, double lambda,
+                                                           int32_t *child)
+{
+#pragma clang fp contract(off)
+    extern __shared__ __align__(16) unsigned char hb_lds[];
+    double *ds = reinterpret_cast<double *>(hb_lds);                  // HB_CHUNK x k
+    int32_t *ms = reinterpret_cast<int32_t *>(ds + HB_CHUNK * k);     // HB_CHUNK
+    const int64_t p = blockIdx.x;
+    if (p >= np) return;
+    const int lane = threadIdx.x;
+    const int64_t s0 = start[p];
+    const int64_t m = start[p + 1] - s0;
+    const double target = (double)m / (double)k;
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    int64_t s = 0;
+    for (int64_t r0 = 0; r0 < m; r0 += HB_CHUNK) {
+        const int cnt = (int)(m - r0 < HB_CHUNK ? m - r0 : HB_CHUNK);
+        if (lane < cnt) ms[lane] = members[s0 + r0 + lane];
+        __syncthreads();
+        for (int e = lane; e < cnt * k; e += 64) {
+            const int q = e / k, j = e - q * k;
+            ds[e] = D[(int64_t)ms[q] * k + j];
+        }
+        __syncthreads();
+        for (int q = 0; q < cnt; ++q) {
+            double v = inf;
+            int idx = lane;
+            if (lane < k) {
+                const double dev = (double)s - target;
+                const double pen = lambda * (2.0 * dev + 1.0);
+                v = ds[q * k + lane] + pen;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(v, o);
+                const int oi = __shfl_xor(idx, o);
+                if (ov < v || (ov == v && oi < idx)) {
+                    v = ov;
+                    idx = oi;
+                }
+            }
+            if (lane == idx) ++s;
+            if (lane == 0) child[ms[q]] = (int32_t)(p * k + idx);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+namespace {
+
+// Definition 3 hubs of given clusters: the member nearest the cluster's
+// mean by (d2, id); an empty cluster takes the nearest point that is not yet
+// a hub (clusters in index order).
+ann_status hubs_of_clusters(const float *base, int64_t n, int dim, int nh, const double *mu,
+                            const int32_t *assign, int32_t *hub_ids, unsigned long long *bits,
+                            int32_t *taken, Best *partial, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_u64, dim3(grid_for(nh)), dim3(256), 0, st, bits, (int64_t)nh,
+                       0xFFFFFFFFFFFFFFFFull);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(fill_i32, dim3(grid_for(nh)), dim3(256), 0, st, hub_ids, (int64_t)nh,
+                       0x7fffffff);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(hub_min_kernel, dim3(grid_for(n, 256, 1 << 22)), dim3(256), 0, st, base, n, dim,
+                       mu, assign, bits);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(hub_id_kernel, dim3(grid_for(n, 256, 1 << 22)), dim3(256), 0, st, base, n, dim,
+                       mu, assign, bits, hub_ids);
+    ANN_LAUNCHED();
+    // empty clusters (no member): nearest point that is not yet a hub
+    std::vector<int32_t> hh((size_t)nh);
+    ANN_HIP(hipMemcpyAsync(hh.data(), hub_ids, sizeof(int32_t) * nh, hipMemcpyDeviceToHost, st));
+    ANN_HIP(hipStreamSynchronize(st));
+    bool any_empty = false;
+    for (int c = 0; c < nh; ++c) any_empty |= (hh[c] == 0x7fffffff);
+    if (any_empty) {
+        hipLaunchKernelGGL(fill_i32, dim3(grid_for(n)), dim3(256), 0, st, taken, n, 0);
+        ANN_LAUNCHED();
+        // flag the hubs of non-empty clusters
+        for (int c = 0; c < nh; ++c)
+            if (hh[c] == 0x7fffffff) hh[c] = -1;
+        ANN_HIP(hipMemcpyAsync(hub_ids, hh.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(mark_taken_kernel, dim3(grid_for(nh)), dim3(256), 0, st, hub_ids, nh, taken);
+        ANN_LAUNCHED();
+        const int blocks = grid_for(n, 256, 1024);
+        for (int c = 0; c < nh; ++c) {
+            if (hh[c] >= 0) continue;
+            hipLaunchKernelGGL(empty_scan_kernel, dim3(blocks), dim3(256), 0, st, base, n, dim,
+                               mu + (int64_t)c * dim, taken, partial);
+            ANN_LAUNCHED();
+            std::vector<Best> pb((size_t)blocks);
+            ANN_HIP(hipMemcpyAsync(pb.data(), partial, sizeof(Best) * blocks, hipMemcpyDeviceToHost, st));
+            ANN_HIP(hipStreamSynchronize(st));
+            Best b = pb[0];
+            for (int q = 1; q < blocks; ++q)
+                if (pb[q].v < b.v || (pb[q].v == b.v && pb[q].id < b.id)) b = pb[q];
+            hh[c] = (int32_t)b.id;
+            int32_t one = 1;
+            ANN_HIP(hipMemcpyAsync(taken + b.id, &one, 4, hipMemcpyHostToDevice, st));
+            ANN_HIP(hipStreamSynchronize(st));
+        }
+        ANN_HIP(hipMemcpyAsync(hub_ids, hh.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, st));
+        ANN_HIP(hipStreamSynchronize(st));
+    }
+    return ANN_OK;
+}
+
 }  // namespace
 
 size_t select_hubs_ws(int64_t n, int dim, int nh)
@@ -279,54 +421,8 @@ ann_status select_hubs_run(const float *base, int64_t n, int dim, int nh, int it
         ANN_HIP(hipStreamSynchronize(st));
         if (!h) break;
     }
-    // hubs
-    hipLaunchKernelGGL(fill_u64, dim3(grid_for(nh)), dim3(256), 0, st, bits, (int64_t)nh,
-                       0xFFFFFFFFFFFFFFFFull);
-    ANN_LAUNCHED();
-    hipLaunchKernelGGL(fill_i32, dim3(grid_for(nh)), dim3(256), 0, st, hub_ids, (int64_t)nh,
-                       0x7fffffff);
-    ANN_LAUNCHED();
-    hipLaunchKernelGGL(hub_min_kernel, dim3(grid_for(n, 256, 1 << 22)), dim3(256), 0, st, base, n, dim,
-                       mu, assign, bits);
-    ANN_LAUNCHED();
-    hipLaunchKernelGGL(hub_id_kernel, dim3(grid_for(n, 256, 1 << 22)), dim3(256), 0, st, base, n, dim,
-                       mu, assign, bits, hub_ids);
-    ANN_LAUNCHED();
-    // empty clusters (no member): nearest point that is not yet a hub
-    std::vector<int32_t> hh((size_t)nh);
-    ANN_HIP(hipMemcpyAsync(hh.data(), hub_ids, sizeof(int32_t) * nh, hipMemcpyDeviceToHost, st));
-    ANN_HIP(hipStreamSynchronize(st));
-    bool any_empty = false;
-    for (int c = 0; c < nh; ++c) any_empty |= (hh[c] == 0x7fffffff);
-    if (any_empty) {
-        hipLaunchKernelGGL(fill_i32, dim3(grid_for(n)), dim3(256), 0, st, taken, n, 0);
-        ANN_LAUNCHED();
-        // flag the hubs of non-empty clusters
-        for (int c = 0; c < nh; ++c)
-            if (hh[c] == 0x7fffffff) hh[c] = -1;
-        ANN_HIP(hipMemcpyAsync(hub_ids, hh.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(mark_taken_kernel, dim3(grid_for(nh)), dim3(256), 0, st, hub_ids, nh, taken);
-        ANN_LAUNCHED();
-        const int blocks = grid_for(n, 256, 1024);
-        for (int c = 0; c < nh; ++c) {
-            if (hh[c] >= 0) continue;
-            hipLaunchKernelGGL(empty_scan_kernel, dim3(blocks), dim3(256), 0, st, base, n, dim,
-                               mu + (int64_t)c * dim, taken, partial);
-            ANN_LAUNCHED();
-            std::vector<Best> pb((size_t)blocks);
-            ANN_HIP(hipMemcpyAsync(pb.data(), partial, sizeof(Best) * blocks, hipMemcpyDeviceToHost, st));
-            ANN_HIP(hipStreamSynchronize(st));
-            Best b = pb[0];
-            for (int q = 1; q < blocks; ++q)
-                if (pb[q].v < b.v || (pb[q].v == b.v && pb[q].id < b.id)) b = pb[q];
-            hh[c] = (int32_t)b.id;
-            int32_t one = 1;
-            ANN_HIP(hipMemcpyAsync(taken + b.id, &one, 4, hipMemcpyHostToDevice, st));
-            ANN_HIP(hipStreamSynchronize(st));
-        }
-        ANN_HIP(hipMemcpyAsync(hub_ids, hh.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice, st));
-        ANN_HIP(hipStreamSynchronize(st));
-    }
+    ann_status hs = hubs_of_clusters(base, n, dim, nh, mu, assign, hub_ids, bits, taken, partial, st);
+    if (hs != ANN_OK) return hs;
     if (steps_out) *steps_out = steps;
     return ANN_OK;
 }
@@ -334,6 +430,154 @@ ann_status select_hubs_run(const float *base, int64_t n, int dim, int nh, int it
 }  // namespace ann
 
 using namespace ann;
+
+namespace ann {
+namespace {
+
+int64_t ipow(int64_t b, int e)
+{
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+size_t hbkm_ws(int64_t n, int dim, int k, int levels)
+{
+    const int64_t nc = ipow(k, levels), np = ipow(k, levels - 1);
+    size_t b = round_up((size_t)n * k * 8, 256);                 // distances to the children
+    b += round_up((size_t)n * 4, 256) * 4;                        // parent, child, members, taken
+    b += round_up((size_t)(np + 1) * 8, 256);                     // member offsets
+    b += round_up((size_t)nc * 4, 256);                           // initial members
+    b += round_up((size_t)nc * dim * 8, 256) * 3;                 // mu, parent mu, sums
+    b += round_up((size_t)nc * 8, 256) * 2;                       // count, best bits
+    b += round_up(4096 * sizeof(Best), 256);
+    return b + 1024;
+}
+
+ann_status hbkm_run(const float *base, int64_t n, int dim, int k, int levels, double lambda,
+                    int iters, int32_t *hub_ids, double *centroids_out, int32_t *assign_out,
+                    void *ws, hipStream_t st)
+{
+    const int64_t nc_max = ipow(k, levels), np_max = ipow(k, levels - 1);
+    Carve cv{static_cast<unsigned char *>(ws)};
+    double *D = cv.take<double>((size_t)n * k);
+    int32_t *cur = cv.take<int32_t>((size_t)n);
+    int32_t *nxt = cv.take<int32_t>((size_t)n);
+    int32_t *mem_d = cv.take<int32_t>((size_t)n);
+    int32_t *taken = cv.take<int32_t>((size_t)n);
+    int64_t *start_d = cv.take<int64_t>((size_t)np_max + 1);
+    int32_t *init_d = cv.take<int32_t>((size_t)nc_max);
+    double *mu = cv.take<double>((size_t)nc_max * dim);
+    double *pmu = cv.take<double>((size_t)nc_max * dim);
+    double *sums = cv.take<double>((size_t)nc_max * dim);
+    int64_t *count = cv.take<int64_t>((size_t)nc_max);
+    unsigned long long *bits = cv.take<unsigned long long>((size_t)nc_max);
+    Best *partial = cv.take<Best>(4096);
+
+    hipLaunchKernelGGL(fill_i32, dim3(grid_for(n)), dim3(256), 0, st, cur, n, 0);
+    ANN_LAUNCHED();
+    std::vector<int32_t> lab((size_t)n), members((size_t)n), init;
+    std::vector<int64_t> start;
+    const size_t pass_lds = (size_t)HB_CHUNK * k * 8 + HB_CHUNK * 4;
+    int64_t np = 1;
+    for (int l = 1; l <= levels; ++l) {
+        const int64_t nc = np * k;
+        // members of every parent in id order, and each child's first member
+        ANN_HIP(hipMemcpyAsync(lab.data(), cur, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st));
+        ANN_HIP(hipStreamSynchronize(st));
+        start.assign((size_t)np + 1, 0);
+        for (int64_t i = 0; i < n; ++i) start[(size_t)lab[(size_t)i] + 1]++;
+        for (int64_t p = 0; p < np; ++p) start[(size_t)p + 1] += start[(size_t)p];
+        {
+            std::vector<int64_t> fill(start.begin(), start.end() - 1);
+            for (int64_t i = 0; i < n; ++i) members[(size_t)fill[(size_t)lab[(size_t)i]]++] = (int32_t)i;
+        }
+        init.assign((size_t)nc, -1);
+        for (int64_t p = 0; p < np; ++p) {
+            const int64_t m = start[(size_t)p + 1] - start[(size_t)p];
+            if (m == 0) continue;
+            for (int j = 0; j < k; ++j)
+                init[(size_t)(p * k + j)] = members[(size_t)(start[(size_t)p] + (2 * j + 1) * m / (2 * k))];
+        }
+        ANN_HIP(hipMemcpyAsync(mem_d, members.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+        ANN_HIP(hipMemcpyAsync(start_d, start.data(), sizeof(int64_t) * (size_t)(np + 1),
+                               hipMemcpyHostToDevice, st));
+        ANN_HIP(hipMemcpyAsync(init_d, init.data(), sizeof(int32_t) * (size_t)nc, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(init_children_kernel, dim3((unsigned)((nc * dim + 255) / 256)), dim3(256), 0,
+                           st, base, dim, init_d, nc, k, pmu, mu);
+        ANN_LAUNCHED();
+        const int64_t md = nc * dim;
+        for (int t = 0; t < iters; ++t) {
+            hipLaunchKernelGGL(child_dist_kernel, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, st,
+                               base, n, dim, cur, mu, k, D);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(balanced_pass_kernel, dim3((unsigned)np), dim3(64), pass_lds, st, mem_d,
+                               start_d, np, D, k, lambda, nxt);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(fill_f64, dim3(grid_for(md)), dim3(256), 0, st, sums, md);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(fill_u64, dim3(grid_for(nc)), dim3(256), 0, st,
+                               (unsigned long long *)count, nc, 0ull);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base,
+                               n, dim, nxt, sums, count);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(update_kernel, dim3((unsigned)((md + 255) / 256)), dim3(256), 0, st, sums,
+                               count, (int)nc, dim, mu);
+            ANN_LAUNCHED();
+        }
+        std::swap(cur, nxt);
+        std::swap(mu, pmu);
+        np = nc;
+    }
+    // cur: final clusters, pmu: their centroids
+    ANN_HIP(hipMemcpyAsync(assign_out, cur, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    if (centroids_out)
+        ANN_HIP(hipMemcpyAsync(centroids_out, pmu, sizeof(double) * (size_t)np * dim,
+                               hipMemcpyDeviceToDevice, st));
+    ann_status hs = hubs_of_clusters(base, n, dim, (int)np, pmu, cur, hub_ids, bits, taken, partial, st);
+    if (hs != ANN_OK) return hs;
+    ANN_HIP(hipStreamSynchronize(st));
+    return ANN_OK;
+}
+
+bool hbkm_shape_ok(int64_t n, int32_t k, int32_t levels)
+{
+    if (k < 2 || k > 64 || levels < 1 || levels > 20) return false;
+    int64_t nc = 1;
+    for (int l = 0; l < levels; ++l) {
+        nc *= k;
+        if (nc > n || nc > (1 << 20)) return false;
+    }
+    return true;
+}
+
+}  // namespace
+}  // namespace ann
+
+extern "C" size_t ann_select_hubs_hbkm_workspace_size(int64_t n, int32_t dim, int32_t k,
+                                                      int32_t levels)
+{
+    if (n < 1 || dim < 1 || !hbkm_shape_ok(n, k, levels)) return 0;
+    return hbkm_ws(n, dim, k, levels);
+}
+
+extern "C" ann_status ann_select_hubs_hbkm(const float *base, int64_t n, int32_t dim, int32_t k,
+                                           int32_t levels, double lambda, int32_t iters,
+                                           int32_t *hub_ids, double *centroids, int32_t *assign,
+                                           void *workspace, size_t ws_bytes, void *stream)
+{
+    ANN_REQUIRE(base && hub_ids && assign && workspace, "a required pointer is NULL");
+    ANN_REQUIRE(n >= 1 && n <= 0x7FFFFFFF, "n must be in [1, 2^31)");
+    ANN_REQUIRE(dim >= 1, "dim must be >= 1");
+    ANN_REQUIRE(hbkm_shape_ok(n, k, levels),
+                "need 2 <= k <= 64, levels >= 1 and k^levels <= min(n, 2^20)");
+    ANN_REQUIRE(lambda >= 0.0 && lambda < 1e300, "lambda must be finite and >= 0");
+    ANN_REQUIRE(iters >= 1, "iters must be >= 1");
+    ANN_REQUIRE(ws_bytes >= hbkm_ws(n, dim, k, levels), "workspace too small");
+    return hbkm_run(base, n, dim, k, levels, lambda, iters, hub_ids, centroids, assign, workspace,
+                    static_cast<hipStream_t>(stream));
+}
 
 extern "C" ann_status ann_select_hubs(const float *base, int64_t n, int32_t dim, int32_t n_hubs,
                                       int32_t iters, const int32_t *init_ids, int32_t *hub_ids,

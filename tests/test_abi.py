@@ -221,3 +221,25 @@ def test_grouped_build_rejects_bad_arguments_without_gpu_work():
     assert ann.ann_graph_from_candidates_workspace_size(64, 8, 4) > ws.nbytes
     assert ann.ann_group_candidates_workspace_size(8, 8, 64, 32) > 0
     assert ann.ann_group_candidates_workspace_size(8, 0, 64, 32) == 0
+
+
+def test_hbkm_rejects_bad_shapes_without_gpu_work():
+    from paper_2506_15986_amd import ann
+    base = np.zeros((100, 8), np.float32)
+    out = np.zeros(4096, np.int32)
+    ws = np.zeros(256, np.uint8)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
+
+    def call(k=4, levels=2, lam=1.0, iters=3, n=100):
+        return ann._lib.ann_select_hubs_hbkm(P(base), n, 8, k, levels, lam, iters, P(out), None,
+                                             P(out), P(ws), ws.nbytes, None)
+
+    assert call(k=1) == ann.ANN_EINVAL
+    assert call(k=65) == ann.ANN_EINVAL
+    assert call(levels=0) == ann.ANN_EINVAL
+    assert call(k=4, levels=4) == ann.ANN_EINVAL          # 256 clusters > 100 points
+    assert call(lam=-1.0) == ann.ANN_EINVAL
+    assert call(iters=0) == ann.ANN_EINVAL
+    assert call() == ann.ANN_EINVAL                       # workspace too small
+    assert ann.ann_select_hubs_hbkm_workspace_size(100, 8, 4, 2) > 256
+    assert ann.ann_select_hubs_hbkm_workspace_size(100, 8, 4, 4) == 0

@@ -67,3 +67,39 @@ def test_hub_features_match_oracle():
     assert (wsz.cpu().numpy() == ref_ws).all()
     assert np.allclose(fr.cpu().numpy(), raw, rtol=1e-5, atol=1e-6)
     assert np.allclose(f.cpu().numpy(), ref, rtol=0, atol=1e-4)
+
+
+@pytest.mark.parametrize("which,k,levels,lam,iters", [
+    ("int", 8, 2, 1.0, 5),       # integers 0..255, 64 clusters
+    ("tiny", 4, 3, 0.5, 4),      # grid data, 64 clusters over 3 rounds
+    ("tiny", 16, 1, 0.0, 6),     # no size term: Lloyd from spaced members
+    ("int", 4, 2, 1e9, 2),       # a dominant size term: exact balance
+])
+def test_hbkm_hubs_bit_exact(which, k, levels, lam, iters):
+    ann = _ann()
+    ix = int_index() if which == "int" else tiny_index()
+    base = ix["base"]
+    say("case: HBKM %s k=%d levels=%d lambda=%g iters=%d" % (which, k, levels, lam, iters))
+    hub, cen, asg = ann.ann_select_hubs_hbkm(_dev(base), k, levels, lam, iters)
+    torch.cuda.synchronize()
+    ref = oracle.hbkm_hubs(base, k, levels, lam, iters)
+    assert (asg.cpu().numpy() == ref["assign"]).all()
+    assert (cen.cpu().numpy() == ref["centroids"]).all()
+    assert (hub.cpu().numpy() == ref["hub_ids"]).all()
+
+
+def test_hbkm_more_clusters_than_distinct_points():
+    # 64 clusters of 80 points with only 20 distinct rows: empty children and
+    # the empty-cluster hub rule
+    ann = _ann()
+    r = np.random.default_rng(9)
+    rows = r.integers(0, 256, size=(20, 32)).astype(np.float32)
+    base = rows[r.integers(0, 20, size=80)]
+    say("case: HBKM with repeated rows, 64 clusters")
+    hub, cen, asg = ann.ann_select_hubs_hbkm(_dev(base), 8, 2, 0.0, 3)
+    torch.cuda.synchronize()
+    ref = oracle.hbkm_hubs(base, 8, 2, 0.0, 3)
+    assert (asg.cpu().numpy() == ref["assign"]).all()
+    assert (cen.cpu().numpy() == ref["centroids"]).all()
+    assert (hub.cpu().numpy() == ref["hub_ids"]).all()
+    assert len(set(hub.cpu().numpy().tolist())) == 64
