@@ -148,7 +148,10 @@ def main():
     ap.add_argument("--tau", type=float, default=0.07)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--legs", default="medoid,gate,ablation,serve")
+    ap.add_argument("--legs", default="medoid,gate,ablation,serve",
+                    help="also: hbkm (GATE on hierarchical balanced k-means hubs, one model per "
+                         "--hbkm-lambdas value)")
+    ap.add_argument("--hbkm-lambdas", default="0,1,10")
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
     ap.add_argument("--save-state", default="")
     ap.add_argument("--load-state", default="")
@@ -521,6 +524,26 @@ def main():
             u_rows, u_L95 = sweep(e0, "untrained")
             abl["untrained_towers"] = dict(L95=u_L95, sweep=u_rows)
             del g0
+        if "hbkm" in legs and tq is not None:
+            # the same entry model on hierarchical balanced k-means hubs
+            # (Algorithm 2), against the Lloyd hubs above
+            abl["hbkm"] = []
+            for lam in [float(x) for x in args.hbkm_lambdas.split(",") if x]:
+                gd = gate.prepare_gate(index, tq, w, n_hubs=args.hubs, hubs="hbkm", hbkm_lambda=lam,
+                                       log=log)
+                gh = gate.train_gate(index, gd, tq, w, hidden=args.hidden, dout=args.dout,
+                                     epochs=args.epochs, lr=args.lr, tau=args.tau, log=log)
+                eh, _, _ = gh.select(q_d)
+                h_rows, h_L95 = sweep(eh, "hbkm lambda=%g" % lam)
+                r95 = next((r for r in h_rows if r["L"] == h_L95), None)
+                abl["hbkm"].append(dict(L95=h_L95, ndc=r95["ndc"] if r95 else None,
+                                        hubs_s=round(gd.info["hubs_s"], 2), **gd.info["hbkm"],
+                                        val_top1=gh.info.get("val_top1"),
+                                        val_nearest_hub_top1=gh.info.get("val_nearest_hub_top1")))
+                log("hbkm lambda=%g: L95 %s, sizes %d..%d, objective %.3g (Lloyd %.3g)" %
+                    (lam, h_L95, gd.info["hbkm"]["size_min"], gd.info["hbkm"]["size_max"],
+                     gd.info["hbkm"]["size_objective"], gdata.info.get("size_objective", float("nan"))))
+                del gh, gd
         if args.save_state:
             gate.save_state(args.save_state, index, g, dict(
                 L_gate=L_gate, L_medoid=med["L"] if med else None,

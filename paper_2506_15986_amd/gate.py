@@ -126,19 +126,35 @@ class GateData:
 
 def prepare_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
                  kmeans_iters: int = 20, M: int = 8,
-                 ladder=(10, 16, 24, 32, 48, 64, 96, 128, 192, 256), log=print) -> GateData:
-    """Hubs (Definition 3 on Lloyd k-means), hub topology features, hub-tower
-    inputs and the training labels."""
+                 ladder=(10, 16, 24, 32, 48, 64, 96, 128, 192, 256), hubs: str = "lloyd",
+                 hbkm_lambda: float = 0.0, hbkm_iters: int = 10, log=print) -> GateData:
+    """Hubs (Definition 3 on Lloyd k-means, or with hubs="hbkm" on the
+    hierarchical balanced k-means of Algorithm 2 with k = n_hubs^(1/2), two
+    levels), hub topology features, hub-tower inputs and the training
+    labels."""
     base, dev = index.base, index.base.device
     n, d = base.shape
     info = {}
     t = time.time()
-    init = torch.from_numpy(synth.kmeans_init(w, n, n_hubs)).to(dev)
-    hub_ids, cen, assign, steps = ann.ann_select_hubs(base, n_hubs, kmeans_iters, init)
+    if hubs == "hbkm":
+        k = int(round(math.sqrt(n_hubs)))
+        if k * k != n_hubs:
+            raise ValueError("HBKM hubs need n_hubs = k^2 (got %d)" % n_hubs)
+        hub_ids, cen, assign = ann.ann_select_hubs_hbkm(base, k, 2, hbkm_lambda, hbkm_iters)
+        steps = 2 * hbkm_iters
+        sizes = torch.bincount(assign.long(), minlength=n_hubs).double()
+        info["hbkm"] = dict(k=k, levels=2, lam=hbkm_lambda, iters=hbkm_iters,
+                            size_objective=float(((sizes - n / n_hubs) ** 2).sum().item()),
+                            size_min=int(sizes.min().item()), size_max=int(sizes.max().item()))
+    else:
+        init = torch.from_numpy(synth.kmeans_init(w, n, n_hubs)).to(dev)
+        hub_ids, cen, assign, steps = ann.ann_select_hubs(base, n_hubs, kmeans_iters, init)
+        sizes = torch.bincount(assign.long(), minlength=n_hubs).double()
+        info["size_objective"] = float(((sizes - n / n_hubs) ** 2).sum().item())
     torch.cuda.synchronize()
     info["kmeans_steps"] = steps
     info["hubs_s"] = time.time() - t
-    log("hubs: %d Lloyd steps, %.1fs" % (steps, info["hubs_s"]))
+    log("hubs (%s): %d steps, %.1fs" % (hubs, steps, info["hubs_s"]))
 
     t = time.time()
     # inputs scaled by a power of two into [-1, 1] (exact in BF16)
