@@ -56,6 +56,7 @@ def _declare(L):
     L.oracle_kmeans_hubs.argtypes = [_P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
                                      _P, _P, _P]
     L.oracle_kmeans_hubs.restype = ctypes.c_int
+    L.oracle_hop_table.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _P, _I64, _P]
     L.oracle_hbkm.argtypes = [_P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F64,
                               ctypes.c_int, _P, _P, _P]
     L.oracle_hub_features.argtypes = [_P, _I64, ctypes.c_int, _P, ctypes.c_int, _I32, _P,
@@ -232,6 +233,40 @@ def hbkm_hubs(base, k: int, levels: int, lam: float, iters: int):
     lib().oracle_hbkm(_ptr(base), n, d, k, levels, float(lam), iters, _ptr(asg), _ptr(cen),
                       _ptr(hub))
     return dict(hub_ids=hub, centroids=cen, assign=asg)
+
+
+def hop_table(graph, hub_ids, targets):
+    """Definition 4 hop counts: H[q, h] = shortest-path length along the
+    graph's edges from hub h to targets[q] (the query's nearest neighbour);
+    255 when unreachable or more than 254 hops.  uint8 [nq, nh]."""
+    graph = _i32(graph)
+    hub_ids, targets = _i32(hub_ids), _i32(targets)
+    out = np.empty((targets.shape[0], hub_ids.shape[0]), np.uint8)
+    lib().oracle_hop_table(_ptr(graph), graph.shape[0], graph.shape[1], _ptr(hub_ids),
+                           hub_ids.shape[0], _ptr(targets), targets.shape[0], _ptr(out))
+    return out
+
+
+def sample_queues(H, t_pos: int, t_neg: int):
+    """Positive and negative queries of every hub (Definition 4): with m_h
+    the smallest hop count any query has from hub h, q is positive for h when
+    H[q, h] <= m_h + t_pos and negative when H[q, h] >= m_h + t_neg (the
+    negatives' "analogous" definition read with t_neg; unreachable counts as
+    far).  Hubs no query reaches have neither.  Returns two lists of int64
+    query-index arrays, one entry per hub."""
+    H = np.asarray(H)
+    pos, neg = [], []
+    for h in range(H.shape[1]):
+        col = H[:, h].astype(np.int64)
+        reach = col < 255
+        if not reach.any():
+            pos.append(np.zeros(0, np.int64))
+            neg.append(np.zeros(0, np.int64))
+            continue
+        m = col[reach].min()
+        pos.append(np.flatnonzero(reach & (col <= m + t_pos)))
+        neg.append(np.flatnonzero(~reach | (col >= m + t_neg)))
+    return pos, neg
 
 
 def hub_graph(emb, s: int):

@@ -765,3 +765,39 @@ void oracle_hbkm(const float *base, i64 n, int d, int k, int levels, double lamb
     free(members);
     free(dist);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Hop counts of Definition 4: H(q, V_h) is the length of the shortest path  */
+/* along G's (directed) edges from hub h to the nearest neighbour of q.      */
+/* One breadth-first search per hub; out[q * nh + h] = H, or 255 when the    */
+/* target is unreachable or more than 254 hops away.                         */
+
+void oracle_hop_table(const i32 *graph, i64 n, int R, const i32 *hubs, int nh,
+                      const i32 *targets, i64 nq, unsigned char *out)
+{
+#pragma omp parallel
+    {
+        int *dist = (int *)malloc(sizeof(int) * (size_t)n);
+        i32 *queue = (i32 *)malloc(sizeof(i32) * (size_t)n);
+#pragma omp for schedule(dynamic, 1)
+        for (int h = 0; h < nh; ++h) {
+            for (i64 v = 0; v < n; ++v) dist[v] = -1;
+            i64 head = 0, tail = 0;
+            dist[hubs[h]] = 0;
+            queue[tail++] = hubs[h];
+            while (head < tail) {
+                i32 v = queue[head++];
+                for (int s = 0; s < R; ++s) {
+                    i32 w = graph[(i64)v * R + s];
+                    if (w >= 0 && dist[w] < 0) { dist[w] = dist[v] + 1; queue[tail++] = w; }
+                }
+            }
+            for (i64 q = 0; q < nq; ++q) {
+                int d = dist[targets[q]];
+                out[q * nh + h] = (unsigned char)(d < 0 || d > 254 ? 255 : d);
+            }
+        }
+        free(dist);
+        free(queue);
+    }
+}

@@ -111,6 +111,46 @@ def train_step_grads(qparams, hparams, xq, xh, labels, tau, bf16=True, q_scale=1
     return loss, gq, gh, eq, eh
 
 
+def hub_contrastive(eh, eq, P: int, N: int, tau: float):
+    """Eq. 4 read hub-anchored: hub i (row i of eh) owns query rows
+    i*(P+N) .. i*(P+N)+P-1 (its positives) and the next N (its negatives).
+    With s_iq = <e_h_i, e_q> / tau and LSE_i over the hub's P + N scores,
+
+        L(V_i) = - sum_{q in pos_i} log softmax_i(q) = P * LSE_i - sum_{pos_i} s_iq,
+
+    and the batch loss is the mean over hubs.  Returns (loss, deh, deq)."""
+    Bh = eh.shape[0]
+    W = P + N
+    loss = 0.0
+    deh = np.zeros_like(eh)
+    deq = np.zeros_like(eq)
+    for i in range(Bh):
+        rows = eq[i * W:(i + 1) * W]
+        s = rows @ eh[i] / tau
+        smax = s.max()
+        ex = np.exp(s - smax)
+        lse = np.log(ex.sum()) + smax
+        loss += P * lse - s[:P].sum()
+        ds = P * ex / ex.sum()
+        ds[:P] -= 1.0
+        ds /= Bh
+        deh[i] = ds @ rows / tau
+        deq[i * W:(i + 1) * W] = np.outer(ds, eh[i]) / tau
+    return loss / Bh, deh, deq
+
+
+def train_step_grads_hub(qparams, hparams, xq, xh, P, N, tau, bf16=True, q_scale=1.0):
+    """Forward/backward of one hub-anchored batch (hub_contrastive): xh holds
+    the batch's hub inputs, xq their P + N queries each.  Returns (loss,
+    q grads, h grads, eq, eh)."""
+    eq, cq = tower_forward(qparams, xq, bf16, q_scale)
+    eh, ch = tower_forward(hparams, xh, bf16)
+    loss, deh, deq = hub_contrastive(eh, eq, P, N, tau)
+    gq = tower_backward(cq, deq, bf16)
+    gh = tower_backward(ch, deh, bf16)
+    return loss, gq, gh, eq, eh
+
+
 def adam_update(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam step (Kingma & Ba) on float64 copies; t counts from 1."""
     m = b1 * m + (1.0 - b1) * g

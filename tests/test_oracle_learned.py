@@ -304,3 +304,61 @@ def test_hbkm_dominant_penalty_balances_exactly_and_levels_nest():
     s0 = np.bincount(oracle.hbkm_hubs(base, 4, 2, 0.0, 4)["assign"], minlength=16)
     s5 = np.bincount(h2["assign"], minlength=16)
     assert ((s5 - 256) ** 2).sum() < ((s0 - 256) ** 2).sum()
+
+
+# ---------------------------------------------------------------- Definition 4 and Eq. 4
+def test_hop_table_path_graph_and_unreachable():
+    # directed path 0 -> 1 -> ... -> 9 and an isolated node 10
+    g = -np.ones((11, 2), np.int32)
+    for v in range(9):
+        g[v, 0] = v + 1
+    H = oracle.hop_table(g, np.array([0, 4], np.int32), np.array([0, 3, 9, 10], np.int32))
+    assert H[:, 0].tolist() == [0, 3, 9, 255]
+    assert H[:, 1].tolist() == [255, 255, 5, 255]       # edges only go forward
+
+
+def test_hop_table_matches_library_shortest_paths():
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    r = np.random.default_rng(7)
+    n, R = 400, 3
+    g = r.integers(-1, n, size=(n, R)).astype(np.int32)       # -1 = empty slot
+    hubs = np.array([0, 17, 250, 399], np.int32)
+    targets = r.integers(0, n, size=60).astype(np.int32)
+    H = oracle.hop_table(g, hubs, targets)
+    rows, cols = np.nonzero(g >= 0)
+    A = csr_matrix((np.ones(len(rows)), (rows, g[rows, cols])), shape=(n, n))
+    D = shortest_path(A, directed=True, unweighted=True, indices=hubs)
+    want = np.where(np.isfinite(D[:, targets].T), D[:, targets].T, 255).astype(np.uint8)
+    assert (H == want).all()
+
+
+def test_sample_queues_by_definition():
+    H = np.array([[2, 255], [3, 255], [5, 255], [20, 255], [255, 255]], np.uint8)
+    pos, neg = oracle.sample_queues(H, 3, 15)
+    assert pos[0].tolist() == [0, 1, 2] and neg[0].tolist() == [3, 4]   # m = 2
+    assert pos[1].size == 0 and neg[1].size == 0                        # no query reaches hub 1
+
+
+def test_hub_contrastive_closed_form_and_gradients():
+    T = towers
+    r = np.random.default_rng(3)
+    P, N, tau = 3, 5, 0.1
+    # all scores equal: L(V_i) = P log(P + N) for every hub
+    eh = np.tile([[1.0, 0.0]], (2, 1))
+    eq = np.tile([[1.0, 0.0]], (2 * (P + N), 1))
+    loss, _, _ = T.hub_contrastive(eh, eq, P, N, tau)
+    assert np.isclose(loss, P * np.log(P + N))
+    # finite differences of the loss w.r.t. both embedding sets
+    eh = r.normal(size=(2, 4))
+    eq = r.normal(size=(2 * (P + N), 4))
+    loss, deh, deq = T.hub_contrastive(eh, eq, P, N, tau)
+    eps = 1e-6
+    for (arr, grad) in ((eh, deh), (eq, deq)):
+        for idx in [(0, 1), (1, 3), (arr.shape[0] - 1, 0)]:
+            a2 = arr.copy()
+            a2[idx] += eps
+            lp = T.hub_contrastive(a2 if arr is eh else eh, a2 if arr is eq else eq, P, N, tau)[0]
+            a2[idx] -= 2 * eps
+            lm = T.hub_contrastive(a2 if arr is eh else eh, a2 if arr is eq else eq, P, N, tau)[0]
+            assert np.isclose((lp - lm) / (2 * eps), grad[idx], rtol=1e-5, atol=1e-8)
