@@ -150,8 +150,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--legs", default="medoid,gate,ablation,serve",
                     help="also: hbkm (GATE on hierarchical balanced k-means hubs, one model per "
-                         "--hbkm-lambdas value)")
+                         "--hbkm-lambdas value), queues (GATE trained on Definition 4 queues with "
+                         "the hub-anchored Eq. 4 loss)")
     ap.add_argument("--hbkm-lambdas", default="0,1,10")
+    ap.add_argument("--queue-variants", default="3:16:48",
+                    help="queues leg: t_pos:P:N triples, comma separated (t_neg stays 15)")
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
     ap.add_argument("--save-state", default="")
     ap.add_argument("--load-state", default="")
@@ -544,6 +547,26 @@ def main():
                     (lam, h_L95, gd.info["hbkm"]["size_min"], gd.info["hbkm"]["size_max"],
                      gd.info["hbkm"]["size_objective"], gdata.info.get("size_objective", float("nan"))))
                 del gh, gd
+        if "queues" in legs and tq is not None:
+            # the paper's training signal: Definition 4 queues and Eq. 4 read
+            # hub-anchored, on the same hubs, features and towers
+            abl["queues"] = []
+            for var in [v for v in args.queue_variants.split(",") if v]:
+                tp, P, N = [int(x) for x in var.split(":")]
+                gq = gate.train_gate(index, gdata, tq, w, hidden=args.hidden, dout=args.dout,
+                                     epochs=args.epochs, lr=args.lr, tau=args.tau,
+                                     objective="queues", t_pos=tp, queue_P=P, queue_N=N, log=log)
+                eq_, _, _ = gq.select(q_d)
+                q_rows, q_L95 = sweep(eq_, "queues %s" % var)
+                r95 = next((r for r in q_rows if r["L"] == q_L95), None)
+                abl["queues"].append(dict(
+                    L95=q_L95, ndc=r95["ndc"] if r95 else None, P=P, N=N,
+                    **{k: gq.info.get(k) for k in (
+                        "queue_hubs_eligible", "queue_pos_mean", "queue_neg_mean", "t_pos", "t_neg",
+                        "train_s", "train_steps", "val_top1", "loss_per_epoch")}))
+                log("queues objective t_pos=%d P=%d N=%d: L95 %s (labels objective %s)" %
+                    (tp, P, N, q_L95, L_gate))
+                del gq
         if args.save_state:
             gate.save_state(args.save_state, index, g, dict(
                 L_gate=L_gate, L_medoid=med["L"] if med else None,

@@ -381,6 +381,39 @@ ann_status ann_train_step(ann_tower *query_tower, ann_tower *hub_tower,
                           float tau, float lr, int32_t step, float *loss, float *q_emb,
                           float *h_emb, void *workspace, size_t ws_bytes, void *stream);
 
+size_t ann_train_hub_workspace_size(int32_t hubs, int32_t P, int32_t N, int32_t din_q,
+                                    int32_t din_h, int32_t hidden, int32_t dout);
+
+/* One training step of Eq. 4 read hub-anchored over each hub's positive and
+ * negative queues (Definition 4): the batch holds `hubs` hubs (rows
+ * hub_idx[i] of hub_in) and hubs x (P + N) queries (rows q_idx[...] of
+ * train_q), hub i owning q_idx[i*(P+N) .. i*(P+N)+P-1] as positives and the
+ * next N as negatives.  With s_iq = <e_h_i, e_q> / tau and LSE_i over hub i's
+ * P + N scores:
+ *   L = mean_i [ P * LSE_i - sum_{q positive for i} s_iq ]
+ * (the printed per-hub sum of -log softmax over the positives).  Gradients,
+ * loss, embeddings and Adam as ann_train_step.  P >= 1, N >= 0. */
+ann_status ann_train_step_hub(ann_tower *query_tower, ann_tower *hub_tower,
+                              const ann_tower_grads *query_grads, const ann_tower_grads *hub_grads,
+                              const ann_adam_state *query_adam, const ann_adam_state *hub_adam,
+                              const float *train_q, const int32_t *q_idx, const int32_t *hub_idx,
+                              int32_t hubs, int32_t P, int32_t N, const float *hub_in, float tau,
+                              float lr, int32_t step, float *loss, float *q_emb, float *h_emb,
+                              void *workspace, size_t ws_bytes, void *stream);
+
+/* Hop counts of Definition 4: out[q * n_hubs + h] (uint8, device) = the
+ * length of the shortest path along the graph's edges from hub_ids[h] to
+ * targets[q] (the query's nearest neighbour), 255 when unreachable or more
+ * than 254 hops away.  Breadth-first search from 64 hubs at a time (one bit
+ * per hub in a 64-bit word per node).  Hub and target ids are checked on the
+ * host (EINVAL when out of range).
+ *   workspace  ann_hop_table_workspace_size(n) bytes.  Synchronises. */
+size_t ann_hop_table_workspace_size(int64_t n);
+
+ann_status ann_hop_table(const int32_t *graph, int64_t n, int32_t R, const int32_t *hub_ids,
+                         int32_t n_hubs, const int32_t *targets, int64_t nq, uint8_t *out,
+                         void *workspace, size_t ws_bytes, void *stream);
+
 /* Navigation graph over hubs.  Rows of hub_emb are unit vectors, so
  * |e_i - e_j|^2 = 2 - 2 cos(e_i, e_j) and the order by squared L2 distance is
  * the cosine order: row i = the s hubs j != i of largest cosine with hub i,

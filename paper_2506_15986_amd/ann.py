@@ -522,6 +522,66 @@ def ann_train_step(qt: Tower, ht: Tower, train_q, batch_idx, labels, hub_in, tau
     return loss, qe, he
 
 
+_sig("ann_train_hub_workspace_size", _SZ, _I32, _I32, _I32, _I32, _I32, _I32, _I32)
+_sig("ann_train_step_hub", _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _I32, _P, _F32,
+     _F32, _I32, _P, _P, _P, _P, _SZ, _P)
+_sig("ann_hop_table_workspace_size", _SZ, _I64)
+_sig("ann_hop_table", _I32, _P, _I64, _I32, _P, _I32, _P, _I64, _P, _P, _SZ, _P)
+
+
+def ann_train_hub_workspace_size(hubs: int, P: int, N: int, din_q: int, din_h: int, hidden: int,
+                                 dout: int) -> int:
+    return int(_lib.ann_train_hub_workspace_size(hubs, P, N, din_q, din_h, hidden, dout))
+
+
+def ann_train_step_hub(qt: Tower, ht: Tower, train_q, q_idx, hub_idx, P: int, N: int, hub_in,
+                       tau: float, lr: float, step: int, ws=None, want_emb: bool = False,
+                       stream=None):
+    """One hub-anchored training step (Eq. 4 over Definition 4 queues;
+    step 0 = gradients only).  q_idx: hubs x (P + N) query rows, positives
+    first.  Returns (loss tensor, q_emb, h_emb)."""
+    dev = train_q.device
+    Bh = hub_idx.shape[0]
+    rows = Bh * (P + N)
+    assert q_idx.numel() == rows
+    q_s, h_s = qt.struct(), ht.struct()
+    qg, hg = qt.grads_struct(), ht.grads_struct()
+    qa, ha = qt.adam_struct(), ht.adam_struct()
+    nb = ann_train_hub_workspace_size(Bh, P, N, qt.din, ht.din, qt.hidden, qt.dout)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    qe = torch.empty((rows, qt.dout), dtype=torch.float32, device=dev) if want_emb else None
+    he = torch.empty((Bh, ht.dout), dtype=torch.float32, device=dev) if want_emb else None
+    _check(_lib.ann_train_step_hub(ctypes.byref(q_s), ctypes.byref(h_s), ctypes.byref(qg),
+                                   ctypes.byref(hg), ctypes.byref(qa), ctypes.byref(ha),
+                                   _ptr(train_q), _ptr(q_idx), _ptr(hub_idx), Bh, P, N,
+                                   _ptr(hub_in), float(tau), float(lr), int(step), _ptr(loss),
+                                   _ptr(qe), _ptr(he), _ptr(ws), ws.numel(), _stream(stream)))
+    return loss, qe, he
+
+
+def ann_hop_table_workspace_size(n: int) -> int:
+    return int(_lib.ann_hop_table_workspace_size(n))
+
+
+def ann_hop_table(graph: torch.Tensor, hub_ids: torch.Tensor, targets: torch.Tensor, stream=None):
+    """Definition 4 hop counts, uint8 [nq, n_hubs] (255: unreachable or
+    farther than 254 hops)."""
+    _dev(graph, torch.int32)
+    _dev(hub_ids, torch.int32)
+    _dev(targets, torch.int32)
+    n, R = graph.shape
+    nq, nh = targets.shape[0], hub_ids.shape[0]
+    out = torch.empty((nq, nh), dtype=torch.uint8, device=graph.device)
+    ws = torch.empty(max(256, ann_hop_table_workspace_size(n)), dtype=torch.uint8,
+                     device=graph.device)
+    _check(_lib.ann_hop_table(_ptr(graph), n, R, _ptr(hub_ids), nh, _ptr(targets), nq, _ptr(out),
+                              _ptr(ws), ws.numel(), _stream(stream)))
+    del ws
+    return out
+
+
 def ann_navgraph_build(hub_emb: torch.Tensor, s: int, stream=None):
     """Returns (hub graph int32 [n_hubs, s], hub entry index)."""
     _dev(hub_emb, torch.float32)

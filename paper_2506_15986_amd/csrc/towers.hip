@@ -232,6 +232,40 @@ __global__ void softmax_ce_kernel(const float *s, int rows, int cols, const int3
     if (lane == 0) loss_rows[r] = logf(se) + mx - row[y];
 }
 
+// Eq. 4 read hub-anchored: row i of s (Bh rows of `cols` scores) owns the
+// block of W = P + N columns starting at i * W, its P positives then its N
+// negatives.  One wavefront per hub row: loss_i = P * LSE_i - sum_pos s and
+// ds = (P * softmax - [positive]) * inv_b inside the block, 0 elsewhere.
+__global__ void hub_ce_kernel(const float *s, int rows, int cols, int P, int N, float inv_b,
+                              float *ds, float *loss_rows)
+{
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const int lane = threadIdx.x & 63;
+    const int W = P + N;
+    const float *row = s + r * cols + r * W;
+    float mx = -__int_as_float(0x7f800000);
+    for (int c = lane; c < W; c += 64) mx = fmaxf(mx, row[c]);
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    float se = 0.f, sp = 0.f;
+    for (int c = lane; c < W; c += 64) {
+        se += expf(row[c] - mx);
+        if (c < P) sp += row[c];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        se += __shfl_xor(se, o);
+        sp += __shfl_xor(sp, o);
+    }
+    float *drow = ds + r * cols;
+    for (int c = lane; c < cols; c += 64) {
+        const int j = c - (int)(r * W);
+        float g = 0.f;
+        if (j >= 0 && j < W) g = ((float)P * expf(row[j] - mx) / se - (j < P ? 1.f : 0.f)) * inv_b;
+        drow[c] = g;
+    }
+    if (lane == 0) loss_rows[r] = (float)P * (logf(se) + mx) - sp;
+}
+
 // fixed-order column sums: out[c] = sum_r x[r][c]
 __global__ void bias_grad_kernel(const float *x, int rows, int cols, float *out)
 {
@@ -486,6 +520,15 @@ size_t train_step_ws(int batch, int nh, int din_q, int din_h, int hidden, int do
     return b;
 }
 
+size_t train_hub_ws(int bh, int P, int N, int din_q, int din_h, int hidden, int dout)
+{
+    const int rows = bh * (P + N);
+    size_t b = tower_bufs_bytes(rows, din_q, hidden, dout) + tower_bufs_bytes(bh, din_h, hidden, dout);
+    b += round_up((size_t)bh * rows * 4, 256) * 2;     // scores, their gradient
+    b += round_up((size_t)bh * 4, 256) + 1024;
+    return b;
+}
+
 // forward of one tower over rows of x (FP32, rows x din) -> unit embeddings
 ann_status tower_forward_run(const ann_tower &w, const float *x, const int32_t *idx, int rows,
                              float *out, void *ws, hipStream_t st)
@@ -618,6 +661,82 @@ extern "C" ann_status ann_train_step(ann_tower *qt, ann_tower *ht, const ann_tow
     TRY(gemm_f32(gh, st));
     TRY(tower_bwd(*qt, *qg, bq, batch, st));
     TRY(tower_bwd(*ht, *hg, bh, n_hubs, st));
+    if (step > 0) {
+        TRY(adam(*qt, *qg, *qa, step, lr, st));
+        TRY(adam(*ht, *hg, *ha, step, lr, st));
+    }
+    return ANN_OK;
+}
+
+extern "C" size_t ann_train_hub_workspace_size(int32_t hubs, int32_t P, int32_t N, int32_t din_q,
+                                               int32_t din_h, int32_t hidden, int32_t dout)
+{
+    if (hubs < 1 || P < 1 || N < 0) return 0;
+    return train_hub_ws(hubs, P, N, din_q, din_h, hidden, dout);
+}
+
+extern "C" ann_status ann_train_step_hub(ann_tower *qt, ann_tower *ht, const ann_tower_grads *qg,
+                                         const ann_tower_grads *hg, const ann_adam_state *qa,
+                                         const ann_adam_state *ha, const float *train_q,
+                                         const int32_t *q_idx, const int32_t *hub_idx,
+                                         int32_t hubs, int32_t P, int32_t N, const float *hub_in,
+                                         float tau, float lr, int32_t step, float *loss,
+                                         float *q_emb, float *h_emb, void *workspace,
+                                         size_t ws_bytes, void *stream)
+{
+    ann_status s = check_tower(qt, "query");
+    if (s != ANN_OK) return s;
+    s = check_tower(ht, "hub");
+    if (s != ANN_OK) return s;
+    ANN_REQUIRE(qg && hg, "gradient buffers are NULL");
+    ANN_REQUIRE(qg->gW1 && qg->gb1 && qg->gW2 && qg->gb2 && hg->gW1 && hg->gb1 && hg->gW2 && hg->gb2,
+                "a gradient pointer is NULL");
+    ANN_REQUIRE(train_q && q_idx && hub_idx && hub_in && loss && workspace,
+                "a required pointer is NULL");
+    ANN_REQUIRE(hubs >= 1 && P >= 1 && N >= 0, "need hubs >= 1, P >= 1, N >= 0");
+    ANN_REQUIRE(qt->dout == ht->dout && qt->hidden == ht->hidden,
+                "towers must share hidden and output sizes");
+    ANN_REQUIRE(tau > 0.f, "tau must be > 0");
+    ANN_REQUIRE(step >= 0, "step must be >= 0");
+    ANN_REQUIRE(step == 0 || (qa && ha), "Adam state needed when step > 0");
+    ANN_REQUIRE(ws_bytes >= train_hub_ws(hubs, P, N, qt->din, ht->din, qt->hidden, qt->dout),
+                "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int rows = hubs * (P + N);
+    Carve cv{static_cast<unsigned char *>(workspace)};
+    TowerBufs bq = carve_tower(cv, rows, qt->din, qt->hidden, qt->dout);
+    TowerBufs bh = carve_tower(cv, hubs, ht->din, ht->hidden, ht->dout);
+    float *sc = cv.take<float>((size_t)hubs * rows);
+    float *dsc = cv.take<float>((size_t)hubs * rows);
+    float *lrow = cv.take<float>((size_t)hubs);
+    if (q_emb) bq.e = q_emb;
+    if (h_emb) bh.e = h_emb;
+
+    // forward: the batch's queries and hubs through their towers
+    hipLaunchKernelGGL(gather_bf16_kernel, dim3(gridn((int64_t)rows * qt->din)), dim3(256), 0, st,
+                       train_q, qt->din, q_idx, rows, qt->in_scale, bq.xb);
+    ANN_LAUNCHED();
+    TRY(tower_fwd(*qt, bq, rows, st));
+    hipLaunchKernelGGL(gather_bf16_kernel, dim3(gridn((int64_t)hubs * ht->din)), dim3(256), 0, st,
+                       hub_in, ht->din, hub_idx, hubs, ht->in_scale, bh.xb);
+    ANN_LAUNCHED();
+    TRY(tower_fwd(*ht, bh, hubs, st));
+    const int e = qt->dout;
+    // scores [hubs x rows] = Eh . Eq^T / tau (only each hub's own block is used)
+    GemmF lg{bh.e, e, 1, bq.e, e, 1, hubs, rows, e, 1.f / tau, sc, rows};
+    TRY(gemm_f32(lg, st));
+    hipLaunchKernelGGL(hub_ce_kernel, dim3((hubs + 3) / 4), dim3(256), 0, st, sc, hubs, rows, P, N,
+                       1.f / (float)hubs, dsc, lrow);
+    ANN_LAUNCHED();
+    hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, st, lrow, hubs, loss);
+    ANN_LAUNCHED();
+    // dEh [hubs x e] = dS . Eq / tau ; dEq [rows x e] = dS^T . Eh / tau
+    GemmF gh{dsc, rows, 1, bq.e, 1, e, hubs, e, rows, 1.f / tau, bh.de, e};
+    TRY(gemm_f32(gh, st));
+    GemmF gq{dsc, 1, rows, bh.e, 1, e, rows, e, hubs, 1.f / tau, bq.de, e};
+    TRY(gemm_f32(gq, st));
+    TRY(tower_bwd(*qt, *qg, bq, rows, st));
+    TRY(tower_bwd(*ht, *hg, bh, hubs, st));
     if (step > 0) {
         TRY(adam(*qt, *qg, *qa, step, lr, st));
         TRY(adam(*ht, *hg, *ha, step, lr, st));

@@ -122,6 +122,7 @@ class GateData:
     cand: torch.Tensor
     scale: float
     info: dict
+    nn: torch.Tensor | None = None     # each training query's nearest base point
 
 
 def prepare_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs: int = 1024,
@@ -179,17 +180,27 @@ def prepare_gate(index: Index, train_q: torch.Tensor, w: synth.Workload, n_hubs:
     info["label_flags"] = int((flags.cpu().numpy() != 0).sum())
     log("labels: %.1fs, reached %.3f, nearest-hub agreement %.3f" %
         (info["labels_s"], info["labels_reached"], info["label_is_nearest_hub"]))
-    return GateData(hub_ids, hub_in, labels, cand, scale, info)
+    return GateData(hub_ids, hub_in, labels, cand, scale, info, nn=truth[:, 0].contiguous())
 
 
 def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Workload,
                hidden: int = 128, dout: int = 64, epochs: int = 20, batch: int = 1024,
                lr: float = 1e-3, tau: float = 0.07, s: int = 16, L_h: int = 32,
                theta: float = -math.inf, train: bool = True, holdout: float = 0.1,
-               init: str = "random", tune_L_h: bool = True, log=print) -> Gate:
+               init: str = "random", tune_L_h: bool = True, objective: str = "labels",
+               t_pos: int = 3, t_neg: int = 15, queue_hubs: int = 64, queue_P: int = 16,
+               queue_N: int = 48, log=print) -> Gate:
     """Trains the towers on the first (1 - holdout) of the training queries
     (contrastive loss, Adam), embeds the hubs, builds the navigation graph and
-    reports top-1 label agreement on the trained and the held-out queries."""
+    reports top-1 label agreement on the trained and the held-out queries.
+
+    objective "labels": each query against all hubs with its label hub as the
+    positive.  "queues": Definition 4 queues (hop counts from every hub to
+    each query's nearest neighbour; positives within t_pos hops of the hub's
+    closest query, negatives t_neg or more hops beyond it) and Eq. 4 read
+    hub-anchored, queue_hubs hubs per step with queue_P positives and
+    queue_N negatives each; as many steps per epoch as fill the training
+    queries once (queue_hubs * (queue_P + queue_N) query rows per step)."""
     dev = index.base.device
     d = index.dim
     n_hubs = data.hub_ids.shape[0]
@@ -209,7 +220,50 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     losses = []
     nb = ann.ann_train_workspace_size(batch, n_hubs, d, hub_in.shape[1], hidden, dout)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
-    if train:
+    if train and objective == "queues":
+        H = ann.ann_hop_table(index.graph, data.hub_ids, data.nn[:nt].contiguous())
+        Hl = H.to(torch.int32)
+        reach = Hl < 255
+        big = torch.full_like(Hl, 1 << 20)
+        m = torch.where(reach, Hl, big).min(dim=0).values            # per hub
+        pos = reach & (Hl <= m + t_pos)
+        neg = (~reach) | (Hl >= m + t_neg)
+        has = reach.any(dim=0)
+        pos &= has
+        neg &= has
+        # queues as concatenated query lists (hub-major), with offsets
+        ph, pq = torch.nonzero(pos.t(), as_tuple=True)
+        nh_, nq_ = torch.nonzero(neg.t(), as_tuple=True)
+        pos_off = np.zeros(n_hubs + 1, np.int64)
+        neg_off = np.zeros(n_hubs + 1, np.int64)
+        pos_off[1:] = np.cumsum(torch.bincount(ph, minlength=n_hubs).cpu().numpy())
+        neg_off[1:] = np.cumsum(torch.bincount(nh_, minlength=n_hubs).cpu().numpy())
+        pos_q, neg_q = pq.to(torch.int64), nq_.to(torch.int64)
+        eligible = np.flatnonzero((np.diff(pos_off) > 0) & (np.diff(neg_off) > 0))
+        info.update(queue_hubs_eligible=int(eligible.size),
+                    queue_pos_mean=float(np.diff(pos_off)[eligible].mean()) if eligible.size else 0.0,
+                    queue_neg_mean=float(np.diff(neg_off)[eligible].mean()) if eligible.size else 0.0,
+                    t_pos=t_pos, t_neg=t_neg)
+        del H, Hl, reach, big, pos, neg
+        rows = queue_hubs * (queue_P + queue_N)
+        spe = max(1, -(-nt // rows))
+        nb = ann.ann_train_hub_workspace_size(queue_hubs, queue_P, queue_N, d, hub_in.shape[1], hidden,
+                                              dout)
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        for ep in range(epochs):
+            for _ in range(spe):
+                step += 1
+                hb, pp, nn = synth.queue_batch(w, step, eligible, pos_off, neg_off, queue_hubs,
+                                               queue_P, queue_N)
+                qi = torch.cat([pos_q[torch.from_numpy(pp).to(dev)],
+                                neg_q[torch.from_numpy(nn).to(dev)]], dim=1)
+                loss, _, _ = ann.ann_train_step_hub(qt, ht, train_q, qi.reshape(-1).to(torch.int32),
+                                                    torch.from_numpy(hb.astype(np.int32)).to(dev),
+                                                    queue_P, queue_N, hub_in, tau, lr, step, ws=ws)
+            losses.append(loss.item())
+        log("queues: %d of %d hubs with both queues, %.0f positives / %.0f negatives per hub" %
+            (eligible.size, n_hubs, info["queue_pos_mean"], info["queue_neg_mean"]))
+    elif train:
         for ep in range(epochs):
             order = torch.from_numpy(synth.batch_order(w, nt, ep).astype(np.int32)).to(dev)
             for b0 in range(0, nt - batch + 1, batch):
@@ -218,7 +272,7 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
                                                 tau, lr, step, ws=ws)
             losses.append(loss.item())
     torch.cuda.synchronize()
-    info.update(train_s=time.time() - t, train_steps=step, hidden=hidden, dout=dout,
+    info.update(train_s=time.time() - t, train_steps=step, hidden=hidden, dout=dout, objective=objective,
                 epochs=epochs, lr=lr, tau=tau, holdout=n_hold,
                 loss_per_epoch=[round(x, 4) for x in losses])
     if losses:

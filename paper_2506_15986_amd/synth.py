@@ -198,6 +198,23 @@ def batch_order(w: Workload, n: int, epoch: int) -> np.ndarray:
     return rng_for(w, "shuffle", epoch).permutation(n).astype(np.int64)
 
 
+def queue_batch(w: Workload, step: int, eligible: np.ndarray, pos_off: np.ndarray,
+                neg_off: np.ndarray, hubs: int, P: int, N: int):
+    """Seeded choice for one hub-anchored training step: `hubs` hubs drawn
+    without replacement from `eligible`, and for each P positions into its
+    positive queue and N into its negative queue, with replacement (queue h
+    spans off[h] .. off[h+1] of the concatenated queues).  Returns (hub
+    indices [b], positive positions [b, P], negative positions [b, N])."""
+    r = rng_for(w, "shuffle", 1_000_000 + step)
+    hb = r.choice(eligible, size=min(hubs, eligible.size), replace=False).astype(np.int64)
+    pp = np.empty((hb.size, P), np.int64)
+    nn = np.empty((hb.size, N), np.int64)
+    for i, h in enumerate(hb):
+        pp[i] = pos_off[h] + r.integers(0, pos_off[h + 1] - pos_off[h], size=P)
+        nn[i] = neg_off[h] + r.integers(0, neg_off[h + 1] - neg_off[h], size=N)
+    return hb, pp, nn
+
+
 def request_stream(w: Workload, n_requests: int, rate: float, max_batch: int = 512):
     """Poisson arrivals: (arrival_s, batch_size, k) per request."""
     r = rng_for(w, "arrivals")

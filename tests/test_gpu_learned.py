@@ -259,3 +259,47 @@ def test_ladder_labels_match_oracle(which):
     else:                   # FP32 vs FP64 near ties may move a cost
         assert (tab == ref_tab).mean() >= 0.98
         assert (lab == ref_lab).mean() >= 0.97
+
+
+@pytest.mark.parametrize("P,N", [(4, 12), (1, 0), (8, 60)])
+def test_hub_anchored_step_gradients_match_oracle(P, N):
+    # Eq. 4 over per-hub queues: 16 hubs of the batch, P positives and N
+    # negatives each (rows with repeats, as sampling with replacement gives)
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    tq = synth.train_queries(ix["w"], 512)
+    r = np.random.default_rng(P * 100 + N)
+    hubs = r.choice(hub_in.shape[0], 16, replace=False).astype(np.int32)
+    q_idx = r.integers(0, tq.shape[0], size=16 * (P + N)).astype(np.int32)
+    say("case: hub-anchored step, P=%d N=%d" % (P, N))
+    qt, ht = ann.Tower(*qp, in_scale=0.0625), ann.Tower(*hp)
+    loss, qe, he = ann.ann_train_step_hub(qt, ht, _dev(tq), _dev(q_idx), _dev(hubs), P, N,
+                                          _dev(hub_in), 0.07, 1e-3, 0, want_emb=True)
+    torch.cuda.synchronize()
+    ref_loss, gq, gh, eq, eh = T.train_step_grads_hub(qp, hp, tq[q_idx].astype(np.float64),
+                                                      hub_in[hubs].astype(np.float64), P, N, 0.07,
+                                                      bf16=True, q_scale=0.0625)
+    assert abs(loss.item() - ref_loss) <= 1e-4 * max(abs(ref_loss), 1.0)
+    for got, ref in zip([t.cpu().numpy() for t in qt.g + ht.g], list(gq) + list(gh)):
+        if np.linalg.norm(ref) == 0:
+            assert np.abs(got).max() <= 1e-6
+        else:
+            assert _rel(got, ref) <= 1e-3
+
+
+def test_hop_table_matches_oracle():
+    # two batches of hubs (100 > 64); then a graph without its repair slots,
+    # where some targets are unreachable (255)
+    ann = _ann()
+    ix = int_index()
+    r = np.random.default_rng(5)
+    hubs = r.choice(ix["base"].shape[0], 100, replace=False).astype(np.int32)
+    targets = ix["truth"][:, 0].astype(np.int32)
+    for name, g in (("graph", ix["graph"]), ("without repair slots", ix["graph"][:, :-2])):
+        g = np.ascontiguousarray(g)
+        say("case: hop table, %s" % name)
+        H = ann.ann_hop_table(_dev(g), _dev(hubs), _dev(targets))
+        torch.cuda.synchronize()
+        ref = oracle.hop_table(g, hubs, targets)
+        assert (H.cpu().numpy() == ref).all(), name
+    assert (ref == 255).any()
