@@ -159,3 +159,76 @@ def adam_update(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     vh = v / (1.0 - b2 ** t)
     p = p - lr * mh / (np.sqrt(vh) + eps)
     return p, m, v
+
+
+# ---------------------------------------------------------------- Eq. 3 fusion
+def fusion_forward(params, p, U, mask, heads: int):
+    """Eq. 3 multi-head attention of the hub vector over its topology tokens.
+
+    params = (WQ [m*dk x dp], WK [m*dk x dU], WV [m*dk x dU], WO [dF x m*dk]);
+    p [nh x dp] the hub vectors, U [nh x S x dU] the tokens, mask [nh x S]
+    (1 = token present).  Head j uses rows j*dk .. j*dk+dk-1 of WQ/WK/WV:
+        a_j = softmax_s( <p WQ_j, U_s WK_j> / sqrt(dk) )  over present s
+        F   = concat_j( sum_s a_j,s U_s WV_j ) WO^T
+    A hub without tokens gets F = 0.  Returns (F [nh x dF], cache)."""
+    WQ, WK, WV, WO = [np.asarray(w, np.float64) for w in params]
+    p, U = np.asarray(p, np.float64), np.asarray(U, np.float64)
+    m = heads
+    dk = WQ.shape[0] // m
+    q = p @ WQ.T                                  # nh x m*dk
+    K = U @ WK.T                                  # nh x S x m*dk
+    V = U @ WV.T
+    nh, S = U.shape[0], U.shape[1]
+    a = np.zeros((nh, m, S))
+    O = np.zeros((nh, m * dk))
+    for i in range(nh):
+        pres = np.asarray(mask[i], bool)
+        if not pres.any():
+            continue
+        for j in range(m):
+            sl = slice(j * dk, (j + 1) * dk)
+            sc = K[i, :, sl] @ q[i, sl] / np.sqrt(dk)
+            sc = np.where(pres, sc, -np.inf)
+            e = np.exp(sc - sc[pres].max())
+            a[i, j] = e / e.sum()
+            O[i, sl] = a[i, j] @ V[i, :, sl]
+    F = O @ WO.T
+    return F, dict(p=p, U=U, q=q, K=K, V=V, a=a, O=O, WQ=WQ, WK=WK, WV=WV, WO=WO, m=m, dk=dk)
+
+
+def fusion_backward(cache, dF):
+    """Gradients of the four matrices given dL/dF.  Returns (gWQ, gWK, gWV, gWO)."""
+    p, U, q, K, V, a, O = (cache[k] for k in ("p", "U", "q", "K", "V", "a", "O"))
+    WO, m, dk = cache["WO"], cache["m"], cache["dk"]
+    dF = np.asarray(dF, np.float64)
+    gWO = dF.T @ O
+    dO = dF @ WO                                  # nh x m*dk
+    nh, S = U.shape[0], U.shape[1]
+    dq = np.zeros_like(q)
+    dK = np.zeros_like(K)
+    dV = np.zeros_like(V)
+    for i in range(nh):
+        for j in range(m):
+            sl = slice(j * dk, (j + 1) * dk)
+            aj = a[i, j]
+            dV[i, :, sl] = np.outer(aj, dO[i, sl])
+            da = V[i, :, sl] @ dO[i, sl]
+            ds = aj * (da - np.dot(aj, da))
+            dq[i, sl] = ds @ K[i, :, sl] / np.sqrt(dk)
+            dK[i, :, sl] = np.outer(ds, q[i, sl]) / np.sqrt(dk)
+    gWQ = dq.T @ p
+    gWK = np.einsum("ist,isc->tc", dK, U)
+    gWV = np.einsum("ist,isc->tc", dV, U)
+    return gWQ, gWK, gWV, gWO
+
+
+def tower_backward_input(cache, de, bf16=True, in_scale=1.0):
+    """dL/d(tower input) given dL/d e_hat (the input's BF16 rounding taken
+    as the identity): in_scale * dz1 W1, with dz1 as in tower_backward."""
+    e, nrm = cache["e"], cache["nrm"]
+    dz2 = (de - e * np.sum(e * de, axis=1, keepdims=True)) / nrm
+    dz2r = _rnd(dz2, bf16)
+    da1 = dz2r @ cache["W2r"]
+    dz1 = da1 * (cache["z1"] > 0)
+    dz1r = _rnd(dz1, bf16)
+    return in_scale * (dz1r @ cache["W1r"])

@@ -362,3 +362,76 @@ def test_hub_contrastive_closed_form_and_gradients():
             a2[idx] -= 2 * eps
             lm = T.hub_contrastive(a2 if arr is eh else eh, a2 if arr is eq else eq, P, N, tau)[0]
             assert np.isclose((lp - lm) / (2 * eps), grad[idx], rtol=1e-5, atol=1e-8)
+
+
+# ---------------------------------------------------------------- Eq. 3 fusion
+def _fusion_case(seed, nh=3, S=5, d=6, m=2, dk=3, dF=4):
+    r = np.random.default_rng(seed)
+    params = (r.normal(size=(m * dk, d)), r.normal(size=(m * dk, d)), r.normal(size=(m * dk, d)),
+              r.normal(size=(dF, m * dk)))
+    p = r.normal(size=(nh, d))
+    U = r.normal(size=(nh, S, d))
+    mask = np.ones((nh, S), np.uint8)
+    mask[1, 3:] = 0
+    mask[2, :] = 0                                 # a hub without tokens
+    return params, p, U, mask, m
+
+
+def test_fusion_single_token_is_linear_and_no_token_is_zero():
+    # one present token: every softmax is 1, so F = (U_0 WV^T) WO^T
+    params, p, U, mask, m = _fusion_case(1)
+    mask[:] = 0
+    mask[0, 2] = 1
+    F, _ = towers.fusion_forward(params, p, U, mask, m)
+    WQ, WK, WV, WO = params
+    assert np.allclose(F[0], (U[0, 2] @ WV.T) @ WO.T)
+    assert (F[1] == 0).all() and (F[2] == 0).all()
+
+
+def test_fusion_matches_per_head_softmax_by_hand():
+    params, p, U, mask, m = _fusion_case(2)
+    F, _ = towers.fusion_forward(params, p, U, mask, m)
+    WQ, WK, WV, WO = params
+    dk = WQ.shape[0] // m
+    i = 1                                          # tokens 0..2 present
+    heads = []
+    for j in range(m):
+        sl = slice(j * dk, (j + 1) * dk)
+        sc = np.array([(p[i] @ WQ[sl].T) @ (U[i, s] @ WK[sl].T) for s in range(3)]) / np.sqrt(dk)
+        w = np.exp(sc) / np.exp(sc).sum()
+        heads.append(sum(w[s] * (U[i, s] @ WV[sl].T) for s in range(3)))
+    assert np.allclose(F[i], np.concatenate(heads) @ WO.T)
+
+
+def test_fusion_gradients_match_finite_differences():
+    params, p, U, mask, m = _fusion_case(3)
+    r = np.random.default_rng(4)
+    dF = r.normal(size=(3, 4))
+    F, cache = towers.fusion_forward(params, p, U, mask, m)
+    grads = towers.fusion_backward(cache, dF)
+    eps = 1e-6
+    for w_i in range(4):
+        for idx in [(0, 0), (1, 2), (params[w_i].shape[0] - 1, params[w_i].shape[1] - 1)]:
+            pp = [np.array(x, np.float64) for x in params]
+            pp[w_i][idx] += eps
+            lp = (towers.fusion_forward(pp, p, U, mask, m)[0] * dF).sum()
+            pp[w_i][idx] -= 2 * eps
+            lm = (towers.fusion_forward(pp, p, U, mask, m)[0] * dF).sum()
+            assert np.isclose((lp - lm) / (2 * eps), grads[w_i][idx], rtol=1e-5, atol=1e-8)
+
+
+def test_tower_input_gradient_matches_finite_differences():
+    r = np.random.default_rng(5)
+    params = (r.normal(size=(7, 5)) * 0.5, r.normal(size=7), r.normal(size=(4, 7)) * 0.5, r.normal(size=4))
+    x = r.normal(size=(3, 5))
+    de = r.normal(size=(3, 4))
+    e, cache = towers.tower_forward(params, x, bf16=False, in_scale=0.5)
+    dx = towers.tower_backward_input(cache, de, bf16=False, in_scale=0.5)
+    eps = 1e-6
+    for idx in [(0, 0), (1, 3), (2, 4)]:
+        x2 = x.copy()
+        x2[idx] += eps
+        lp = (towers.tower_forward(params, x2, bf16=False, in_scale=0.5)[0] * de).sum()
+        x2[idx] -= 2 * eps
+        lm = (towers.tower_forward(params, x2, bf16=False, in_scale=0.5)[0] * de).sum()
+        assert np.isclose((lp - lm) / (2 * eps), dx[idx], rtol=1e-5, atol=1e-8)
