@@ -151,7 +151,7 @@ def main():
     ap.add_argument("--legs", default="medoid,gate,ablation,serve",
                     help="also: hbkm (GATE on hierarchical balanced k-means hubs, one model per "
                          "--hbkm-lambdas value), queues (GATE trained on Definition 4 queues with "
-                         "the hub-anchored Eq. 4 loss)")
+                         "the hub-anchored Eq. 4 loss), fusion (GATE with the Eq. 3 fusion embedding)")
     ap.add_argument("--hbkm-lambdas", default="0,1,10")
     ap.add_argument("--queue-variants", default="3:16:48",
                     help="queues leg: t_pos:P:N triples, comma separated (t_neg stays 15)")
@@ -547,6 +547,20 @@ def main():
                     (lam, h_L95, gd.info["hbkm"]["size_min"], gd.info["hbkm"]["size_max"],
                      gd.info["hbkm"]["size_objective"], gdata.info.get("size_objective", float("nan"))))
                 del gh, gd
+        if "fusion" in legs and tq is not None:
+            # Eq. 3 fusion embedding in the hub tower's input (the default model is
+            # the "without fusion" side)
+            gf = gate.train_gate(index, gdata, tq, w, hidden=args.hidden, dout=args.dout,
+                                 epochs=args.epochs, lr=args.lr, tau=args.tau, fusion=True, log=log)
+            ef, _, _ = gf.select(q_d)
+            f_rows, f_L95 = sweep(ef, "fusion")
+            r95 = next((r for r in f_rows if r["L"] == f_L95), None)
+            abl["fusion"] = dict(L95=f_L95, ndc=r95["ndc"] if r95 else None,
+                                 **{k: gf.info.get(k) for k in ("fusion", "train_s", "train_steps",
+                                                                 "val_top1", "loss_per_epoch")})
+            log("fusion embedding: L95 %s (without fusion %s), held-out agreement %s" %
+                (f_L95, L_gate, gf.info.get("val_top1")))
+            del gf
         if "queues" in legs and tq is not None:
             # the paper's training signal: Definition 4 queues and Eq. 4 read
             # hub-anchored, on the same hubs, features and towers

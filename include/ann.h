@@ -372,14 +372,17 @@ size_t ann_train_workspace_size(int32_t batch, int32_t n_hubs, int32_t din_q, in
  * *loss (device FP32), the embeddings to q_emb / h_emb when non-NULL, and
  * when step >= 1 applies Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias
  * correction with t = step) to both towers and refreshes their BF16 copies.
- * step == 0 computes gradients only. */
+ * step == 0 computes gradients only.  hub_in_grad (n_hubs x din_h, device,
+ * or NULL) receives dL/d hub_in (the input's BF16 rounding taken as the
+ * identity), for an upstream module such as the fusion embedding. */
 ann_status ann_train_step(ann_tower *query_tower, ann_tower *hub_tower,
                           const ann_tower_grads *qg, const ann_tower_grads *hg,
                           const ann_adam_state *qa, const ann_adam_state *ha,
                           const float *train_q, const int32_t *batch_idx, int32_t batch,
                           const int32_t *labels, const float *hub_in, int32_t n_hubs,
                           float tau, float lr, int32_t step, float *loss, float *q_emb,
-                          float *h_emb, void *workspace, size_t ws_bytes, void *stream);
+                          float *h_emb, float *hub_in_grad, void *workspace, size_t ws_bytes,
+                          void *stream);
 
 size_t ann_train_hub_workspace_size(int32_t hubs, int32_t P, int32_t N, int32_t din_q,
                                     int32_t din_h, int32_t hidden, int32_t dout);
@@ -400,6 +403,43 @@ ann_status ann_train_step_hub(ann_tower *query_tower, ann_tower *hub_tower,
                               int32_t hubs, int32_t P, int32_t N, const float *hub_in, float tau,
                               float lr, int32_t step, float *loss, float *q_emb, float *h_emb,
                               void *workspace, size_t ws_bytes, void *stream);
+
+/* Fusion embedding augmentation (Eq. 3): multi-head attention of each hub's
+ * vector p (dp values) over its S topology tokens U (du values each, masked
+ * slots absent):
+ *   q = p WQ^T, K_s = U_s WK^T, V_s = U_s WV^T   (heads x dk channels; head j
+ *                                                 owns channels j*dk .. j*dk+dk-1)
+ *   a_j = softmax over present s of <q_j, K_s,j> / sqrt(dk)
+ *   F = concat_j( sum_s a_j,s V_s,j ) WO^T         (df values)
+ * A hub without present tokens gets F = 0.  FP32, fixed summation order.
+ * Limits: heads <= 16, heads * dk <= 64, df <= 64, S <= 64. */
+typedef struct ann_fusion {
+    int32_t heads, dk, dp, du, df;
+    float *WQ;   /* heads*dk x dp */
+    float *WK;   /* heads*dk x du */
+    float *WV;   /* heads*dk x du */
+    float *WO;   /* df x heads*dk */
+} ann_fusion;
+
+/* F (n_hubs x df) from p (n_hubs x dp), U (n_hubs x S x du) and mask
+ * (n_hubs x S, 1 = present); all device.  Enqueues only. */
+ann_status ann_fusion_forward(const ann_fusion *f, const float *p, const float *U,
+                              const uint8_t *mask, int32_t n_hubs, int32_t S, float *F,
+                              void *stream);
+
+size_t ann_fusion_workspace_size(const ann_fusion *f, int32_t n_hubs);
+
+/* Gradients of the four matrices (same shapes, overwritten) given dL/dF
+ * (n_hubs x df): per-hub partial gradients summed in hub order. */
+ann_status ann_fusion_backward(const ann_fusion *f, const float *p, const float *U,
+                               const uint8_t *mask, int32_t n_hubs, int32_t S, const float *dF,
+                               float *gWQ, float *gWK, float *gWV, float *gWO, void *workspace,
+                               size_t ws_bytes, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction with t =
+ * step >= 1) on `count` FP32 parameters with their moment buffers. */
+ann_status ann_adam_step(float *param, const float *grad, float *m, float *v, int64_t count,
+                         float lr, int32_t step, void *stream);
 
 /* Hop counts of Definition 4: out[q * n_hubs + h] (uint8, device) = the
  * length of the shortest path along the graph's edges from hub_ids[h] to

@@ -112,7 +112,7 @@ _sig("ann_train_workspace_size", _SZ, _I32, _I32, _I32, _I32, _I32, _I32)
 _sig("ann_train_step", _I32, ctypes.POINTER(ann_tower), ctypes.POINTER(ann_tower),
      ctypes.POINTER(ann_tower_grads), ctypes.POINTER(ann_tower_grads),
      ctypes.POINTER(ann_adam_state), ctypes.POINTER(ann_adam_state), _P, _P, _I32, _P, _P, _I32,
-     _F32, _F32, _I32, _P, _P, _P, _P, _SZ, _P)
+     _F32, _F32, _I32, _P, _P, _P, _P, _P, _SZ, _P)
 _sig("ann_navgraph_workspace_size", _SZ, _I32, _I32, _I32)
 _sig("ann_navgraph_build", _I32, _P, _I32, _I32, _I32, _P, ctypes.POINTER(_I32), _P, _SZ, _P)
 _sig("ann_entry_workspace_size", _SZ, ctypes.POINTER(ann_entry_model), _I32)
@@ -499,9 +499,11 @@ class Tower:
 
 
 def ann_train_step(qt: Tower, ht: Tower, train_q, batch_idx, labels, hub_in, tau: float,
-                   lr: float, step: int, ws=None, want_emb: bool = False, stream=None):
+                   lr: float, step: int, ws=None, want_emb: bool = False, stream=None,
+                   hub_in_grad=None):
     """One training step (step 0 = gradients only).  Returns (loss tensor,
-    q_emb, h_emb) with the embeddings only when want_emb."""
+    q_emb, h_emb) with the embeddings only when want_emb; hub_in_grad (a
+    tensor shaped like hub_in) receives dL/d hub_in when given."""
     dev = train_q.device
     B = batch_idx.shape[0]
     nh = hub_in.shape[0]
@@ -517,8 +519,8 @@ def ann_train_step(qt: Tower, ht: Tower, train_q, batch_idx, labels, hub_in, tau
     _check(_lib.ann_train_step(ctypes.byref(q_s), ctypes.byref(h_s), ctypes.byref(qg),
                                ctypes.byref(hg), ctypes.byref(qa), ctypes.byref(ha), _ptr(train_q),
                                _ptr(batch_idx), B, _ptr(labels), _ptr(hub_in), nh, float(tau),
-                               float(lr), int(step), _ptr(loss), _ptr(qe), _ptr(he), _ptr(ws),
-                               ws.numel(), _stream(stream)))
+                               float(lr), int(step), _ptr(loss), _ptr(qe), _ptr(he),
+                               _ptr(hub_in_grad), _ptr(ws), ws.numel(), _stream(stream)))
     return loss, qe, he
 
 
@@ -580,6 +582,80 @@ def ann_hop_table(graph: torch.Tensor, hub_ids: torch.Tensor, targets: torch.Ten
                               _ptr(ws), ws.numel(), _stream(stream)))
     del ws
     return out
+
+
+class ann_fusion(ctypes.Structure):
+    _fields_ = [("heads", _I32), ("dk", _I32), ("dp", _I32), ("du", _I32), ("df", _I32),
+                ("WQ", _P), ("WK", _P), ("WV", _P), ("WO", _P)]
+
+
+_sig("ann_fusion_forward", _I32, ctypes.POINTER(ann_fusion), _P, _P, _P, _I32, _I32, _P, _P)
+_sig("ann_fusion_workspace_size", _SZ, ctypes.POINTER(ann_fusion), _I32)
+_sig("ann_fusion_backward", _I32, ctypes.POINTER(ann_fusion), _P, _P, _P, _I32, _I32, _P, _P, _P,
+     _P, _P, _P, _SZ, _P)
+_sig("ann_adam_step", _I32, _P, _P, _P, _P, _I64, _F32, _I32, _P)
+
+
+def ann_adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                  lr: float, step: int, stream=None):
+    _check(_lib.ann_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), float(lr),
+                              int(step), _stream(stream)))
+
+
+class Fusion:
+    """Eq. 3 fusion embedding (ann_fusion_*): WQ, WK, WV [heads*dk x d],
+    WO [df x heads*dk] on the device, with gradients and Adam moments."""
+
+    def __init__(self, WQ, WK, WV, WO, heads: int, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()  # noqa: E731
+        self.W = [f(WQ), f(WK), f(WV), f(WO)]
+        self.heads = int(heads)
+        self.dk = self.W[0].shape[0] // self.heads
+        self.dp, self.du = self.W[0].shape[1], self.W[1].shape[1]
+        self.df = self.W[3].shape[0]
+        self.g = [torch.zeros_like(t) for t in self.W]
+        self.m = [torch.zeros_like(t) for t in self.W]
+        self.v = [torch.zeros_like(t) for t in self.W]
+
+    def struct(self) -> ann_fusion:
+        return ann_fusion(self.heads, self.dk, self.dp, self.du, self.df,
+                          *[t.data_ptr() for t in self.W])
+
+    def forward(self, p, U, mask, stream=None) -> torch.Tensor:
+        nh, S = U.shape[0], U.shape[1]
+        F = torch.empty((nh, self.df), dtype=torch.float32, device=p.device)
+        st = self.struct()
+        _check(_lib.ann_fusion_forward(ctypes.byref(st), _ptr(p), _ptr(U), _ptr(mask), nh, S,
+                                       _ptr(F), _stream(stream)))
+        return F
+
+    def backward(self, p, U, mask, dF, stream=None):
+        """Writes the four gradients into self.g."""
+        nh, S = U.shape[0], U.shape[1]
+        st = self.struct()
+        nb = max(256, int(_lib.ann_fusion_workspace_size(ctypes.byref(st), nh)))
+        ws = torch.empty(nb, dtype=torch.uint8, device=p.device)
+        _check(_lib.ann_fusion_backward(ctypes.byref(st), _ptr(p), _ptr(U), _ptr(mask), nh, S,
+                                        _ptr(dF), *[_ptr(t) for t in self.g], _ptr(ws), nb,
+                                        _stream(stream)))
+
+    def adam(self, lr: float, step: int, stream=None):
+        for W, g, m, v in zip(self.W, self.g, self.m, self.v):
+            ann_adam_step(W, g, m, v, lr, step, stream)
+
+
+def ann_fusion_forward(fusion: Fusion, p, U, mask, stream=None) -> torch.Tensor:
+    return fusion.forward(p, U, mask, stream)
+
+
+def ann_fusion_backward(fusion: Fusion, p, U, mask, dF, stream=None):
+    fusion.backward(p, U, mask, dF, stream)
+    return fusion.g
+
+
+def ann_fusion_workspace_size(fusion: Fusion, n_hubs: int) -> int:
+    st = fusion.struct()
+    return int(_lib.ann_fusion_workspace_size(ctypes.byref(st), n_hubs))
 
 
 def ann_navgraph_build(hub_emb: torch.Tensor, s: int, stream=None):

@@ -307,6 +307,13 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_
     }
 }
 
+__global__ void scale_kernel(float *x, int64_t count, float a)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] *= a;
+}
+
 inline dim3 grid2(int M, int N) { return dim3((N + GT - 1) / GT, (M + GT - 1) / GT); }
 inline int gridn(int64_t n) { return (int)((n + 255) / 256 > 4096 ? 4096 : (n + 255) / 256); }
 
@@ -608,8 +615,8 @@ extern "C" ann_status ann_train_step(ann_tower *qt, ann_tower *ht, const ann_tow
                                      const int32_t *batch_idx, int32_t batch,
                                      const int32_t *labels, const float *hub_in, int32_t n_hubs,
                                      float tau, float lr, int32_t step, float *loss,
-                                     float *q_emb, float *h_emb, void *workspace,
-                                     size_t ws_bytes, void *stream)
+                                     float *q_emb, float *h_emb, float *hub_in_grad,
+                                     void *workspace, size_t ws_bytes, void *stream)
 {
     ann_status s = check_tower(qt, "query");
     if (s != ANN_OK) return s;
@@ -661,6 +668,28 @@ extern "C" ann_status ann_train_step(ann_tower *qt, ann_tower *ht, const ann_tow
     TRY(gemm_f32(gh, st));
     TRY(tower_bwd(*qt, *qg, bq, batch, st));
     TRY(tower_bwd(*ht, *hg, bh, n_hubs, st));
+    if (hub_in_grad) {
+        // dL/d hub_in [n_hubs x din_h] = in_scale * (dz1b . W1b)
+        GemmArgs g{};
+        g.A = bh.dz1b;
+        g.sam = ht->hidden;
+        g.sak = 1;
+        g.B = ht->W1b;
+        g.sbn = 1;
+        g.sbk = ht->din;
+        g.M = n_hubs;
+        g.N = ht->din;
+        g.K = ht->hidden;
+        g.C = hub_in_grad;
+        g.ldc = ht->din;
+        TRY(gemm_bf16(g, st));
+        if (ht->in_scale != 1.f) {
+            const int64_t cnt = (int64_t)n_hubs * ht->din;
+            hipLaunchKernelGGL(scale_kernel, dim3(gridn(cnt)), dim3(256), 0, st, hub_in_grad, cnt,
+                               ht->in_scale);
+            ANN_LAUNCHED();
+        }
+    }
     if (step > 0) {
         TRY(adam(*qt, *qg, *qa, step, lr, st));
         TRY(adam(*ht, *hg, *ha, step, lr, st));

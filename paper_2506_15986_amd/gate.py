@@ -189,7 +189,8 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
                theta: float = -math.inf, train: bool = True, holdout: float = 0.1,
                init: str = "random", tune_L_h: bool = True, objective: str = "labels",
                t_pos: int = 3, t_neg: int = 15, queue_hubs: int = 64, queue_P: int = 16,
-               queue_N: int = 48, log=print) -> Gate:
+               queue_N: int = 48, fusion: bool = False, fusion_heads: int = 4,
+               fusion_dk: int = 16, fusion_df: int = 64, log=print) -> Gate:
     """Trains the towers on the first (1 - holdout) of the training queries
     (contrastive loss, Adam), embeds the hubs, builds the navigation graph and
     reports top-1 label agreement on the trained and the held-out queries.
@@ -200,12 +201,32 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     closest query, negatives t_neg or more hops beyond it) and Eq. 4 read
     hub-anchored, queue_hubs hubs per step with queue_P positives and
     queue_N negatives each; as many steps per epoch as fill the training
-    queries once (queue_hubs * (queue_P + queue_N) query rows per step)."""
+    queries once (queue_hubs * (queue_P + queue_N) query rows per step).
+
+    fusion: the hub tower reads [hub vector | F | features] with F the Eq. 3
+    fusion embedding of the hub vector over its topology tokens (the relative
+    positions x_w - x_hub of its graph neighbours, scaled like the vectors;
+    empty slots masked), trained with the towers through the hub tower's input
+    gradient (labels objective)."""
     dev = index.base.device
     d = index.dim
     n_hubs = data.hub_ids.shape[0]
     info = dict(data.info)
     hub_in, labels = data.hub_in, data.labels
+    fu = None
+    if fusion:
+        base = index.base
+        hid = data.hub_ids.long()
+        nbr = index.graph[hid].long()                                  # n_hubs x R
+        tok_mask = (nbr >= 0).to(torch.uint8).contiguous()
+        p_vec = (base[hid] * data.scale).contiguous()
+        U = ((base[nbr.clamp(min=0)] - base[hid][:, None, :]) * data.scale
+             * tok_mask[:, :, None].float()).contiguous()
+        C = fusion_heads * fusion_dk
+        fw = synth.tower_init(w, [(C, d), (C, d), (C, d), (fusion_df, C)], salt=3)
+        fu = ann.Fusion(fw[0], fw[2], fw[4], fw[6], heads=fusion_heads, device=dev)
+        feat = hub_in[:, d:]
+        hub_in = torch.cat([hub_in[:, :d], fu.forward(p_vec, U, tok_mask), feat], dim=1).contiguous()
     qp = synth.tower_init(w, [(hidden, d), (dout, hidden)])
     hp = synth.tower_init(w, [(hidden, hub_in.shape[1]), (dout, hidden)])
     if init == "tied":
@@ -263,6 +284,20 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
             losses.append(loss.item())
         log("queues: %d of %d hubs with both queues, %.0f positives / %.0f negatives per hub" %
             (eligible.size, n_hubs, info["queue_pos_mean"], info["queue_neg_mean"]))
+    elif train and fu is not None:
+        dx = torch.empty_like(hub_in)
+        fd = fu.df
+        for ep in range(epochs):
+            order = torch.from_numpy(synth.batch_order(w, nt, ep).astype(np.int32)).to(dev)
+            for b0 in range(0, nt - batch + 1, batch):
+                step += 1
+                hub_in[:, d:d + fd] = fu.forward(p_vec, U, tok_mask)
+                loss, _, _ = ann.ann_train_step(qt, ht, train_q, order[b0:b0 + batch], labels, hub_in,
+                                                tau, lr, step, ws=ws, hub_in_grad=dx)
+                fu.backward(p_vec, U, tok_mask, dx[:, d:d + fd].contiguous())
+                fu.adam(lr, step)
+            losses.append(loss.item())
+        hub_in[:, d:d + fd] = fu.forward(p_vec, U, tok_mask)
     elif train:
         for ep in range(epochs):
             order = torch.from_numpy(synth.batch_order(w, nt, ep).astype(np.int32)).to(dev)
@@ -273,6 +308,7 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
             losses.append(loss.item())
     torch.cuda.synchronize()
     info.update(train_s=time.time() - t, train_steps=step, hidden=hidden, dout=dout, objective=objective,
+                fusion=dict(heads=fusion_heads, dk=fusion_dk, df=fusion_df) if fusion else None,
                 epochs=epochs, lr=lr, tau=tau, holdout=n_hold,
                 loss_per_epoch=[round(x, 4) for x in losses])
     if losses:

@@ -180,11 +180,12 @@ def kmeans_init(w: Workload, n: int, n_hubs: int) -> np.ndarray:
     return rng_for(w, "init").permutation(n)[:n_hubs].astype(np.int32)
 
 
-def tower_init(w: Workload, shapes: list[tuple[int, int]]) -> list[np.ndarray]:
+def tower_init(w: Workload, shapes: list[tuple[int, int]], salt: int = 0) -> list[np.ndarray]:
     """Uniform(-1/sqrt(fan_in), +1/sqrt(fan_in)) weights/biases, float32.
 
-    shapes are (out, in) per linear layer; returns [W0, b0, W1, b1, ...]."""
-    r = rng_for(w, "tower")
+    shapes are (out, in) per linear layer; returns [W0, b0, W1, b1, ...].
+    salt picks an independent substream (0: the towers')."""
+    r = rng_for(w, "tower", salt)
     out = []
     for (o, i) in shapes:
         lim = 1.0 / np.sqrt(i)

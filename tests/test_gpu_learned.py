@@ -303,3 +303,51 @@ def test_hop_table_matches_oracle():
         ref = oracle.hop_table(g, hubs, targets)
         assert (H.cpu().numpy() == ref).all(), name
     assert (ref == 255).any()
+
+
+def test_fusion_forward_backward_match_oracle():
+    # 4 heads of 16 channels over 32 tokens of 128 values; ragged masks and
+    # one hub without tokens
+    ann = _ann()
+    r = np.random.default_rng(21)
+    nh, S, d, heads, dk, df = 50, 32, 128, 4, 16, 64
+    C = heads * dk
+    Ws = [r.normal(0, 1 / np.sqrt(d), size=(C, d)), r.normal(0, 1 / np.sqrt(d), size=(C, d)),
+          r.normal(0, 1 / np.sqrt(d), size=(C, d)), r.normal(0, 1 / np.sqrt(C), size=(df, C))]
+    Ws = [w.astype(np.float32) for w in Ws]
+    p = r.normal(size=(nh, d)).astype(np.float32)
+    U = r.normal(size=(nh, S, d)).astype(np.float32)
+    mask = (r.random((nh, S)) < 0.8).astype(np.uint8)
+    mask[7] = 0
+    dF = r.normal(size=(nh, df)).astype(np.float32)
+    say("case: fusion forward / backward")
+    fu = ann.Fusion(*Ws, heads=heads)
+    F = fu.forward(_dev(p), _dev(U), _dev(mask))
+    fu.backward(_dev(p), _dev(U), _dev(mask), _dev(dF))
+    torch.cuda.synchronize()
+    ref, cache = T.fusion_forward([w.astype(np.float64) for w in Ws], p, U, mask, heads)
+    assert _rel(F.cpu().numpy(), ref) <= 1e-5
+    assert (F.cpu().numpy()[7] == 0).all()
+    grads = T.fusion_backward(cache, dF.astype(np.float64))
+    for got, want in zip(fu.g, grads):
+        assert _rel(got.cpu().numpy(), want) <= 1e-4
+
+
+def test_train_step_hub_input_gradient_matches_oracle():
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    tq = synth.train_queries(ix["w"], 512)
+    r = np.random.default_rng(2)
+    labels = r.integers(0, hub_in.shape[0], size=tq.shape[0]).astype(np.int32)
+    idx = r.permutation(tq.shape[0])[:256].astype(np.int32)
+    say("case: train step with the hub input gradient")
+    qt, ht = ann.Tower(*qp, in_scale=0.0625), ann.Tower(*hp)
+    dx = torch.empty(hub_in.shape, dtype=torch.float32, device="cuda")
+    ann.ann_train_step(qt, ht, _dev(tq), _dev(idx), _dev(labels), _dev(hub_in), 0.07, 1e-3, 0,
+                       hub_in_grad=dx)
+    torch.cuda.synchronize()
+    eq, cq = T.tower_forward(qp, tq[idx].astype(np.float64), True, 0.0625)
+    eh, ch = T.tower_forward(hp, hub_in.astype(np.float64), True)
+    _, _, deh, _ = T.infonce(eq, eh, labels[idx], 0.07)
+    ref = T.tower_backward_input(ch, deh, bf16=True)
+    assert _rel(dx.cpu().numpy(), ref) <= 1e-3
