@@ -172,6 +172,43 @@ def build_graph_grouped(base, groups, knn_k: int, R: int, alpha: float):
     return g, m, nf, nr, cand, cd2
 
 
+def merge_candidates(pool_ids, pool_d2, knn_ids, knn_d2):
+    """Row-wise union of two candidate lists (the point's own search pool and
+    its exact kNN list), point i's own id dropped, duplicates once, ordered by
+    (d2, id); -1 / +inf padded to the two widths together."""
+    n = pool_ids.shape[0]
+    W = pool_ids.shape[1] + knn_ids.shape[1]
+    ids = np.full((n, W), -1, np.int32)
+    dd = np.full((n, W), np.inf)
+    for i in range(n):
+        seen = {}
+        for a, b in ((pool_ids[i], pool_d2[i]), (knn_ids[i], knn_d2[i])):
+            for c, v in zip(a.tolist(), b.tolist()):
+                if c >= 0 and c != i:
+                    seen[c] = v
+        items = sorted((v, c) for c, v in seen.items())
+        ids[i, :len(items)] = [c for _, c in items]
+        dd[i, :len(items)] = [v for v, _ in items]
+    return ids, dd
+
+
+def build_graph_nsg(base, knn_k: int, L: int, R: int):
+    """NSG-style graph: exact kNN(knn_k); each point searched for from the
+    medoid on the kNN graph's first min(knn_k, 64) columns with beam width L;
+    its pool merged with its kNN list (merge_candidates); pruning at alpha = 1
+    to R - 2; repair with bridges from the merged lists first.
+    Returns (graph, medoid, n_forward, n_reverse, cand_ids, cand_d2)."""
+    base = _f32(base)
+    cand, cd2 = knn(base, base, knn_k, exclude_self=True)
+    m = medoid(base)
+    g0 = np.ascontiguousarray(cand[:, :min(knn_k, 64)])
+    res = search(base, g0, base, m, L, L)
+    ids, dd = merge_candidates(res["ids"], res["d2"], cand, cd2)
+    g = alpha_prune(base, ids, dd, R, 1.0)
+    g, nf, nr = repair(base, g, m, ids)
+    return g, m, nf, nr, ids, dd
+
+
 def search(base, graph, queries, entry, k, L, k_max: int | None = None,
            trace_cap: int = 0, want_visited: bool = False, threads: int = 0):
     """Best-first beam search (Algorithm 1 reading).

@@ -277,3 +277,34 @@ def test_knn_in_home_group_singleton_and_duplicates():
     assert ids[3].tolist() == [-1, -1, -1]
     assert ids[2].tolist() == [0, 1, 4] and dd[2].tolist() == [0.0, 0.0, 0.0]
     assert ids[0].tolist() == [1, 2, 4]
+
+
+# ---------------------------------------------------------------- NSG-style candidates
+def test_merge_candidates_by_hand():
+    pool_ids = np.array([[0, 3, 5, -1], [2, 0, 1, 4]], np.int32)
+    pool_d2 = np.array([[0.0, 2.0, 9.0, np.inf], [1.0, 3.0, 0.0, 3.0]])
+    knn_ids = np.array([[3, 2], [0, 6]], np.int32)
+    knn_d2 = np.array([[2.0, 5.0], [3.0, 7.0]])
+    ids, dd = oracle.merge_candidates(pool_ids, pool_d2, knn_ids, knn_d2)
+    # row 0: self (0) dropped, 3 once; row 1: self (1) dropped, ties by id
+    assert ids[0].tolist() == [3, 2, 5, -1, -1, -1]
+    assert dd[0, :3].tolist() == [2.0, 5.0, 9.0] and np.isinf(dd[0, 3:]).all()
+    assert ids[1].tolist() == [2, 0, 4, 6, -1, -1]
+    assert dd[1, :4].tolist() == [1.0, 3.0, 3.0, 7.0]
+
+
+def test_nsg_graph_strongly_connected_and_sorted_rows():
+    w = synth.scaled(synth.WORKLOADS["tiny"], n=1500)
+    base = synth.base(w)
+    g, med, nf, nr, cand, cd2 = oracle.build_graph_nsg(base, 64, 40, 16)
+    assert _reach(g, med) == set(range(1500))
+    assert _reach(g, med, reverse=True) == set(range(1500))
+    # candidate rows: sorted by (d2, id), no self, no repeats
+    for p in range(0, 1500, 53):
+        row = [c for c in cand[p].tolist() if c >= 0]
+        assert p not in row and len(set(row)) == len(row)
+        keys = [(cd2[p, j], row[j]) for j in range(len(row))]
+        assert keys == sorted(keys)
+    # alpha = 1 keeps no more than alpha = 1.2 would from the same lists
+    g12 = oracle.alpha_prune(base, cand, cd2, 16, 1.2)
+    assert ((g[:, :14] >= 0).sum() <= (g12[:, :14] >= 0).sum())
