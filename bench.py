@@ -137,6 +137,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--R", type=int, default=32, help="graph out-degree")
     ap.add_argument("--knn-k", type=int, default=128, help="kNN candidates before pruning")
+    ap.add_argument("--alpha", type=float, default=1.2, help="pruning parameter of the graph")
     ap.add_argument("--partitions", type=int, default=0,
                     help="candidate lists from this many overlapping k-means groups instead of "
                          "the all-pairs kNN (0: all pairs)")
@@ -151,8 +152,14 @@ def main():
     ap.add_argument("--legs", default="medoid,gate,ablation,serve",
                     help="also: hbkm (GATE on hierarchical balanced k-means hubs, one model per "
                          "--hbkm-lambdas value), queues (GATE trained on Definition 4 queues with "
-                         "the hub-anchored Eq. 4 loss), fusion (GATE with the Eq. 3 fusion embedding)")
+                         "the hub-anchored Eq. 4 loss), fusion (GATE with the Eq. 3 fusion embedding), "
+                         "nsg (medoid and GATE on an NSG-style graph)")
     ap.add_argument("--hbkm-lambdas", default="0,1,10")
+    ap.add_argument("--nsg-L", default="128",
+                    help="nsg leg: beam widths of the per-point build searches, one graph each")
+    ap.add_argument("--nsg-path", type=int, default=0,
+                    help="nsg leg: also take the first this many expanded nodes of each build "
+                         "search as candidates")
     ap.add_argument("--queue-variants", default="3:16:48",
                     help="queues leg: t_pos:P:N triples, comma separated (t_neg stays 15)")
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
@@ -193,11 +200,12 @@ def main():
         log("state loaded from %s: medoid %d, L gate %s, L medoid %s" %
             (args.load_state, index.medoid, state.get("L_gate"), state.get("L_medoid")))
     else:
-        index = gate.build_index(base_d, knn_k, R, 1.2, partitions=parts, overlap=args.overlap,
+        index = gate.build_index(base_d, knn_k, R, args.alpha, partitions=parts, overlap=args.overlap,
                                  w=w, log=log)
         g = None
-    log("graph: kNN %d%s -> alpha 1.2 -> R %d, medoid %d, bridges %s (%.1fs)" %
-        (knn_k, " in %d groups x %d" % (parts, args.overlap) if parts else "", R, index.medoid,
+    log("graph: kNN %d%s -> alpha %g -> R %d, medoid %d, bridges %s (%.1fs)" %
+        (knn_k, " in %d groups x %d" % (parts, args.overlap) if parts else "", args.alpha, R,
+         index.medoid,
          index.bridges, index.build_s))
     gt_ids, gt_dist = ann.ann_gt_knn(base_d, q_d, k)
     gt, gtd = gt_ids.cpu().numpy(), gt_dist.cpu().numpy()
@@ -581,6 +589,47 @@ def main():
                 log("queues objective t_pos=%d P=%d N=%d: L95 %s (labels objective %s)" %
                     (tp, P, N, q_L95, L_gate))
                 del gq
+        if "nsg" in legs and tq is not None:
+            # NSG-style graphs (search-built candidates, alpha = 1) against the
+            # kNN + alpha = 1.2 graph above: medoid and GATE entry on each
+            abl["nsg"] = []
+            keep = index
+            deg = lambda gr: round(float((gr >= 0).sum(1).float().mean().item()), 2)  # noqa: E731
+            pick = lambda rows, L: next((r for r in rows if r["L"] == L), None)   # noqa: E731
+            for Lb in [int(x) for x in args.nsg_L.split(",") if x]:
+                nix = gate.build_index_nsg(base_d, knn_k, R, Lb, path=args.nsg_path, log=log)
+                log("nsg graph: L_build %d, kNN %d, R %d, medoid %d, bridges %s, %d of %d edges "
+                    "from the search pools alone (%.1fs)" %
+                    (Lb, knn_k, R, nix.medoid, nix.bridges, nix.edge_stats["from_pool_only"],
+                     nix.edge_stats["edges"], nix.build_s))
+                index = nix
+                m_rows, m_L95 = sweep(None, "nsg%d medoid" % Lb)
+                gdn = gate.prepare_gate(index, tq, w, n_hubs=args.hubs, log=log)
+                gn = gate.train_gate(index, gdn, tq, w, hidden=args.hidden, dout=args.dout,
+                                     epochs=args.epochs, lr=args.lr, tau=args.tau, log=log)
+                en, _, _ = gn.select(q_d)
+                n_rows, n_L95 = sweep(en, "nsg%d gate" % Lb)
+                n_t = timed(n_L95, gn.model, en, "nsg%d-gate" % Lb) if n_L95 is not None else None
+                abl["nsg"].append(dict(
+                    L_build=Lb, path=args.nsg_path, build_s=round(nix.build_s, 1),
+                    bridges=nix.bridges,
+                    degree_mean=deg(nix.graph), **nix.edge_stats,
+                    medoid=dict(L95=m_L95, ndc=(pick(m_rows, m_L95) or {}).get("ndc"),
+                                best_recall=max(r["recall"] for r in m_rows), sweep=m_rows),
+                    gate=dict(L95=n_L95, ndc=(pick(n_rows, n_L95) or {}).get("ndc"), sweep=n_rows,
+                              timed={k: n_t[k] for k in (
+                                  "qps", "ms_per_step", "search_ms", "recall", "ndc", "hops",
+                                  "achieved_gbs", "plan")} if n_t else None)))
+                log("nsg graph L_build %d: medoid L95 %s, GATE L95 %s, %s QPS "
+                    "(kNN + alpha graph: GATE L95 %s, %s QPS)" %
+                    (Lb, m_L95, n_L95, n_t["qps"] if n_t else None, L_gate, gres["qps"]))
+                index = keep
+                del nix, gdn, gn
+            abl["nsg_default_graph"] = dict(
+                gate_L95=L_gate, gate_qps=gres["qps"], gate_ndc=gres["ndc"], gate_hops=gres["hops"],
+                medoid_L95=med["L"] if med and med["reached_target"] else None,
+                degree_mean=deg(keep.graph))
+            del keep
         if args.save_state:
             gate.save_state(args.save_state, index, g, dict(
                 L_gate=L_gate, L_medoid=med["L"] if med else None,
@@ -644,11 +693,11 @@ def main():
         warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(
-            workload="%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d%s/alpha1.2/R%d "
+            workload="%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d%s/alpha%g/R%d "
                      "+ repair; %d hubs; towers %d->%d->%d" %
                      (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k,
                       " within %d overlapping groups (x%d)" % (parts, args.overlap) if parts else "",
-                      R, args.hubs, w.d, args.hidden, args.dout),
+                      args.alpha, R, args.hubs, w.d, args.hidden, args.dout),
             recall_targets=targets,
             entry="gate" if head is gres else "medoid", k=k, L=head["L"],
             recall_at_10=head["recall"], recall_target=TARGET,

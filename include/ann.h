@@ -240,6 +240,28 @@ ann_status ann_graph_from_candidates(const float *base, int64_t n, int32_t dim,
                                      int32_t *bridges, void *workspace, size_t ws_bytes,
                                      void *stream);
 
+/* Candidate lists of an NSG-style graph (the base index the paper builds on,
+ * whose candidates come from a search for each point plus its nearest
+ * neighbours): row i of the output is the union of row i of a_ids
+ * (n x a_w int32, device; e.g. the pool of a search for base point i) and
+ * row i of b_ids (n x b_w int32, device; e.g. its exact kNN list), with -1
+ * entries, i itself and repeats dropped, ordered by (FP64 squared L2 to
+ * base point i, id), then -1 / +inf padded to a_w + b_w.  The distances are
+ * recomputed here (eight partial sums over dimensions j mod 8, combined
+ * pairwise; exact on data held on a dyadic grid), so the input lists carry
+ * ids only.  The result feeds ann_graph_from_candidates with
+ * knn_k = a_w + b_w and alpha = 1 (NSG's MRNG rule).
+ *   out_ids   n x (a_w + b_w) int32 (device), out_d2 the same shape FP64
+ *   workspace ann_merge_candidates_workspace_size() bytes (an error flag)
+ * Errors: EINVAL unless 1 <= a_w + b_w <= 1024, or when an input id lies
+ * outside [-1, n) (such an id counts as absent in the output, which is
+ * still written).  Synchronises `stream`. */
+size_t ann_merge_candidates_workspace_size(void);
+
+ann_status ann_merge_candidates(const float *base, int64_t n, int32_t dim, const int32_t *a_ids,
+                                int32_t a_w, const int32_t *b_ids, int32_t b_w, int32_t *out_ids,
+                                double *out_d2, void *workspace, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Hub nodes and their topology features (hub extraction and feature         */
 /* distillation sections).                                                   */

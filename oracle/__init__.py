@@ -192,18 +192,26 @@ def merge_candidates(pool_ids, pool_d2, knn_ids, knn_d2):
     return ids, dd
 
 
-def build_graph_nsg(base, knn_k: int, L: int, R: int):
+def build_graph_nsg(base, knn_k: int, L: int, R: int, path: int = 0):
     """NSG-style graph: exact kNN(knn_k); each point searched for from the
     medoid on the kNN graph's first min(knn_k, 64) columns with beam width L;
-    its pool merged with its kNN list (merge_candidates); pruning at alpha = 1
-    to R - 2; repair with bridges from the merged lists first.
+    its pool, and with path > 0 also the first `path` nodes that search
+    expanded, merged with its kNN list (merge_candidates); pruning at
+    alpha = 1 to R - 2; repair with bridges from the merged lists first.
     Returns (graph, medoid, n_forward, n_reverse, cand_ids, cand_d2)."""
     base = _f32(base)
     cand, cd2 = knn(base, base, knn_k, exclude_self=True)
     m = medoid(base)
     g0 = np.ascontiguousarray(cand[:, :min(knn_k, 64)])
-    res = search(base, g0, base, m, L, L)
-    ids, dd = merge_candidates(res["ids"], res["d2"], cand, cd2)
+    res = search(base, g0, base, m, L, L, trace_cap=path)
+    a_ids, a_d2 = res["ids"], res["d2"]
+    if path > 0:
+        tr = res["trace"]
+        td2 = np.array([[sqdist(base[i], base[c]) if c >= 0 else np.inf for c in tr[i]]
+                        for i in range(tr.shape[0])])
+        a_ids = np.concatenate([a_ids, tr], 1)
+        a_d2 = np.concatenate([a_d2, td2], 1)
+    ids, dd = merge_candidates(a_ids, a_d2, cand, cd2)
     g = alpha_prune(base, ids, dd, R, 1.0)
     g, nf, nr = repair(base, g, m, ids)
     return g, m, nf, nr, ids, dd

@@ -361,6 +361,43 @@ def ann_graph_from_candidates(base: torch.Tensor, cand: torch.Tensor, cand_d2: t
     return graph, int(m.value), (int(br[0]), int(br[1]))
 
 
+_sig("ann_merge_candidates_workspace_size", _SZ)
+_sig("ann_merge_candidates", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _P, _P, _SZ, _P)
+
+
+def ann_merge_candidates_workspace_size() -> int:
+    return int(_lib.ann_merge_candidates_workspace_size())
+
+
+def ann_merge_candidates(base: torch.Tensor, a_ids: torch.Tensor | None,
+                         b_ids: torch.Tensor | None, stream=None):
+    """Row-wise union of two id lists (n x a_w, n x b_w int32; either may be
+    None), row i's own id and repeats dropped, ordered by (FP64 squared L2 to
+    base row i, id).  Returns (ids int32, d2 float64), n x (a_w + b_w)."""
+    _dev(base, torch.float32)
+    n, dim = base.shape
+    aw = bw = 0
+    if a_ids is not None:
+        _dev(a_ids, torch.int32)
+        if a_ids.shape[0] != n:
+            raise ValueError("a_ids must have one row per base point")
+        aw = a_ids.shape[1]
+    if b_ids is not None:
+        _dev(b_ids, torch.int32)
+        if b_ids.shape[0] != n:
+            raise ValueError("b_ids must have one row per base point")
+        bw = b_ids.shape[1]
+    W = aw + bw
+    ids = torch.empty((n, W), dtype=torch.int32, device=base.device)
+    d2 = torch.empty((n, W), dtype=torch.float64, device=base.device)
+    ws = torch.empty(max(256, ann_merge_candidates_workspace_size()), dtype=torch.uint8,
+                     device=base.device)
+    _check(_lib.ann_merge_candidates(_ptr(base), n, dim, _ptr(a_ids), aw, _ptr(b_ids), bw,
+                                     _ptr(ids), _ptr(d2), _ptr(ws), ws.numel(), _stream(stream)))
+    del ws
+    return ids, d2
+
+
 _sig("ann_select_hubs_hbkm_workspace_size", _SZ, _I64, _I32, _I32, _I32)
 _sig("ann_select_hubs_hbkm", _I32, _P, _I64, _I32, _I32, _I32, ctypes.c_double, _I32, _P, _P, _P,
      _P, _SZ, _P)

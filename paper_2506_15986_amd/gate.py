@@ -88,6 +88,58 @@ def build_index(base: torch.Tensor, knn_k: int = 128, R: int = 32, alpha: float 
     return Index(base, graph, med, bridges, R, time.time() - t)
 
 
+def build_index_nsg(base: torch.Tensor, knn_k: int = 128, R: int = 32, L_build: int = 128,
+                    path: int = 0, chunk: int = 1 << 18, log=None) -> Index:
+    """NSG-style proximity graph (the base index the paper assumes): exact
+    kNN lists (knn_k, self excluded); every base point searched for from the
+    medoid over the kNN graph's first min(knn_k, 64) columns with beam width
+    L_build (the whole pool kept, and with path > 0 also the first `path`
+    nodes the search expanded); these and the kNN list merged per point
+    (ann_merge_candidates); MRNG pruning (alpha = 1) to R - 2, medoid and
+    repair (ann_graph_from_candidates)."""
+    t = time.time()
+    n, dim = base.shape
+    if L_build + path + knn_k > 1024:
+        raise ValueError("L_build + path + knn_k must be <= 1024")
+    knn_ids, _ = ann.ann_gt_knn(base, base, knn_k, exclude_self=True)
+    if log:
+        log("  nsg: kNN %d lists (%.1fs)" % (knn_k, time.time() - t))
+    g0 = knn_ids[:, :min(knn_k, 64)].contiguous()
+    med = ann.ann_medoid(base)
+    plan = ann.default_plan(n, dim, g0.shape[1], L_build)
+    pool = torch.empty((n, L_build + path), dtype=torch.int32, device=base.device)
+    ws = ann.workspace("search", n, dim, min(chunk, n), device=base.device)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        ids, _, _, tr = ann.ann_search(base, g0, base[s:e], None, med, L_build, L_build,
+                                       plan=plan, want_stats=False, trace_cap=path, ws=ws)
+        pool[s:e, :L_build] = ids
+        if path:
+            pool[s:e, L_build:] = tr
+        del ids, tr
+    torch.cuda.synchronize()
+    del ws, g0
+    if log:
+        log("  nsg: %d search pools of width %d (%.1fs)" % (n, L_build, time.time() - t))
+    cand, cd2 = ann.ann_merge_candidates(base, pool, knn_ids)
+    del pool
+    graph, med2, bridges = ann.ann_graph_from_candidates(base, cand, cd2, R, 1.0)
+    del cand, cd2
+    torch.cuda.synchronize()
+    ix = Index(base, graph, med2, bridges, R, time.time() - t)
+    # how many pruned-graph edges (slots before the two repair slots) came
+    # from the search pools alone, not from the kNN lists
+    edges = from_pool = 0
+    for s in range(0, n, 1 << 16):
+        g = graph[s:s + (1 << 16), :R - 2]
+        inl = (g[:, :, None] == knn_ids[s:s + (1 << 16), None, :]).any(-1)
+        edges += int((g >= 0).sum().item())
+        from_pool += int(((g >= 0) & ~inl).sum().item())
+    ix.edge_stats = dict(edges=edges, from_pool_only=from_pool)
+    del knn_ids
+    return ix
+
+
 @dataclasses.dataclass
 class Gate:
     qtower: ann.Tower

@@ -243,3 +243,26 @@ def test_hbkm_rejects_bad_shapes_without_gpu_work():
     assert call() == ann.ANN_EINVAL                       # workspace too small
     assert ann.ann_select_hubs_hbkm_workspace_size(100, 8, 4, 2) > 256
     assert ann.ann_select_hubs_hbkm_workspace_size(100, 8, 4, 4) == 0
+
+
+def test_merge_candidates_rejects_bad_widths_without_gpu_work():
+    from paper_2506_15986_amd import ann
+    base = np.zeros((100, 8), np.float32)
+    ids = np.zeros(100 * 1024, np.int32)
+    d2 = np.zeros(100 * 1024, np.float64)
+    ws = np.zeros(256, np.uint8)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
+
+    def call(aw=8, bw=8, a=ids, b=ids, wsb=256, n=100):
+        return ann._lib.ann_merge_candidates(P(base), n, 8, P(a) if a is not None else None, aw,
+                                             P(b) if b is not None else None, bw, P(ids), P(d2),
+                                             P(ws), wsb, None)
+
+    assert ann.ann_merge_candidates_workspace_size() == 256
+    assert call(aw=0, bw=0) == ann.ANN_EINVAL
+    assert call(aw=1000, bw=25) == ann.ANN_EINVAL          # union wider than 1024
+    assert call(aw=-1) == ann.ANN_EINVAL
+    assert call(a=None) == ann.ANN_EINVAL
+    assert call(aw=0, b=None) == ann.ANN_EINVAL
+    assert call(wsb=128) == ann.ANN_EINVAL
+    assert call(n=0) == ann.ANN_EINVAL

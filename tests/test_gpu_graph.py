@@ -185,3 +185,68 @@ def test_build_graph_partitioned_bit_exact():
     torch.cuda.synchronize()
     assert m2 == med and br2 == (nf, nr)
     assert (g2.cpu().numpy() == ref).all()
+
+
+def _merge_inputs(n, d, aw, bw, seed):
+    r = np.random.default_rng(seed)
+    base = (np.rint(r.normal(size=(n, d)) * 2 ** 10) / 2 ** 10).astype(np.float32)
+    base[n // 2:n // 2 + 5] = base[3]            # equal distances, told apart by id
+    a = r.integers(-1, n, size=(n, aw)).astype(np.int32)
+    b = r.integers(-1, n, size=(n, bw)).astype(np.int32)
+    if aw and bw:
+        b[:, :min(aw, bw) // 2] = a[:, :min(aw, bw) // 2]   # repeats across the lists
+    if aw:
+        a[::7, 0] = np.arange(0, n, 7)                      # the row's own id
+    return base, a, b
+
+
+def _d2_rows(base, ids):
+    # FP64 squared distances of row i to ids[i]; exact on this grid
+    diff = base[np.maximum(ids, 0)].astype(np.float64) - base[:, None, :].astype(np.float64)
+    return np.where(ids >= 0, (diff * diff).sum(-1), np.inf)
+
+
+@pytest.mark.parametrize("n,d,aw,bw", [(300, 40, 37, 20), (129, 8, 0, 5), (200, 72, 300, 128),
+                                       (64, 16, 900, 124), (97, 128, 1, 0)])
+def test_merge_candidates_matches_oracle(n, d, aw, bw):
+    say("case: merge_candidates n=%d d=%d aw=%d bw=%d" % (n, d, aw, bw))
+    base, a, b = _merge_inputs(n, d, aw, bw, n + aw)
+    ids, d2 = _ann().ann_merge_candidates(_dev(base), _dev(a) if aw else None,
+                                          _dev(b) if bw else None)
+    torch.cuda.synchronize()
+    ea = a if aw else np.zeros((n, 0), np.int32)
+    eb = b if bw else np.zeros((n, 0), np.int32)
+    ref_ids, ref_d2 = oracle.merge_candidates(ea, _d2_rows(base, ea), eb, _d2_rows(base, eb))
+    assert (ids.cpu().numpy() == ref_ids).all()
+    assert (d2.cpu().numpy() == ref_d2).all()
+
+
+def test_merge_candidates_rejects_ids_out_of_range():
+    ann = _ann()
+    base, a, b = _merge_inputs(100, 8, 10, 10, 5)
+    a[17, 3] = 100
+    say("case: merge_candidates id out of range")
+    with pytest.raises(RuntimeError):
+        ann.ann_merge_candidates(_dev(base), _dev(a), _dev(b))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,d,knn_k,L,R,path", [(3000, 32, 32, 40, 16, 0),
+                                                (2000, 64, 64, 100, 24, 0),
+                                                (2500, 32, 16, 16, 24, 64)])
+def test_nsg_graph_bit_exact(n, d, knn_k, L, R, path):
+    from paper_2506_15986_amd import gate
+    r = np.random.default_rng(n)
+    if path:
+        # uniform data: here the expanded nodes change about a fifth of the rows
+        base = r.integers(0, 256, size=(n, d))
+    else:
+        cen = r.integers(30, 220, size=(12, d))
+        base = np.clip(cen[r.integers(0, 12, n)] + r.integers(-25, 26, size=(n, d)), 0, 255)
+    base = base.astype(np.float32)
+    say("case: nsg graph n=%d d=%d knn_k=%d L=%d R=%d path=%d" % (n, d, knn_k, L, R, path))
+    ix = gate.build_index_nsg(_dev(base), knn_k, R, L, path=path)
+    g, m, nf, nr, _, _ = oracle.build_graph_nsg(base, knn_k, L, R, path=path)
+    assert ix.medoid == m
+    assert ix.bridges == (nf, nr)
+    assert (ix.graph.cpu().numpy() == g).all()
