@@ -440,17 +440,31 @@ def main():
             if Lk[kq] is None:
                 Lk[kq] = grid[-1]
         Lmax = max(Lk.values())
+        # one plan for every launch, tuned on the mix (even odds of the two k)
+        mix_big = np.random.default_rng(3).random(nqm) < 0.5
+        k_mix = torch.from_numpy(np.where(mix_big, 100, 10).astype(np.int32)).to(dev)
+        L_mix = torch.from_numpy(np.where(mix_big, Lk[100], Lk[10]).astype(np.int32)).to(dev)
+        splan, _ = ann.ann_autotune_search(base_d, index.graph, qm_d, em, index.medoid, k_mix,
+                                           L_mix, 100, Lmax)
+        log("serving plan (tuned on the mix): %s" % splan)
         srv = serve.Server(base_d, index.graph, index.medoid, model=model, slots=4,
-                           slot_rows=4096, k_max=100, L_max=Lmax,
-                           plan=ann.default_plan(w.n, w.d, R, Lmax))
-        out = dict(mix="30% shifted queries, k 10/100", L_by_k=Lk, loads=[])
-        qs = np.concatenate([qm] * 4)
-        truth = np.concatenate([gt100] * 4)
-        # capacity: every request waiting at the start (the server saturated)
-        sat = srv.serve(serve.poisson_schedule(qs, 1e12, sizes=(1, 512),
-                                               kL=((10, Lk[10]), (100, Lk[100])), seed=7))
+                           slot_rows=4096, k_max=100, L_max=Lmax, plan=splan)
+        out = dict(mix="30% shifted queries, k 10/100", L_by_k=Lk, plan=splan.as_dict(), loads=[])
+        reps = 16
+        qs = np.concatenate([qm] * reps)
+        truth = np.concatenate([gt100] * reps)
+        # capacity: every request waiting at the start (the server saturated);
+        # the median of three runs
+        srv.serve(serve.poisson_schedule(qm, 1e12, sizes=(1, 512),
+                                         kL=((10, Lk[10]), (100, Lk[100])), seed=7))
+        sats = [srv.serve(serve.poisson_schedule(qs, 1e12, sizes=(1, 512),
+                                                 kL=((10, Lk[10]), (100, Lk[100])), seed=7))
+                for _ in range(3)]
+        sat = sorted(sats, key=lambda x: x["qps"])[1]
         out["capacity_qps"] = sat["qps"]
-        log("serving capacity (all requests waiting): %s" % sat)
+        out["capacity_runs_qps"] = [x["qps"] for x in sats]
+        log("serving capacity (all requests waiting, median of %s): %s" %
+            ([x["qps"] for x in sats], sat))
         for frac in (0.5, 0.8):
             rate = frac * sat["qps"] / 256.5
             sched = serve.poisson_schedule(qs, rate, sizes=(1, 512),

@@ -11,6 +11,10 @@ behind it.  Requests that arrive while others are on the GPU are admitted as
 soon as a slot frees, and the slots' work overlaps on the device.  The rows
 each slot holds follow from a device-memory budget.
 
+Inside a launch the admitted requests are laid out widest beam first (the
+persistent search hands out rows in order), so the longest searches do not
+start last and stretch the launch.
+
 Every query's result depends only on its own vector, k, L and entry (one
 wavefront per query, per-row tower products), so a request's results are the
 same alone and in any mix.
@@ -69,8 +73,10 @@ class Server:
 
     def __init__(self, base: torch.Tensor, graph: torch.Tensor, medoid: int,
                  model: ann.EntryModel | None = None, slots: int = 4, slot_rows: int = 0,
-                 mem_budget: int = 256 << 20, k_max: int = 100, L_max: int = 256, plan=None):
+                 mem_budget: int = 256 << 20, k_max: int = 100, L_max: int = 256, plan=None,
+                 longest_first: bool = True):
         self.base, self.graph, self.medoid, self.model = base, graph, int(medoid), model
+        self.longest_first = bool(longest_first)
         self.device = base.device
         n, self.dim = base.shape
         self.k_max = int(k_max)
@@ -111,16 +117,25 @@ class Server:
 
     def _launch(self, s: _Slot):
         rows = 0
+        take = []
         while self.queue and rows + self.queue[0].queries.shape[0] <= s.rows:
             r = self.queue.popleft()
+            take.append(r)
+            rows += r.queries.shape[0]
+        if not rows:
+            return
+        if self.longest_first:
+            # the persistent launch hands out rows in order: the widest
+            # searches start first and the short ones fill in behind them
+            take.sort(key=lambda r: -r.L)
+        rows = 0
+        for r in take:
             b = r.queries.shape[0]
             s.hq[rows:rows + b].numpy()[:] = r.queries
             s.hk[rows:rows + b] = r.k
             s.hL[rows:rows + b] = r.L
             s.reqs.append(r)
             rows += b
-        if not rows:
-            return
         s.used = rows
         s.batch.c.nq = rows
         with torch.cuda.stream(s.stream):
