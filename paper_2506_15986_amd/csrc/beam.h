@@ -65,6 +65,17 @@ __device__ inline bool key_less(K ka, uint32_t ia, K kb, uint32_t ib)
     return ka < kb || (ka == kb && (ia & kIdMask) < (ib & kIdMask));
 }
 
+// the same order for ids whose expanded bit is already clear: one 64-bit
+// compare of (key, id) for 32-bit keys
+__device__ inline bool pair_less(uint32_t ka, uint32_t ia, uint32_t kb, uint32_t ib)
+{
+    return (((uint64_t)ka << 32) | ia) < (((uint64_t)kb << 32) | ib);
+}
+__device__ inline bool pair_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib)
+{
+    return (ka < kb) | ((ka == kb) & (ia < ib));
+}
+
 __device__ inline void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -92,29 +103,36 @@ __device__ inline int lower_bound(const K *ak, const uint32_t *ai, int cnt, K k,
 // the wavefront): steps of 2^t from the largest power of two <= cnt down to
 // 1, each adding its step when the entry ending that step is below the key.
 // Branch-free per lane (probes past cnt are clamped and ignored).
+// cnt must hold the same value in every active lane: it is read from the
+// first one, so that the step count lives in a scalar register and the loop
+// needs no per-lane exec masking.  Every probe reads a clamped index and the
+// tests combine without short-circuit, so the body has no branch.
 template <typename K>
 __device__ inline int lower_bound_uniform(const K *ak, const uint32_t *ai, int cnt, K k, uint32_t id)
 {
-    int lo = 0;
+    cnt = __builtin_amdgcn_readfirstlane(cnt);
     if (cnt <= 0) return 0;
+    const uint32_t idm = id & kIdMask;
+    int lo = 0;
     for (int step = 1 << (31 - __builtin_clz((unsigned)cnt)); step > 0; step >>= 1) {
         const int probe = lo + step - 1;
         const int j = probe < cnt ? probe : cnt - 1;
-        const bool below = probe < cnt && key_less(ak[j], ai[j], k, id);
+        const bool below = (probe < cnt) & pair_less(ak[j], ai[j] & kIdMask, k, idm);
         lo += below ? step : 0;
     }
     return lo;
 }
 
-// number of entries <= x in the non-decreasing a[0..cnt), by fixed steps
-// (the same number for every lane when cnt is uniform)
+// number of entries <= x in the non-decreasing a[0..cnt), by fixed steps;
+// cnt as for lower_bound_uniform
 __device__ inline int count_at_most(const int32_t *a, int cnt, int x)
 {
-    int lo = 0;
+    cnt = __builtin_amdgcn_readfirstlane(cnt);
     if (cnt <= 0) return 0;
+    int lo = 0;
     for (int step = 1 << (31 - __builtin_clz((unsigned)cnt)); step > 0; step >>= 1) {
         const int probe = lo + step - 1;
-        const bool in = probe < cnt && a[probe < cnt ? probe : cnt - 1] <= x;
+        const bool in = (probe < cnt) & (a[probe < cnt ? probe : cnt - 1] <= x);
         lo += in ? step : 0;
     }
     return lo;

@@ -213,10 +213,10 @@ struct Searcher {
         const int lane = beam::lane_id();
         // ---- merge the new keys into the pool.  A new key's place is its
         // insertion point in the old pool plus its rank among the new keys
-        // (a scalar loop over the new keys, readlane); an old entry moves
-        // down by the number of new keys inserted at or before it.  The
-        // insertion points, stored by rank, are non-decreasing, so that
-        // number is a binary search over them.
+        // (a scalar loop over the new keys, readlane).  The new keys' places
+        // are marked in a bit mask; every unmarked place takes the old entry
+        // whose index is the place minus the marked places before it.  The
+        // insertion points, stored by rank, give the cursor's new place.
         K *ak = keys(cur);
         uint32_t *ai = ids(cur);
         K kk = KT::kMax;
@@ -241,7 +241,8 @@ struct Searcher {
         int rank = 0;
         for (uint64_t mm = vmask; mm; mm &= mm - 1) {
             const int t = __ffsll((unsigned long long)mm) - 1;
-            if (beam::key_less(beam::readlane(kk, t), beam::readlane(ii, t), kk, ii)) ++rank;
+            // new ids carry no expanded bit
+            if (beam::pair_less(beam::readlane(kk, t), beam::readlane(ii, t), kk, ii)) ++rank;
         }
         // the smallest new key: expanded next if it beats the old pool's
         // next unexpanded entry
@@ -255,24 +256,47 @@ struct Searcher {
         }
         K *bk = keys(cur ^ 1);
         uint32_t *bi = ids(cur ^ 1);
-        if (valid && pos + rank < Lq) {
-            bk[pos + rank] = kk;
-            bi[pos + rank] = ii;
+        const int fnew = pos + rank;
+        const bool placed = valid && fnew < Lq;
+        if (placed) {
+            bk[fnew] = kk;
+            bi[fnew] = ii;
         }
         // insertion points by rank (the staging ids are in registers now)
         int32_t *sp = reinterpret_cast<int32_t *>(si);
         if (valid) sp[rank] = pos;
+        // occupancy bits of the new keys' places in the merged pool (the
+        // staging keys are in registers too, so their LDS holds the bits)
+        const int outn = __builtin_amdgcn_readfirstlane((cnt + mv < Lq) ? cnt + mv : Lq);
+        const int nw = (outn + 63) >> 6;
+        uint32_t *occ = reinterpret_cast<uint32_t *>(sk);
+        if (lane < 2 * nw) occ[lane] = 0u;
         beam::wave_sync();
-        for (int j = lane; j < cnt; j += 64) {
-            const int f = j + beam::count_at_most(sp, mv, j);
-            if (f < Lq) {
-                bk[f] = ak[j];
-                bi[f] = ai[j];
+        if (placed) atomicOr(&occ[fnew >> 5], 1u << (fnew & 31));
+        beam::wave_sync();
+        // every other place o takes old entry o - (new keys placed before o):
+        // a count of the bits below the lane in the place's 64-bit word
+        int before = 0;
+        for (int c = 0; c < nw; ++c) {
+            const uint32_t lo = __builtin_amdgcn_readfirstlane(occ[2 * c]);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane(occ[2 * c + 1]);
+            const int o = (c << 6) + lane;
+            const uint32_t word = lane < 32 ? lo : hi;
+            if (o < outn && !((word >> (lane & 31)) & 1u)) {
+                const int j = o - before -
+                              (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+                const K kv = ak[j];
+                const uint32_t iv = ai[j];
+                bk[o] = kv;
+                bi[o] = iv;
             }
+            before += __popc(lo) + __popc(hi);
         }
         const int oc = cursor + beam::count_at_most(sp, mv, cursor);
-        cursor = f0 < oc ? f0 : oc;
-        cnt = (cnt + mv < Lq) ? cnt + mv : Lq;
+        // cursor and count are the same in every lane; say so, so that they
+        // stay in scalar registers
+        cursor = __builtin_amdgcn_readfirstlane(f0 < oc ? f0 : oc);
+        cnt = outn;
         cur ^= 1;
         beam::wave_sync();
     }
