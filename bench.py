@@ -67,12 +67,16 @@ def log(*a):
 
 
 def search_source_hash() -> str:
-    """Digest of the search kernel's sources: counter figures taken on another
-    version of the kernel are not reported."""
+    """Digest of the search kernel's sources with comments and blank space
+    removed: counter figures taken on another version of the kernel's code
+    are not reported (a comment edit keeps them)."""
     h = hashlib.sha256()
     for f in SEARCH_SOURCES:
-        with open(os.path.join(ROOT, "paper_2506_15986_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2506_15986_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

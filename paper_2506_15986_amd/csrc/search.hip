@@ -6,9 +6,10 @@
 // every neighbour in the LDS visited filter, compacts the unseen ones (slot
 // order is kept), gathers their vectors in groups of G lanes with 16-byte
 // loads (G*16 contiguous bytes per group and instruction), reduces the FP32
-// (or FP64) squared L2 distance with xor shuffles, sorts the new keys with a
-// wave bitonic sort and merges them into the pool (binary-search ranks,
-// ping-pong buffers).  Keys are (distance, id), so ties go to the smaller id.
+// (or FP64) squared L2 distance with lane shuffles, and merges the new keys
+// into the pool (binary-search insertion points, ranks among the new keys,
+// occupancy bits for the old entries' places, ping-pong buffers).  Keys are
+// (distance, id), so ties go to the smaller id.
 //
 // When the visited filter is a hash table that had to drop an id, a dropped
 // node may be seen again.  Its key is recomputed bit-identically, so it is
