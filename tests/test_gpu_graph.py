@@ -250,3 +250,14 @@ def test_nsg_graph_bit_exact(n, d, knn_k, L, R, path):
     assert ix.medoid == m
     assert ix.bridges == (nf, nr)
     assert (ix.graph.cpu().numpy() == g).all()
+
+
+def test_merge_candidates_single_point_and_self_only():
+    base = np.array([[0.5, -1.0, 2.0, 0.25]], np.float32)
+    a = np.array([[0, -1, 0]], np.int32)
+    b = np.array([[-1, 0]], np.int32)
+    say("case: merge_candidates n=1")
+    ids, d2 = _ann().ann_merge_candidates(_dev(base), _dev(a), _dev(b))
+    torch.cuda.synchronize()
+    assert ids.cpu().numpy().tolist() == [[-1] * 5]
+    assert np.isinf(d2.cpu().numpy()).all()
