@@ -139,6 +139,9 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="override base size")
     ap.add_argument("--n-train", type=int, default=0, help="override training-query count")
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--select-epoch", action="store_true",
+                    help="keep the towers of the epoch with the best held-out label agreement "
+                         "(--epochs is then a budget)")
     ap.add_argument("--R", type=int, default=32, help="graph out-degree")
     ap.add_argument("--knn-k", type=int, default=128, help="kNN candidates before pruning")
     ap.add_argument("--alpha", type=float, default=1.2, help="pruning parameter of the graph")
@@ -524,7 +527,8 @@ def main():
             t = time.time()
             gdata = gate.prepare_gate(index, tq, w, n_hubs=args.hubs, log=log)
             g = gate.train_gate(index, gdata, tq, w, hidden=args.hidden, dout=args.dout,
-                                epochs=args.epochs, lr=args.lr, tau=args.tau, log=log)
+                                epochs=args.epochs, lr=args.lr, tau=args.tau,
+                                select_best=args.select_epoch, log=log)
             ginfo = dict(g.info, build_s=round(time.time() - t, 1))
         else:
             ginfo = dict(g.info)
@@ -561,7 +565,8 @@ def main():
                 gd = gate.prepare_gate(index, tq, w, n_hubs=args.hubs, hubs="hbkm", hbkm_lambda=lam,
                                        log=log)
                 gh = gate.train_gate(index, gd, tq, w, hidden=args.hidden, dout=args.dout,
-                                     epochs=args.epochs, lr=args.lr, tau=args.tau, log=log)
+                                     epochs=args.epochs, lr=args.lr, tau=args.tau,
+                                     select_best=args.select_epoch, log=log)
                 eh, _, _ = gh.select(q_d)
                 h_rows, h_L95 = sweep(eh, "hbkm lambda=%g" % lam)
                 r95 = next((r for r in h_rows if r["L"] == h_L95), None)
@@ -624,7 +629,8 @@ def main():
                 m_rows, m_L95 = sweep(None, "nsg%d medoid" % Lb)
                 gdn = gate.prepare_gate(index, tq, w, n_hubs=args.hubs, log=log)
                 gn = gate.train_gate(index, gdn, tq, w, hidden=args.hidden, dout=args.dout,
-                                     epochs=args.epochs, lr=args.lr, tau=args.tau, log=log)
+                                     epochs=args.epochs, lr=args.lr, tau=args.tau,
+                                     select_best=args.select_epoch, log=log)
                 en, _, _ = gn.select(q_d)
                 n_rows, n_L95 = sweep(en, "nsg%d gate" % Lb)
                 n_t = timed(n_L95, gn.model, en, "nsg%d-gate" % Lb) if n_L95 is not None else None

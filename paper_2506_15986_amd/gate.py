@@ -241,11 +241,15 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
                theta: float = -math.inf, train: bool = True, holdout: float = 0.1,
                init: str = "random", tune_L_h: bool = True, objective: str = "labels",
                t_pos: int = 3, t_neg: int = 15, queue_hubs: int = 64, queue_P: int = 16,
-               queue_N: int = 48, fusion: bool = False, fusion_heads: int = 4,
+               queue_N: int = 48, select_best: bool = False, val_every: int = 1,
+               fusion: bool = False, fusion_heads: int = 4,
                fusion_dk: int = 16, fusion_df: int = 64, log=print) -> Gate:
     """Trains the towers on the first (1 - holdout) of the training queries
     (contrastive loss, Adam), embeds the hubs, builds the navigation graph and
     reports top-1 label agreement on the trained and the held-out queries.
+    With select_best (labels objective), the entry model's held-out label
+    agreement is measured every val_every epochs and the towers of the best
+    epoch are kept: `epochs` is then a budget, not a fixed count.
 
     objective "labels": each query against all hubs with its label hub as the
     positive.  "queues": Definition 4 queues (hop counts from every hub to
@@ -351,6 +355,8 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
             losses.append(loss.item())
         hub_in[:, d:d + fd] = fu.forward(p_vec, U, tok_mask)
     elif train:
+        best = (-1.0, -1, None)
+        val_curve = []
         for ep in range(epochs):
             order = torch.from_numpy(synth.batch_order(w, nt, ep).astype(np.int32)).to(dev)
             for b0 in range(0, nt - batch + 1, batch):
@@ -358,6 +364,26 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
                 loss, _, _ = ann.ann_train_step(qt, ht, train_q, order[b0:b0 + batch], labels, hub_in,
                                                 tau, lr, step, ws=ws)
             losses.append(loss.item())
+            if select_best and n_hold and (ep % val_every == val_every - 1 or ep == epochs - 1):
+                # held-out label agreement of the entry model as it stands
+                hemb = ht.forward(hub_in)
+                hg, he = ann.ann_navgraph_build(hemb, s)
+                mdl = ann.EntryModel(qt, hemb, hg, data.hub_ids, he, index.medoid, L_h=L_h,
+                                     theta=theta)
+                _, _, bh = ann.ann_entry_select(mdl, train_q[nt:], want_score=True)
+                acc = float((bh == labels[nt:]).float().mean().item())
+                val_curve.append((ep + 1, round(acc, 4)))
+                if acc > best[0]:
+                    best = (acc, ep + 1, [t.clone() for t in qt.params() + ht.params()])
+                del mdl, hemb, hg
+        if best[2] is not None:
+            for dst, src in zip(qt.params() + ht.params(), best[2]):
+                dst.copy_(src)
+            qt.sync()
+            ht.sync()
+            info.update(selected_epoch=best[1], val_curve=val_curve)
+            log("training: held-out agreement best after epoch %d of %d (%.3f)" %
+                (best[1], epochs, best[0]))
     torch.cuda.synchronize()
     info.update(train_s=time.time() - t, train_steps=step, hidden=hidden, dout=dout, objective=objective,
                 fusion=dict(heads=fusion_heads, dk=fusion_dk, df=fusion_df) if fusion else None,
