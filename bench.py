@@ -170,6 +170,8 @@ def main():
     ap.add_argument("--queue-variants", default="3:16:48",
                     help="queues leg: t_pos:P:N triples, comma separated (t_neg stays 15)")
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
+    ap.add_argument("--shuffle-queries", type=int, default=0,
+                    help="permute the test queries with this seed (0: generator order)")
     ap.add_argument("--save-state", default="")
     ap.add_argument("--load-state", default="")
     ap.add_argument("--targets", default="0.95",
@@ -196,6 +198,8 @@ def main():
     t0 = time.time()
     base = synth.base(w)
     queries = synth.queries(w)
+    if args.shuffle_queries:
+        queries = queries[np.random.default_rng(args.shuffle_queries).permutation(queries.shape[0])]
     log("data: %d x %d base, %d queries (%.1fs)" % (w.n, w.d, queries.shape[0], time.time() - t0))
     base_d = torch.from_numpy(base).to(dev)
     q_d = torch.from_numpy(queries).to(dev)

@@ -130,6 +130,10 @@ ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_t L_max,
  *             known on the host, so NULL means pool_cap 256)
  *   workspace ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0) bytes
  * With nq == 0 the per-query pointers may be NULL and nothing is enqueued.
+ * Queries are taken widest-expected-first: a pre-pass orders them by L[i]
+ * times the FP32 squared distance from query i to its entry, largest first
+ * (the order lives in the workspace), so that the longest searches do not
+ * start last; every query's results are the same in any order.
  * Each query expands the best not-yet-expanded pool entry until none is left;
  * the FP32 (or FP64) distance of every newly seen neighbour is one distance
  * computation.  Ties are broken by the smaller id. */

@@ -28,7 +28,11 @@ ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_
                          int32_t medoid, const int32_t *k, const int32_t *L, int32_t k_max,
                          int32_t *out_ids, float *out_dist, int32_t *stats, int32_t *trace,
                          int32_t trace_cap, const ann_search_plan &p, uint32_t *counter,
-                         hipStream_t st);
+                         hipStream_t st, bool widest_first = false);
+
+// bytes of the search workspace: the work counter, and for a launch that
+// orders its queries widest-expected-first, the order and its keys
+size_t search_ws_bytes(int64_t nq);
 ann_status validate_plan(const ann_search_plan &p);
 size_t search_wave_lds(const ann_search_plan &p, int64_t n, int dim);
 // host-side checks of ann_search's arguments; resolves a NULL plan to the

@@ -75,7 +75,7 @@ ann_status query_run(const ann_query_batch &b, int stages, hipStream_t st)
     if ((stages & ANN_STAGE_SEARCH) && b.nq > 0)
         return search_launch(b.base, b.n, b.dim, b.graph, b.R, b.queries, b.nq, b.entry_ids,
                              b.medoid, b.k, b.L, b.k_max, b.out_ids, b.out_dist, b.stats,
-                             nullptr, 0, p, static_cast<uint32_t *>(b.search_ws), st);
+                             nullptr, 0, p, static_cast<uint32_t *>(b.search_ws), st, true);
     return ANN_OK;
 }
 
@@ -190,13 +190,13 @@ extern "C" ann_status ann_autotune_search(const float *base, int64_t n, int32_t 
         if (!runs[c]) continue;
         ann_status s = search_launch(base, n, dim, graph, R, queries, nq, entry_ids, medoid, k, L,
                                      k_max, out_ids, out_dist, stats, nullptr, 0, plans[c],
-                                     static_cast<uint32_t *>(search_ws), st);
+                                     static_cast<uint32_t *>(search_ws), st, true);
         if (s != ANN_OK) return s;
         ANN_HIP(hipEventRecord(ev.a, st));
         for (int r = 0; r < reps; ++r) {
             s = search_launch(base, n, dim, graph, R, queries, nq, entry_ids, medoid, k, L, k_max,
                               out_ids, out_dist, stats, nullptr, 0, plans[c],
-                              static_cast<uint32_t *>(search_ws), st);
+                              static_cast<uint32_t *>(search_ws), st, true);
             if (s != ANN_OK) return s;
         }
         ANN_HIP(hipEventRecord(ev.b, st));

@@ -20,6 +20,7 @@
 // visited set; only the executed distance count grows.
 #include "beam.h"
 #include "common.h"
+#include "internal.h"
 #include "search_core.h"
 
 namespace ann {
@@ -38,10 +39,12 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
     s.setup(smem + (size_t)wave * a.wave_lds, a.pool_cap, a.visited_log2, a.filter, a.n, a.base,
             a.dim, a.graph, a.R);
     for (;;) {
-        int qi = 0;
-        if (lane == 0) qi = (int)atomicAdd(a.counter, 1u);
-        qi = __shfl(qi, 0);
-        if (qi >= a.nq) break;
+        int slot = 0;
+        if (lane == 0) slot = (int)atomicAdd(a.counter, 1u);
+        slot = __shfl(slot, 0);
+        if (slot >= a.nq) break;
+        const int qi = a.order ? a.order[slot] : slot;
+        if (qi < 0 || qi >= a.nq) continue;
         const int kq = a.k[qi];
         const int Lq = a.L[qi];
         const int entry = a.entry ? a.entry[qi] : a.medoid;
@@ -73,6 +76,80 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
             st[3] = r.lost ? 1 : 0;
         }
     }
+}
+
+// ---- widest-expected-first order.  A query whose entry lies far from it,
+// or whose beam is wide, usually needs more hops; a persistent launch that
+// starts such queries last waits for them at the end.  The queries are
+// therefore taken in order of L times the FP32 squared distance from the
+// query to its entry vector, largest first, binned by the top 13 bits of
+// that value (exponent and 4 mantissa bits: bins 4.4 % wide) with a counting
+// sort in one workgroup.  Results do not depend on the order; only the
+// launch's tail does.  (Within a bin the order follows LDS atomics and may
+// vary between runs.)
+constexpr int ORDER_BITS = 13;
+constexpr int ORDER_BINS = 1 << ORDER_BITS;
+constexpr int ORDER_PER_THREAD = ORDER_BINS / 1024;
+
+// one wavefront per query: its bin of L x distance to the entry vector
+__global__ void __launch_bounds__(256) order_key_kernel(const float *base, int64_t n, int dim,
+                                                        const float *queries, int nq,
+                                                        const int32_t *entry, int medoid,
+                                                        const int32_t *L, uint32_t *key)
+{
+    const int q = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    const int e = entry ? entry[q] : medoid;
+    float acc = 0.0f;
+    if (e >= 0 && (int64_t)e < n) {
+        const float *x = base + (size_t)e * dim;
+        const float *y = queries + (size_t)q * dim;
+        for (int j = lane; j < dim; j += 64) {
+            const float d = y[j] - x[j];
+            acc += d * d;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) {
+        const int Lq = L[q];
+        key[q] = __float_as_uint(acc * (float)(Lq > 0 ? Lq : 0)) >> (32 - ORDER_BITS);
+    }
+}
+
+// counting sort of the bins, largest first, in one workgroup: counts in LDS,
+// a descending exclusive scan (thread t owns places ORDER_PER_THREAD * t ...
+// of the descending bin list), then each query takes the next place of its bin
+__global__ void __launch_bounds__(1024) order_sort_kernel(const uint32_t *key, int nq,
+                                                          int32_t *order)
+{
+    __shared__ uint32_t hist[ORDER_BINS];
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    for (int i = t; i < ORDER_BINS; i += 1024) hist[i] = 0u;
+    __syncthreads();
+    for (int q = t; q < nq; q += 1024) atomicAdd(&hist[key[q]], 1u);
+    __syncthreads();
+    uint32_t c[ORDER_PER_THREAD], sum = 0u;
+    for (int i = 0; i < ORDER_PER_THREAD; ++i) {
+        c[i] = hist[ORDER_BINS - 1 - (ORDER_PER_THREAD * t + i)];
+        sum += c[i];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t ? part[t - 1] : 0u;
+    for (int i = 0; i < ORDER_PER_THREAD; ++i) {
+        hist[ORDER_BINS - 1 - (ORDER_PER_THREAD * t + i)] = run;
+        run += c[i];
+    }
+    __syncthreads();
+    for (int q = t; q < nq; q += 1024) order[atomicAdd(&hist[key[q]], 1u)] = q;
 }
 
 template <int G, int CPL, bool F64, int FILT>
@@ -182,12 +259,18 @@ size_t search_wave_lds(const ann_search_plan &p, int64_t n, int dim)
     return wave_lds_bytes(p.pool_cap, f, p.fp64 != 0, dim);
 }
 
+size_t search_ws_bytes(int64_t nq)
+{
+    if (nq <= 1) return 256;
+    return 256 + 2 * round_up((size_t)nq * 4, 256);
+}
+
 ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_t *graph,
                          int32_t R, const float *queries, int32_t nq, const int32_t *entry_ids,
                          int32_t medoid, const int32_t *k, const int32_t *L, int32_t k_max,
                          int32_t *out_ids, float *out_dist, int32_t *stats, int32_t *trace,
                          int32_t trace_cap, const ann_search_plan &p, uint32_t *counter,
-                         hipStream_t st)
+                         hipStream_t st, bool widest_first)
 {
     SearchArgs a{};
     a.base = base;
@@ -215,6 +298,19 @@ ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_
         if (fs != ANN_OK) return fs;
     }
     a.wave_lds = wave_lds_bytes(p.pool_cap, a.filter, p.fp64 != 0, dim);
+    a.order = nullptr;
+    if (widest_first && nq > 1) {
+        // the workspace after the counter: order, keys
+        Carve cv{reinterpret_cast<unsigned char *>(counter) + 256};
+        int32_t *order = cv.take<int32_t>((size_t)nq);
+        uint32_t *key = cv.take<uint32_t>((size_t)nq);
+        hipLaunchKernelGGL(order_key_kernel, dim3((nq + 3) / 4), dim3(256), 0, st, base, n, dim,
+                           queries, nq, entry_ids, medoid, L, key);
+        ANN_LAUNCHED();
+        hipLaunchKernelGGL(order_sort_kernel, dim3(1), dim3(1024), 0, st, key, nq, order);
+        ANN_LAUNCHED();
+        a.order = order;
+    }
     if (p.waves_per_query > 1) return launch_search_mw(a, p.waves_per_query, p.blocks, st);
     if (p.fp64) return dispatch<true>(a, p.group, p.blocks, p.waves_per_block, st);
     return dispatch<false>(a, p.group, p.blocks, p.waves_per_block, st);
@@ -315,5 +411,6 @@ extern "C" ann_status ann_search(const float *base, int64_t n, int32_t dim, cons
     if (nq == 0) return ANN_OK;
     return search_launch(base, n, dim, graph, R, queries, nq, entry_ids, medoid, k, L, k_max,
                          out_ids, out_dist, stats, trace, trace_cap, p,
-                         static_cast<uint32_t *>(workspace), static_cast<hipStream_t>(stream));
+                         static_cast<uint32_t *>(workspace), static_cast<hipStream_t>(stream),
+                         true);
 }

@@ -28,6 +28,7 @@ struct SearchArgs {
     int visited_log2;
     beam::FilterShape filter;
     uint32_t *counter;
+    const int32_t *order;   // NULL, or the order in which the queries are taken
     size_t wave_lds;
 };
 

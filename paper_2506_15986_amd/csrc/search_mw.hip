@@ -30,9 +30,11 @@ __global__ void __launch_bounds__(256) search_mw_kernel(SearchArgs a)
     for (;;) {
         if (threadIdx.x == 0) ctrl[1] = (int)atomicAdd(a.counter, 1u);
         __syncthreads();
-        const int qi = __builtin_amdgcn_readfirstlane(((volatile int *)ctrl)[1]);
+        const int slot = __builtin_amdgcn_readfirstlane(((volatile int *)ctrl)[1]);
         __syncthreads();
-        if (qi >= a.nq) break;
+        if (slot >= a.nq) break;
+        const int qi = a.order ? a.order[slot] : slot;
+        if (qi < 0 || qi >= a.nq) continue;
         const int kq = a.k[qi];
         const int Lq = a.L[qi];
         const int entry = a.entry ? a.entry[qi] : a.medoid;

@@ -8,7 +8,7 @@ extern "C" size_t ann_workspace_size(int32_t op, int64_t n, int32_t dim, int32_t
     (void)dim;
     switch (op) {
     case ANN_OP_SEARCH:
-        return 256;
+        return search_ws_bytes(p0);
     case ANN_OP_BUILD_GRAPH:
         return build_graph_ws(n, dim, p0, p1);
     case ANN_OP_GT_KNN:

@@ -46,10 +46,12 @@ def test_search_rejects_bad_arguments_before_any_device_work(lib):
     fake = ctypes.c_void_p(0x10000)      # never dereferenced: validation fails first
     odd = ctypes.c_void_p(0x10004)       # not 16-byte aligned
 
+    wsb = ann.workspace_size("search", 1000, 32, 4)    # counter, query order and its keys
+
     def call(**kw):
         a = dict(base=fake, n=1000, dim=32, graph=fake, R=16, queries=fake, nq=4, entry=None,
                  medoid=0, k=fake, L=fake, k_max=10, ids=fake, dist=fake, stats=None, trace=None,
-                 trace_cap=0, plan=None, ws=fake, wsb=256, stream=None)
+                 trace_cap=0, plan=None, ws=fake, wsb=wsb, stream=None)
         a.update(kw)
         return lib.ann_search(a["base"], a["n"], a["dim"], a["graph"], a["R"], a["queries"],
                               a["nq"], a["entry"], a["medoid"], a["k"], a["L"], a["k_max"],
@@ -66,6 +68,7 @@ def test_search_rejects_bad_arguments_before_any_device_work(lib):
     assert call(medoid=1000) == ann.ANN_EINVAL
     assert call(base=odd) == ann.ANN_EINVAL
     assert call(wsb=16) == ann.ANN_EINVAL
+    assert call(wsb=wsb - 1) == ann.ANN_EINVAL
     assert call(k_max=0) == ann.ANN_EINVAL
     bad = ann.ann_search_plan(pool_cap=1040, visited_log2=12, group=8, waves_per_block=1,
                               blocks=0, fp64=0)
@@ -98,7 +101,9 @@ def test_default_plan_and_workspace():
     assert ann.default_plan(10, 32, 16, 600).pool_cap == 608
     with pytest.raises(ann.AnnError):
         ann.default_plan(10, 32, 16, 1025)
-    assert ann.workspace_size("search", 1000, 32, 10) >= 4
+    assert ann.workspace_size("search", 1000, 32, 1) == 256
+    assert ann.workspace_size("search", 1000, 32, 10) >= 256 + 2 * 40
+    assert ann.workspace_size("search", 1000, 32, 100000) >= 256 + 2 * 400000
 
 
 def test_kernel_names_unique_across_translation_units():

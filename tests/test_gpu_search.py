@@ -300,3 +300,26 @@ def test_pool_wider_than_512_matches_oracle():
         assert (got["ids"] == ref["ids"]).all(), L
         assert (got["stats"][:, 2] == ref["hops"]).all(), L
         assert (got["dist"] == ref["d2"].astype(np.float32)).all(), L
+
+
+@pytest.mark.parametrize("wpq", [1, 2])
+def test_results_do_not_depend_on_query_order(wpq):
+    # the launch takes queries widest-expected-first (L x distance to the
+    # entry); every query's ids, distances, counts and trace stay its own
+    ix = int_index()
+    nq = ix["q"].shape[0]
+    r = np.random.default_rng(11)
+    ent = r.integers(0, ix["base"].shape[0], nq).astype(np.int32)
+    ks = r.integers(1, 11, nq).astype(np.int32)
+    Ls = (ks + r.integers(0, 120, nq)).astype(np.int32)
+    perm = r.permutation(nq)
+    plan = _plan(ix, int(Ls.max()), group=16, waves_per_block=2 if wpq == 2 else 1,
+                 waves_per_query=wpq)
+    say("case: query order invariance wpq=%d" % wpq)
+    a = _run(ix, ent, ks, Ls, plan, trace_cap=256, k_max=10)
+    ixp = dict(ix, q=ix["q"][perm])
+    b = _run(ixp, ent[perm], ks[perm], Ls[perm], plan, trace_cap=256, k_max=10)
+    for key in ("ids", "dist", "stats", "trace"):
+        assert (a[key][perm] == b[key]).all(), key
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ent, ks, Ls, k_max=10)
+    assert (a["ids"] == ref["ids"]).all()
