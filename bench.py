@@ -170,6 +170,7 @@ def main():
     ap.add_argument("--queue-variants", default="3:16:48",
                     help="queues leg: t_pos:P:N triples, comma separated (t_neg stays 15)")
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
+    ap.add_argument("--pipe", type=int, default=2, help="batches in flight in the pipelined steps")
     ap.add_argument("--shuffle-queries", type=int, default=0,
                     help="permute the test queries with this seed (0: generator order)")
     ap.add_argument("--save-state", default="")
@@ -182,6 +183,7 @@ def main():
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
+    PIPE = max(2, args.pipe)
     targets = sorted(set([TARGET] + [float(x) for x in args.targets.split(",") if x]))
 
     import torch
@@ -291,27 +293,28 @@ def main():
         return best, rows
 
     def pipelined(b, g_entry, g_search, L, plan, model):
-        """The same K steps with two batches in flight: the entry stage runs
-        on its own stream, and the searches of consecutive batches on two
+        """The same K steps with PIPE batches in flight: the entry stage runs
+        on its own stream, and the searches of consecutive batches on PIPE
         streams (one per buffer set), so the next batch's search fills the
         compute units that the current one's last queries leave idle.  Events
         order each buffer's entry stage after its previous search and each
         search after its entry stage."""
-        b2 = ann.QueryBatch(base_d, index.graph, index.medoid, q_d, kk,
-                            torch.full((nq,), L, dtype=torch.int32, device=dev), k, plan=plan,
-                            model=model, entry_ids=None if model is not None else b.entry_ids)
-        pairs = [(g_entry, g_search),
-                 (b2.graph_exec(ann.ANN_STAGE_ENTRY) if model is not None else None,
-                  b2.graph_exec(ann.ANN_STAGE_SEARCH))]
+        extra = [ann.QueryBatch(base_d, index.graph, index.medoid, q_d, kk,
+                                torch.full((nq,), L, dtype=torch.int32, device=dev), k, plan=plan,
+                                model=model, entry_ids=None if model is not None else b.entry_ids)
+                 for _ in range(PIPE - 1)]
+        pairs = [(g_entry, g_search)] + [
+            (bx.graph_exec(ann.ANN_STAGE_ENTRY) if model is not None else None,
+             bx.graph_exec(ann.ANN_STAGE_SEARCH)) for bx in extra]
         s_e = torch.cuda.Stream(device=dev)
-        s_s = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
-        ready = [torch.cuda.Event(), torch.cuda.Event()]
-        done = [torch.cuda.Event(), torch.cuda.Event()]
-        for x in range(2):
+        s_s = [torch.cuda.Stream(device=dev) for _ in range(PIPE)]
+        ready = [torch.cuda.Event() for _ in range(PIPE)]
+        done = [torch.cuda.Event() for _ in range(PIPE)]
+        for x in range(PIPE):
             done[x].record(s_s[x])
 
         def pstep(i):
-            x = i & 1
+            x = i % PIPE
             ge, gs = pairs[x]
             if ge is not None:
                 s_e.wait_event(done[x])
@@ -329,14 +332,16 @@ def main():
             pstep(i)
         torch.cuda.synchronize()
         wall = time.time() - t0
-        same = bool((b2.ids.cpu().numpy() == b.ids.cpu().numpy()).all())
-        for gx in pairs[1]:
-            if gx is not None:
-                gx.close()
+        same = all(bool((bx.ids.cpu().numpy() == b.ids.cpu().numpy()).all()) for bx in extra)
+        for pr in pairs[1:]:
+            for gx in pr:
+                if gx is not None:
+                    gx.close()
         res = dict(qps=round(nq * args.steps / wall, 1),
                    ms_per_step=round(wall * 1000.0 / args.steps, 4), results_equal=same)
-        log("pipelined steps (two batches in flight): %.3f ms/step -> %.0f QPS (results equal: %s)" %
-            (res["ms_per_step"], res["qps"], same))
+        res["batches_in_flight"] = PIPE
+        log("pipelined steps (%d batches in flight): %.3f ms/step -> %.0f QPS (results equal: %s)" %
+            (PIPE, res["ms_per_step"], res["qps"], same))
         return res
 
     def timed(L, model, entry, label):
