@@ -133,8 +133,8 @@ def recall_tie_aware(dist: np.ndarray, truth_dist: np.ndarray, k: int = 10) -> n
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="sift1m")
     ap.add_argument("--n", type=int, default=0, help="override base size")
     ap.add_argument("--n-train", type=int, default=0, help="override training-query count")
