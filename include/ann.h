@@ -94,7 +94,12 @@ typedef struct ann_search_plan {
     int32_t waves_per_query; /* wavefronts that share one query: 1 (0 = 1), or 2 / 4 (FP32, group 16;
                                 the workgroup is then one query's waves, so
                                 waves_per_block must equal waves_per_query) */
+    int32_t query_order;     /* ANN_ORDER_WIDEST_FIRST (0) or ANN_ORDER_AS_GIVEN (1), see ann_search */
 } ann_search_plan;
+
+/* Order in which a search launch takes its queries (results are the same in
+ * any order; only the launch's duration depends on it). */
+enum { ANN_ORDER_WIDEST_FIRST = 0, ANN_ORDER_AS_GIVEN = 1 };
 
 /* Visited filter forms (per wavefront, in LDS).  Every form answers "seen"
  * only for ids it was given; the hash forms may forget an id, which costs a
@@ -130,10 +135,13 @@ ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_t L_max,
  *             known on the host, so NULL means pool_cap 256)
  *   workspace ann_workspace_size(ANN_OP_SEARCH, n, dim, nq, 0) bytes
  * With nq == 0 the per-query pointers may be NULL and nothing is enqueued.
- * Queries are taken widest-expected-first: a pre-pass orders them by L[i]
- * times the FP32 squared distance from query i to its entry, largest first
- * (the order lives in the workspace), so that the longest searches do not
- * start last; every query's results are the same in any order.
+ * With plan->query_order == ANN_ORDER_WIDEST_FIRST (the default) queries are
+ * taken widest-expected-first: a pre-pass orders them by L[i] times the FP32
+ * squared distance from query i to its entry, largest first (the order lives
+ * in the workspace), so that the longest searches do not start last.  With
+ * ANN_ORDER_AS_GIVEN they are taken in index order (for pipelines that keep
+ * several launches in flight, where the next launch fills the tail).  Every
+ * query's results are the same in any order.
  * Each query expands the best not-yet-expanded pool entry until none is left;
  * the FP32 (or FP64) distance of every newly seen neighbour is one distance
  * computation.  Ties are broken by the smaller id. */

@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 ANN_OK, ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE, ANN_ENOTSUP = 0, 1, 2, 3, 4
 ANN_FILTER_AUTO, ANN_FILTER_BITSET, ANN_FILTER_TAG16, ANN_FILTER_ID32 = 0, 1, 2, 3
+ANN_ORDER_WIDEST_FIRST, ANN_ORDER_AS_GIVEN = 0, 1
 OP = dict(search=1, build_graph=2, gt_knn=3, select_hubs=4, entry_select=5, make_labels=6,
           hub_features=7, train_step=8)
 
@@ -38,7 +39,8 @@ class ann_search_plan(ctypes.Structure):
     _fields_ = [("pool_cap", ctypes.c_int32), ("visited_log2", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("fp64", ctypes.c_int32),
-                ("filter", ctypes.c_int32), ("waves_per_query", ctypes.c_int32)]
+                ("filter", ctypes.c_int32), ("waves_per_query", ctypes.c_int32),
+                ("query_order", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

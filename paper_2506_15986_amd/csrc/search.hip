@@ -241,6 +241,8 @@ ann_status validate_plan(const ann_search_plan &p)
                 "plan.waves_per_block must equal waves_per_query when it is above 1");
     ANN_SUPPORTED(p.waves_per_query <= 1 || (p.group == 16 && p.fp64 == 0),
                   "several waves per query need group 16 and FP32");
+    ANN_REQUIRE(p.query_order == ANN_ORDER_WIDEST_FIRST || p.query_order == ANN_ORDER_AS_GIVEN,
+                "plan.query_order must be one of ANN_ORDER_*");
     return ANN_OK;
 }
 
@@ -299,7 +301,7 @@ ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_
     }
     a.wave_lds = wave_lds_bytes(p.pool_cap, a.filter, p.fp64 != 0, dim);
     a.order = nullptr;
-    if (widest_first && nq > 1) {
+    if (widest_first && p.query_order == ANN_ORDER_WIDEST_FIRST && nq > 1) {
         // the workspace after the counter: order, keys
         Carve cv{reinterpret_cast<unsigned char *>(counter) + 256};
         int32_t *order = cv.take<int32_t>((size_t)nq);
@@ -335,6 +337,7 @@ extern "C" ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_
     p.waves_per_block = 1;
     p.blocks = 0;
     p.fp64 = 0;
+    p.query_order = ANN_ORDER_WIDEST_FIRST;
     (void)R;
     *plan = p;
     return ANN_OK;
