@@ -87,6 +87,8 @@ def test_search_rejects_bad_arguments_before_any_device_work(lib):
     assert call(plan=ctypes.byref(bad), dim=132) == ann.ANN_ENOTSUP  # group 8: dim <= 128
     bad.group = 12
     assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
+    bad.group, bad.query_order = 8, 2
+    assert call(plan=ctypes.byref(bad)) == ann.ANN_EINVAL
     # nq == 0 is valid and enqueues nothing
     assert call(nq=0) == ann.ANN_OK
 

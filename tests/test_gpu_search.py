@@ -321,5 +321,9 @@ def test_results_do_not_depend_on_query_order(wpq):
     b = _run(ixp, ent[perm], ks[perm], Ls[perm], plan, trace_cap=256, k_max=10)
     for key in ("ids", "dist", "stats", "trace"):
         assert (a[key][perm] == b[key]).all(), key
+    plan.query_order = _ann().ANN_ORDER_AS_GIVEN          # no pre-pass: index order
+    c = _run(ix, ent, ks, Ls, plan, trace_cap=256, k_max=10)
+    for key in ("ids", "dist", "stats", "trace"):
+        assert (a[key] == c[key]).all(), key
     ref = oracle.search(ix["base"], ix["graph"], ix["q"], ent, ks, Ls, k_max=10)
     assert (a["ids"] == ref["ids"]).all()
