@@ -189,3 +189,29 @@ def test_tune_hub_search_width():
     cos = qe @ model.hub_emb.cpu().numpy().astype(np.float64).T
     hit = np.abs(cos[np.arange(len(qe)), bh.cpu().numpy()] - cos.max(1)) <= 1e-6
     assert hit.mean() >= 0.99 or L == 64
+
+
+def test_training_keeps_the_epoch_with_the_best_held_out_agreement():
+    # select_best: the towers left after training are the ones of the best
+    # epoch on the held-out queries (recomputed here from the returned towers)
+    from paper_2506_15986_amd import gate
+    ann = _ann()
+    w = synth.scaled(synth.WORKLOADS["tiny"], n=10_000, n_queries=100, n_train=4_000)
+    base = _dev(synth.base(w))
+    say("case: epoch selection on the tiny workload")
+    index = gate.build_index(base, 64, 16, 1.2, w=w, log=None)
+    tq = _dev(synth.train_queries(w))
+    gd = gate.prepare_gate(index, tq, w, n_hubs=64, log=lambda *a: None)
+    g = gate.train_gate(index, gd, tq, w, hidden=32, dout=16, epochs=6, batch=256,
+                        select_best=True, tune_L_h=False, log=lambda *a: None)
+    curve = g.info["val_curve"]
+    assert [e for e, _ in curve] == list(range(1, 7))
+    best = max(a for _, a in curve)
+    assert g.info["selected_epoch"] == next(e for e, a in curve if a == best)
+    nt = tq.shape[0] - int(round(0.1 * tq.shape[0]))
+    hemb = g.htower.forward(g.hub_in)
+    hg, he = ann.ann_navgraph_build(hemb, 16)
+    mdl = ann.EntryModel(g.qtower, hemb, hg, gd.hub_ids, he, index.medoid, L_h=32)
+    _, _, bh = ann.ann_entry_select(mdl, tq[nt:].contiguous(), want_score=True)
+    acc = float((bh == gd.labels[nt:]).float().mean().item())
+    assert round(acc, 4) == best
