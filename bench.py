@@ -26,8 +26,11 @@ the QPS there are reported.
 
 The --load-state form replays the same timed GATE step without rebuilding or
 sweeping; it is the command the kernel profiles are taken on, so that the
-profiler sees only the timed launches.  Prints one JSON line on stdout;
-progress goes to stderr.
+profiler sees only the timed launches.  Prints one compact JSON line on
+stdout, last (the headline, the medoid comparison, the roofline and the CPU
+oracle's rate and its query-by-query parity with the GPU's batch); the full
+record (sweeps, autotune rows, ablations, serving) goes to --details;
+progress goes to stderr (one line per swept width with --verbose).
 """
 from __future__ import annotations
 
@@ -175,6 +178,10 @@ def main():
                     help="permute the test queries with this seed (0: generator order)")
     ap.add_argument("--save-state", default="")
     ap.add_argument("--load-state", default="")
+    ap.add_argument("--details", default=os.path.join("gpurun_out", "bench_details.json"),
+                    help="file for the full record (sweeps, autotune rows, ablations); the stdout "
+                         "line carries the summary only ('' = do not write)")
+    ap.add_argument("--verbose", action="store_true", help="one progress line per swept width")
     ap.add_argument("--targets", default="0.95",
                     help="recall@10 targets to report (the headline is 0.95)")
     args = ap.parse_args()
@@ -242,8 +249,9 @@ def main():
             st = out[2].cpu().numpy()
             rows.append(dict(L=L, recall=round(rec, 5), ndc=round(float(st[:, 0].mean()), 1),
                              hops=round(float(st[:, 2].mean()), 1)))
-            log("  %s L=%4d recall@10=%.4f ndc=%.0f hops=%.0f" % (label, L, rec, st[:, 0].mean(),
-                                                                  st[:, 2].mean()))
+            if args.verbose:
+                log("  %s L=%4d recall@10=%.4f ndc=%.0f hops=%.0f" % (label, L, rec, st[:, 0].mean(),
+                                                                      st[:, 2].mean()))
             return rec
 
         prev = None
@@ -260,6 +268,9 @@ def main():
                 break
             prev = L
         rows.sort(key=lambda r: r["L"])
+        best = max(rows, key=lambda r: r["recall"])
+        log("sweep %s: %d widths, L for recall %.2f: %s, best recall %.4f at L = %d" %
+            (label, len(rows), TARGET, L95, best["recall"], best["L"]))
         return rows, L95
 
     def extra_targets(rows, model, entry, label):
@@ -387,17 +398,17 @@ def main():
         exact = ann.make_plan(**dict(plan.as_dict(), visited_log2=13, filter=ann.ANN_FILTER_ID32,
                                      waves_per_block=1, waves_per_query=1))
         e = b.entry_ids if model is not None else entry
-        if state is not None and state.get("exact_%s" % label):
-            ex = state["exact_%s" % label]     # counted by the run that saved the state
-        else:
-            xs = ann.ann_search(base_d, index.graph, q_d, e, index.medoid, kk, b.L, k_max=k,
-                                plan=exact)[2].cpu().numpy()
-            d = w.d
-            ex = dict(lossy=int(((xs[:, 3] & 1) != 0).sum()), ndc=float(xs[:, 0].mean()),
-                      hops=float(xs[:, 2].mean()),
-                      bytes=float((4 * d * xs[:, 0].astype(np.float64) +
-                                   4 * R * xs[:, 2].astype(np.float64) + 4 * d + 8 * k).sum()))
+        xs = ann.ann_search(base_d, index.graph, q_d, e, index.medoid, kk, b.L, k_max=k,
+                            plan=exact)[2].cpu().numpy()
+        d = w.d
+        ex = dict(lossy=int(((xs[:, 3] & 1) != 0).sum()), ndc=float(xs[:, 0].mean()),
+                  hops=float(xs[:, 2].mean()),
+                  bytes=float((4 * d * xs[:, 0].astype(np.float64) +
+                               4 * R * xs[:, 2].astype(np.float64) + 4 * d + 8 * k).sum()))
         exacts[label] = ex
+        arrays[label] = dict(ids=ids, dist=dist, ndc=xs[:, 0].copy(), hops=xs[:, 2].copy(),
+                             entry=(e.cpu().numpy() if e is not None
+                                    else np.full(nq, index.medoid, np.int32)))
         lossy, bytes_launch = ex["lossy"], ex["bytes"]
         sm = float(np.mean(search_ms))
         res = dict(L=L, recall=round(rec, 5), recall_tie_aware=round(rec_t, 5),
@@ -451,7 +462,8 @@ def main():
             for Lx in grid:
                 ids = index.search(qm_d, Lx, kt, em)[0].cpu().numpy()
                 rec = float((ids[:, :kq, None] == gt100[:, None, :kq]).any(-1).mean())
-                log("  serving mix k=%d L=%d recall@%d=%.4f" % (kq, Lx, kq, rec))
+                if args.verbose:
+                    log("  serving mix k=%d L=%d recall@%d=%.4f" % (kq, Lx, kq, rec))
                 if rec >= TARGET:
                     Lk[kq] = Lx
                     break
@@ -515,7 +527,8 @@ def main():
         return out
 
     exacts = {}
-    med, med_rows, gres, ginfo, abl = None, [], None, {}, {}
+    arrays = {}     # per timed leg: the GPU's outputs, exact counts and entries
+    med, med_rows, gres, ginfo, abl, g_rows = None, [], None, {}, {}, []
     # ---- medoid entry
     if "medoid" in legs:
         if state is not None:
@@ -676,6 +689,22 @@ def main():
         del tq
 
     head = gres if (gres is not None and gres["reached_target"]) or med is None else med
+    head_label = "gate" if head is gres else "medoid"
+
+    # ---- the highest recall both entries reach, when the medoid never
+    # reaches the target: the medoid at its best swept width against GATE at
+    # the smallest swept width whose recall reaches that value
+    common = None
+    if med is not None and gres is not None and not med["reached_target"] and g_rows:
+        r_m = med["recall"]
+        Lc = next((r["L"] for r in g_rows if r["recall"] >= r_m), None)
+        if Lc is not None:
+            rc = timed(Lc, g.model, ent, "gate@medoid-best")
+            common = dict(recall=r_m, medoid_L=med["L"], medoid_qps=med["qps"], gate_L=Lc,
+                          gate_recall=rc["recall"], gate_qps=rc["qps"],
+                          gate_over_medoid=round(rc["qps"] / med["qps"], 2))
+            log("highest recall both entries reach: %.4f; medoid L=%d %.0f QPS, GATE L=%d "
+                "(recall %.4f) %.0f QPS" % (r_m, med["L"], med["qps"], Lc, rc["recall"], rc["qps"]))
 
     # ---- counter calibration: a plain elementwise kernel that reads and
     # writes COPY_BYTES each
@@ -686,36 +715,47 @@ def main():
     torch.cuda.synchronize()
     del src_t, dst_t
 
-    # ---- CPU baseline: the oracle on a bounded sample of the same queries
+    # ---- CPU baseline: the oracle on the same queries, entries and L as the
+    # headline; its first pass over the whole batch is also compared with the
+    # GPU's results query by query
     cpu = None
     if not args.no_cpu:
         import oracle
         g_host = index.graph.cpu().numpy()
-        if head is gres:
-            ent_host = g.select(q_d)[0].cpu().numpy()
-        else:
-            ent_host = np.full(nq, index.medoid, np.int32)
+        ga = arrays[head_label]
+        ent_host = ga["entry"]
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         cores = min(cores, 16)
         L_cpu = head["L"]
-        tot_q, tot_t = 0, 0.0
+        tot_q, tot_t, first = 0, 0.0, None
         while tot_t < args.cpu_seconds:
             t0 = time.time()
-            oracle.search(base, g_host, queries, ent_host, k, L_cpu, threads=cores)
+            r = oracle.search(base, g_host, queries, ent_host, k, L_cpu, threads=cores)
             tot_t += time.time() - t0
             tot_q += nq
+            first = first or r
         m1 = min(nq, 1000)
         t0 = time.time()
         oracle.search(base, g_host, queries[:m1], ent_host[:m1], k, L_cpu, threads=1)
         t1 = time.time() - t0
+        # parity of the timed batch: ids, distances (within 1e-5 relative;
+        # exact on integer data), exact distance counts and hops
+        rd = first["d2"]
+        tol = 1e-5 * np.maximum(rd, 1e-6)
+        dist_bad = (np.abs(ga["dist"].astype(np.float64) - rd) > tol).any(1)
+        ids_bad = (ga["ids"] != first["ids"]).any(1)
+        parity = dict(queries=int(nq), ids_differ=int(ids_bad.sum()),
+                      dist_beyond_tol=int(dist_bad.sum()),
+                      dist_bitwise_differ=int((ga["dist"].astype(np.float64) != rd).any(1).sum()),
+                      ndc_differ=int((ga["ndc"] != first["ndc"]).sum()),
+                      hops_differ=int((ga["hops"] != first["hops"]).sum()))
         cpu = dict(value=round(tot_q / tot_t, 2), unit="queries/s", cores=int(cores), kind="oracle",
                    sample="all %d queries x %d passes, %s entries (GPU-selected), L=%d, k=%d, "
-                          "FP64 search only" % (nq, tot_q // nq, "GATE" if head is gres else
-                                                "medoid", L_cpu, k),
-                   one_thread=dict(value=round(m1 / t1, 2), sample="first %d queries" % m1),
-                   host=host_cpu())
-        log("cpu oracle: %d queries in %.1fs on %d threads -> %.1f QPS; 1 thread %.1f QPS" %
-            (tot_q, tot_t, cores, tot_q / tot_t, m1 / t1))
+                          "FP64 search only" % (nq, tot_q // nq, head_label, L_cpu, k),
+                   one_thread=round(m1 / t1, 2), parity_vs_gpu=parity,
+                   host=host_cpu()["model"])
+        log("cpu oracle: %d queries in %.1fs on %d threads -> %.1f QPS; 1 thread %.1f QPS; "
+            "parity over the batch: %s" % (tot_q, tot_t, cores, tot_q / tot_t, m1 / t1, parity))
 
     achieved = head["achieved_gbs"]
     tr = measured_traffic(args.workload, head["L"], nq, head["plan"]) if head is gres else None
@@ -723,30 +763,49 @@ def main():
     if tr is not None:
         traffic = dict(read_bytes=tr[0], write_bytes=tr[1], bytes=tr[0] + tr[1],
                        gbs=round((tr[0] + tr[1]) / (head["search_ms"] / 1000.0) / 1e9, 1))
-    res = dict(
+    workload = ("%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d%s/alpha%g/R%d "
+                "+ repair; %d hubs; towers %d->%d->%d" %
+                (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k,
+                 " within %d overlapping groups (x%d)" % (parts, args.overlap) if parts else "",
+                 args.alpha, R, args.hubs, w.d, args.hidden, args.dout))
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=traffic["bytes"] if traffic else None)
+    summary = dict(
         metric=METRIC, value=head["qps"], unit="queries/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(
-            workload="%s: N=%d d=%d %s, %d queries, %d training queries; graph kNN%d%s/alpha%g/R%d "
-                     "+ repair; %d hubs; towers %d->%d->%d" %
-                     (w.name, w.n, w.d, WORKLOAD_TEXT.get(w.name, ""), nq, w.n_train, knn_k,
-                      " within %d overlapping groups (x%d)" % (parts, args.overlap) if parts else "",
-                      args.alpha, R, args.hubs, w.d, args.hidden, args.dout),
-            recall_targets=targets,
-            entry="gate" if head is gres else "medoid", k=k, L=head["L"],
-            recall_at_10=head["recall"], recall_target=TARGET,
-            gate=gres, medoid=med, medoid_sweep=med_rows, ablation=abl, gate_build=ginfo,
-            graph_build_s=round(index.build_s, 2), bridges=list(index.bridges),
-            state=args.load_state or None),
-        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                      kernel="search_kernel", bytes_per_launch=head["bytes_per_launch"],
-                      launch_ms=head["search_ms"], kernel_hash=search_source_hash()),
+            workload=workload, entry=head_label, k=k, L=head["L"], recall_at_10=head["recall"],
+            recall_target=TARGET, reached_target=head["reached_target"],
+            ms_per_step_sequential=head.get("ms_per_step_sequential"),
+            entry_ms=head["entry_ms"], search_ms=head["search_ms"],
+            medoid=dict(reached_target=med["reached_target"], L=med["L"], recall=med["recall"],
+                        qps=med["qps"]) if med else None,
+            highest_common_recall=common,
+            gate_L_h=(ginfo.get("L_h") if ginfo else None),
+            details=args.details or None),
+        roofline=roofline,
         cpu_baseline=cpu,
     )
-    print(json.dumps(res), flush=True)
-
+    if args.details:
+        full = dict(summary, config=dict(
+            summary["config"], workload_text=workload, recall_targets=targets, gate=gres, medoid=med,
+            medoid_sweep=med_rows, ablation=abl, gate_build=ginfo,
+            graph_build_s=round(index.build_s, 2), bridges=list(index.bridges),
+            state=args.load_state or None),
+            roofline_detail=dict(roofline, traffic=traffic, kernel="search_kernel",
+                                 bytes_per_launch=head["bytes_per_launch"],
+                                 launch_ms=head["search_ms"], kernel_hash=search_source_hash()))
+        d = os.path.dirname(args.details)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.details, "w") as f:
+            json.dump(full, f, indent=1, default=str)
+        log("full record written to %s" % args.details)
+    line = json.dumps(summary, separators=(",", ":"))
+    sys.stderr.flush()
+    print(line, flush=True)
 
 if __name__ == "__main__":
     main()
