@@ -308,3 +308,30 @@ def test_nsg_graph_strongly_connected_and_sorted_rows():
     # alpha = 1 keeps no more than alpha = 1.2 would from the same lists
     g12 = oracle.alpha_prune(base, cand, cd2, 16, 1.2)
     assert ((g[:, :14] >= 0).sum() <= (g12[:, :14] >= 0).sum())
+
+
+def test_nsg_graph_two_clusters_on_a_line_by_hand():
+    # ids 0..4 at x = 0..4 and ids 5..9 at x = 100..104.  knn_k = 2 keeps each
+    # cluster to itself; the medoid (mean 52) ties between x = 4 and x = 100
+    # and takes the smaller id, 4.  Searches from 4 over the kNN graph (width
+    # 4) never leave the left cluster: for every right-hand point the pool is
+    # [4, 3, 2, 1] (x = 0 is revealed last and rejected).  Merged with the kNN
+    # list and pruned at alpha = 1 to R - 2 = 2, a line keeps the nearest point
+    # on each side, so the left rows are path rows, while row 5 (x = 100)
+    # keeps 6 and the search-built 4 (|x6 - x4| = 97 > |x5 - x4| = 96) and row
+    # 9 (x = 104) loses 4 to 8 (99 <= 100).  Repair: 5..9 are unreached from 4;
+    # 5's first reached candidate with a free slot R - 2 is 4 (one forward
+    # bridge 4 -> 5); every node then reaches 4 through 5 -> 4 (no reverse
+    # bridge).  The plain kNN + alpha = 1 graph instead needs a reverse bridge
+    # 5 -> 4 in slot R - 1.
+    base = np.zeros((10, 4), np.float32)
+    base[:, 0] = [0, 1, 2, 3, 4, 100, 101, 102, 103, 104]
+    g, med, nf, nr, cand, _ = oracle.build_graph_nsg(base, 2, 4, 4)
+    want = [[1, -1, -1, -1], [0, 2, -1, -1], [1, 3, -1, -1], [2, 4, -1, -1], [3, -1, 5, -1],
+            [6, 4, -1, -1], [5, 7, -1, -1], [6, 8, -1, -1], [7, 9, -1, -1], [8, -1, -1, -1]]
+    assert med == 4 and (nf, nr) == (1, 0)
+    assert g.tolist() == want
+    assert cand[5].tolist()[:6] == [6, 7, 4, 3, 2, 1]
+    gp, medp, nfp, nrp, _, _ = oracle.build_graph(base, 2, 4, 1.0)
+    assert medp == 4 and (nfp, nrp) == (1, 1)
+    assert gp[5].tolist() == [6, -1, -1, 4] and gp[4].tolist() == [3, -1, 5, -1]

@@ -216,6 +216,42 @@ def test_hub_features_path_graph_closed_form():
     assert (f[24:] == 0).all()
 
 
+def test_hub_features_cluster_columns_on_a_two_cluster_path():
+    # a 40-point path split into clusters 0..19 and 20..39, plus directed
+    # edges 35 -> 16, 36 -> 16, 37 -> 16 in slot 2 (first slots keep their
+    # path neighbour at distance 1, so nu = 1; MaxDeg 3, MinDeg 1 -> x = 2 on
+    # the walk, whose nodes all have degree <= 2 there: the walk is the BFS
+    # ball of depth 5).  mean in-degree = (78 + 3) / 40 = 2.025.
+    #   hub 18 (cluster 0): walk 13..23; nodes 20..23 lie in cluster 1 -> col
+    #     19 = 4 / 10; in-degrees 2 except node 16 (5) -> col 21 = (25 / 11)
+    #     / 2.025; out-degrees all 2 -> col 20 = (22 / 11) / 3; centroid
+    #     (9.5, 3) -> col 17 = sqrt(8.5^2 + 3^2)
+    #   hub 30 (cluster 1): walk 25..35, all in cluster 1 -> col 19 = 0;
+    #     in-degrees all 2 -> col 21 = 2 / 2.025; node 35 has out-degree 3 ->
+    #     col 20 = (23 / 11) / 3; centroid (29.5, -4) -> col 17 = sqrt(16.25)
+    n = 40
+    base, g2 = _path(n)
+    g = -np.ones((n, 3), np.int32)
+    g[:, :2] = g2
+    g[35:38, 2] = 16
+    assign = (np.arange(n) >= 20).astype(np.int32)
+    hubs = np.array([18, 30], np.int32)
+    cen = np.zeros((2, 4))
+    cen[0, :2] = [9.5, 3.0]
+    cen[1, :2] = [29.5, -4.0]
+    f, ws = oracle.hub_features(base, g, 0, hubs, assign, cen, h=5, standardize=False)
+    assert ws.tolist() == [[1, 2, 2, 2, 2, 2]] * 2
+    mean_in = 81.0 / 40.0
+    assert abs(f[0, 17] - math.sqrt(8.5 ** 2 + 9.0)) < 1e-12
+    assert abs(f[1, 17] - math.sqrt(16.25)) < 1e-12
+    assert abs(f[0, 19] - 0.4) < 1e-15 and f[1, 19] == 0.0
+    assert abs(f[0, 20] - 2.0 / 3.0) < 1e-12 and abs(f[1, 20] - 23.0 / 33.0) < 1e-12
+    assert abs(f[0, 21] - (25.0 / 11.0) / mean_in) < 1e-12
+    assert abs(f[1, 21] - 2.0 / mean_in) < 1e-12
+    assert abs(f[0, 1] - 2.0 / mean_in) < 1e-12        # the hub's own in-degree
+    assert abs(f[0, 16] - 20.0 / 20.0) < 1e-12          # cluster size / (n / n_hubs)
+
+
 def test_hub_features_nearest_and_farthest_sampling():
     # node 0 at the origin links to 6 points at distances 1,2,3,4,5,6; every
     # other node has degree 1 -> MinDeg 1, MaxDeg 6, x(0) = max(2, 1) = 2:
