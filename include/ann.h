@@ -455,6 +455,18 @@ typedef struct ann_fusion {
     float *WO;   /* df x heads*dk */
 } ann_fusion;
 
+/* The fusion embedding's inputs for each hub (Eq. 3 with the topology tokens
+ * read as the relative positions of the hub's graph neighbours): p row c =
+ * base row hub_ids[c] * scale (n_hubs x dim), U[c][s] = (base row w - base row
+ * hub_ids[c]) * scale for the neighbour w in graph slot s of the hub
+ * (n_hubs x R x dim; zeros for an empty slot), mask[c][s] = 1 when slot s
+ * holds a neighbour (n_hubs x R uint8).  FP32 (subtract, then multiply by
+ * scale, a power of two in practice).  Enqueues only; ids are not checked on
+ * the device (the hub ids and graph must lie in [0, n), -1 for empty slots). */
+ann_status ann_fusion_tokens(const float *base, int64_t n, int32_t dim, const int32_t *graph,
+                             int32_t R, const int32_t *hub_ids, int32_t n_hubs, float scale,
+                             float *p, float *U, uint8_t *mask, void *stream);
+
 /* F (n_hubs x df) from p (n_hubs x dp), U (n_hubs x S x du) and mask
  * (n_hubs x S, 1 = present); all device.  Enqueues only. */
 ann_status ann_fusion_forward(const ann_fusion *f, const float *p, const float *U,
@@ -487,6 +499,32 @@ size_t ann_hop_table_workspace_size(int64_t n);
 ann_status ann_hop_table(const int32_t *graph, int64_t n, int32_t R, const int32_t *hub_ids,
                          int32_t n_hubs, const int32_t *targets, int64_t nq, uint8_t *out,
                          void *workspace, size_t ws_bytes, void *stream);
+
+/* Positive and negative query queues of Definition 4 from a hop table
+ * (hops: nq x n_hubs uint8, device, as ann_hop_table writes it, 255 =
+ * unreachable).  With m_h the smallest hop count of hub h over all queries,
+ * query q is a positive of h when H(q, h) <= m_h + t_pos and a negative when
+ * H(q, h) == 255 or H(q, h) >= m_h + t_neg (the definition's negatives,
+ * "defined analogously", read with t_neg); a hub that reaches no query has
+ * neither.  Queue h lists its query indices in increasing order; the queues
+ * are concatenated hub after hub:
+ *   pos_off, neg_off  n_hubs + 1 int64 (device): queue h spans
+ *                     [off[h], off[h + 1]) of pos_q / neg_q
+ *   pos_q, neg_q      int32 (device) with room for pos_cap / neg_cap entries
+ *                     (NULL allowed with capacity 0)
+ *   totals            host int64[2]: the two queues' total lengths
+ * The call computes the offsets, copies the totals to the host
+ * (synchronising `stream`), and fills the lists when they fit; when a
+ * capacity is too small it returns ANN_ENOMEM after writing only the
+ * offsets and totals, so a caller can size the lists and call again.
+ *   workspace  ann_make_queues_workspace_size(nq, n_hubs) bytes
+ * Requires 1 <= nq < 2^31, 1 <= n_hubs <= 2^20, t_pos, t_neg >= 0. */
+size_t ann_make_queues_workspace_size(int64_t nq, int32_t n_hubs);
+
+ann_status ann_make_queues(const uint8_t *hops, int64_t nq, int32_t n_hubs, int32_t t_pos,
+                           int32_t t_neg, int64_t *pos_off, int64_t *neg_off, int32_t *pos_q,
+                           int64_t pos_cap, int32_t *neg_q, int64_t neg_cap, int64_t *totals,
+                           void *workspace, size_t ws_bytes, void *stream);
 
 /* Navigation graph over hubs.  Rows of hub_emb are unit vectors, so
  * |e_i - e_j|^2 = 2 - 2 cos(e_i, e_j) and the order by squared L2 distance is

@@ -606,6 +606,42 @@ def ann_hop_table_workspace_size(n: int) -> int:
     return int(_lib.ann_hop_table_workspace_size(n))
 
 
+
+_sig("ann_make_queues_workspace_size", _SZ, _I64, _I32)
+_sig("ann_make_queues", _I32, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _I64,
+     ctypes.POINTER(ctypes.c_int64), _P, _SZ, _P)
+
+
+def ann_make_queues_workspace_size(nq: int, n_hubs: int) -> int:
+    return int(_lib.ann_make_queues_workspace_size(nq, n_hubs))
+
+
+def ann_make_queues(hops: torch.Tensor, t_pos: int, t_neg: int, stream=None):
+    """Definition 4 queues from a hop table (nq x n_hubs uint8).  Returns
+    (pos_off int64 [n_hubs+1], pos_q int32, neg_off, neg_q): queue h spans
+    off[h]..off[h+1].  Two library calls: the first sizes the lists."""
+    assert hops.is_cuda and hops.dtype == torch.uint8 and hops.is_contiguous()
+    nq, nh = hops.shape
+    dev = hops.device
+    pos_off = torch.empty(nh + 1, dtype=torch.int64, device=dev)
+    neg_off = torch.empty(nh + 1, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(256, ann_make_queues_workspace_size(nq, nh)), dtype=torch.uint8,
+                     device=dev)
+    tot = (ctypes.c_int64 * 2)()
+    pos_q = torch.empty(0, dtype=torch.int32, device=dev)
+    neg_q = torch.empty(0, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        st = _lib.ann_make_queues(_ptr(hops), nq, nh, int(t_pos), int(t_neg), _ptr(pos_off),
+                                  _ptr(neg_off), _ptr(pos_q) if pos_q.numel() else None,
+                                  pos_q.numel(), _ptr(neg_q) if neg_q.numel() else None,
+                                  neg_q.numel(), tot, _ptr(ws), ws.numel(), _stream(stream))
+        if st != ANN_ENOMEM:
+            _check(st)
+            break
+        pos_q = torch.empty(int(tot[0]), dtype=torch.int32, device=dev)
+        neg_q = torch.empty(int(tot[1]), dtype=torch.int32, device=dev)
+    return pos_off, pos_q, neg_off, neg_q
+
 def ann_hop_table(graph: torch.Tensor, hub_ids: torch.Tensor, targets: torch.Tensor, stream=None):
     """Definition 4 hop counts, uint8 [nq, n_hubs] (255: unreachable or
     farther than 254 hops)."""
@@ -639,6 +675,28 @@ def ann_adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: t
                   lr: float, step: int, stream=None):
     _check(_lib.ann_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), float(lr),
                               int(step), _stream(stream)))
+
+
+_sig("ann_fusion_tokens", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _F32, _P, _P, _P, _P)
+
+
+def ann_fusion_tokens(base: torch.Tensor, graph: torch.Tensor, hub_ids: torch.Tensor,
+                      scale: float, stream=None):
+    """Fusion-embedding inputs per hub: (p [n_hubs, d], U [n_hubs, R, d],
+    mask [n_hubs, R] uint8), from the hubs' vectors and graph neighbours."""
+    _dev(base, torch.float32)
+    _dev(graph, torch.int32)
+    _dev(hub_ids, torch.int32)
+    n, d = base.shape
+    R = graph.shape[1]
+    nh = hub_ids.shape[0]
+    dev = base.device
+    p = torch.empty((nh, d), dtype=torch.float32, device=dev)
+    U = torch.empty((nh, R, d), dtype=torch.float32, device=dev)
+    mask = torch.empty((nh, R), dtype=torch.uint8, device=dev)
+    _check(_lib.ann_fusion_tokens(_ptr(base), n, d, _ptr(graph), R, _ptr(hub_ids), nh, float(scale),
+                                  _ptr(p), _ptr(U), _ptr(mask), _stream(stream)))
+    return p, U, mask
 
 
 class Fusion:
@@ -723,22 +781,19 @@ class EntryModel:
         self._ws = None
 
     def tune_L_h(self, sample_queries, agree: float = 0.995, ladder=(8, 12, 16, 24, 32, 48, 64)):
-        """Smallest hub-search width whose best hub matches the exact cosine
-        argmax over all hubs for at least `agree` of the sample queries (the
-        argmax is taken on the host from the embeddings the towers produce).
-        Sets and returns it."""
-        qe = self.qtower.forward(sample_queries).cpu().numpy().astype(np.float64)
-        he = self.hub_emb.cpu().numpy().astype(np.float64)
-        cos = qe @ he.T
-        best = cos.max(1)
-        rows = np.arange(qe.shape[0])
+        """Smallest hub-search width whose best hub matches the exact nearest
+        hub embedding (ann_gt_knn over the unit hub embeddings, i.e. the
+        cosine argmax; a tie within 1e-6 in cosine counts as agreement) for at
+        least `agree` of the sample queries.  Sets and returns it."""
+        qe = self.qtower.forward(sample_queries)
+        _, d2 = ann_gt_knn(self.hub_emb, qe, 1)
+        best = 1.0 - 0.5 * d2[:, 0]
         choice, rates = int(ladder[-1]), []
         for L in ladder:
             self.c.L_h = int(L)
             self.c.hub_plan = ann_search_plan()
-            _, _, bh = ann_entry_select(self, sample_queries, want_score=True)
-            # a tie in cosine counts as agreement
-            ok = float((np.abs(cos[rows, bh.cpu().numpy()] - best) <= 1e-6).mean())
+            _, sc, _ = ann_entry_select(self, sample_queries, want_score=True)
+            ok = int(((sc - best).abs() <= 1e-6).sum().item()) / max(1, sc.shape[0])
             rates.append((int(L), round(ok, 5)))
             if ok >= agree:
                 choice = int(L)

@@ -232,10 +232,50 @@ FusionArgs fu_args(const ann_fusion &f, const float *p, const float *U, const ui
     return a;
 }
 
+// Tokens of the fusion embedding for hub c (one workgroup per hub): its
+// vector p = x_hub * scale and, per graph slot s, U_s = (x_w - x_hub) * scale
+// for the neighbour w in that slot (0 and mask 0 for an empty slot).
+__global__ void __launch_bounds__(256) fusion_tokens_kernel(const float *base, int dim,
+                                                            const int32_t *graph, int R,
+                                                            const int32_t *hub_ids, float scale,
+                                                            float *p, float *U, uint8_t *mask)
+{
+    const int c = blockIdx.x;
+    const int64_t hub = hub_ids[c];
+    const float *xh = base + hub * dim;
+    for (int j = threadIdx.x; j < dim; j += blockDim.x) p[(int64_t)c * dim + j] = xh[j] * scale;
+    for (int s = 0; s < R; ++s) {
+        const int32_t w = graph[hub * R + s];
+        float *u = U + ((int64_t)c * R + s) * dim;
+        if (threadIdx.x == 0) mask[(int64_t)c * R + s] = w >= 0 ? 1 : 0;
+        if (w < 0) {
+            for (int j = threadIdx.x; j < dim; j += blockDim.x) u[j] = 0.f;
+        } else {
+            const float *xw = base + (int64_t)w * dim;
+            for (int j = threadIdx.x; j < dim; j += blockDim.x) u[j] = (xw[j] - xh[j]) * scale;
+        }
+    }
+}
+
 }  // namespace
 }  // namespace ann
 
 using namespace ann;
+
+extern "C" ann_status ann_fusion_tokens(const float *base, int64_t n, int32_t dim,
+                                        const int32_t *graph, int32_t R, const int32_t *hub_ids,
+                                        int32_t n_hubs, float scale, float *p, float *U,
+                                        uint8_t *mask, void *stream)
+{
+    ANN_REQUIRE(n >= 1 && dim >= 1 && R >= 1 && n_hubs >= 0, "need n, dim, R >= 1, n_hubs >= 0");
+    if (n_hubs == 0) return ANN_OK;
+    ANN_REQUIRE(base && graph && hub_ids && p && U && mask, "a required pointer is NULL");
+    hipLaunchKernelGGL(fusion_tokens_kernel, dim3((unsigned)n_hubs), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), base, dim, graph, R, hub_ids, scale, p, U,
+                       mask);
+    ANN_LAUNCHED();
+    return ANN_OK;
+}
 
 extern "C" size_t ann_fusion_workspace_size(const ann_fusion *f, int32_t n_hubs)
 {

@@ -271,13 +271,8 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     hub_in, labels = data.hub_in, data.labels
     fu = None
     if fusion:
-        base = index.base
-        hid = data.hub_ids.long()
-        nbr = index.graph[hid].long()                                  # n_hubs x R
-        tok_mask = (nbr >= 0).to(torch.uint8).contiguous()
-        p_vec = (base[hid] * data.scale).contiguous()
-        U = ((base[nbr.clamp(min=0)] - base[hid][:, None, :]) * data.scale
-             * tok_mask[:, :, None].float()).contiguous()
+        p_vec, U, tok_mask = ann.ann_fusion_tokens(index.base, index.graph, data.hub_ids,
+                                                   data.scale)
         C = fusion_heads * fusion_dk
         fw = synth.tower_init(w, [(C, d), (C, d), (C, d), (fusion_df, C)], salt=3)
         fu = ann.Fusion(fw[0], fw[2], fw[4], fw[6], heads=fusion_heads, device=dev)
@@ -299,29 +294,15 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
     if train and objective == "queues":
         H = ann.ann_hop_table(index.graph, data.hub_ids, data.nn[:nt].contiguous())
-        Hl = H.to(torch.int32)
-        reach = Hl < 255
-        big = torch.full_like(Hl, 1 << 20)
-        m = torch.where(reach, Hl, big).min(dim=0).values            # per hub
-        pos = reach & (Hl <= m + t_pos)
-        neg = (~reach) | (Hl >= m + t_neg)
-        has = reach.any(dim=0)
-        pos &= has
-        neg &= has
-        # queues as concatenated query lists (hub-major), with offsets
-        ph, pq = torch.nonzero(pos.t(), as_tuple=True)
-        nh_, nq_ = torch.nonzero(neg.t(), as_tuple=True)
-        pos_off = np.zeros(n_hubs + 1, np.int64)
-        neg_off = np.zeros(n_hubs + 1, np.int64)
-        pos_off[1:] = np.cumsum(torch.bincount(ph, minlength=n_hubs).cpu().numpy())
-        neg_off[1:] = np.cumsum(torch.bincount(nh_, minlength=n_hubs).cpu().numpy())
-        pos_q, neg_q = pq.to(torch.int64), nq_.to(torch.int64)
+        # Definition 4 queues (hub-major lists with offsets), built in the library
+        pos_off_d, pos_q, neg_off_d, neg_q = ann.ann_make_queues(H, t_pos, t_neg)
+        pos_off, neg_off = pos_off_d.cpu().numpy(), neg_off_d.cpu().numpy()
         eligible = np.flatnonzero((np.diff(pos_off) > 0) & (np.diff(neg_off) > 0))
         info.update(queue_hubs_eligible=int(eligible.size),
                     queue_pos_mean=float(np.diff(pos_off)[eligible].mean()) if eligible.size else 0.0,
                     queue_neg_mean=float(np.diff(neg_off)[eligible].mean()) if eligible.size else 0.0,
                     t_pos=t_pos, t_neg=t_neg)
-        del H, Hl, reach, big, pos, neg
+        del H
         rows = queue_hubs * (queue_P + queue_N)
         spe = max(1, -(-nt // rows))
         nb = ann.ann_train_hub_workspace_size(queue_hubs, queue_P, queue_N, d, hub_in.shape[1], hidden,

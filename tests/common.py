@@ -78,3 +78,48 @@ def near_tie_certificate(base, graph, q, entry, L, tr_gpu, tr_cpu, tol=1e-5):
     if len(picks) == 2 and close(picks[0], picks[1]):
         return True
     return any(close(d, kL) for d in picks)
+
+
+def tower_certificate(params, x, e_gpu, in_scale=1.0, tol=1e-4):
+    """Checks GPU tower embeddings against the oracle's (FP64 on the same BF16
+    operands).  Derivation of the tolerance: the BF16 x BF16 products are
+    exact in FP32, so the GPU's first-layer pre-activation z1 differs from the
+    FP64 one only by FP32 summation error, at most eps_j = (K + 2) 2^-24
+    (sum_k |x_k w_jk| + |b_j|) over K inputs; the second layer and the
+    normalisation add errors of the same relative size (~1e-6), far below
+    tol = 1e-4 on the unit row (L2 norm of the difference).  The one step
+    that can amplify them is the re-rounding of the hidden activation to
+    BF16: where relu(z1_j) lies within eps_j of a rounding boundary the GPU
+    may round it to the neighbouring BF16 value (one ulp, 2^-8 relative),
+    which moves the output row by up to (2 / |z2|) |delta a_j| |W2[:, j]|.
+    A row beyond tol is certified when its error is within tol plus that
+    bound summed over its ambiguous hidden elements.
+
+    Returns (rows beyond tol, rows certified by ambiguous roundings, indices
+    of uncertified rows)."""
+    from oracle import towers as T
+    e_ref, c = T.tower_forward(params, x, bf16=True, in_scale=in_scale)
+    e_gpu = np.asarray(e_gpu, np.float64)
+    err = np.linalg.norm(e_gpu - e_ref, axis=1)
+    bad = np.flatnonzero(err > tol)
+    if bad.size == 0:
+        return 0, 0, []
+    b1 = np.asarray(params[1], np.float64)
+    b2 = np.asarray(params[3], np.float64)
+    xr, W1r, W2r = c["xr"], c["W1r"], c["W2r"]
+    K = xr.shape[1]
+    col = np.linalg.norm(W2r, axis=0)                 # |W2[:, j]|
+    unc, cert = [], 0
+    for i in bad:
+        eps = (K + 2) * 2.0 ** -24 * (np.abs(xr[i]) @ np.abs(W1r).T + np.abs(b1))
+        z = c["z1"][i]
+        lo = T.bf16_round(np.maximum(z - eps, 0.0))
+        hi = T.bf16_round(np.maximum(z + eps, 0.0))
+        amb = np.abs(hi - lo)
+        z2 = c["a1r"][i] @ W2r.T + b2
+        bound = tol + 2.0 / np.linalg.norm(z2) * float((amb * col).sum())
+        if err[i] <= bound and amb.any():
+            cert += 1
+        else:
+            unc.append(int(i))
+    return int(bad.size), cert, unc

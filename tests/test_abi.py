@@ -273,3 +273,25 @@ def test_merge_candidates_rejects_bad_widths_without_gpu_work():
     assert call(aw=0, b=None) == ann.ANN_EINVAL
     assert call(wsb=128) == ann.ANN_EINVAL
     assert call(n=0) == ann.ANN_EINVAL
+
+
+def test_queue_builder_rejects_bad_arguments_on_the_host(lib):
+    from paper_2506_15986_amd import ann
+    fake = ctypes.c_void_p(0x10000)      # never dereferenced: validation fails first
+    tot = (ctypes.c_int64 * 2)()
+    wsb = ann.ann_make_queues_workspace_size(300, 70)
+
+    def q(**kw):
+        a = dict(hops=fake, nq=300, nh=70, tp=3, tn=15, po=fake, no=fake, pq=None, pc=0, nq_=None,
+                 nc=0, ws=fake, wsb=wsb)
+        a.update(kw)
+        return ann._lib.ann_make_queues(a["hops"], a["nq"], a["nh"], a["tp"], a["tn"], a["po"],
+                                        a["no"], a["pq"], a["pc"], a["nq_"], a["nc"], tot, a["ws"],
+                                        a["wsb"], None)
+
+    assert q(hops=None) == ann.ANN_EINVAL
+    assert q(nq=0) == ann.ANN_EINVAL
+    assert q(nh=0) == ann.ANN_EINVAL
+    assert q(tp=-1) == ann.ANN_EINVAL
+    assert q(pc=5) == ann.ANN_EINVAL              # capacity without a buffer
+    assert q(wsb=wsb - 1) == ann.ANN_EINVAL

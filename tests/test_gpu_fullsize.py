@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 N_SAMPLE_ROWS = 16
 N_SAMPLE_QUERIES = 48
-L_BENCH = 152
+L_BENCH = 136     # the benchmark's beam width for recall@10 = 0.95 with GATE entries
 
 
 def _ann():
@@ -110,6 +110,7 @@ def test_hubs_sampled_clusters_at_1m(full):
 
 
 def test_gate_search_in_the_bench_configuration_at_1m(full):
+    from tests.common import near_tie_certificate
     ann = full["ann"]
     from paper_2506_15986_amd import gate
     base, q, g = full["base"], full["q"], full["graph"]
@@ -119,22 +120,34 @@ def test_gate_search_in_the_bench_configuration_at_1m(full):
     tq = torch.from_numpy(synth.train_queries(full["w"])).to(bd.device)
     gm = gate.build_gate(index, tq, full["w"], log=say)
     del tq
-    say("case: entry selection, sampled against the oracle on the GPU embeddings")
+    L_h = int(gm.model.c.L_h)
+    say("case: entry selection for all %d queries against the oracle at the model's L_h = %d"
+        % (nq, L_h))
     ent, sc, bh = ann.ann_entry_select(gm.model, qd, want_score=True)
+    qe_d = gm.qtower.forward(qd)
     torch.cuda.synchronize()
-    ent_h, bh_h = ent.cpu().numpy(), bh.cpu().numpy()
-    s = np.random.default_rng(13).choice(nq, N_SAMPLE_QUERIES, replace=False)
-    qe = gm.qtower.forward(qd[torch.from_numpy(s).to(bd.device)]).cpu().numpy()
-    he = gm.hub_emb.cpu().numpy()
-    ref_ent, ref_cos, ref_bh = oracle.entry_select(qe, he, gm.hub_graph.cpu().numpy(),
-                                                   gm.hub_ids.cpu().numpy(), 32, -np.inf,
+    ent_h, bh_h, qe = ent.cpu().numpy(), bh.cpu().numpy(), qe_d.cpu().numpy()
+    he, hg = gm.hub_emb.cpu().numpy(), gm.hub_graph.cpu().numpy()
+    hub_ids = gm.hub_ids.cpu().numpy()
+    ref_ent, ref_cos, ref_bh = oracle.entry_select(qe, he, hg, hub_ids, L_h, -np.inf,
                                                    index.medoid, gm.hub_entry)
-    cos = qe.astype(np.float64) @ he.astype(np.float64).T
-    for i, qi in enumerate(s):
-        if bh_h[qi] != ref_bh[i]:
-            assert abs(cos[i, bh_h[qi]] - cos[i, ref_bh[i]]) <= 1e-5, qi
-    assert (bh_h[s] == ref_bh).mean() >= 0.95
-    say("case: autotuned plan and graph replay at L=%d" % L_BENCH)
+    assert (ent_h == hub_ids[bh_h]).all()
+    mis = np.flatnonzero(bh_h != ref_bh)
+    say("entry selection: %d of %d best hubs differ from the oracle's" % (mis.size, nq))
+    if mis.size:
+        # the same hub search with traces, for a divergence certificate each
+        md = torch.from_numpy(mis).to(bd.device)
+        tids, _, _, ttr = ann.ann_search(gm.hub_emb, gm.hub_graph, qe_d[md].contiguous(), None,
+                                         gm.hub_entry, 1, L_h, plan=gm.model.c.hub_plan,
+                                         trace_cap=1024)
+        tids, ttr = tids.cpu().numpy(), ttr.cpu().numpy()
+        assert (tids[:, 0] == bh_h[mis]).all()
+        rt = oracle.search(he, hg, qe[mis], gm.hub_entry, 1, L_h, trace_cap=1024)
+        for t in range(mis.size):
+            assert near_tie_certificate(he, hg, qe[mis[t]], gm.hub_entry, L_h, ttr[t],
+                                        rt["trace"][t]), mis[t]
+    assert mis.size <= nq // 100
+    say("case: autotuned plan and graph replay at the benchmark's L = %d" % L_BENCH)
     kk = torch.full((nq,), 10, dtype=torch.int32, device=bd.device)
     LL = torch.full((nq,), L_BENCH, dtype=torch.int32, device=bd.device)
     plan, _ = ann.ann_autotune_search(bd, index.graph, qd, ent, index.medoid, kk, LL, 10, L_BENCH,
@@ -143,23 +156,30 @@ def test_gate_search_in_the_bench_configuration_at_1m(full):
     gx = b.graph_exec(ann.ANN_STAGE_ALL)
     gx.launch()
     torch.cuda.synchronize()
-    ids, dist = b.ids.cpu().numpy(), b.dist.cpu().numpy()
+    ids, dist, st = b.ids.cpu().numpy(), b.dist.cpu().numpy(), b.stats.cpu().numpy()
     assert (b.entry_ids.cpu().numpy() == ent_h).all()
-    say("case: sampled queries against the oracle search (FP32 exact on integers)")
-    ref = oracle.search(base, g, q[s], ent_h[s], 10, L_BENCH)
-    assert (ids[s] == ref["ids"]).all()
-    assert (b.stats.cpu().numpy()[s, 2] == ref["hops"]).all()
+    say("case: all %d queries against the oracle search (FP32 exact on integers)" % nq)
+    ref = oracle.search(base, g, q, ent_h, 10, L_BENCH)
+    assert (ids == ref["ids"]).all()
+    assert (dist.astype(np.float64) == ref["d2"]).all()
+    assert (st[:, 2] == ref["hops"]).all()
+    ok = (st[:, 3] & 1) == 0            # visited table never overflowed: exact counts
+    assert (st[ok, 0] == ref["ndc"][ok]).all()
+    say("case: distance counts of every query with a filter that does not forget")
+    exact = ann.make_plan(**dict(plan.as_dict(), visited_log2=13, filter=ann.ANN_FILTER_ID32,
+                                 waves_per_block=1, waves_per_query=1))
+    xs = ann.ann_search(bd, index.graph, qd, ent, index.medoid, kk, LL, k_max=10,
+                        plan=exact)[2].cpu().numpy()
+    assert ((xs[:, 3] & 1) == 0).all()
+    assert (xs[:, 0] == ref["ndc"]).all() and (xs[:, 2] == ref["hops"]).all()
     say("case: whole-batch properties")
-    assert (ids >= 0).all() and (ids < base.shape[0]).all()
-    exact = ((base[ids.reshape(-1)].astype(np.float64) -
-              np.repeat(q, 10, axis=0).astype(np.float64)) ** 2).sum(1).reshape(nq, 10)
-    assert (dist.astype(np.float64) == exact).all()
     assert ((dist[:, 1:] > dist[:, :-1]) |
             ((dist[:, 1:] == dist[:, :-1]) & (ids[:, 1:] > ids[:, :-1]))).all()
     gt, _ = ann.ann_gt_knn(bd, qd, 10)
     rec = (ids[:, :, None] == gt.cpu().numpy()[:, None, :]).any(-1).mean()
-    say("recall@10 at L=%d: %.4f" % (L_BENCH, rec))
-    assert rec >= 0.94
+    say("recall@10 at L=%d: %.4f (mean ndc %.1f, hops %.1f)" % (L_BENCH, rec, ref["ndc"].mean(),
+                                                                ref["hops"].mean()))
+    assert rec >= 0.949
     gx.close()
 
 

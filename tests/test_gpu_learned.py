@@ -10,7 +10,7 @@ import torch
 import oracle
 from oracle import towers as T
 from paper_2506_15986_amd import synth
-from tests.common import int_index, say, tiny_index
+from tests.common import int_index, say, tiny_index, tower_certificate
 
 pytestmark = pytest.mark.gpu
 
@@ -42,11 +42,23 @@ def test_tower_forward_matches_oracle():
     ix, km, hub_in, qp, hp = _setup()
     ann = _ann()
     say("case: tower forward")
-    t = ann.Tower(*qp)
-    e = t.forward(_dev(ix["q"])).cpu().numpy()
-    ref, _ = T.tower_forward(qp, ix["q"].astype(np.float64), bf16=True)
-    assert np.abs(e - ref).max() < 2e-3
-    assert np.allclose(np.linalg.norm(e, axis=1), 1.0, atol=1e-5)
+    for params, x in ((qp, ix["q"]), (hp, hub_in)):
+        t = ann.Tower(*params)
+        e = t.forward(_dev(x)).cpu().numpy()
+        beyond, cert, unc = tower_certificate(params, x.astype(np.float64), e)
+        say("tower rows beyond 1e-4: %d, certified by BF16 re-rounding of a hidden element: %d"
+            % (beyond, cert))
+        assert not unc, unc
+        assert np.allclose(np.linalg.norm(e, axis=1), 1.0, atol=1e-5)
+    # a larger batch of queries (the 1M x 128 recipe's integers, scaled into
+    # [-1, 1] as the entry model does)
+    xi = int_index()["q"].astype(np.float64)
+    qpi = synth.tower_init(ix["w"], [(128, 128), (64, 128)])
+    t = ann.Tower(*qpi, in_scale=1.0 / 256)
+    e = t.forward(_dev(xi.astype(np.float32))).cpu().numpy()
+    beyond, cert, unc = tower_certificate(qpi, xi, e, in_scale=1.0 / 256)
+    say("integer queries: rows beyond 1e-4: %d, certified: %d" % (beyond, cert))
+    assert not unc, unc
 
 
 def _rel(a, b):
@@ -305,6 +317,68 @@ def test_hop_table_matches_oracle():
     assert (ref == 255).any()
 
 
+def _queues_vs_oracle(ann, H, t_pos, t_neg):
+    Hd = _dev(H)
+    po, pq, no, nq_ = ann.ann_make_queues(Hd, t_pos, t_neg)
+    torch.cuda.synchronize()
+    po, pq, no, nq_ = (t.cpu().numpy() for t in (po, pq, no, nq_))
+    pos, neg = oracle.sample_queues(H, t_pos, t_neg)
+    assert po[0] == 0 and no[0] == 0
+    assert (np.diff(po) == [len(x) for x in pos]).all()
+    assert (np.diff(no) == [len(x) for x in neg]).all()
+    for h in range(H.shape[1]):
+        assert (pq[po[h]:po[h + 1]] == pos[h]).all(), h
+        assert (nq_[no[h]:no[h + 1]] == neg[h]).all(), h
+    return int(po[-1]), int(no[-1])
+
+
+@pytest.mark.parametrize("t_pos,t_neg", [(3, 15), (0, 1), (1, 4), (200, 300)])
+def test_definition4_queues_match_oracle(t_pos, t_neg):
+    # the hop table of 100 hubs over 300 training queries' nearest neighbours,
+    # on the graph without its repair slots (unreachable pairs present), then
+    # a hand table: a hub that reaches no query, ragged tiles (nq = 300 is
+    # not a multiple of 256) and hubs beyond the first 64
+    ann = _ann()
+    ix = int_index()
+    g = np.ascontiguousarray(ix["graph"][:, :-2])
+    r = np.random.default_rng(6)
+    hubs = r.choice(ix["base"].shape[0], 100, replace=False).astype(np.int32)
+    tq = synth.train_queries(ix["w"], 300)
+    targets = oracle.knn(ix["base"], tq, 1)[0][:, 0].astype(np.int32)
+    say("case: Definition 4 queues, t_pos %d, t_neg %d" % (t_pos, t_neg))
+    H = ann.ann_hop_table(_dev(g), _dev(hubs), _dev(targets)).cpu().numpy()
+    assert (H == 255).any()
+    npos, nneg = _queues_vs_oracle(ann, H, t_pos, t_neg)
+    assert npos > 0 and nneg > 0
+    Hh = np.random.default_rng(7).integers(0, 40, size=(300, 70)).astype(np.uint8)
+    Hh[:, 5] = 255                                    # reaches no query: no queues
+    Hh[::3, 66] = 255
+    Hh[17, 66] = 0
+    _queues_vs_oracle(ann, Hh, t_pos, t_neg)
+
+
+def test_fusion_tokens_match_their_definition():
+    # p = x_hub * scale, U_s = (x_w - x_hub) * scale for the neighbour in slot s
+    # (0 and mask 0 for an empty slot); FP32 subtract then an exact power-of-two
+    # scale, so the result is bitwise that of the definition in FP32
+    ann = _ann()
+    ix = int_index()
+    g = ix["graph"].copy()
+    g[::5, -3:] = -1                                  # some empty slots
+    hubs = np.array([0, 17, 19_999, 512, 17], np.int32)
+    scale = 1.0 / 256
+    say("case: fusion tokens")
+    p, U, m = ann.ann_fusion_tokens(_dev(ix["base"]), _dev(g), _dev(hubs), scale)
+    torch.cuda.synchronize()
+    x = ix["base"]
+    nb = g[hubs]
+    want_m = (nb >= 0).astype(np.uint8)
+    want_U = ((x[np.maximum(nb, 0)] - x[hubs][:, None, :]) * np.float32(scale)) * want_m[:, :, None]
+    assert (m.cpu().numpy() == want_m).all()
+    assert (p.cpu().numpy() == x[hubs] * np.float32(scale)).all()
+    assert (U.cpu().numpy() == want_U.astype(np.float32)).all()
+
+
 def test_fusion_forward_backward_match_oracle():
     # 4 heads of 16 channels over 32 tokens of 128 values; ragged masks and
     # one hub without tokens
@@ -351,3 +425,64 @@ def test_train_step_hub_input_gradient_matches_oracle():
     _, _, deh, _ = T.infonce(eq, eh, labels[idx], 0.07)
     ref = T.tower_backward_input(ch, deh, bf16=True)
     assert _rel(dx.cpu().numpy(), ref) <= 1e-3
+
+
+def test_labels_dead_end_graph_by_hand():
+    # the hand-traced graph of the oracle's pins: from E the widths 1 and 2
+    # stall at a dead end, width 4 reaches the true neighbour with 7 distance
+    # computations (width 8 would cost 8); from F width 1 reaches it with 4
+    from tests.test_oracle_search import _dead_end_graph
+    base, g, q = _dead_end_graph()
+    say("case: labels on the hand-traced dead-end graph")
+    lab, tab, flags = _ann().ann_make_labels(_dev(base), _dev(g), _dev(q), _dev(np.array([[0]], np.int32)),
+                                             1, _dev(np.array([[0, 1]], np.int32)),
+                                             _dev(np.array([1, 5, 4], np.int32)), [1, 2, 4, 8])
+    torch.cuda.synchronize()
+    assert tab.cpu().numpy().tolist() == [[7, 4]]
+    assert lab.cpu().numpy().tolist() == [1] and flags.cpu().numpy().tolist() == [0]
+    lab, tab, _ = _ann().ann_make_labels(_dev(base), _dev(g), _dev(q), _dev(np.array([[0]], np.int32)),
+                                         1, _dev(np.array([[2, 0]], np.int32)),
+                                         _dev(np.array([1, 5, 4], np.int32)), [1, 2])
+    torch.cuda.synchronize()
+    assert tab.cpu().numpy().tolist() == [[-1, -1]] and lab.cpu().numpy().tolist() == [2]
+
+
+def test_trained_entry_beats_untrained_towers_and_medoid():
+    # What the trained network gains over the method without it (the paper's
+    # ablation without the learned part): the same index, hubs, features and
+    # labels, one entry model trained and one left at its initial weights,
+    # and the plain method's medoid entry, compared on held-out test queries
+    # at fixed beam widths.  200,000 points of the 1M x 128 recipe (256
+    # components), 256 hubs, 30,000 training queries, 2,000 test queries.
+    ann = _ann()
+    from paper_2506_15986_amd import gate
+    w = synth.scaled(synth.WORKLOADS["sift1m"], n=200_000, n_queries=2_000, n_train=30_000)
+    dev = torch.device("cuda:0")
+    say("case: gain test: data, graph, hubs, labels (200k x 128)")
+    bd = torch.from_numpy(synth.base(w)).to(dev)
+    qd = torch.from_numpy(synth.queries(w)).to(dev)
+    tq = torch.from_numpy(synth.train_queries(w)).to(dev)
+    index = gate.build_index(bd, 128, 32, 1.2)
+    data = gate.prepare_gate(index, tq, w, n_hubs=256, log=say)
+    say("case: gain test: trained and untrained towers")
+    trained = gate.train_gate(index, data, tq, w, epochs=20, log=say)
+    untrained = gate.train_gate(index, data, tq, w, train=False, log=say)
+    gt = ann.ann_gt_knn(bd, qd, 10)[0].cpu().numpy()
+    rows = {}
+    for name, ent in (("trained", trained.select(qd)[0]), ("untrained", untrained.select(qd)[0]),
+                      ("medoid", None)):
+        for L in (32, 64, 128):
+            ids, _, st, _ = index.search(qd, L, 10, ent)
+            rec = float((ids.cpu().numpy()[:, :, None] == gt[:, None, :]).any(-1).mean())
+            rows[name, L] = (rec, float(st[:, 0].float().mean().item()))
+    say("gain test (recall@10, mean ndc): %s" % rows)
+    say("held-out label agreement: trained %.3f, untrained %.3f" %
+        (trained.info["val_top1"], untrained.info["val_top1"]))
+    assert trained.info["val_top1"] >= untrained.info["val_top1"] + 0.2
+    for L in (32, 64, 128):
+        rt = rows["trained", L][0]
+        assert rt >= rows["untrained", L][0] + 0.2, L
+        assert rt >= rows["medoid", L][0] + 0.2, L
+    # the trained entry reaches at L = 64 at least the recall that the other
+    # two do not reach at twice that width
+    assert rows["trained", 64][0] > max(rows["untrained", 128][0], rows["medoid", 128][0])

@@ -471,3 +471,13 @@ def test_tower_input_gradient_matches_finite_differences():
         x2[idx] -= 2 * eps
         lm = (towers.tower_forward(params, x2, bf16=False, in_scale=0.5)[0] * de).sum()
         assert np.isclose((lp - lm) / (2 * eps), dx[idx], rtol=1e-5, atol=1e-8)
+
+
+def test_sample_queues_hand_table():
+    # hub 0: hops (2, 5, 255, 3, 20) -> m = 2; t_pos 1: positives H <= 3 ->
+    # queries 0, 3; t_neg 10: negatives H >= 12 or unreachable -> 2, 4.
+    # hub 1 reaches no query: neither queue.  hub 2: all at 0 -> all positive
+    H = np.array([[2, 255, 0], [5, 255, 0], [255, 255, 0], [3, 255, 0], [20, 255, 0]], np.uint8)
+    pos, neg = oracle.sample_queues(H, 1, 10)
+    assert [p.tolist() for p in pos] == [[0, 3], [], [0, 1, 2, 3, 4]]
+    assert [n.tolist() for n in neg] == [[2, 4], [], []]
