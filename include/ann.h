@@ -156,6 +156,31 @@ ann_status ann_search(const float *base, int64_t n, int32_t dim,
                       void *workspace, size_t ws_bytes, void *stream);
 
 
+/* ann_search without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and errors are those of ann_search;
+ * the scratch that ann_search takes from `workspace` (the persistent
+ * launch's work counter, and the widest-first query order with its keys)
+ * lives instead in a fixed array inside this library: 256 bytes + 8 bytes per
+ * query for up to ANN_NOALLOC_MAX_QUERIES queries (about 8 MiB), one copy
+ * per GPU, resolved on the first call on each device and held until the
+ * process ends.  The call allocates nothing (no hipMalloc, no allocating
+ * library routine).  nq above ANN_NOALLOC_MAX_QUERIES returns ANN_EINVAL.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (the counter is cleared by a kernel at the start of each call):
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads) race and give undefined results; serialise them on one stream. */
+enum { ANN_NOALLOC_MAX_QUERIES = 1 << 20 };
+
+ann_status ann_search_noalloc(const float *base, int64_t n, int32_t dim,
+                              const int32_t *graph, int32_t R,
+                              const float *queries, int32_t nq,
+                              const int32_t *entry_ids, int32_t medoid,
+                              const int32_t *k, const int32_t *L, int32_t k_max,
+                              int32_t *out_ids, float *out_dist, int32_t *stats,
+                              int32_t *trace, int32_t trace_cap,
+                              const ann_search_plan *plan, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Graph construction (the proximity graph G of Definition 1).              */
 

@@ -73,6 +73,11 @@ _sig("ann_search", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _I32, _P, _P, _
      _P, _I32, ctypes.POINTER(ann_search_plan), _P, _SZ, _P)
 
 
+_sig("ann_search_noalloc", _I32, _P, _I64, _I32, _P, _I32, _P, _I32, _P, _I32, _P, _P, _I32, _P,
+     _P, _P, _P, _I32, ctypes.POINTER(ann_search_plan), _P)
+ANN_NOALLOC_MAX_QUERIES = 1 << 20
+
+
 _sig("ann_gt_knn", _I32, _P, _I64, _I32, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P)
 _sig("ann_medoid", _I32, _P, _I64, _I32, ctypes.POINTER(_I32), _P, _SZ, _P)
 _sig("ann_build_graph", _I32, _P, _I64, _I32, _I32, _I32, _F32, _P, ctypes.POINTER(_I32),
@@ -210,6 +215,32 @@ def ann_search(base: torch.Tensor, graph: torch.Tensor, queries: torch.Tensor,
                            ctypes.byref(plan) if plan is not None else None,
                            _ptr(ws), ws.numel(), _stream(stream)))
     return ids, dist, stats, trace
+
+
+def ann_search_noalloc(base: torch.Tensor, graph: torch.Tensor, queries: torch.Tensor,
+                       entry_ids: torch.Tensor | None, medoid: int, k: torch.Tensor,
+                       L: torch.Tensor, k_max: int, out, plan: ann_search_plan | None = None,
+                       trace=None, stream=None):
+    """ann_search without a workspace: the library's fixed scratch array
+    serves as the work counter and query order (at most
+    ANN_NOALLOC_MAX_QUERIES queries).  k and L are int32 device tensors; the
+    outputs (ids, dist, stats or None) are caller tensors, filled in place;
+    trace is an int32 [nq, trace_cap] tensor or None.  Allocates nothing."""
+    _dev(base, torch.float32)
+    _dev(graph, torch.int32)
+    _dev(queries, torch.float32)
+    n, dim = base.shape
+    nq = queries.shape[0]
+    ids, dist, stats = out
+    if entry_ids is not None:
+        _dev(entry_ids, torch.int32)
+    _check(_lib.ann_search_noalloc(_ptr(base), n, dim, _ptr(graph), graph.shape[1], _ptr(queries),
+                                   nq, _ptr(entry_ids), int(medoid), _ptr(k), _ptr(L), int(k_max),
+                                   _ptr(ids), _ptr(dist), _ptr(stats), _ptr(trace),
+                                   int(trace.shape[1]) if trace is not None else 0,
+                                   ctypes.byref(plan) if plan is not None else None,
+                                   _stream(stream)))
+    return ids, dist, stats
 
 
 def ann_gt_knn(base: torch.Tensor, queries: torch.Tensor, k: int, exclude_self: bool = False,

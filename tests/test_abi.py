@@ -295,3 +295,15 @@ def test_queue_builder_rejects_bad_arguments_on_the_host(lib):
     assert q(tp=-1) == ann.ANN_EINVAL
     assert q(pc=5) == ann.ANN_EINVAL              # capacity without a buffer
     assert q(wsb=wsb - 1) == ann.ANN_EINVAL
+
+
+def test_noalloc_search_rejects_bad_arguments_on_the_host(lib):
+    from paper_2506_15986_amd import ann
+    fake = ctypes.c_void_p(0x10000)      # never dereferenced: validation fails first
+    big = ann.ANN_NOALLOC_MAX_QUERIES + 1
+    st = ann._lib.ann_search_noalloc(fake, 1000, 32, fake, 16, fake, big, None, 0, fake, fake, 10,
+                                     fake, fake, None, None, 0, None, None)
+    assert st == ann.ANN_EINVAL and "at most" in ann.last_error()
+    st = ann._lib.ann_search_noalloc(fake, 1000, 32, fake, 16, fake, -1, None, 0, fake, fake, 10,
+                                     fake, fake, None, None, 0, None, None)
+    assert st == ann.ANN_EINVAL
