@@ -1035,6 +1035,20 @@ class QueryBatch:
             _ptr(self.entry_ws), self.entry_ws.numel() if self.entry_ws is not None else 0,
             _ptr(self.search_ws), self.search_ws.numel())
 
+    def rebind(self, queries, k, L, entry_ids, ids, dist):
+        """Points the batch at other rows of the same shape (device tensors
+        whose row count is at most the one the workspaces were sized for):
+        the queries, their k and L, the entry ids and the outputs."""
+        nq = queries.shape[0]
+        assert nq <= self.queries.shape[0], "rebind: more rows than the batch was sized for"
+        for t in (queries, k, L, ids, dist) + ((entry_ids,) if entry_ids is not None else ()):
+            assert t.is_cuda and t.is_contiguous()
+        self.c.queries, self.c.k, self.c.L = _ptr(queries), _ptr(k), _ptr(L)
+        self.c.entry_ids = _ptr(entry_ids) if entry_ids is not None else self.c.entry_ids
+        self.c.out_ids, self.c.out_dist, self.c.stats = _ptr(ids), _ptr(dist), None
+        self.c.nq = nq
+        self._bound = (queries, k, L, entry_ids, ids, dist)     # kept alive with the batch
+
     def run(self, stages: int = ANN_STAGE_ALL, stream=None):
         _check(_lib.ann_query_run(ctypes.byref(self.c), stages, _stream(stream)))
         return self.ids, self.dist, self.stats

@@ -24,8 +24,6 @@ constexpr uint32_t kExpanded = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 constexpr int kMaxProbe = 32;
 
-enum Metric { L2 = 0, NEG_IP = 1 };
-
 template <bool F64> struct Key;
 template <> struct Key<false> {
     using K = uint32_t;

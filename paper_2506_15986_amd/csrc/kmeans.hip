@@ -13,6 +13,7 @@
 // after an assignment step that changes nothing, or after `iters` steps.
 // Hub of a cluster: the member nearest its mean by (d2, id); an empty
 // cluster takes the nearest point that is not yet a hub (cluster order).
+#include <cmath>
 #include <vector>
 
 #include "common.h"
@@ -30,6 +31,14 @@ __device__ inline double term(float x, double m)
 #pragma clang fp contract(off)
     double t = (double)x - m;
     return t * t;
+}
+
+__device__ inline double d2_to(const float *x, const double *m, int dim)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int j = 0; j < dim; ++j) s = s + term(x[j], m[j]);
+    return s;
 }
 
 __global__ void __launch_bounds__(256) assign_kernel(const float *base, int64_t n, int dim,
@@ -98,6 +107,219 @@ __global__ void __launch_bounds__(256) assign_kernel(const float *base, int64_t 
     }
 }
 
+// ---- assignment on the matrix cores, with a certified shortlist.
+//
+// The step above spends 3 FP64 operations per (point, centroid, dimension).
+// Here the matrix cores compute the dot products x . mu~ in FP32
+// (v_mfma_f32_16x16x4_f32; mu~ = the FP32 rounding of the FP64 centroid) and
+// each pair gets the estimate s = (|x|^2 + |mu|^2) - 2 x . mu~ in FP32 with a
+// rigorous bound E on its distance from the FP64 distance of the plain
+// step (coefficients ea, eb from the host: FP32 rounding of the norms, of mu~,
+// of the dot product's accumulation over dim terms and of s itself).  Every
+// centroid whose lower bound s - E does not exceed the smallest upper bound
+// s + E of the point is kept on a shortlist (the plain step's argmin is
+// always on it); the point then takes its only candidate, or the plain
+// step's FP64 argmin over its few candidates, or -- when more than MLIST
+// centroids tie that closely (repeated centroids) -- over all centroids.
+// The result is the plain step's assignment bit for bit.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int MP = 64;     // points per block (16 per wavefront)
+constexpr int MC = 64;     // centroids per pass (four 16-wide MFMA tiles)
+constexpr int MK = 32;     // dimensions per LDS stage
+constexpr int MLIST = 8;   // shortlist capacity per point
+
+struct ShortArgs {
+    const float *base;
+    int64_t n;
+    int dim;
+    const double *mu;      // nh x dim FP64 centroids
+    const float *mu32;     // their FP32 rounding
+    const float *cn2;      // |mu|^2 per centroid (FP64 sum, rounded to FP32)
+    const float *cn;       // |mu|
+    const float *xn2;      // |x|^2 per point
+    const float *xn;       // |x|
+    int nh;
+    float ea, eb;          // E = ea (|x|^2 + |mu|^2) + eb |x| |mu|
+    int32_t *assign;
+    int32_t *changed;
+};
+
+__global__ void point_norms_kernel(const float *base, int64_t n, int dim, float *xn2, float *xn)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < dim; ++j) {
+        const double v = base[i * dim + j];
+        s = s + v * v;
+    }
+    xn2[i] = (float)s;
+    xn[i] = (float)sqrt(s);
+}
+
+__global__ void centroid_prep_kernel(const double *mu, int nh, int dim, float *mu32, float *cn2,
+                                     float *cn)
+{
+#pragma clang fp contract(off)
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nh) return;
+    double s = 0.0;
+    for (int j = 0; j < dim; ++j) {
+        const double v = mu[(int64_t)c * dim + j];
+        mu32[(int64_t)c * dim + j] = (float)v;
+        s = s + v * v;
+    }
+    cn2[c] = (float)s;
+    cn[c] = (float)sqrt(s);
+}
+
+__global__ void __launch_bounds__(256) assign_mfma_kernel(ShortArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ float xs[MP][MK + 1];
+    __shared__ float ms[MC][MK + 1];
+    __shared__ float U[MP];
+    __shared__ int cnt[MP];
+    __shared__ int lc[MP][MLIST];
+    __shared__ float ll[MP][MLIST];
+    const float inf = __builtin_inff();
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int64_t p0 = (int64_t)blockIdx.x * MP;
+    if (t < MP) {
+        U[t] = inf;
+        cnt[t] = 0;
+    }
+    // this lane's rows of the 16 x 16 output tiles: points 16w + 4 (lane >> 4) + i
+    float X[4], XN[4];
+    bool live[4];
+    for (int i = 0; i < 4; ++i) {
+        const int64_t pi = p0 + 16 * w + 4 * (lane >> 4) + i;
+        live[i] = pi < a.n;
+        X[i] = live[i] ? a.xn2[pi] : 0.f;
+        XN[i] = live[i] ? a.xn[pi] : 0.f;
+    }
+    for (int c0 = 0; c0 < a.nh; c0 += MC) {
+        v4f acc[4];
+        for (int b = 0; b < 4; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < a.dim; k0 += MK) {
+            __syncthreads();
+            for (int e = t; e < MP * (MK / 4); e += 256) {
+                const int r = e / (MK / 4), j = 4 * (e % (MK / 4));
+                const int64_t gi = p0 + r;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gi < a.n && k0 + j < a.dim)
+                    v = *reinterpret_cast<const float4 *>(a.base + gi * a.dim + k0 + j);
+                xs[r][j] = v.x;
+                xs[r][j + 1] = v.y;
+                xs[r][j + 2] = v.z;
+                xs[r][j + 3] = v.w;
+                const int c = c0 + r;
+                float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (c < a.nh && k0 + j < a.dim)
+                    m = *reinterpret_cast<const float4 *>(a.mu32 + (int64_t)c * a.dim + k0 + j);
+                ms[r][j] = m.x;
+                ms[r][j + 1] = m.y;
+                ms[r][j + 2] = m.z;
+                ms[r][j + 3] = m.w;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < MK / 4; ++q) {
+                const float av = xs[16 * w + (lane & 15)][4 * q + (lane >> 4)];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float bv = ms[16 * b + (lane & 15)][4 * q + (lane >> 4)];
+                    acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[b], 0, 0, 0);
+                }
+            }
+        }
+        // bounds of this pass's pairs; the smallest upper bound per point
+        float lo[4][4], hmin[4];
+        for (int i = 0; i < 4; ++i) {
+            hmin[i] = inf;
+            for (int b = 0; b < 4; ++b) {
+                const int c = c0 + 16 * b + (lane & 15);
+                lo[i][b] = inf;
+                if (!live[i] || c >= a.nh) continue;
+                const float C = a.cn2[c];
+                const float s1 = X[i] + C;
+                const float sv = s1 - 2.f * acc[b][i];
+                const float e1 = a.ea * s1;
+                const float e2 = a.eb * (XN[i] * a.cn[c]);
+                const float E = e1 + e2;
+                lo[i][b] = sv - E;
+                const float hv = sv + E;
+                hmin[i] = hv < hmin[i] ? hv : hmin[i];
+            }
+            for (int o = 1; o < 16; o <<= 1) {
+                const float h2 = __shfl_xor(hmin[i], o);
+                hmin[i] = h2 < hmin[i] ? h2 : hmin[i];
+            }
+        }
+        __syncthreads();
+        if ((lane & 15) == 0)
+            for (int i = 0; i < 4; ++i) {
+                const int P = 16 * w + 4 * (lane >> 4) + i;
+                if (hmin[i] < U[P]) U[P] = hmin[i];
+            }
+        __syncthreads();
+        // drop candidates whose lower bound now exceeds the point's bound
+        if (t < MP && cnt[t] <= MLIST) {
+            int m = 0;
+            for (int r = 0; r < cnt[t]; ++r)
+                if (ll[t][r] <= U[t]) {
+                    lc[t][m] = lc[t][r];
+                    ll[t][m] = ll[t][r];
+                    ++m;
+                }
+            cnt[t] = m;
+        }
+        __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+            const int P = 16 * w + 4 * (lane >> 4) + i;
+            const float u = U[P];
+            for (int b = 0; b < 4; ++b)
+                if (lo[i][b] <= u && lo[i][b] < inf) {
+                    const int slot = atomicAdd(&cnt[P], 1);
+                    if (slot < MLIST) {
+                        lc[P][slot] = c0 + 16 * b + (lane & 15);
+                        ll[P][slot] = lo[i][b];
+                    }
+                }
+        }
+    }
+    __syncthreads();
+    if (t >= MP) return;
+    const int64_t i = p0 + t;
+    if (i >= a.n) return;
+    const float *x = a.base + i * a.dim;
+    int bc;
+    if (cnt[t] == 1) {
+        bc = lc[t][0];
+    } else {
+        // the plain step's FP64 argmin, over the shortlist or (when it
+        // overflowed) over every centroid
+        const bool all = cnt[t] > MLIST || cnt[t] == 0;
+        const int m = all ? a.nh : cnt[t];
+        double bv = __longlong_as_double(0x7ff0000000000000ll);
+        bc = 0x7fffffff;
+        for (int r = 0; r < m; ++r) {
+            const int c = all ? r : lc[t][r];
+            const double v = d2_to(x, a.mu + (int64_t)c * a.dim, a.dim);
+            if (v < bv || (v == bv && c < bc)) {
+                bv = v;
+                bc = c;
+            }
+        }
+    }
+    if (a.assign[i] != bc) {
+        a.assign[i] = bc;
+        *a.changed = 1;
+    }
+}
+
 __global__ void accumulate_kernel(const float *base, int64_t n, int dim, const int32_t *assign,
                                   double *sums, int64_t *count)
 {
@@ -116,14 +338,6 @@ __global__ void update_kernel(const double *sums, const int64_t *count, int nh, 
     if (e >= (int64_t)nh * dim) return;
     const int64_t c = e / dim;
     if (count[c] > 0) mu[e] = sums[e] / (double)count[c];
-}
-
-__device__ inline double d2_to(const float *x, const double *m, int dim)
-{
-#pragma clang fp contract(off)
-    double s = 0.0;
-    for (int j = 0; j < dim; ++j) s = s + term(x[j], m[j]);
-    return s;
 }
 
 __global__ void hub_min_kernel(const float *base, int64_t n, int dim, const double *mu,
@@ -372,6 +586,9 @@ size_t select_hubs_ws(int64_t n, int dim, int nh)
     b += round_up((size_t)nh * 8, 256) * 2;                   // count, best bits
     b += round_up((size_t)n * 4, 256) * 2;                    // assign, taken
     b += round_up(4096 * sizeof(Best), 256) + 1024;
+    b += round_up((size_t)nh * dim * 4, 256);                 // FP32 centroids
+    b += round_up((size_t)nh * 4, 256) * 2;                   // their norms
+    b += round_up((size_t)n * 4, 256) * 2;                    // point norms
     return b;
 }
 
@@ -390,6 +607,28 @@ ann_status select_hubs_run(const float *base, int64_t n, int dim, int nh, int it
     int32_t *taken = cv.take<int32_t>((size_t)n);
     Best *partial = cv.take<Best>(4096);
     int32_t *changed = cv.take<int32_t>(64);
+    float *mu32 = cv.take<float>((size_t)nh * dim);
+    float *cn2 = cv.take<float>((size_t)nh);
+    float *cn = cv.take<float>((size_t)nh);
+    float *xn2 = cv.take<float>((size_t)n);
+    float *xn = cv.take<float>((size_t)n);
+    // the matrix-core assignment needs whole float4 rows
+    const bool mfma = dim % 4 == 0 && aligned(base, 16);
+    ShortArgs sa{};
+    if (mfma) {
+        hipLaunchKernelGGL(point_norms_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           base, n, dim, xn2, xn);
+        ANN_LAUNCHED();
+        // bound coefficients (unit roundoff u = 2^-24): the norms and mu~ are
+        // FP32 roundings, the dot product accumulates dim FP32 terms (gamma),
+        // s and the bounds themselves add a few roundings; margins of >= 30 %
+        const double u = std::ldexp(1.0, -24);
+        const double K = (double)dim + 2.0;
+        const double gam = K * u / (1.0 - K * u);
+        const double gp = gam * (1.0 + u) + u;
+        sa = ShortArgs{base, n, dim, nullptr, mu32, cn2, cn, xn2, xn, nh,
+                       (float)(8.0 * u), (float)(2.1 * gp + 12.0 * u), nullptr, changed};
+    }
 
     const int64_t md = (int64_t)nh * dim;
     hipLaunchKernelGGL(init_mu_kernel, dim3(grid_for(md, 256, 1 << 20)), dim3(256), 0, st, base, dim,
@@ -401,8 +640,18 @@ ann_status select_hubs_run(const float *base, int64_t n, int dim, int nh, int it
     for (int t = 0; t < iters; ++t) {
         hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, changed, 1, 0);
         ANN_LAUNCHED();
-        hipLaunchKernelGGL(assign_kernel, dim3((unsigned)((n + KP - 1) / KP)), dim3(256), 0, st, base,
-                           n, dim, mu, nh, assign, changed);
+        if (mfma) {
+            hipLaunchKernelGGL(centroid_prep_kernel, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0,
+                               st, mu, nh, dim, mu32, cn2, cn);
+            ANN_LAUNCHED();
+            sa.mu = mu;
+            sa.assign = assign;
+            hipLaunchKernelGGL(assign_mfma_kernel, dim3((unsigned)((n + MP - 1) / MP)), dim3(256), 0,
+                               st, sa);
+        } else {
+            hipLaunchKernelGGL(assign_kernel, dim3((unsigned)((n + KP - 1) / KP)), dim3(256), 0, st,
+                               base, n, dim, mu, nh, assign, changed);
+        }
         ANN_LAUNCHED();
         ++steps;
         hipLaunchKernelGGL(fill_f64, dim3(grid_for(md)), dim3(256), 0, st, sums, md);

@@ -388,9 +388,26 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) {
                 v4i acc = {0, 0, 0, 0};
+                // pairs of 32-byte k-steps on the 64-deep CDNA4 instruction:
+                // each lane's 16 bytes are its two 8-byte chunks, the same
+                // (row or column, k) correspondence for both operands, so the
+                // integer dot product is unchanged
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-                    acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(areg[rb][ks], bf[ks], acc, 0, 0, 0);
+                for (int ks = 0; ks + 1 < KS; ks += 2) {
+                    const v4i av = {(int)areg[rb][ks], (int)(areg[rb][ks] >> 32),
+                                    (int)areg[rb][ks + 1], (int)(areg[rb][ks + 1] >> 32)};
+                    const v4i bv = {(int)bf[ks], (int)(bf[ks] >> 32), (int)bf[ks + 1],
+                                    (int)(bf[ks + 1] >> 32)};
+                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc, 0, 0, 0);
+                }
+                if (KS & 1) {
+                    // the odd last chunk with zeros beside it (the same
+                    // instruction throughout: mixing the 32- and 64-deep forms
+                    // on one accumulator gave wrong sums on the GPU)
+                    const v4i av = {(int)areg[rb][KS - 1], (int)(areg[rb][KS - 1] >> 32), 0, 0};
+                    const v4i bv = {(int)bf[KS - 1], (int)(bf[KS - 1] >> 32), 0, 0};
+                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc, 0, 0, 0);
+                }
                 bool p[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) p[i] = 2 * acc[i] - bnc > tv[rb][i];

@@ -32,7 +32,7 @@ template <int G, int CPL, bool F64, int FILT>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    using S = Searcher<G, CPL, F64, L2, FILT>;
+    using S = Searcher<G, CPL, F64, FILT>;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     S s;

@@ -49,7 +49,7 @@ inline size_t wave_lds_bytes(int pool_cap, const beam::FilterShape &f, bool f64,
     return (b + 15) / 16 * 16;
 }
 
-template <int G, int CPL, bool F64, int METRIC, int FILT>
+template <int G, int CPL, bool F64, int FILT>
 struct Searcher {
     using KT = beam::Key<F64>;
     using K = typename KT::K;
@@ -119,12 +119,8 @@ struct Searcher {
 
     __device__ static inline D partial(const float4 &x, const float4 &y)
     {
-        if (METRIC == beam::L2) {
-            D a = (D)x.x - (D)y.x, b = (D)x.y - (D)y.y, c = (D)x.z - (D)y.z, d = (D)x.w - (D)y.w;
-            return a * a + b * b + c * c + d * d;
-        } else {
-            return (D)x.x * (D)y.x + (D)x.y * (D)y.y + (D)x.z * (D)y.z + (D)x.w * (D)y.w;
-        }
+        D a = (D)x.x - (D)y.x, b = (D)x.y - (D)y.y, c = (D)x.z - (D)y.z, d = (D)x.w - (D)y.w;
+        return a * a + b * b + c * c + d * d;
     }
 
     // keys of the m candidates si[0..m) into sk[0..m); with W waves sharing
@@ -176,7 +172,7 @@ struct Searcher {
                     }
                     acc = beam::group_sum<G>(acc);
                     const int c = cb + gi;
-                    if (gl == 0 && c < m) sk[c] = KT::of(METRIC == beam::L2 ? acc : -acc);
+                    if (gl == 0 && c < m) sk[c] = KT::of(acc);
                 }
             }
         }
@@ -471,8 +467,7 @@ struct Searcher {
             float dv = __int_as_float(0x7f800000);
             if (t < kq && t < cnt) {
                 id = (int32_t)(ai[t] & beam::kIdMask);
-                float v = KT::value(ak[t]);
-                dv = METRIC == beam::L2 ? v : -v;
+                dv = KT::value(ak[t]);
             }
             oid[t] = id;
             odist[t] = dv;

@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) search_mw_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int ctrl[2];
-    using S = Searcher<16, CPL, false, L2, FILT>;
+    using S = Searcher<16, CPL, false, FILT>;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     S s;

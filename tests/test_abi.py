@@ -297,6 +297,33 @@ def test_queue_builder_rejects_bad_arguments_on_the_host(lib):
     assert q(wsb=wsb - 1) == ann.ANN_EINVAL
 
 
+def test_serving_row_pool_first_fit_and_merge():
+    # the serving loop's row allocator: ranges never overlap, freed ranges
+    # merge with their neighbours, and the pool's use is the rows held
+    import random
+    from paper_2506_15986_amd.serve import RowPool
+    p = RowPool(100)
+    assert p.alloc(30) == 0 and p.alloc(30) == 30 and p.alloc(50) == -1 and p.largest() == 40
+    p.release(0, 30)
+    assert p.free == [(0, 30), (60, 40)]
+    p.release(30, 30)
+    assert p.free == [(0, 100)]
+    held = []
+    rnd = random.Random(1)
+    for _ in range(3000):
+        if held and rnd.random() < 0.5:
+            p.release(*held.pop(rnd.randrange(len(held))))
+        else:
+            n = rnd.randint(1, 30)
+            st = p.alloc(n)
+            if st >= 0:
+                assert all(st + n <= a or a + b <= st for a, b in held)
+                held.append((st, n))
+        fr = p.free
+        assert all(fr[i][0] + fr[i][1] < fr[i + 1][0] for i in range(len(fr) - 1))
+        assert p.in_use() == sum(b for _, b in held)
+
+
 def test_noalloc_search_rejects_bad_arguments_on_the_host(lib):
     from paper_2506_15986_amd import ann
     fake = ctypes.c_void_p(0x10000)      # never dereferenced: validation fails first

@@ -35,6 +35,36 @@ def test_select_hubs_bit_exact(which, nh):
     assert (hub.cpu().numpy() == ref["hub_ids"]).all()
 
 
+@pytest.mark.parametrize("case", ["repeated", "wide", "odd_dim"])
+def test_select_hubs_bit_exact_special_shapes(case):
+    # repeated: 5 distinct rows behind 3,000 points and 64 centroids, so many
+    # centroids coincide (exact ties, shortlists longer than their capacity:
+    # the all-centroid fallback); wide: 960 dimensions (30 LDS stages per
+    # pass) on the 2^-14 grid; odd_dim: 6 dimensions (no float4 rows: the
+    # FP64 assignment kernel)
+    r = np.random.default_rng(31)
+    if case == "repeated":
+        rows = r.integers(0, 256, size=(5, 64)).astype(np.float32)
+        base = rows[r.integers(0, 5, size=3000)]
+        nh = 64
+    elif case == "wide":
+        w = synth.scaled(synth.WORKLOADS["gist1m"], n=2000)
+        base = synth.base(w)
+        nh = 40
+    else:
+        base = (np.rint(r.normal(0, 4, size=(3000, 6)) * 2 ** 12) / 2 ** 12).astype(np.float32)
+        nh = 24
+    init = r.choice(base.shape[0], nh, replace=False).astype(np.int32)
+    say("case: select_hubs %s" % case)
+    ref = oracle.kmeans_hubs(base, nh, 20, init)
+    hub, cen, asg, steps = _ann().ann_select_hubs(_dev(base), nh, 20, _dev(init))
+    torch.cuda.synchronize()
+    assert steps == ref["steps"]
+    assert (asg.cpu().numpy() == ref["assign"]).all()
+    assert (cen.cpu().numpy() == ref["centroids"]).all()
+    assert (hub.cpu().numpy() == ref["hub_ids"]).all()
+
+
 def test_select_hubs_empty_cluster():
     x = np.zeros((8, 4), np.float32)
     x[:, 0] = [0, 0, 10, 11, 0, 0, 10, 11]

@@ -58,3 +58,29 @@ def test_rejects_requests_that_do_not_fit():
         srv.submit(serve.Request(1, ix["q"][:2], 10, 64))
     with pytest.raises(ValueError):
         srv.submit(serve.Request(2, ix["q"][:2], 11, 10))
+
+
+def test_admission_is_by_rows_of_the_pool():
+    # a 64-row pool, launches of at most 40 rows and 4 streams: two 40-row
+    # requests cannot share the pool, so they run one at a time although
+    # streams are free; 16-row requests go two to a launch (32 rows) and two
+    # launches fit in the pool at once; results equal the alone runs
+    from paper_2506_15986_amd import ann, serve
+    ix = tiny_index()
+    w = synth.scaled(ix["w"], n_queries=640)
+    qs = synth.queries(w)
+    base, g = _dev(ix["base"]), _dev(ix["graph"])
+    for b, most in ((40, 1), (16, 2)):
+        sched = [serve.Request(i, qs[i * b:(i + 1) * b], 10, 32, 0.0) for i in range(640 // b)]
+        srv = serve.Server(base, g, ix["medoid"], slots=4, slot_rows=40, pool_rows=64, k_max=10,
+                           L_max=32)
+        say("case: pool of 64 rows, launches of <= 40, requests of %d rows" % b)
+        st = srv.serve(sched)
+        say("stats: %s" % st)
+        assert st["requests"] == len(sched)
+        assert st["max_rows_in_use"] <= 64
+        assert st["max_slots_busy"] == most
+        for r in sched:
+            ids, _, _, _ = ann.ann_search(base, g, _dev(r.queries), None, ix["medoid"], 10, 32,
+                                          plan=srv.plan)
+            assert (ids.cpu().numpy() == r.ids).all(), r.rid
