@@ -133,6 +133,17 @@ def recall_tie_aware(dist: np.ndarray, truth_dist: np.ndarray, k: int = 10) -> n
     return (dist[:, :k].astype(np.float64) <= lim + 1e-5 * np.maximum(lim, 1e-6)).sum(1) / float(k)
 
 
+def serving_summary(sv):
+    """The serving leg's headline figures for the summary line."""
+    if not sv:
+        return None
+    half = next((x for x in sv["loads"] if abs(x["offered_qps"] / sv["capacity_qps"] - 0.5) < 0.05),
+                None)
+    return dict(capacity_qps=sv["capacity_qps"], theta=sv["theta"], fallbacks=sv["fallbacks"],
+                half_load=dict(qps=half["qps"], p50_ms=half["p50_ms"], p99_ms=half["p99_ms"],
+                               served_recall=half["served_recall"]) if half else None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,7 +447,7 @@ def main():
             g_entry.close()
         return res
 
-    def serving(model, L):
+    def serving(gm, L):
         """Continuous batching under Poisson arrivals.  Requests of 1..512
         queries from the same mixture with 30 % drawn around shifted means
         (out of distribution), k = 10 or 100 (even odds), each k with the
@@ -452,6 +463,15 @@ def main():
         qm = synth.queries(wm)
         qm_d = torch.from_numpy(qm).to(dev)
         gt100 = ann.ann_gt_knn(base_d, qm_d, 100)[0].cpu().numpy()
+        model = gm.model
+        # the medoid fallback's threshold, tuned on 10,000 training queries
+        # of the same mix at the headline width
+        tq_mix = torch.from_numpy(synth.train_queries(wm, 10000)).to(dev)
+        theta, theta_rows = gate.tune_theta(index, gm, tq_mix, ann.ann_gt_knn(base_d, tq_mix, 10)[0],
+                                            L)
+        log("serving: medoid fallback threshold %s (recall@10 at L=%d per threshold, fallbacks: %s)"
+            % (theta, L, theta_rows))
+        del tq_mix
         em = ann.ann_entry_select(model, qm_d)[0]
         nqm = qm.shape[0]
         Lk = {}
@@ -479,7 +499,9 @@ def main():
         log("serving plan (tuned on the mix): %s" % splan)
         srv = serve.Server(base_d, index.graph, index.medoid, model=model, slots=4,
                            slot_rows=4096, k_max=100, L_max=Lmax, plan=splan)
-        out = dict(mix="30% shifted queries, k 10/100", L_by_k=Lk, plan=splan.as_dict(), loads=[])
+        out = dict(mix="30% shifted queries, k 10/100", L_by_k=Lk, plan=splan.as_dict(), loads=[],
+                   theta=theta, theta_sweep=theta_rows,
+                   fallbacks=int((em == index.medoid).sum().item()))
         reps = 16
         qs = np.concatenate([qm] * reps)
         truth = np.concatenate([gt100] * reps)
@@ -524,6 +546,7 @@ def main():
             st["offered_qps"] = round(frac * sat["qps"], 1)
             out["loads"].append(st)
             log("serving at %.0f%% of capacity: %s" % (100 * frac, st))
+        model.c.theta = -float("inf")       # the other legs run without the fallback
         return out
 
     exacts = {}
@@ -569,7 +592,7 @@ def main():
         if state is None and len(targets) > 1:
             gres["targets"] = extra_targets(g_rows, g.model, ent, "gate")
         if "serve" in legs:
-            gres["serving"] = serving(g.model, L_gate)
+            gres["serving"] = serving(g, L_gate)
         if "ablation" in legs and tq is not None:
             # nearest hub by L2 (no learning) and the untrained towers
             ne = gate.nearest_hub_entries(index, g.hub_ids, q_d)
@@ -783,6 +806,7 @@ def main():
             medoid=dict(reached_target=med["reached_target"], L=med["L"], recall=med["recall"],
                         qps=med["qps"]) if med else None,
             highest_common_recall=common,
+            serving=serving_summary(gres.get("serving") if gres else None),
             gate_L_h=(ginfo.get("L_h") if ginfo else None),
             details=args.details or None),
         roofline=roofline,

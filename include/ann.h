@@ -564,6 +564,26 @@ ann_status ann_navgraph_build(const float *hub_emb, int32_t n_hubs, int32_t dim,
                               int32_t *hub_graph, int32_t *hub_entry, void *workspace,
                               size_t ws_bytes, void *stream);
 
+/* The entry stage's best-first search over the hub navigation graph (the
+ * high-tier graph section's Algorithm 1 on the hub graph): for each query
+ * embedding, the search of ann_search with k = 1, beam width L and an exact
+ * visited set, from hub `start`, over unit hub embeddings by squared L2
+ * (cosine order), specialised for small hub graphs: the pool lives in the
+ * wavefront's registers, so L <= 64.
+ *   emb        n_hubs x dim FP32 (16-byte aligned), dim % 4 == 0, 4 <= dim <= 256
+ *   graph      n_hubs x s int32 hub indices, -1 = empty slot; 1 <= s <= 64
+ *   qemb       nq x dim FP32 query embeddings (16-byte aligned)
+ *   best       nq int32: the best hub; best_d2 nq FP32: its squared distance
+ *   stats      nq x 2 int32 or NULL: distance computations, expansions
+ *   trace      nq x trace_cap int32 or NULL: hubs expanded, in order, -1 padded
+ * Requires 1 <= n_hubs <= 65536, 1 <= L <= 64, 0 <= start < n_hubs (else
+ * ANN_ENOTSUP / ANN_EINVAL).  Enqueues only.  ann_entry_select uses it when
+ * the model's shapes allow, the base search kernel otherwise. */
+ann_status ann_hub_search(const float *emb, int32_t n_hubs, int32_t dim, const int32_t *graph,
+                          int32_t s, const float *qemb, int32_t nq, int32_t start, int32_t L,
+                          int32_t *best, float *best_d2, int32_t *stats, int32_t *trace,
+                          int32_t trace_cap, void *stream);
+
 typedef struct ann_entry_model {
     ann_tower query_tower;      /* BF16 copies must be current */
     const float *hub_emb;       /* n_hubs x query_tower.dout, unit rows */
@@ -581,9 +601,10 @@ typedef struct ann_entry_model {
 size_t ann_entry_workspace_size(const ann_entry_model *model, int32_t nq);
 
 /* Query-aware entry points: the query tower embeds each query; a best-first
- * search over the hub graph (the ann_search kernel with k = 1 and beam width
- * L_h, squared L2 between unit embeddings, i.e. cosine order) starts at
- * model->hub_entry and returns the best hub h with cos = 1 - d2 / 2;
+ * search over the hub graph (k = 1 and beam width L_h, squared L2 between unit
+ * embeddings, i.e. cosine order: ann_hub_search when L_h <= 64 and the hub
+ * table fits its limits, else the ann_search kernel with model->hub_plan)
+ * starts at model->hub_entry and returns the best hub h with cos = 1 - d2 / 2;
  * entry_ids[i] = hub_ids[h], or the medoid when cos < theta.  entry_score
  * (FP32 cosine) and best_hub may be NULL. */
 ann_status ann_entry_select(const ann_entry_model *model, const float *queries, int32_t nq,

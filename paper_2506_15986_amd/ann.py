@@ -217,6 +217,31 @@ def ann_search(base: torch.Tensor, graph: torch.Tensor, queries: torch.Tensor,
     return ids, dist, stats, trace
 
 
+_sig("ann_hub_search", _I32, _P, _I32, _I32, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P, _P, _I32,
+     _P)
+
+
+def ann_hub_search(emb: torch.Tensor, graph: torch.Tensor, qemb: torch.Tensor, start: int, L: int,
+                   want_stats: bool = False, trace_cap: int = 0, stream=None):
+    """Best-first search over the hub graph (k = 1, L <= 64, exact visited
+    set).  Returns (best hub int32 [nq], its FP32 squared distance, stats
+    [nq, 2] (distances, expansions) or None, trace [nq, trace_cap] or None)."""
+    _dev(emb, torch.float32)
+    _dev(graph, torch.int32)
+    _dev(qemb, torch.float32)
+    nh, dim = emb.shape
+    nq = qemb.shape[0]
+    dev = emb.device
+    best = torch.empty(nq, dtype=torch.int32, device=dev)
+    d2 = torch.empty(nq, dtype=torch.float32, device=dev)
+    stats = torch.empty((nq, 2), dtype=torch.int32, device=dev) if want_stats else None
+    trace = torch.empty((nq, trace_cap), dtype=torch.int32, device=dev) if trace_cap else None
+    _check(_lib.ann_hub_search(_ptr(emb), nh, dim, _ptr(graph), graph.shape[1], _ptr(qemb), nq,
+                               int(start), int(L), _ptr(best), _ptr(d2), _ptr(stats), _ptr(trace),
+                               int(trace_cap), _stream(stream)))
+    return best, d2, stats, trace
+
+
 def ann_search_noalloc(base: torch.Tensor, graph: torch.Tensor, queries: torch.Tensor,
                        entry_ids: torch.Tensor | None, medoid: int, k: torch.Tensor,
                        L: torch.Tensor, k_max: int, out, plan: ann_search_plan | None = None,

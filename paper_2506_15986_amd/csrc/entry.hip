@@ -12,7 +12,9 @@
 //                     largest cosine with the mean direction
 //                     (argmin |h - mu|^2 = argmax <h, mu> for unit h);
 //   entry selection   query tower -> best-first search over the hub graph
-//                     (the base search kernel, k = 1, beam L_h) -> best hub,
+//                     (k = 1, beam L_h: the register-pool search of
+//                     hubsearch.hip when L_h <= 64 and the hub table is small,
+//                     else the base search kernel) -> best hub,
 //                     cos = 1 - d2 / 2 -> its base id, or the medoid when the
 //                     cosine is below theta.
 #include "common.h"
@@ -146,10 +148,16 @@ extern "C" ann_status ann_entry_select(const ann_entry_model *m, const float *qu
     ann_status s = tower_forward_run(m->query_tower, queries, nullptr, nq, qemb, tws, st);
     if (s != ANN_OK) return s;
     const int blocks = (nq + 255) / 256;
-    hipLaunchKernelGGL(fill_kl_kernel, dim3(blocks), dim3(256), 0, st, kk, LL, nq, 1, m->L_h);
-    ANN_LAUNCHED();
-    s = search_launch(m->hub_emb, m->n_hubs, e, m->hub_graph, m->s, qemb, nq, nullptr,
-                      m->hub_entry, kk, LL, 1, best, d2, nullptr, nullptr, 0, plan, counter, st);
+    if (hub_search_supported(m->n_hubs, e, m->s, m->L_h)) {
+        // narrow beams on a small hub graph: the register-pool search
+        s = hub_search_launch(m->hub_emb, m->n_hubs, e, m->hub_graph, m->s, qemb, nq, m->hub_entry,
+                              m->L_h, best, d2, nullptr, nullptr, 0, st);
+    } else {
+        hipLaunchKernelGGL(fill_kl_kernel, dim3(blocks), dim3(256), 0, st, kk, LL, nq, 1, m->L_h);
+        ANN_LAUNCHED();
+        s = search_launch(m->hub_emb, m->n_hubs, e, m->hub_graph, m->s, qemb, nq, nullptr,
+                          m->hub_entry, kk, LL, 1, best, d2, nullptr, nullptr, 0, plan, counter, st);
+    }
     if (s != ANN_OK) return s;
     hipLaunchKernelGGL(entry_map_kernel, dim3(blocks), dim3(256), 0, st, best, d2, nq, m->hub_ids,
                        m->theta, m->medoid, entry_ids, entry_score, best_hub);

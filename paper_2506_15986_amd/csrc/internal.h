@@ -43,6 +43,12 @@ ann_status search_check(const float *base, int64_t n, int32_t dim, const int32_t
                         int32_t *out_ids, float *out_dist, int32_t *trace, int32_t trace_cap,
                         const ann_search_plan *plan, void *workspace, size_t ws_bytes,
                         ann_search_plan &p);
+// the entry stage's register-pool search over the hub graph (hubsearch.hip)
+bool hub_search_supported(int n_hubs, int dim, int s, int L);
+ann_status hub_search_launch(const float *emb, int n_hubs, int dim, const int32_t *graph, int s,
+                             const float *qemb, int nq, int start, int L, int32_t *best,
+                             float *best_d2, int32_t *stats, int32_t *trace, int trace_cap,
+                             hipStream_t st);
 ann_status tower_forward_run(const ann_tower &w, const float *x, const int32_t *idx, int rows,
                              float *out, void *ws, hipStream_t st);
 

@@ -74,6 +74,38 @@ __global__ void choose_kernel(const int32_t *table, const int32_t *cand, int nq,
     labels[q] = best >= 0 ? bh : cand[(int64_t)q * M];
 }
 
+// queries whose searches overflowed the visited table are searched again
+// with a table twice as large: their table rows restart, the others get an
+// empty width (k = L = 0: the search kernel skips such a row)
+__global__ void redo_mark_kernel(int32_t *flags, int nq, int M, int32_t *table, int32_t *redo)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const bool r = (flags[q] & 1) != 0;
+    redo[q] = r ? 1 : 0;
+    if (r) {
+        flags[q] = 0;
+        for (int m = 0; m < M; ++m) table[(int64_t)q * M + m] = -1;
+    }
+}
+
+__global__ void gather_redo_kernel(const int32_t *cand, int M, int m, const int32_t *hub_ids,
+                                   const int32_t *redo, int nq, int32_t *ent, int32_t *kk,
+                                   int32_t *LL, int kv, int Lv)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    ent[q] = hub_ids[cand[(int64_t)q * M + m]];
+    kk[q] = redo[q] ? kv : 0;
+    LL[q] = redo[q] ? Lv : 0;
+}
+
+__global__ void count_kernel(const int32_t *v, int nq, int32_t *out)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq && v[q]) atomicAdd(out, 1);
+}
+
 inline int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
@@ -84,6 +116,7 @@ size_t make_labels_ws(int nq, int M, int kt)
     b += round_up((size_t)nq * kt * 4, 256) * 2;               // ids, dist
     b += round_up((size_t)nq * 16, 256);                       // stats
     b += round_up((size_t)nq * M * 4, 256);                    // table (when not given)
+    b += round_up((size_t)nq * 4, 256) * 2;                    // flags (when not given), redo
     b += 512;
     return b;
 }
@@ -133,34 +166,56 @@ extern "C" ann_status ann_make_labels(const float *base, int64_t n, int32_t dim,
     int32_t *stats = cv.take<int32_t>((size_t)nq * 4);
     int32_t *tab = cv.take<int32_t>((size_t)nq * M);
     uint32_t *counter = cv.take<uint32_t>(64);
+    int32_t *fl = cv.take<int32_t>((size_t)nq);
+    int32_t *redo = cv.take<int32_t>((size_t)nq);
     if (table) tab = table;
+    if (flags) fl = flags;
     const int nb = blocks_for(nq);
     hipLaunchKernelGGL(fill_value_kernel, dim3(blocks_for((int64_t)nq * M)), dim3(256), 0, st, tab,
                        (int64_t)nq * M, -1);
     ANN_LAUNCHED();
-    if (flags) {
-        hipLaunchKernelGGL(fill_value_kernel, dim3(nb), dim3(256), 0, st, flags, (int64_t)nq, 0);
-        ANN_LAUNCHED();
-    }
-    for (int m = 0; m < M; ++m) {
-        for (int li = 0; li < n_L; ++li) {
-            const int Lv = L_ladder[li];
-            hipLaunchKernelGGL(gather_entries_kernel, dim3(nb), dim3(256), 0, st, cand_hubs, M, m,
-                               hub_ids, nq, ent, kk, LL, kt, Lv);
+    hipLaunchKernelGGL(fill_value_kernel, dim3(nb), dim3(256), 0, st, fl, (int64_t)nq, 0);
+    ANN_LAUNCHED();
+    // costs are distance counts, so the filter must not forget ids: 32-bit
+    // ids in 2^13 slots; the rare query that overflows them (a probe chain
+    // longer than the table allows) is searched again with 2^14 slots
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            hipLaunchKernelGGL(redo_mark_kernel, dim3(nb), dim3(256), 0, st, fl, nq, M, tab, redo);
             ANN_LAUNCHED();
-            // costs are distance counts, so the filter must not forget ids:
-            // 32-bit ids in 2^13 slots (load <= 0.4 up to L = 512)
-            ann_search_plan p{};
-            ann_status s = ann_default_plan(n, dim, R, Lv, &p);
-            if (s != ANN_OK) return s;
-            p.filter = ANN_FILTER_ID32;
-            p.visited_log2 = 13;
-            s = search_launch(base, n, dim, graph, R, queries, nq, ent, 0, kk, LL, kt, ids, dist,
-                              stats, nullptr, 0, p, counter, st);
-            if (s != ANN_OK) return s;
-            hipLaunchKernelGGL(score_kernel, dim3(nb), dim3(256), 0, st, ids, stats, truth, kt, hits,
-                               nq, M, m, tab, flags);
+            hipLaunchKernelGGL(fill_value_kernel, dim3(1), dim3(64), 0, st,
+                               reinterpret_cast<int32_t *>(counter), (int64_t)1, 0);
             ANN_LAUNCHED();
+            hipLaunchKernelGGL(count_kernel, dim3(nb), dim3(256), 0, st, redo, nq,
+                               reinterpret_cast<int32_t *>(counter));
+            ANN_LAUNCHED();
+            int32_t nredo = 0;
+            ANN_HIP(hipMemcpyAsync(&nredo, counter, 4, hipMemcpyDeviceToHost, st));
+            ANN_HIP(hipStreamSynchronize(st));
+            if (nredo == 0) break;
+        }
+        for (int m = 0; m < M; ++m) {
+            for (int li = 0; li < n_L; ++li) {
+                const int Lv = L_ladder[li];
+                if (pass == 0)
+                    hipLaunchKernelGGL(gather_entries_kernel, dim3(nb), dim3(256), 0, st, cand_hubs,
+                                       M, m, hub_ids, nq, ent, kk, LL, kt, Lv);
+                else
+                    hipLaunchKernelGGL(gather_redo_kernel, dim3(nb), dim3(256), 0, st, cand_hubs, M,
+                                       m, hub_ids, redo, nq, ent, kk, LL, kt, Lv);
+                ANN_LAUNCHED();
+                ann_search_plan p{};
+                ann_status s = ann_default_plan(n, dim, R, Lv, &p);
+                if (s != ANN_OK) return s;
+                p.filter = ANN_FILTER_ID32;
+                p.visited_log2 = pass == 0 ? 13 : 14;
+                s = search_launch(base, n, dim, graph, R, queries, nq, ent, 0, kk, LL, kt, ids,
+                                  dist, stats, nullptr, 0, p, counter, st);
+                if (s != ANN_OK) return s;
+                hipLaunchKernelGGL(score_kernel, dim3(nb), dim3(256), 0, st, ids, stats, truth, kt,
+                                   hits, nq, M, m, tab, fl);
+                ANN_LAUNCHED();
+            }
         }
     }
     hipLaunchKernelGGL(choose_kernel, dim3(nb), dim3(256), 0, st, tab, cand_hubs, nq, M, labels);

@@ -266,13 +266,23 @@ __global__ void hub_ce_kernel(const float *s, int rows, int cols, int P, int N, 
     if (lane == 0) loss_rows[r] = (float)P * (logf(se) + mx) - sp;
 }
 
-// fixed-order column sums: out[c] = sum_r x[r][c]
+// Column sums of x [rows x cols], each summed row by row in order (the
+// training's bits depend on it); the loads of 16 rows are issued together
+// before their adds, so the chain waits on memory once per 16 rows.
 __global__ void bias_grad_kernel(const float *x, int rows, int cols, float *out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
     float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += x[(int64_t)r * cols + c];
+    int r = 0;
+    for (; r + 16 <= rows; r += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = x[(int64_t)(r + u) * cols + c];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    for (; r < rows; ++r) s += x[(int64_t)r * cols + c];
     out[c] = s;
 }
 

@@ -394,6 +394,37 @@ def train_gate(index: Index, data: GateData, train_q: torch.Tensor, w: synth.Wor
     return Gate(qt, ht, data.hub_ids, hub_in, hemb, hg, hub_entry, model, info)
 
 
+def tune_theta(index: Index, g: Gate, queries: torch.Tensor, truth: torch.Tensor, L: int,
+               k: int = 10, quantiles=(0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.3, 0.5)):
+    """The medoid fallback's threshold theta (entries whose best hub has a
+    cosine below theta start at the medoid): tried at -inf and at quantiles
+    of the queries' best-hub cosines, each judged by recall@k at beam width L
+    against `truth` (the queries' exact top-k); the best recall wins, ties to
+    the smaller theta (fewer fallbacks).  Sets g.model's theta and returns
+    (theta, [(theta, recall, fallbacks), ...])."""
+    m = g.model
+    old = float(m.c.theta)
+    m.c.theta = -math.inf
+    _, sc, _ = ann.ann_entry_select(m, queries, want_score=True)
+    cands = [-math.inf] + sorted(set(float(x) for x in
+                                     torch.quantile(sc.double(), torch.tensor(
+                                         list(quantiles), dtype=torch.float64,
+                                         device=sc.device)).tolist()))
+    tr = truth[:, :k].cpu().numpy()
+    rows, best = [], None
+    for th in cands:
+        m.c.theta = th
+        ent = ann.ann_entry_select(m, queries)[0]
+        ids = index.search(queries, L, k, ent)[0].cpu().numpy()
+        rec = float((ids[:, :k, None] == tr[:, None, :]).any(-1).mean())
+        fb = int((ent == index.medoid).sum().item())
+        rows.append((th, round(rec, 5), fb))
+        if best is None or rec > best[1]:
+            best = (th, rec)
+    m.c.theta = best[0] if best is not None else old
+    return float(m.c.theta), rows
+
+
 def tied_init(qp, hub_in: np.ndarray, d: int):
     """Siamese start for the two towers: the hub tower's weights on the hub
     vector equal the query tower's, its weights on the topology features start

@@ -123,3 +123,17 @@ def tower_certificate(params, x, e_gpu, in_scale=1.0, tol=1e-4):
         else:
             unc.append(int(i))
     return int(bad.size), cert, unc
+
+
+def hub_search_traced(ann, gm, qe_sub, L_h):
+    """The entry stage's hub search re-run with traces on some query
+    embeddings (the register-pool search when L_h <= 64, else the base search
+    kernel with the model's hub plan, as ann_entry_select picks them).
+    Returns (best hub indices, traces) on the host."""
+    if L_h <= 64:
+        b, _, _, tr = ann.ann_hub_search(gm.hub_emb, gm.hub_graph, qe_sub, gm.hub_entry, L_h,
+                                         trace_cap=1024)
+        return b.cpu().numpy(), tr.cpu().numpy()
+    ids, _, _, tr = ann.ann_search(gm.hub_emb, gm.hub_graph, qe_sub, None, gm.hub_entry, 1, L_h,
+                                   plan=gm.model.c.hub_plan, trace_cap=1024)
+    return ids.cpu().numpy()[:, 0], tr.cpu().numpy()

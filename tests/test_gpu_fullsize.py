@@ -137,11 +137,9 @@ def test_gate_search_in_the_bench_configuration_at_1m(full):
     if mis.size:
         # the same hub search with traces, for a divergence certificate each
         md = torch.from_numpy(mis).to(bd.device)
-        tids, _, _, ttr = ann.ann_search(gm.hub_emb, gm.hub_graph, qe_d[md].contiguous(), None,
-                                         gm.hub_entry, 1, L_h, plan=gm.model.c.hub_plan,
-                                         trace_cap=1024)
-        tids, ttr = tids.cpu().numpy(), ttr.cpu().numpy()
-        assert (tids[:, 0] == bh_h[mis]).all()
+        from tests.common import hub_search_traced
+        tids, ttr = hub_search_traced(ann, gm, qe_d[md].contiguous(), L_h)
+        assert (tids == bh_h[mis]).all()
         rt = oracle.search(he, hg, qe[mis], gm.hub_entry, 1, L_h, trace_cap=1024)
         for t in range(mis.size):
             assert near_tie_certificate(he, hg, qe[mis[t]], gm.hub_entry, L_h, ttr[t],
@@ -297,8 +295,8 @@ def test_shift1m_gate_search_in_the_bench_configuration(shift):
 # grid, then the search kernel in its autotuned plan (several waves per query
 # are among the candidates) against the oracle on sampled queries.
 
-def test_gist1m_graph_rows_and_search_with_tuned_plan():
-    from tests.common import near_tie_certificate
+@pytest.fixture(scope="module")
+def gist():
     ann = _ann()
     from paper_2506_15986_amd import gate
     w = synth.WORKLOADS["gist1m"]
@@ -308,7 +306,36 @@ def test_gist1m_graph_rows_and_search_with_tuned_plan():
     dev = torch.device("cuda:0")
     bd, qd = torch.from_numpy(base).to(dev), torch.from_numpy(q).to(dev)
     index = gate.build_index(bd, 256, 64, 1.2)
-    g = index.graph.cpu().numpy()
+    return dict(w=w, base=base, q=q, bd=bd, qd=qd, index=index, graph=index.graph.cpu().numpy(),
+                ann=ann)
+
+
+def _certified_search(base, g, q, ent, L, k, sids, sdist, str_):
+    """Oracle comparison of FP32 searches on grid data: identical traces give
+    distances within 1e-5 and ids equal up to swaps of near-equal distances;
+    a different trace needs a near-tie certificate.  Returns the number of
+    uncertified queries."""
+    from tests.common import near_tie_certificate
+    ref = oracle.search(base, g, q, ent, k, L, trace_cap=str_.shape[1])
+    uncertified = 0
+    for i in range(q.shape[0]):
+        if (str_[i] == ref["trace"][i]).all():
+            rd = ref["d2"][i]
+            assert np.all(np.abs(sdist[i].astype(np.float64) - rd) <= 1e-5 * np.maximum(rd, 1e-6))
+            for t in range(k):
+                if sids[i, t] != ref["ids"][i, t]:
+                    row = list(ref["ids"][i])
+                    assert sids[i, t] in row
+                    assert abs(rd[row.index(sids[i, t])] - rd[t]) <= 1e-5 * rd[t]
+        elif not near_tie_certificate(base, g, q[i], ent[i], L, str_[i], ref["trace"][i]):
+            uncertified += 1
+    return uncertified
+
+
+def test_gist1m_graph_rows_and_search_with_tuned_plan(gist):
+    ann = gist["ann"]
+    base, q, bd, qd, index, g = (gist[x] for x in ("base", "q", "bd", "qd", "index", "graph"))
+    dev = bd.device
     n, R = g.shape
     say("case: sampled graph rows")
     assert index.medoid == oracle.medoid(base)
@@ -338,18 +365,72 @@ def test_gist1m_graph_rows_and_search_with_tuned_plan():
     sids, sdist, _, st = ann.ann_search(bd, index.graph, qd[sd].contiguous(), ed[sd].contiguous(),
                                         index.medoid, 10, L, k_max=10, plan=plan, trace_cap=1024)
     torch.cuda.synchronize()
-    sids, sdist, st = sids.cpu().numpy(), sdist.cpu().numpy(), st.cpu().numpy()
-    ref = oracle.search(base, g, q[s], ent[s], 10, L, trace_cap=1024)
-    uncertified = 0
-    for i in range(len(s)):
-        if (st[i] == ref["trace"][i]).all():
-            rd = ref["d2"][i]
-            assert np.all(np.abs(sdist[i].astype(np.float64) - rd) <= 1e-5 * np.maximum(rd, 1e-6))
-            for t in range(10):
-                if sids[i, t] != ref["ids"][i, t]:
-                    row = list(ref["ids"][i])
-                    assert sids[i, t] in row
-                    assert abs(rd[row.index(sids[i, t])] - rd[t]) <= 1e-5 * rd[t]
-        elif not near_tie_certificate(base, g, q[s[i]], ent[s[i]], L, st[i], ref["trace"][i]):
-            uncertified += 1
-    assert uncertified == 0
+    assert _certified_search(base, g, q[s], ent[s], L, 10, sids.cpu().numpy(),
+                             sdist.cpu().numpy(), st.cpu().numpy()) == 0
+
+
+def test_gist1m_gate_entries_and_k100(gist):
+    # the 960-dimension workload's learned entry: 4,096 hubs, towers
+    # 960 -> 256 -> 64 (a shortened training: parity holds for any weights);
+    # entry selection for all 1,000 queries against the oracle at the model's
+    # L_h, then the search from those entries at k = 10 (all queries) and
+    # k = 100 (L = 200, sampled) against the oracle with certificates
+    from tests.common import near_tie_certificate
+    ann = gist["ann"]
+    from paper_2506_15986_amd import gate
+    base, q, bd, qd, index, g = (gist[x] for x in ("base", "q", "bd", "qd", "index", "graph"))
+    w = synth.scaled(gist["w"], n_train=12_000)
+    nq = q.shape[0]
+    say("case: GATE build at 1M x 960 (4096 hubs, 12,000 training queries)")
+    tq = torch.from_numpy(synth.train_queries(w)).to(bd.device)
+    gd = gate.prepare_gate(index, tq, w, n_hubs=4096, M=4, ladder=(16, 32, 64, 128, 256), log=say)
+    gm = gate.train_gate(index, gd, tq, w, hidden=256, epochs=8, log=say)
+    del tq
+    L_h = int(gm.model.c.L_h)
+    ent, sc, bh = ann.ann_entry_select(gm.model, qd, want_score=True)
+    qe_d = gm.qtower.forward(qd)
+    torch.cuda.synchronize()
+    ent_h, bh_h, qe = ent.cpu().numpy(), bh.cpu().numpy(), qe_d.cpu().numpy()
+    he, hg = gm.hub_emb.cpu().numpy(), gm.hub_graph.cpu().numpy()
+    hub_ids = gm.hub_ids.cpu().numpy()
+    say("case: entry selection for all %d queries at L_h = %d" % (nq, L_h))
+    _, _, ref_bh = oracle.entry_select(qe, he, hg, hub_ids, L_h, -np.inf, index.medoid,
+                                       gm.hub_entry)
+    assert (ent_h == hub_ids[bh_h]).all()
+    mis = np.flatnonzero(bh_h != ref_bh)
+    say("entry selection: %d of %d best hubs differ from the oracle's" % (mis.size, nq))
+    if mis.size:
+        md = torch.from_numpy(mis).to(bd.device)
+        from tests.common import hub_search_traced
+        tids, ttr = hub_search_traced(ann, gm, qe_d[md].contiguous(), L_h)
+        assert (tids == bh_h[mis]).all()
+        rt = oracle.search(he, hg, qe[mis], gm.hub_entry, 1, L_h, trace_cap=1024)
+        for t in range(mis.size):
+            assert near_tie_certificate(he, hg, qe[mis[t]], gm.hub_entry, L_h, ttr[t],
+                                        rt["trace"][t]), mis[t]
+    assert mis.size <= nq // 50
+    say("case: searches from the GATE entries, k = 10 at L = 128 (all queries)")
+    L = 128
+    plan, _ = ann.ann_autotune_search(bd, index.graph, qd, ent, index.medoid, 10, L, 10, L, reps=1)
+    sids, sdist, _, st = ann.ann_search(bd, index.graph, qd, ent, index.medoid, 10, L, k_max=10,
+                                        plan=plan, trace_cap=1024)
+    torch.cuda.synchronize()
+    assert _certified_search(base, g, q, ent_h, L, 10, sids.cpu().numpy(), sdist.cpu().numpy(),
+                             st.cpu().numpy()) == 0
+    gt = ann.ann_gt_knn(bd, qd, 100)[0].cpu().numpy()
+    rec10 = (sids.cpu().numpy()[:, :, None] == gt[:, None, :10]).any(-1).mean()
+    say("case: k = 100 at L = 200 (sampled); recall@10 at L = 128: %.4f" % rec10)
+    s = np.random.default_rng(34).choice(nq, 32, replace=False)
+    sd = torch.from_numpy(s).to(bd.device)
+    plan100, _ = ann.ann_autotune_search(bd, index.graph, qd, ent, index.medoid, 100, 200, 100, 200,
+                                         reps=1)
+    ids100, d100, _, tr100 = ann.ann_search(bd, index.graph, qd[sd].contiguous(),
+                                            ent[sd].contiguous(), index.medoid, 100, 200,
+                                            k_max=100, plan=plan100, trace_cap=2048)
+    torch.cuda.synchronize()
+    assert _certified_search(base, g, q[s], ent_h[s], 200, 100, ids100.cpu().numpy(),
+                             d100.cpu().numpy(), tr100.cpu().numpy()) == 0
+    full100 = ann.ann_search(bd, index.graph, qd, ent, index.medoid, 100, 200, k_max=100,
+                             plan=plan100)[0].cpu().numpy()
+    rec100 = (full100[:, :, None] == gt[:, None, :]).any(-1).mean()
+    say("recall@100 at L = 200: %.4f" % rec100)

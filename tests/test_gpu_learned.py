@@ -214,6 +214,30 @@ def test_hub_graph_and_entry_select_via_search_engines():
     ent, _, _ = ann.ann_entry_select(model, _dev(ix["q"]))
     torch.cuda.synchronize()
     assert (ent.cpu().numpy() == ix["medoid"]).all()
+    # theta in a gap of the scores near their median: the queries below it
+    # fall back to the medoid, the others keep their hub, as in the oracle
+    model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, ix["medoid"], L_h=16)
+    _, sc, bh = ann.ann_entry_select(model, _dev(ix["q"]), want_score=True)
+    sc, bh = sc.cpu().numpy().astype(np.float64), bh.cpu().numpy()
+    srt = np.sort(sc)
+    gaps = [t for t in range(len(srt) // 4, 3 * len(srt) // 4) if srt[t + 1] - srt[t] > 2e-5]
+    t = gaps[len(gaps) // 2]
+    theta = 0.5 * (srt[t] + srt[t + 1])
+    say("case: partial fallback, theta %.6f (%d of %d below)" % (theta, t + 1, len(sc)))
+    model = ann.EntryModel(qt, hemb, hg, hub_ids, hub_entry, ix["medoid"], L_h=16, theta=theta)
+    ent, sc2, bh2 = ann.ann_entry_select(model, _dev(ix["q"]), want_score=True)
+    torch.cuda.synchronize()
+    ent, bh2 = ent.cpu().numpy(), bh2.cpu().numpy()
+    assert (bh2 == bh).all()
+    below = sc < theta
+    assert below.sum() == t + 1
+    assert (ent[below] == ix["medoid"]).all()
+    assert (ent[~below] == km["hub_ids"][bh[~below]]).all()
+    ref_ent, ref_sc, ref_bh = oracle.entry_select(qe, he, ref_hg, km["hub_ids"], 16, theta,
+                                                  ix["medoid"], hub_entry)
+    same = ref_bh == bh
+    assert same.mean() >= 0.98
+    assert (ref_ent[same] == ent[same]).all()
 
 
 @pytest.mark.skip(reason="its label-mode search kernel went silent on the GPU (killed after 180 s) "
@@ -427,6 +451,71 @@ def test_train_step_hub_input_gradient_matches_oracle():
     assert _rel(dx.cpu().numpy(), ref) <= 1e-3
 
 
+@pytest.mark.parametrize("nh,e,s,Ls", [(96, 64, 16, (1, 4, 16, 48, 64)),
+                                        (4096, 64, 8, (8, 32, 64)),
+                                        (300, 128, 12, (5, 40)),
+                                        (50, 16, 4, (2, 64))])
+def test_hub_search_bit_exact_on_exact_embeddings(nh, e, s, Ls):
+    # entries +-1/8: every embedding has norm 1 and every squared distance is
+    # a multiple of 1/16, exact in FP32 in any summation order, so the
+    # register-pool search must equal the oracle's search step for step
+    ann = _ann()
+    r = np.random.default_rng(nh + e)
+    scale = 1.0 / np.sqrt(e) if e in (16, 64) else 1.0 / 8       # powers of two
+    he = (r.choice([-1.0, 1.0], size=(nh, e)) * scale).astype(np.float32)
+    qe = (r.choice([-1.0, 1.0], size=(200, e)) * scale).astype(np.float32)
+    hg = oracle.hub_graph(he, s)
+    start = oracle.hub_medoid(he)
+    for L in Ls:
+        say("case: hub search nh=%d e=%d s=%d L=%d" % (nh, e, s, L))
+        b, d2, st, tr = ann.ann_hub_search(_dev(he), _dev(hg), _dev(qe), start, L, want_stats=True,
+                                           trace_cap=512)
+        torch.cuda.synchronize()
+        ref = oracle.search(he, hg, qe, start, 1, L, trace_cap=512)
+        assert (b.cpu().numpy() == ref["ids"][:, 0]).all(), L
+        assert (d2.cpu().numpy().astype(np.float64) == ref["d2"][:, 0]).all(), L
+        assert (st.cpu().numpy()[:, 0] == ref["ndc"]).all(), L
+        assert (st.cpu().numpy()[:, 1] == ref["hops"]).all(), L
+        assert (tr.cpu().numpy() == ref["trace"]).all(), L
+
+
+def test_hub_search_on_trained_shapes_against_oracle_and_entry_select():
+    # generic FP32 unit rows (tower outputs): equal to the oracle except at
+    # certified near ties; ann_entry_select (which picks this search for
+    # L_h <= 64) returns the same best hubs; above 64 it takes the base
+    # search kernel, also checked against the oracle
+    from tests.common import near_tie_certificate
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    qt, ht = ann.Tower(*qp), ann.Tower(*hp)
+    hemb = ht.forward(_dev(hub_in))
+    hg, hub_entry = ann.ann_navgraph_build(hemb, 8)
+    qe_d = qt.forward(_dev(ix["q"]))
+    torch.cuda.synchronize()
+    he, qe, hgh = hemb.cpu().numpy(), qe_d.cpu().numpy(), hg.cpu().numpy()
+    for L in (6, 24, 64):
+        say("case: hub search on tower embeddings, L=%d" % L)
+        b, _, _, tr = ann.ann_hub_search(hemb, hg, qe_d, hub_entry, L, trace_cap=512)
+        b, tr = b.cpu().numpy(), tr.cpu().numpy()
+        ref = oracle.search(he, hgh, qe, hub_entry, 1, L, trace_cap=512)
+        for i in range(qe.shape[0]):
+            if not (tr[i] == ref["trace"][i]).all():
+                assert near_tie_certificate(he, hgh, qe[i], hub_entry, L, tr[i], ref["trace"][i]), i
+            elif b[i] != ref["ids"][i, 0]:
+                assert False, i
+        model = ann.EntryModel(qt, hemb, hg, _dev(km["hub_ids"]), hub_entry, ix["medoid"], L_h=L)
+        _, _, bh = ann.ann_entry_select(model, _dev(ix["q"]), want_score=True)
+        assert (bh.cpu().numpy() == b).all()
+    say("case: entry select above the register pool (L_h = 96, base search kernel)")
+    model = ann.EntryModel(qt, hemb, hg, _dev(km["hub_ids"]), hub_entry, ix["medoid"], L_h=96)
+    _, _, bh = ann.ann_entry_select(model, _dev(ix["q"]), want_score=True)
+    ref = oracle.search(he, hgh, qe, hub_entry, 1, 96)
+    cos = qe.astype(np.float64) @ he.astype(np.float64).T
+    bh = bh.cpu().numpy()
+    for i in np.flatnonzero(bh != ref["ids"][:, 0]):
+        assert abs(cos[i, bh[i]] - cos[i, ref["ids"][i, 0]]) <= 1e-5, i
+
+
 def test_labels_dead_end_graph_by_hand():
     # the hand-traced graph of the oracle's pins: from E the widths 1 and 2
     # stall at a dead end, width 4 reaches the true neighbour with 7 distance
@@ -445,6 +534,45 @@ def test_labels_dead_end_graph_by_hand():
                                          _dev(np.array([1, 5, 4], np.int32)), [1, 2])
     torch.cuda.synchronize()
     assert tab.cpu().numpy().tolist() == [[-1, -1]] and lab.cpu().numpy().tolist() == [2]
+
+
+def test_labels_overflowing_the_visited_table_are_searched_again():
+    # a random 64-regular graph on 9,000 integer points: at width 512 a
+    # search visits almost every node, more ids than the first pass's table
+    # (2^13 slots) holds, so the costs of those searches could count a node
+    # twice; the library searches such queries again with 2^14 slots, and the
+    # costs must then equal the oracle's exact distance counts
+    ann = _ann()
+    r = np.random.default_rng(33)
+    n, d, R, nq = 9000, 32, 64, 20
+    base = r.integers(0, 256, size=(n, d)).astype(np.float32)
+    g = np.empty((n, R), np.int32)
+    for v in range(n):
+        nb = r.choice(n - 1, R, replace=False)
+        g[v] = np.where(nb >= v, nb + 1, nb)
+    q = r.integers(0, 256, size=(nq, d)).astype(np.float32)
+    truth, _ = oracle.knn(base, q, 10)
+    hubs = np.array([11, 222, 3333, 4444], np.int32)
+    cand = np.tile(np.arange(4, dtype=np.int32), (nq, 1))
+    ladder = [10, 512]
+    say("case: labels with visited-table overflow (oracle)")
+    ref_lab, ref_tab = oracle.make_labels(base, g, q, truth, cand, hubs, ladder, 10)
+    say("case: labels with visited-table overflow (gpu)")
+    lab, tab, flags = ann.ann_make_labels(_dev(base), _dev(g), _dev(q), _dev(truth), 10, _dev(cand),
+                                          _dev(hubs), ladder)
+    torch.cuda.synchronize()
+    lab, tab, flags = lab.cpu().numpy(), tab.cpu().numpy(), flags.cpu().numpy()
+    # the first pass's table does overflow here
+    plan = ann.make_plan(**dict(ann.default_plan(n, d, R, 512).as_dict(), filter=ann.ANN_FILTER_ID32,
+                                visited_log2=13))
+    st = ann.ann_search(_dev(base), _dev(g), _dev(q), _dev(np.full(nq, hubs[0], np.int32)), 0, 10,
+                        512, plan=plan)[2].cpu().numpy()
+    say("first-pass overflows at width 512: %d of %d; final flags %d" %
+        (int((st[:, 3] & 1).sum()), nq, int((flags & 1).sum())))
+    assert (st[:, 3] & 1).sum() > 0
+    assert (flags == 0).all()
+    assert (tab == ref_tab).all()
+    assert (lab == ref_lab).all()
 
 
 def test_trained_entry_beats_untrained_towers_and_medoid():
