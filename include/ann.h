@@ -320,6 +320,14 @@ ann_status ann_select_hubs(const float *base, int64_t n, int32_t dim, int32_t n_
                            double *centroids, int32_t *assign, int32_t *steps,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* Seeded start for ann_select_hubs (the paper leaves the k-means start
+ * open): n_hubs distinct base ids written to the HOST array ids, drawn by
+ * Floyd's sampling (for j = n - n_hubs .. n - 1 draw t in [0, j], take t or,
+ * if t is taken, j; ids in the order taken) with the i-th draw
+ * t = floor(x_i (j + 1) / 2^64), x_i the i-th SplitMix64 output from state
+ * `seed`.  Host-only; EINVAL unless 1 <= n_hubs <= n < 2^31. */
+ann_status ann_hub_init_ids(int64_t n, int32_t n_hubs, uint64_t seed, int32_t *ids);
+
 /* Hub nodes (Definition 3) on hierarchical balanced k-means clusters
  * (Algorithm 2): levels rounds split every cluster into k children, giving
  * n_c = k^levels clusters (cluster p*k + j of a round is child j of cluster p
@@ -597,6 +605,15 @@ typedef struct ann_entry_model {
     ann_search_plan hub_plan;   /* plan of the hub-graph search; pool_cap 0 = the default
                                    plan for (n_hubs, embed dim, s, L_h) */
 } ann_entry_model;
+
+/* The model as a handle: ann_entry_model_create checks the fields of *desc
+ * (the checks of ann_entry_select that need no queries and no device) and
+ * returns in *out a host copy of it, to pass wherever a model is taken.  The
+ * device pointers in it are borrowed: the caller keeps them alive and owns
+ * them.  ann_entry_model_destroy frees the copy only (NULL is a no-op).
+ * On a non-OK status *out is NULL. */
+ann_status ann_entry_model_create(const ann_entry_model *desc, ann_entry_model **out);
+void ann_entry_model_destroy(ann_entry_model *model);
 
 size_t ann_entry_workspace_size(const ann_entry_model *model, int32_t nq);
 

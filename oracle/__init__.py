@@ -265,6 +265,50 @@ def kmeans_hubs(base, n_hubs: int, iters: int, init_ids):
     return dict(hub_ids=hub, centroids=cen, assign=asg, steps=steps, objective=obj[:steps])
 
 
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, count: int):
+    """The first `count` outputs of SplitMix64 (Steele, Lea and Flood, "Fast
+    splittable pseudorandom number generators", OOPSLA 2014) started from the
+    64-bit state `seed`: each draw adds the golden-ratio increment
+    0x9E3779B97F4A7C15 to the state and returns the new state through the
+    generator's finaliser (two xor-shift-multiply rounds and a last xor-shift)."""
+    out = []
+    state = seed & _MASK64
+    for _ in range(count):
+        state = (state + 0x9E3779B97F4A7C15) & _MASK64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def floyd_sample(n: int, m: int, draw):
+    """m distinct values out of 0..n-1 by Robert Floyd's algorithm (Bentley
+    and Floyd, "Programming pearls: a sample of brilliance", CACM 1987): for
+    j = n - m, ..., n - 1 draw t uniformly from 0..j (draw(j)) and take t, or
+    j when t was taken already.  Returns the values in the order taken."""
+    taken, seen = [], set()
+    for j in range(n - m, n):
+        t = draw(j)
+        v = j if t in seen else t
+        seen.add(v)
+        taken.append(v)
+    return taken
+
+
+def hub_init_ids(n: int, n_hubs: int, seed: int):
+    """Seeded initial centroids for kmeans_hubs (the paper leaves the k-means
+    start open): Floyd's sampling of n_hubs base ids, its i-th draw from
+    0..j being floor(x_i * (j + 1) / 2^64) for the i-th SplitMix64 output x_i
+    (the multiply-shift map of Lemire, "Fast random integer generation in an
+    interval", 2019, without its rejection step)."""
+    xs = iter(splitmix64(seed, n_hubs))
+    return np.array(floyd_sample(n, n_hubs, lambda j: (next(xs) * (j + 1)) >> 64), np.int32)
+
+
 def hbkm_hubs(base, k: int, levels: int, lam: float, iters: int):
     """Hierarchical balanced k-means (Algorithm 2) into k^levels clusters,
     then Definition 3 hubs.  Returns dict(hub_ids, centroids (float64),

@@ -84,6 +84,7 @@ _sig("ann_build_graph", _I32, _P, _I64, _I32, _I32, _I32, _F32, _P, ctypes.POINT
      ctypes.POINTER(_I32 * 2), _P, _SZ, _P)
 _sig("ann_select_hubs", _I32, _P, _I64, _I32, _I32, _I32, _P, _P, _P, _P, ctypes.POINTER(_I32),
      _P, _SZ, _P)
+_sig("ann_hub_init_ids", _I32, _I64, _I32, ctypes.c_uint64, _P)
 _sig("ann_hub_features", _I32, _P, _I64, _I32, _P, _I32, _I32, _P, _I32, _P, _P, _I32, _I32,
      _I32, _P, _P, _P, _SZ, _P)
 _sig("ann_labels_workspace_size", _SZ, _I32, _I32, _I32)
@@ -122,6 +123,9 @@ _sig("ann_train_step", _I32, ctypes.POINTER(ann_tower), ctypes.POINTER(ann_tower
      _F32, _F32, _I32, _P, _P, _P, _P, _P, _SZ, _P)
 _sig("ann_navgraph_workspace_size", _SZ, _I32, _I32, _I32)
 _sig("ann_navgraph_build", _I32, _P, _I32, _I32, _I32, _P, ctypes.POINTER(_I32), _P, _SZ, _P)
+_sig("ann_entry_model_create", _I32, ctypes.POINTER(ann_entry_model),
+     ctypes.POINTER(ctypes.POINTER(ann_entry_model)))
+_sig("ann_entry_model_destroy", None, ctypes.POINTER(ann_entry_model))
 _sig("ann_entry_workspace_size", _SZ, ctypes.POINTER(ann_entry_model), _I32)
 _sig("ann_entry_select", _I32, ctypes.POINTER(ann_entry_model), _P, _I32, _I32, _P, _P, _P, _P,
      _SZ, _P)
@@ -485,14 +489,27 @@ def ann_select_hubs_hbkm(base: torch.Tensor, k: int, levels: int, lam: float, it
     return hub, cen, asg
 
 
-def ann_select_hubs(base: torch.Tensor, n_hubs: int, iters: int, init_ids: torch.Tensor,
-                    stream=None):
-    """Lloyd k-means + Definition 3 hubs.  Returns (hub_ids int32, centroids
-    float64 [n_hubs, dim], assign int32 [n], steps)."""
+def ann_hub_init_ids(n: int, n_hubs: int, seed: int) -> torch.Tensor:
+    """The library's seeded k-means start: n_hubs distinct base ids (int32,
+    host)."""
+    out = torch.empty(n_hubs, dtype=torch.int32)
+    _check(_lib.ann_hub_init_ids(n, n_hubs, seed & ((1 << 64) - 1), _ptr(out)))
+    return out
+
+
+def ann_select_hubs(base: torch.Tensor, n_hubs: int, iters: int,
+                    init_ids: torch.Tensor | None = None, seed: int | None = None, stream=None):
+    """Lloyd k-means + Definition 3 hubs from init_ids (device), or from the
+    seeded start ann_hub_init_ids(n, n_hubs, seed).  Returns (hub_ids int32,
+    centroids float64 [n_hubs, dim], assign int32 [n], steps)."""
     _dev(base, torch.float32)
-    _dev(init_ids, torch.int32)
     n, dim = base.shape
     dev = base.device
+    if init_ids is None:
+        if seed is None:
+            raise ValueError("ann_select_hubs needs init_ids or a seed")
+        init_ids = ann_hub_init_ids(n, n_hubs, seed).to(dev)
+    _dev(init_ids, torch.int32)
     hub = torch.empty(n_hubs, dtype=torch.int32, device=dev)
     cen = torch.empty((n_hubs, dim), dtype=torch.float64, device=dev)
     asg = torch.empty(n, dtype=torch.int32, device=dev)
@@ -875,9 +892,24 @@ class EntryModel:
         return self._ws
 
 
+def ann_entry_model_create(model: EntryModel):
+    """A library handle: a checked host copy of the model's fields, its device
+    pointers borrowed from `model` (keep `model` alive while it is used).
+    Free it with ann_entry_model_destroy."""
+    h = ctypes.POINTER(ann_entry_model)()
+    _check(_lib.ann_entry_model_create(ctypes.byref(model.c), ctypes.byref(h)))
+    return h
+
+
+def ann_entry_model_destroy(handle) -> None:
+    _lib.ann_entry_model_destroy(handle)
+
+
 def ann_entry_select(model: EntryModel, queries: torch.Tensor, want_score: bool = False,
-                     out=None, stream=None):
-    """Returns (entry ids int32 [nq], cosine float32 or None, best hub int32 or None)."""
+                     out=None, stream=None, handle=None):
+    """Returns (entry ids int32 [nq], cosine float32 or None, best hub int32
+    or None).  With `handle` (from ann_entry_model_create(model)) the library
+    reads the model through it."""
     _dev(queries, torch.float32)
     nq, dim = queries.shape
     dev = queries.device
@@ -885,8 +917,9 @@ def ann_entry_select(model: EntryModel, queries: torch.Tensor, want_score: bool 
     sc = torch.empty(nq, dtype=torch.float32, device=dev) if want_score else None
     bh = torch.empty(nq, dtype=torch.int32, device=dev) if want_score else None
     ws = model.workspace(nq, dev)
-    _check(_lib.ann_entry_select(ctypes.byref(model.c), _ptr(queries), nq, dim, _ptr(ent),
-                                 _ptr(sc), _ptr(bh), _ptr(ws), ws.numel(), _stream(stream)))
+    m = handle if handle is not None else ctypes.byref(model.c)
+    _check(_lib.ann_entry_select(m, _ptr(queries), nq, dim, _ptr(ent), _ptr(sc), _ptr(bh),
+                                 _ptr(ws), ws.numel(), _stream(stream)))
     return ent, sc, bh
 
 

@@ -17,6 +17,8 @@
 //                     else the base search kernel) -> best hub,
 //                     cos = 1 - d2 / 2 -> its base id, or the medoid when the
 //                     cosine is below theta.
+#include <new>
+
 #include "common.h"
 #include "internal.h"
 #include "knn.h"
@@ -97,6 +99,39 @@ extern "C" ann_status ann_navgraph_build(const float *hub_emb, int32_t n_hubs, i
     return ann_medoid(hub_emb, n_hubs, dim, hub_entry, mbuf, medoid_ws(n_hubs, dim), stream);
 }
 
+// the checks on a model that need neither queries nor the device
+static ann_status check_model(const ann_entry_model &m)
+{
+    ANN_REQUIRE(m.hub_emb && m.hub_graph && m.hub_ids, "model has a NULL pointer");
+    ANN_REQUIRE(m.query_tower.din >= 1 && m.query_tower.hidden >= 1 && m.query_tower.dout >= 1,
+                "model has a bad query tower shape");
+    ANN_REQUIRE(m.n_hubs >= 1 && m.s >= 1, "bad hub graph shape");
+    ANN_SUPPORTED(m.s <= 64, "hub graph degree must be <= 64");
+    ANN_REQUIRE(m.hub_entry >= 0 && m.hub_entry < m.n_hubs, "hub_entry out of range");
+    ANN_REQUIRE(m.L_h >= 1 && m.L_h <= 512, "L_h must be in [1, 512]");
+    ANN_REQUIRE(m.medoid >= 0, "medoid must be >= 0");
+    ANN_SUPPORTED(m.query_tower.dout % 4 == 0 && m.query_tower.dout <= 1024,
+                  "embedding dim must be a multiple of 4 and <= 1024");
+    ANN_REQUIRE(aligned(m.hub_emb, 16), "hub_emb must be 16-byte aligned");
+    return ANN_OK;
+}
+
+extern "C" ann_status ann_entry_model_create(const ann_entry_model *desc, ann_entry_model **out)
+{
+    ANN_REQUIRE(desc != nullptr && out != nullptr, "a required pointer is NULL");
+    *out = nullptr;
+    ann_status s = check_model(*desc);
+    if (s != ANN_OK) return s;
+    s = validate_plan(entry_plan(*desc));
+    if (s != ANN_OK) return s;
+    ann_entry_model *m = new (std::nothrow) ann_entry_model(*desc);
+    if (!m) return fail(ANN_ENOMEM, "out of host memory for the model handle");
+    *out = m;
+    return ANN_OK;
+}
+
+extern "C" void ann_entry_model_destroy(ann_entry_model *model) { delete model; }
+
 extern "C" size_t ann_entry_workspace_size(const ann_entry_model *m, int32_t nq)
 {
     return m ? entry_select_ws(nq, &m->query_tower) : 0;
@@ -108,17 +143,12 @@ extern "C" ann_status ann_entry_select(const ann_entry_model *m, const float *qu
                                        void *stream)
 {
     ANN_REQUIRE(m != nullptr, "model is NULL");
-    ANN_REQUIRE(m->hub_emb && m->hub_graph && m->hub_ids, "model has a NULL pointer");
+    {
+        ann_status ms = check_model(*m);
+        if (ms != ANN_OK) return ms;
+    }
     ANN_REQUIRE(m->query_tower.din == dim, "query dim %d does not match the tower (%d)", dim,
                 m->query_tower.din);
-    ANN_REQUIRE(m->n_hubs >= 1 && m->s >= 1, "bad hub graph shape");
-    ANN_SUPPORTED(m->s <= 64, "hub graph degree must be <= 64");
-    ANN_REQUIRE(m->hub_entry >= 0 && m->hub_entry < m->n_hubs, "hub_entry out of range");
-    ANN_REQUIRE(m->L_h >= 1 && m->L_h <= 512, "L_h must be in [1, 512]");
-    ANN_REQUIRE(m->medoid >= 0, "medoid must be >= 0");
-    ANN_SUPPORTED(m->query_tower.dout % 4 == 0 && m->query_tower.dout <= 1024,
-                  "embedding dim must be a multiple of 4 and <= 1024");
-    ANN_REQUIRE(aligned(m->hub_emb, 16), "hub_emb must be 16-byte aligned");
     ANN_REQUIRE(nq >= 0, "nq must be >= 0");
     ANN_REQUIRE(nq == 0 || (queries && entry_ids && workspace), "a required pointer is NULL");
     ANN_REQUIRE(ws_bytes >= entry_select_ws(nq, &m->query_tower), "workspace too small");

@@ -14,6 +14,7 @@
 // Hub of a cluster: the member nearest its mean by (d2, id); an empty
 // cluster takes the nearest point that is not yet a hub (cluster order).
 #include <cmath>
+#include <unordered_set>
 #include <vector>
 
 #include "common.h"
@@ -842,4 +843,33 @@ extern "C" ann_status ann_select_hubs(const float *base, int64_t n, int32_t dim,
                 "workspace too small");
     return select_hubs_run(base, n, dim, n_hubs, iters, init_ids, hub_ids, centroids, assign, steps,
                            workspace, static_cast<hipStream_t>(stream));
+}
+
+// Seeded k-means start.  The generator is SplitMix64 (Steele, Lea and Flood,
+// OOPSLA 2014): the state advances by the golden-ratio increment and each
+// output is the state through the generator's finaliser.  The i-th output x
+// picks t in [0, j] as the high word of x * (j + 1) (Lemire's multiply-shift,
+// 2019, no rejection), and Floyd's sampling (Bentley and Floyd, CACM 1987)
+// takes t, or j when t is already taken, for j = n - n_hubs .. n - 1.
+extern "C" ann_status ann_hub_init_ids(int64_t n, int32_t n_hubs, uint64_t seed, int32_t *ids)
+{
+    ANN_REQUIRE(ids != nullptr, "ids is NULL");
+    ANN_REQUIRE(n >= 1 && n <= 0x7FFFFFFF, "n must be in [1, 2^31)");
+    ANN_REQUIRE(n_hubs >= 1 && n_hubs <= n, "n_hubs must be in [1, n]");
+    std::unordered_set<int64_t> taken;
+    taken.reserve((size_t)n_hubs * 2);
+    uint64_t state = seed;
+    int32_t i = 0;
+    for (int64_t j = n - n_hubs; j < n; ++j) {
+        state += 0x9E3779B97F4A7C15ull;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const int64_t t = (int64_t)(((unsigned __int128)z * (uint64_t)(j + 1)) >> 64);
+        const int64_t v = taken.count(t) ? j : t;
+        taken.insert(v);
+        ids[i++] = (int32_t)v;
+    }
+    return ANN_OK;
 }

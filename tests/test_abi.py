@@ -334,3 +334,51 @@ def test_noalloc_search_rejects_bad_arguments_on_the_host(lib):
     st = ann._lib.ann_search_noalloc(fake, 1000, 32, fake, 16, fake, -1, None, 0, fake, fake, 10,
                                      fake, fake, None, None, 0, None, None)
     assert st == ann.ANN_EINVAL
+
+
+def test_seeded_hub_start_matches_oracle_on_the_host(lib):
+    import oracle
+    from paper_2506_15986_amd import ann
+    for n, m, seed in ((10, 10, 3), (1_000_000, 1024, 0), (20_000, 64, 2**63 + 5), (7, 1, 1),
+                       (10_000_000, 1024, 12345)):
+        got = ann.ann_hub_init_ids(n, m, seed).numpy()
+        assert (got == oracle.hub_init_ids(n, m, seed)).all(), (n, m, seed)
+    out = (ctypes.c_int32 * 4)()
+    assert ann._lib.ann_hub_init_ids(3, 4, 0, out) == ann.ANN_EINVAL        # n_hubs > n
+    assert ann._lib.ann_hub_init_ids(3, 0, 0, out) == ann.ANN_EINVAL
+    assert ann._lib.ann_hub_init_ids(2**31, 4, 0, out) == ann.ANN_EINVAL
+    assert ann._lib.ann_hub_init_ids(10, 4, 0, None) == ann.ANN_EINVAL
+
+
+def test_entry_model_handle_checks_fields_on_the_host(lib):
+    from paper_2506_15986_amd import ann
+    fake = 0x10000                       # never dereferenced
+    tw = ann.ann_tower(din=128, hidden=256, dout=64, in_scale=1.0, W1=fake, b1=fake, W2=fake,
+                       b2=fake, W1b=fake, W2b=fake)
+
+    def make(**kw):
+        a = dict(query_tower=tw, hub_emb=fake, hub_graph=fake, n_hubs=1024, s=16, hub_ids=fake,
+                 hub_entry=3, medoid=7, L_h=48, theta=float("-inf"),
+                 hub_plan=ann.ann_search_plan())
+        a.update(kw)
+        return ann.ann_entry_model(**a)
+
+    h = ctypes.POINTER(ann.ann_entry_model)()
+    desc = make()
+    assert ann._lib.ann_entry_model_create(ctypes.byref(desc), ctypes.byref(h)) == ann.ANN_OK
+    assert h.contents.n_hubs == 1024 and h.contents.L_h == 48 and h.contents.hub_entry == 3
+    assert h.contents.hub_emb == fake and h.contents.query_tower.dout == 64
+    desc.L_h = 5                          # a copy: the handle keeps its own fields
+    assert h.contents.L_h == 48
+    ann._lib.ann_entry_model_destroy(h)
+    ann._lib.ann_entry_model_destroy(None)
+    for kw, code in ((dict(hub_emb=None), ann.ANN_EINVAL), (dict(hub_entry=1024), ann.ANN_EINVAL),
+                     (dict(L_h=0), ann.ANN_EINVAL), (dict(L_h=513), ann.ANN_EINVAL),
+                     (dict(s=65), ann.ANN_ENOTSUP), (dict(medoid=-1), ann.ANN_EINVAL),
+                     (dict(hub_emb=fake + 4), ann.ANN_EINVAL),
+                     (dict(hub_plan=ann.make_plan(pool_cap=64, group=12)), ann.ANN_EINVAL)):
+        h = ctypes.POINTER(ann.ann_entry_model)()
+        d = make(**kw)
+        assert ann._lib.ann_entry_model_create(ctypes.byref(d), ctypes.byref(h)) == code, kw
+        assert not h
+    assert ann._lib.ann_entry_model_create(None, ctypes.byref(h)) == ann.ANN_EINVAL

@@ -35,6 +35,24 @@ def test_select_hubs_bit_exact(which, nh):
     assert (hub.cpu().numpy() == ref["hub_ids"]).all()
 
 
+@pytest.mark.parametrize("seed", [0, 2**63 + 11])
+def test_select_hubs_from_a_seed_bit_exact(seed):
+    # the library's seeded start (SplitMix64 + Floyd's sampling) is the
+    # oracle's: the same centroids, assignment and hubs
+    ix = int_index()
+    base = ix["base"]
+    nh = 48
+    say("case: select_hubs from seed %d" % seed)
+    init = oracle.hub_init_ids(base.shape[0], nh, seed)
+    ref = oracle.kmeans_hubs(base, nh, 20, init)
+    hub, cen, asg, steps = _ann().ann_select_hubs(_dev(base), nh, 20, seed=seed)
+    torch.cuda.synchronize()
+    assert steps == ref["steps"]
+    assert (asg.cpu().numpy() == ref["assign"]).all()
+    assert (cen.cpu().numpy() == ref["centroids"]).all()
+    assert (hub.cpu().numpy() == ref["hub_ids"]).all()
+
+
 @pytest.mark.parametrize("case", ["repeated", "wide", "odd_dim"])
 def test_select_hubs_bit_exact_special_shapes(case):
     # repeated: 5 distinct rows behind 3,000 points and 64 centroids, so many

@@ -233,6 +233,16 @@ def test_hub_graph_and_entry_select_via_search_engines():
     assert below.sum() == t + 1
     assert (ent[below] == ix["medoid"]).all()
     assert (ent[~below] == km["hub_ids"][bh[~below]]).all()
+    # the same model behind a library handle gives the same rows, bit for bit
+    say("case: entry select through a model handle")
+    h = ann.ann_entry_model_create(model)
+    try:
+        ent3, sc3, bh3 = ann.ann_entry_select(model, _dev(ix["q"]), want_score=True, handle=h)
+        torch.cuda.synchronize()
+    finally:
+        ann.ann_entry_model_destroy(h)
+    assert (ent3.cpu().numpy() == ent).all() and (bh3.cpu().numpy() == bh2).all()
+    assert (sc3.cpu().numpy().view(np.uint32) == sc2.cpu().numpy().view(np.uint32)).all()
     ref_ent, ref_sc, ref_bh = oracle.entry_select(qe, he, ref_hg, km["hub_ids"], 16, theta,
                                                   ix["medoid"], hub_entry)
     same = ref_bh == bh
@@ -292,9 +302,41 @@ def test_ladder_labels_match_oracle(which):
     assert (flags == 0).all()
     if which == "int":      # FP32 distances are exact: identical trajectories
         assert (tab == ref_tab).all() and (lab == ref_lab).all()
-    else:                   # FP32 vs FP64 near ties may move a cost
-        assert (tab == ref_tab).mean() >= 0.98
-        assert (lab == ref_lab).mean() >= 0.97
+        return
+    # grid data: FP32 vs FP64 near ties may move a cost; every differing cost
+    # needs a certificate, and labels may differ only where a cost does
+    from tests.common import near_tie_certificate
+    ann = _ann()
+    bad = np.argwhere(tab != ref_tab)
+    say("case: ladder labels tiny: %d of %d costs differ, certifying" % (len(bad), tab.size))
+    assert len(bad) <= tab.size // 20
+    plan = ann.default_plan(base.shape[0], base.shape[1], g.shape[1], max(ladder))
+    plan.filter, plan.visited_log2 = ann.ANN_FILTER_ID32, 13
+    for i, m in bad:
+        hub = int(km["hub_ids"][cand[i, m]])
+        certified = False
+        for L in ladder:
+            ids, dd, _, tr = ann.ann_search(_dev(base), _dev(g), _dev(tq[i:i + 1]),
+                                            _dev(np.array([hub], np.int32)), 0, 10, L, plan=plan,
+                                            trace_cap=1024)
+            ids, dd, tr = ids.cpu().numpy()[0], dd.cpu().numpy()[0], tr.cpu().numpy()[0]
+            ref = oracle.search(base, g, tq[i:i + 1], hub, 10, L, trace_cap=1024)
+            if not (tr == ref["trace"][0]).all():
+                # the trajectories part at a near tie (first differing expansion)
+                certified = near_tie_certificate(base, g, tq[i], hub, L, tr, ref["trace"][0])
+                break
+            if set(ids.tolist()) != set(ref["ids"][0].tolist()):
+                # the same trajectory, so the same visited set; the top 10 of
+                # it differ only if its 10th and 11th distances are near tied
+                seen = {hub}
+                for pnode in tr[tr >= 0]:
+                    seen.update(int(v) for v in g[pnode] if v >= 0)
+                ds = sorted(oracle.sqdist(tq[i], base[v]) for v in seen)
+                certified = len(ds) > 10 and abs(ds[9] - ds[10]) <= 1e-5 * max(ds[9], 1e-30)
+                break
+        assert certified, (int(i), int(m))
+    diff_rows = set(int(i) for i, _ in bad)
+    assert all(int(i) in diff_rows for i in np.flatnonzero(lab != ref_lab))
 
 
 @pytest.mark.parametrize("P,N", [(4, 12), (1, 0), (8, 60)])

@@ -481,3 +481,42 @@ def test_sample_queues_hand_table():
     pos, neg = oracle.sample_queues(H, 1, 10)
     assert [p.tolist() for p in pos] == [[0, 3], [], [0, 1, 2, 3, 4]]
     assert [n.tolist() for n in neg] == [[2, 4], [], []]
+
+
+def test_splitmix64_published_outputs():
+    # the generator's commonly printed check values: five outputs from state
+    # 1234567
+    assert oracle.splitmix64(1234567, 5) == [6457827717110365317, 3203168211198807973,
+                                             9817491932198370423, 4593380528125082431,
+                                             16408922859458223821]
+    # outputs are the finaliser of seed + i * increment: a run from a later
+    # state continues the sequence
+    xs = oracle.splitmix64(99, 6)
+    assert oracle.splitmix64(99 + 3 * 0x9E3779B97F4A7C15, 3) == xs[3:]
+
+
+def test_floyd_sample_is_uniform_over_subsets():
+    # every sequence of draws for n = 6, m = 3 (t in 0..3, 0..4, 0..5: 120
+    # sequences) gives 3 distinct values, and each of the 20 subsets comes
+    # from exactly 6 of them
+    import itertools
+    counts = {}
+    for ts in itertools.product(range(4), range(5), range(6)):
+        it = iter(ts)
+        v = oracle.floyd_sample(6, 3, lambda j: next(it))
+        assert len(set(v)) == 3 and all(0 <= x < 6 for x in v)
+        counts[frozenset(v)] = counts.get(frozenset(v), 0) + 1
+    assert len(counts) == 20 and set(counts.values()) == {6}
+
+
+def test_hub_init_ids_ranges_and_special_cases():
+    # m = n takes every id, in order (each later j is taken or its t is)
+    assert (oracle.hub_init_ids(10, 10, 3) == np.arange(10)).all()
+    for n, m, seed in ((7, 1, 1), (1000, 64, 0), (10**7, 1024, 2**64 - 1)):
+        v = oracle.hub_init_ids(n, m, seed)
+        assert len(v) == m and len(set(v.tolist())) == m and v.min() >= 0 and v.max() < n
+    # the draw from 0..j maps the largest 64-bit output to j and 0 to 0
+    assert ((2**64 - 1) * 1000) >> 64 == 999 and (0 * 1000) >> 64 == 0
+    # one id out of n: the first output's top bits, x * n / 2^64
+    x0 = oracle.splitmix64(5, 1)[0]
+    assert oracle.hub_init_ids(1000, 1, 5)[0] == x0 * 1000 // 2**64
