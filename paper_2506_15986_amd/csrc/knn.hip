@@ -227,7 +227,10 @@ constexpr int kCols = 64;
 constexpr int kMaxD = 256;
 constexpr int32_t kInf = 1 << 24;       // above every d2 of the data
 constexpr int32_t kPadNorm = 1 << 28;   // |y'|^2 of padding columns: never passes
+constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 on gfx9-family parts (raw, 32-bit data)
+constexpr int kWaitVmcnt0 = 0x0F70;     // s_waitcnt vmcnt(0), the other counters left alone
 constexpr int kMaxMerged = 4096;        // slices x Kp entries merged per row
+constexpr int kRing = 512;              // candidates a wave stages in LDS before writing them out
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -248,10 +251,18 @@ struct Args {
 
 __host__ __device__ inline size_t stride_for(int ks) { return (size_t)ks * 32 + 8; }
 
+// per wave: the candidate ring (kRing words and kRing (row, slot) tags), or
+// the sort scratch of cap words, which is used only while the ring is empty
+__host__ __device__ inline size_t wave_region(int cap)
+{
+    const size_t ring = (size_t)kRing * 12, sort = (size_t)cap * 8;
+    return ring > sort ? ring : sort;
+}
+
 __host__ inline size_t tile_lds(int ks, int cap)
 {
     return round_up(2 * kCols * stride_for(ks), 16) + 2 * kCols * 4 + 3 * kRowsWG * 4 +
-           4 * (size_t)cap * 8;
+           4 * wave_region(cap);
 }
 
 // One wave: sort the c entries of g through LDS scratch s, keep the best Kp
@@ -287,7 +298,7 @@ __device__ inline int sort_keep(uint64_t *g, int c, int Kp, uint64_t *s, int32_t
 }
 
 template <int KS>
-__global__ void __launch_bounds__(256) tiles_kernel(Args a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 4 ? 3 : 2))) tiles_kernel(Args a)
 {
     constexpr int STRIDE = KS * 32 + 8;
     constexpr int CHUNKS = kCols * KS * 4;          // 8-byte chunks per tile
@@ -296,12 +307,18 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
     int8_t *Bs = reinterpret_cast<int8_t *>(dyn);
     int32_t *Bn = reinterpret_cast<int32_t *>(dyn + (2 * kCols * STRIDE + 15) / 16 * 16);
     int32_t *r_an = Bn + 2 * kCols;
-    int32_t *r_thr = r_an + kRowsWG;
-    int32_t *r_cnt = r_thr + kRowsWG;
+    // per row: |q'|^2 - thr, the bound the distance test compares with (in
+    // LDS, read per column block, to leave registers to the operands)
+    int32_t *r_tv = r_an + kRowsWG;
+    int32_t *r_cnt = r_tv + kRowsWG;
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = t & 63;
-    uint64_t *scratch = reinterpret_cast<uint64_t *>(r_cnt + kRowsWG) + (size_t)w * a.cap;
+    unsigned char *region = reinterpret_cast<unsigned char *>(r_cnt + kRowsWG) + (size_t)w * wave_region(a.cap);
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(region);
+    uint64_t *ring_w = scratch;                                        // (d2 << 32) | column
+    uint32_t *ring_m = reinterpret_cast<uint32_t *>(region + (size_t)kRing * 8);   // (row << 16) | slot
+    int ring_n = 0;          // candidates staged by this wave (uniform)
     const int64_t row0 = (int64_t)blockIdx.x * kRowsWG;
     const int slice = blockIdx.y;
     const int64_t c_begin = (int64_t)slice * a.slice_len;
@@ -313,7 +330,7 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
     {
         const int64_t g = row0 + t;
         r_an[t] = g < a.rows ? a.qn[g] : 0;
-        r_thr[t] = kInf;
+        r_tv[t] = g < a.rows ? a.qn[g] - kInf : 0x7fffffff;
         r_cnt[t] = 0;
     }
     // A operands: row block rb, k-step ks
@@ -327,56 +344,85 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
                                             a.q8 + g * dim + 32 * ks + 8 * (lane >> 4))
                                       : 0ll;
     }
-    // t = |x'|^2 - thr of the 16 rows whose results this lane holds
-    int32_t tv[4][4];
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t g = row0 + 64 * w + 16 * rb + 4 * (lane >> 4) + i;
-            tv[rb][i] = g < a.rows ? a.qn[g] - kInf : 0x7fffffff;
-        }
 
-    long long stage[PER_T];
-    int32_t stage_n = 0;
-    auto fetch = [&](int it) {
+    // Column tiles stream through a register stage and two LDS buffers: tile
+    // it + 1 is requested while tile it is multiplied and written to LDS
+    // after it.
+    struct Stage {
+        long long v[PER_T];
+        int32_t n;
+    };
+    // Buffer loads through resources based at the tile's first column (in
+    // scalar registers): each lane's offsets are the same for every tile, and
+    // bytes past the end of the data read as zeros (those columns carry the
+    // padding norm, so they never pass).
+    int32_t boff[PER_T];
+#pragma unroll
+    for (int e = 0; e < PER_T; ++e) {
+        const int ch = t + 256 * e;
+        boff[e] = ch < CHUNKS ? (ch / (KS * 4)) * dim + 8 * (ch % (KS * 4)) : 0;
+    }
+    auto fetch = [&](int it, Stage &sg) {
+        const int64_t c0 = c_begin + (int64_t)it * kCols;
+        const int64_t left = a.n - c0;
+        const int cols = left < kCols ? (int)left : kCols;
+        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.b8 + c0 * dim), (short)0, cols * dim, kRsrcWord3);
+#pragma unroll
+        for (int e = 0; e < PER_T; ++e) {
+            long long v = 0;
+            if (CHUNKS % 256 == 0 || t + 256 * e < CHUNKS) {
+                const auto u = __builtin_amdgcn_raw_buffer_load_b64(rb, boff[e], 0, 0);
+                v = ((long long)u[1] << 32) | (uint32_t)u[0];
+            }
+            sg.v[e] = v;
+        }
+        const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.bn + c0), (short)0, cols * 4, kRsrcWord3);
+        sg.n = t < kCols ? __builtin_amdgcn_raw_buffer_load_b32(rn, 4 * t, 0, 0) : 0;
+    };
+    auto store = [&](int it, int buf, const Stage &sg) {
         const int64_t c0 = c_begin + (int64_t)it * kCols;
 #pragma unroll
         for (int e = 0; e < PER_T; ++e) {
             const int ch = t + 256 * e;
-            long long v = 0;
-            if (ch < CHUNKS) {
-                const int c = ch / (KS * 4), j = ch % (KS * 4);
-                if (c0 + c < c_end)
-                    v = *reinterpret_cast<const long long *>(a.b8 + (c0 + c) * dim + 8 * j);
-            }
-            stage[e] = v;
-        }
-        if (t < kCols) stage_n = c0 + t < c_end ? a.bn[c0 + t] : kPadNorm;
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < PER_T; ++e) {
-            const int ch = t + 256 * e;
-            if (ch < CHUNKS) {
+            if (CHUNKS % 256 == 0 || ch < CHUNKS) {
                 const int c = ch / (KS * 4), j = ch % (KS * 4);
                 *reinterpret_cast<long long *>(Bs + (size_t)(buf * kCols + c) * STRIDE + 8 * j) =
-                    stage[e];
+                    sg.v[e];
             }
         }
-        if (t < kCols) Bn[buf * kCols + t] = stage_n;
+        // negated, as the distance test adds it; columns past the slice get
+        // the padding norm
+        if (t < kCols) Bn[buf * kCols + t] = c0 + t < c_end ? -sg.n : -kPadNorm;
     };
 
+    // the staged candidates to their rows' buffer slots
+    auto flush_ring = [&]() {
+        const int m = ring_n < kRing ? ring_n : kRing;
+        knn::wsync();
+        for (int e = lane; e < m; e += 64) {
+            const uint32_t tag = ring_m[e];
+            a.buf[((row0 + (tag >> 16)) * a.slices + slice) * (int64_t)a.cap + (tag & 0xffffu)] =
+                ring_w[e];
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        knn::wsync();
+        ring_n = 0;
+    };
+
+    Stage sg;
     if (ntiles > 0) {
-        fetch(0);
-        store(0);
+        fetch(0, sg);
+        store(0, 0, sg);
     }
     __syncthreads();
     for (int it = 0; it < ntiles; ++it) {
         const int cur = it & 1;
-        if (it + 1 < ntiles) fetch(it + 1);
         const int64_t c0 = c_begin + (int64_t)it * kCols;
-#pragma unroll 1
+        // unrolled: a loop here makes the compiler wait for the tile loads in
+        // flight before entering it
+#pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const int cl = 16 * cb + (lane & 15);
             long long bf[KS];
@@ -384,10 +430,15 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
             for (int ks = 0; ks < KS; ++ks)
                 bf[ks] = *reinterpret_cast<const long long *>(
                     Bs + (size_t)(cur * kCols + cl) * STRIDE + 32 * ks + 8 * (lane >> 4));
-            const int32_t bnc = Bn[cur * kCols + cl];
+            // the column's norm, negated in LDS so that 2 * dot - |x'|^2 is one
+            // shift-and-add
+            const int32_t nbc = Bn[cur * kCols + cl];
+            // the four row blocks' products first (independent accumulators,
+            // so the matrix core pipelines them), then the tests
+            v4i acc[4];
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) {
-                v4i acc = {0, 0, 0, 0};
+                acc[rb] = v4i{0, 0, 0, 0};
                 // pairs of 32-byte k-steps on the 64-deep CDNA4 instruction:
                 // each lane's 16 bytes are its two 8-byte chunks, the same
                 // (row or column, k) correspondence for both operands, so the
@@ -398,7 +449,7 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
                                     (int)areg[rb][ks + 1], (int)(areg[rb][ks + 1] >> 32)};
                     const v4i bv = {(int)bf[ks], (int)(bf[ks] >> 32), (int)bf[ks + 1],
                                     (int)(bf[ks + 1] >> 32)};
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc, 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc[rb], 0, 0, 0);
                 }
                 if (KS & 1) {
                     // the odd last chunk with zeros beside it (the same
@@ -406,28 +457,66 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
                     // on one accumulator gave wrong sums on the GPU)
                     const v4i av = {(int)areg[rb][KS - 1], (int)(areg[rb][KS - 1] >> 32), 0, 0};
                     const v4i bv = {(int)bf[KS - 1], (int)(bf[KS - 1] >> 32), 0, 0};
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc, 0, 0, 0);
-                }
-                bool p[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) p[i] = 2 * acc[i] - bnc > tv[rb][i];
-                if (__builtin_amdgcn_ballot_w64(p[0] | p[1] | p[2] | p[3])) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        if (!p[i]) continue;
-                        const int rl = 64 * w + 16 * rb + 4 * (lane >> 4) + i;
-                        const int32_t d2 = r_an[rl] + bnc - 2 * acc[i];
-                        const int slot = atomicAdd(&r_cnt[rl], 1);
-                        a.buf[((row0 + rl) * a.slices + slice) * (int64_t)a.cap + slot] =
-                            ((uint64_t)(uint32_t)d2 << 32) | (uint32_t)(c0 + cl);
-                    }
+                    acc[rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc[rb], 0, 0, 0);
                 }
             }
+            // 2 * dot - |x'|^2 > |q'|^2 - thr  <=>  d2 < thr: one shift-add and
+            // one compare per distance, one ballot for the 16 of this lane
+            bool p[4][4];
+            bool any = false;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int4 tv = *reinterpret_cast<const int4 *>(r_tv + 64 * w + 16 * rb +
+                                                                4 * (lane >> 4));
+                p[rb][0] = (acc[rb][0] << 1) + nbc > tv.x;
+                p[rb][1] = (acc[rb][1] << 1) + nbc > tv.y;
+                p[rb][2] = (acc[rb][2] << 1) + nbc > tv.z;
+                p[rb][3] = (acc[rb][3] << 1) + nbc > tv.w;
+                any |= p[rb][0] | p[rb][1] | p[rb][2] | p[rb][3];
+            }
+            if (__builtin_amdgcn_ballot_w64(any)) {
+                // a candidate takes its row's next buffer slot now and waits
+                // in the wave's LDS ring; the ring goes out to the buffers in
+                // one pass later (global stores here would keep the next
+                // products waiting for them)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(p[rb][i]);
+                        if (!m) continue;
+                        if (p[rb][i]) {
+                            const int rl = 64 * w + 16 * rb + 4 * (lane >> 4) + i;
+                            const int32_t d2 = r_an[rl] - nbc - 2 * acc[rb][i];
+                            const int slot = atomicAdd(&r_cnt[rl], 1);
+                            const uint64_t word =
+                                ((uint64_t)(uint32_t)d2 << 32) | (uint32_t)(c0 + cl);
+                            const int pos = ring_n + (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            if (pos < kRing) {
+                                ring_w[pos] = word;
+                                ring_m[pos] = ((uint32_t)rl << 16) | (uint32_t)slot;
+                            } else {
+                                // ring full (the first tiles, where most pass)
+                                a.buf[((row0 + rl) * a.slices + slice) * (int64_t)a.cap + slot] =
+                                    word;
+                            }
+                        }
+                        ring_n += __popcll(m);
+                    }
+                if (ring_n > kRing)
+                    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the direct stores, on this path only
+            }
+            // the next tile is requested after the first column block's
+            // products: requested before them, the compiler waits for it there
+            if (cb == 0 && it + 1 < ntiles) fetch(it + 1, sg);
         }
-        // sort the rows whose buffers could not take another tile
+        // sort the rows whose buffers could not take another tile, after
+        // writing the ring out; write it out anyway once it is half full
         knn::wsync();
         const int my = 64 * w + lane;
         uint64_t full = __builtin_amdgcn_ballot_w64(r_cnt[my] > a.cap - kCols);
+        if (full || ring_n > kRing / 2) flush_ring();
         if (full) {
             while (full) {
                 const int r = 64 * w + (int)__builtin_ctzll(full);
@@ -437,22 +526,17 @@ __global__ void __launch_bounds__(256) tiles_kernel(Args a)
                 const int keep = sort_keep(g, r_cnt[r], a.Kp, scratch, thr);
                 if (lane == 0) {
                     r_cnt[r] = keep;
-                    r_thr[r] = thr;
+                    r_tv[r] = r_an[r] - thr;
                 }
                 knn::wsync();
             }
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int rl = 64 * w + 16 * rb + 4 * (lane >> 4) + i;
-                    if (row0 + rl < a.rows) tv[rb][i] = r_an[rl] - r_thr[rl];
-                }
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);     // the sorts' stores, as above
         }
-        if (it + 1 < ntiles) store(cur ^ 1);
+        if (it + 1 < ntiles) store(it + 1, cur ^ 1, sg);
         __syncthreads();
     }
     // final sort of every row of this wave; counts out
+    flush_ring();
     for (int r = 64 * w; r < 64 * w + 64; ++r) {
         if (row0 + r >= a.rows) break;
         int c = r_cnt[r];
@@ -546,8 +630,11 @@ Plan plan(int64_t n, int64_t rows, int K)
 {
     Plan p{};
     p.Kp = K + 1;          // room for the row's own column
+    // a row's buffer holds its best Kp and at least one more tile; below 512
+    // entries it also holds Kp more, so that a row is sorted at most once per
+    // Kp new candidates
     p.cap = 64;
-    while (p.cap < p.Kp + kCols) p.cap <<= 1;
+    while (p.cap < p.Kp + kCols || (p.cap < 512 && p.cap < 2 * p.Kp + kCols)) p.cap <<= 1;
     const int64_t blocks = (rows + kRowsWG - 1) / kRowsWG;
     int64_t s = (2048 + blocks - 1) / (blocks > 0 ? blocks : 1);
     const int64_t by_len = n / 4096 > 1 ? n / 4096 : 1;
