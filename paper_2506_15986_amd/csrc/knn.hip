@@ -4,7 +4,7 @@
 // Two distance engines feed the shared top-K selection of knn_core.h:
 //   * integer engine: every value is an integer in [0, 255]; vectors are
 //     shifted by -128 into int8 and the dot products run on the int8 matrix
-//     cores (v_mfma_i32_16x16x32_i8); d2 = |x'|^2 + |y'|^2 - 2 x'.y' is exact
+//     cores (v_mfma_i32_16x16x64_i8); d2 = |x'|^2 + |y'|^2 - 2 x'.y' is exact
 //     in int32;
 //   * FP64 engine: any data; d2 = sum_j (x_j - y_j)^2 in FP64.  On data held
 //     on a dyadic grid (values m * 2^-G with 2G + log2(d (2B)^2) <= 53) every
@@ -247,6 +247,8 @@ struct Args {
     int64_t slice_len;    // multiple of kCols
     uint64_t *buf;        // rows x slices x cap
     int32_t *cnt;         // rows x slices
+    const int32_t *col_id;      // id reported for each column (NULL: its index)
+    const int32_t *start_tile;  // per workgroup: the column tile its pass starts at (NULL: 0)
 };
 
 __host__ __device__ inline size_t stride_for(int ks) { return (size_t)ks * 32 + 8; }
@@ -261,8 +263,8 @@ __host__ __device__ inline size_t wave_region(int cap)
 
 __host__ inline size_t tile_lds(int ks, int cap)
 {
-    return round_up(2 * kCols * stride_for(ks), 16) + 2 * kCols * 4 + 3 * kRowsWG * 4 +
-           4 * wave_region(cap);
+    return round_up(2 * kCols * stride_for(ks), 16) + 2 * kCols * 4 + 2 * kCols * 4 +
+           3 * kRowsWG * 4 + 4 * wave_region(cap);
 }
 
 // One wave: sort the c entries of g through LDS scratch s, keep the best Kp
@@ -306,9 +308,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
     extern __shared__ __align__(16) unsigned char dyn[];
     int8_t *Bs = reinterpret_cast<int8_t *>(dyn);
     int32_t *Bn = reinterpret_cast<int32_t *>(dyn + (2 * kCols * STRIDE + 15) / 16 * 16);
-    int32_t *r_an = Bn + 2 * kCols;
-    // per row: |q'|^2 - thr, the bound the distance test compares with (in
-    // LDS, read per column block, to leave registers to the operands)
+    int32_t *Bid = Bn + 2 * kCols;          // the columns' reported ids
+    int32_t *r_an = Bid + 2 * kCols;
+    // per row: |q'|^2 - thr - 1, the bound the distance test compares with
+    // (in LDS, read per column block, to leave registers to the operands)
     int32_t *r_tv = r_an + kRowsWG;
     int32_t *r_cnt = r_tv + kRowsWG;
     const int t = threadIdx.x;
@@ -326,11 +329,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
     if (c_end > a.n) c_end = a.n;
     const int ntiles = c_end > c_begin ? (int)((c_end - c_begin + kCols - 1) / kCols) : 0;
     const int dim = KS * 32;
+    // the pass visits the slice's tiles cyclically from start0 (the tiles of
+    // the workgroup's own cluster first, when the rows are cluster-ordered)
+    int start0 = a.start_tile ? a.start_tile[blockIdx.x] : 0;
+    if (start0 < 0 || start0 >= ntiles) start0 = 0;
+    auto tile_c0 = [&](int it) {
+        int j = start0 + it;
+        if (j >= ntiles) j -= ntiles;
+        return c_begin + (int64_t)j * kCols;
+    };
 
     {
         const int64_t g = row0 + t;
         r_an[t] = g < a.rows ? a.qn[g] : 0;
-        r_tv[t] = g < a.rows ? a.qn[g] - kInf : 0x7fffffff;
+        r_tv[t] = g < a.rows ? a.qn[g] - kInf - 1 : 0x7fffffff;
         r_cnt[t] = 0;
     }
     // A operands: row block rb, k-step ks
@@ -350,7 +362,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
     // after it.
     struct Stage {
         long long v[PER_T];
-        int32_t n;
+        int32_t n, id;
     };
     // Buffer loads through resources based at the tile's first column (in
     // scalar registers): each lane's offsets are the same for every tile, and
@@ -363,7 +375,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
         boff[e] = ch < CHUNKS ? (ch / (KS * 4)) * dim + 8 * (ch % (KS * 4)) : 0;
     }
     auto fetch = [&](int it, Stage &sg) {
-        const int64_t c0 = c_begin + (int64_t)it * kCols;
+        const int64_t c0 = tile_c0(it);
         const int64_t left = a.n - c0;
         const int cols = left < kCols ? (int)left : kCols;
         const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
@@ -380,9 +392,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
         const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(a.bn + c0), (short)0, cols * 4, kRsrcWord3);
         sg.n = t < kCols ? __builtin_amdgcn_raw_buffer_load_b32(rn, 4 * t, 0, 0) : 0;
+        sg.id = (int32_t)(c0 + t);
+        if (a.col_id) {
+            const __amdgpu_buffer_rsrc_t ri = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.col_id + c0), (short)0, cols * 4, kRsrcWord3);
+            sg.id = t < kCols ? __builtin_amdgcn_raw_buffer_load_b32(ri, 4 * t, 0, 0) : 0;
+        }
     };
     auto store = [&](int it, int buf, const Stage &sg) {
-        const int64_t c0 = c_begin + (int64_t)it * kCols;
+        const int64_t c0 = tile_c0(it);
 #pragma unroll
         for (int e = 0; e < PER_T; ++e) {
             const int ch = t + 256 * e;
@@ -394,7 +412,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
         }
         // negated, as the distance test adds it; columns past the slice get
         // the padding norm
-        if (t < kCols) Bn[buf * kCols + t] = c0 + t < c_end ? -sg.n : -kPadNorm;
+        if (t < kCols) {
+            Bn[buf * kCols + t] = c0 + t < c_end ? -sg.n : -kPadNorm;
+            Bid[buf * kCols + t] = sg.id;
+        }
     };
 
     // the staged candidates to their rows' buffer slots
@@ -419,7 +440,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
     __syncthreads();
     for (int it = 0; it < ntiles; ++it) {
         const int cur = it & 1;
-        const int64_t c0 = c_begin + (int64_t)it * kCols;
         // unrolled: a loop here makes the compiler wait for the tile loads in
         // flight before entering it
 #pragma unroll
@@ -460,8 +480,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
                     acc[rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, acc[rb], 0, 0, 0);
                 }
             }
-            // 2 * dot - |x'|^2 > |q'|^2 - thr  <=>  d2 < thr: one shift-add and
-            // one compare per distance, one ballot for the 16 of this lane
+            // 2 * dot - |x'|^2 > |q'|^2 - thr - 1  <=>  d2 <= thr: one shift-add
+            // and one compare per distance, one ballot for the 16 of this
+            // lane.  An equal d2 is let in (the sort orders ties by id), so
+            // the columns may come in any order.
             bool p[4][4];
             bool any = false;
 #pragma unroll
@@ -489,8 +511,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
                             const int rl = 64 * w + 16 * rb + 4 * (lane >> 4) + i;
                             const int32_t d2 = r_an[rl] - nbc - 2 * acc[rb][i];
                             const int slot = atomicAdd(&r_cnt[rl], 1);
-                            const uint64_t word =
-                                ((uint64_t)(uint32_t)d2 << 32) | (uint32_t)(c0 + cl);
+                            const uint64_t word = ((uint64_t)(uint32_t)d2 << 32) |
+                                                  (uint32_t)Bid[cur * kCols + cl];
                             const int pos = ring_n + (int)__builtin_amdgcn_mbcnt_hi(
                                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                             if (pos < kRing) {
@@ -526,7 +548,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
                 const int keep = sort_keep(g, r_cnt[r], a.Kp, scratch, thr);
                 if (lane == 0) {
                     r_cnt[r] = keep;
-                    r_tv[r] = r_an[r] - thr;
+                    r_tv[r] = r_an[r] - thr - 1;
                 }
                 knn::wsync();
             }
@@ -554,7 +576,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 
 __global__ void __launch_bounds__(64) select_kernel(const uint64_t *buf, const int32_t *cnt,
                                                     int64_t rows, int slices, int cap, int Kp,
                                                     int K, int exclude, const int32_t *self_col,
-                                                    int32_t *out_ids, float *out_f, double *out_d)
+                                                    const int32_t *row_map, int32_t *out_ids,
+                                                    float *out_f, double *out_d)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     uint64_t *s = reinterpret_cast<uint64_t *>(dyn);
@@ -607,6 +630,7 @@ __global__ void __launch_bounds__(64) select_kernel(const uint64_t *buf, const i
         }
     }
     const int have = total - (self_at < total ? 1 : 0);
+    const int64_t go = row_map ? (int64_t)row_map[g] : g;     // the output row
     for (int o = lane; o < K; o += 64) {
         int32_t id = -1;
         double v = __longlong_as_double(0x7ff0000000000000ll);
@@ -615,10 +639,115 @@ __global__ void __launch_bounds__(64) select_kernel(const uint64_t *buf, const i
             id = (int32_t)(uint32_t)e;
             v = (double)(int32_t)(e >> 32);
         }
-        out_ids[g * K + o] = id;
-        if (out_f) out_f[g * K + o] = (float)v;
-        if (out_d) out_d[g * K + o] = v;
+        out_ids[go * K + o] = id;
+        if (out_f) out_f[go * K + o] = (float)v;
+        if (out_d) out_d[go * K + o] = v;
     }
+}
+
+// ---- cluster order for all-pairs passes.  The rows are grouped by their
+// nearest of kClusters sample rows (every (n / kClusters)-th row), and each
+// workgroup visits the columns of its own group first: the best K of a row
+// are then mostly seen early, its threshold is tight for the rest of the
+// pass, and few columns reach the append path.  Only the visiting order
+// changes; the selection is exact in any order.
+constexpr int kClusters = 256;
+constexpr int64_t kClusterMinN = 65536;   // below this the pass is short anyway
+
+// the sample rows (int8) and their norms
+__global__ void sample_rows_kernel(const int8_t *x8, const int32_t *xn, int64_t n, int dim,
+                                   int C, int8_t *c8, int32_t *cn)
+{
+    const int c = blockIdx.x;
+    const int64_t r = (int64_t)c * n / C;
+    for (int j = threadIdx.x; j < dim; j += blockDim.x) c8[(size_t)c * dim + j] = x8[r * dim + j];
+    if (threadIdx.x == 0) cn[c] = xn[r];
+}
+
+// nearest sample row of every row by (|c'|^2 - 2 x'.c', c), int8 dot products
+// in 32-bit; the C sample rows sit in LDS
+template <int W>
+__global__ void __launch_bounds__(256) nearest_sample_kernel(const int8_t *x8, int64_t n,
+                                                             const int8_t *c8, const int32_t *cn,
+                                                             int C, int32_t *cid, int32_t *hist)
+{
+    extern __shared__ __align__(16) unsigned char dyn[];
+    int32_t *cs = reinterpret_cast<int32_t *>(dyn);                 // C x W packed int8
+    int32_t *csn = cs + (size_t)C * W;
+    for (int i = threadIdx.x; i < C * W; i += blockDim.x)
+        cs[i] = reinterpret_cast<const int32_t *>(c8)[i];
+    for (int i = threadIdx.x; i < C; i += blockDim.x) csn[i] = cn[i];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int32_t xr[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) xr[k] = reinterpret_cast<const int32_t *>(x8 + r * (4 * W))[k];
+    int best = 0;
+    int32_t bv = 0x7fffffff;
+    for (int c = 0; c < C; ++c) {
+        const int32_t *cc = cs + (size_t)c * W;
+        int32_t dot = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) dot = __builtin_amdgcn_sdot4(xr[k], cc[k], dot, false);
+        const int32_t v = csn[c] - 2 * dot;
+        if (v < bv) {
+            bv = v;
+            best = c;
+        }
+    }
+    cid[r] = best;
+    atomicAdd(&hist[best], 1);
+}
+
+// exclusive scan of the C group sizes (one thread; C is small): group starts
+// in start[0..C], a running copy in fill[0..C), which may be hist itself
+__global__ void group_starts_kernel(const int32_t *hist, int C, int32_t *start, int32_t *fill)
+{
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int c = 0; c < C; ++c) {
+            const int32_t h = hist[c];
+            start[c] = acc;
+            fill[c] = acc;
+            acc += h;
+        }
+        start[C] = acc;
+    }
+}
+
+// rows placed group by group (the order inside a group is whatever the
+// atomics give; the results do not depend on it)
+__global__ void place_rows_kernel(const int32_t *cid, int64_t n, int32_t *fill, int32_t *perm)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t pos = atomicAdd(&fill[cid[r]], 1);
+    perm[pos] = (int32_t)r;
+}
+
+// the rows in group order: int8 rows and norms
+__global__ void gather_rows8_kernel(const int8_t *x8, const int32_t *xn, const int32_t *perm,
+                                    int64_t n, int dim, int8_t *y8, int32_t *yn)
+{
+    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (p >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t r = perm[p];
+    const int32_t *src = reinterpret_cast<const int32_t *>(x8 + r * dim);
+    int32_t *dst = reinterpret_cast<int32_t *>(y8 + p * dim);
+    for (int k = lane; k < dim / 4; k += 64) dst[k] = src[k];
+    if (lane == 0) yn[p] = xn[r];
+}
+
+// each workgroup's first column tile: the start of the group of its first row
+__global__ void start_tiles_kernel(const int32_t *cid, const int32_t *perm, const int32_t *start,
+                                   int64_t n, int64_t blocks, int32_t *start_tile)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= blocks) return;
+    const int64_t p = b * kRowsWG;
+    start_tile[b] = p < n ? start[cid[perm[p]]] / kCols : 0;
 }
 
 struct Plan {
@@ -648,6 +777,17 @@ Plan plan(int64_t n, int64_t rows, int K)
     return p;
 }
 
+// all-pairs passes over enough rows run in cluster order
+inline bool cluster_order(int64_t n, int64_t rows) { return rows == n && n >= kClusterMinN; }
+
+size_t cluster_ws(int64_t n, int dim)
+{
+    const int64_t blocks = (n + kRowsWG - 1) / kRowsWG;
+    return round_up((size_t)n * 4, 256) * 2 +                         // group of each row, order
+           round_up((size_t)kClusters * dim, 256) + 3 * round_up((size_t)(kClusters + 1) * 4, 256) +
+           round_up((size_t)blocks * 4, 256);
+}
+
 size_t workspace(int64_t n, int64_t rows, int dim, int K)
 {
     const Plan p = plan(n, rows, K);
@@ -655,6 +795,7 @@ size_t workspace(int64_t n, int64_t rows, int dim, int K)
     b += round_up((size_t)rows * p.slices * 4, 256);
     b += round_up((size_t)n * dim, 256) + round_up((size_t)n * 4, 256);
     b += round_up((size_t)rows * dim, 256) + round_up((size_t)rows * 4, 256);
+    if (cluster_order(n, rows)) b += cluster_ws(n, dim);
     return b + 256;
 }
 
@@ -741,17 +882,86 @@ ann_status knn_run(const float *base, int64_t n, int dim, const float *queries, 
         int8_t *q8 = reinterpret_cast<int8_t *>(p);
         p += round_up((size_t)rows * dim, 256);
         int32_t *qn = reinterpret_cast<int32_t *>(p);
-        hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, base, n,
-                           dim, b8, bn);
-        ANN_LAUNCHED();
-        hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st,
-                           queries, rows, dim, q8, qn);
-        ANN_LAUNCHED();
-        a.b8 = b8;
-        a.bn = bn;
+        p += round_up((size_t)rows * 4, 256);
+        const int32_t *row_map = nullptr;
+        a.col_id = nullptr;
+        a.start_tile = nullptr;
+        if (queries == base && self_col == nullptr && i8::cluster_order(n, rows) &&
+            n <= 0x7FFFFFFF) {
+            // all pairs: rows and columns in the order of their nearest sample
+            // row, ids reported through the permutation
+            const int C = i8::kClusters;
+            const int64_t blocks = (n + i8::kRowsWG - 1) / i8::kRowsWG;
+            int32_t *cid = reinterpret_cast<int32_t *>(p);
+            p += round_up((size_t)n * 4, 256);
+            int32_t *perm = reinterpret_cast<int32_t *>(p);
+            p += round_up((size_t)n * 4, 256);
+            int8_t *c8 = reinterpret_cast<int8_t *>(p);
+            p += round_up((size_t)C * dim, 256);
+            int32_t *cn = reinterpret_cast<int32_t *>(p);
+            p += round_up((size_t)(C + 1) * 4, 256);
+            int32_t *hist = reinterpret_cast<int32_t *>(p);
+            p += round_up((size_t)(C + 1) * 4, 256);
+            int32_t *gstart = reinterpret_cast<int32_t *>(p);
+            p += round_up((size_t)(C + 1) * 4, 256);
+            int32_t *start_tile = reinterpret_cast<int32_t *>(p);
+            p += round_up((size_t)blocks * 4, 256);
+            hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st,
+                               base, n, dim, q8, qn);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(i8::sample_rows_kernel, dim3(C), dim3(64), 0, st, q8, qn, n, dim, C,
+                               c8, cn);
+            ANN_LAUNCHED();
+            ANN_HIP(hipMemsetAsync(hist, 0, (size_t)(C + 1) * 4, st));
+            const size_t slds = (size_t)C * dim + (size_t)C * 4;
+            const dim3 rg((unsigned)((n + 255) / 256));
+            switch (dim / 32) {
+#define ANN_NEAREST(W)                                                                              \
+    case W / 8:                                                                                     \
+        ANN_HIP(hipFuncSetAttribute((const void *)i8::nearest_sample_kernel<W>,                    \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds));       \
+        hipLaunchKernelGGL(i8::nearest_sample_kernel<W>, rg, dim3(256), slds, st, q8, n, c8, cn,   \
+                           C, cid, hist);                                                          \
+        break;
+                ANN_NEAREST(8) ANN_NEAREST(16) ANN_NEAREST(24) ANN_NEAREST(32)
+                ANN_NEAREST(40) ANN_NEAREST(48) ANN_NEAREST(56) ANN_NEAREST(64)
+#undef ANN_NEAREST
+            default: return fail(ANN_ENOTSUP, "int8 engine: dim %d", dim);
+            }
+            ANN_LAUNCHED();
+            // the group sizes become the running fill positions
+            hipLaunchKernelGGL(i8::group_starts_kernel, dim3(1), dim3(64), 0, st, hist, C, gstart,
+                               hist);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(i8::place_rows_kernel, rg, dim3(256), 0, st, cid, n, hist, perm);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(i8::gather_rows8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0,
+                               st, q8, qn, perm, n, dim, b8, bn);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(i8::start_tiles_kernel, dim3((unsigned)((blocks + 255) / 256)),
+                               dim3(256), 0, st, cid, perm, gstart, n, blocks, start_tile);
+            ANN_LAUNCHED();
+            a.b8 = b8;
+            a.bn = bn;
+            a.q8 = b8;
+            a.qn = bn;
+            a.col_id = perm;
+            a.start_tile = start_tile;
+            row_map = perm;
+            self_col = perm;
+        } else {
+            hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st,
+                               base, n, dim, b8, bn);
+            ANN_LAUNCHED();
+            hipLaunchKernelGGL(to_int8_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st,
+                               queries, rows, dim, q8, qn);
+            ANN_LAUNCHED();
+            a.b8 = b8;
+            a.bn = bn;
+            a.q8 = q8;
+            a.qn = qn;
+        }
         a.n = n;
-        a.q8 = q8;
-        a.qn = qn;
         a.rows = rows;
         a.Kp = pl.Kp;
         a.cap = pl.cap;
@@ -775,7 +985,7 @@ ann_status knn_run(const float *base, int64_t n, int dim, const float *queries, 
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(i8::select_kernel, dim3((unsigned)rows), dim3(64), lds, st, a.buf, a.cnt,
                            rows, pl.slices, pl.cap, pl.Kp, K, exclude_self ? 1 : 0, self_col,
-                           out_ids, out_f, out_d);
+                           row_map, out_ids, out_f, out_d);
         ANN_LAUNCHED();
     } else {
         KnnArgs a{};

@@ -92,6 +92,35 @@ def test_int8_engine_exclude_self_with_duplicates():
     assert (dist.cpu().numpy() == ref_d2.astype(np.float32)).all()
 
 
+@pytest.mark.parametrize("n,d,k,vmax", [
+    (70_000, 32, 20, 255),
+    (70_000, 128, 128, 255),      # the graph build's shape: 128 dimensions, K = 128
+    (66_000, 64, 30, 3),          # values 0..3: long runs of equal distances
+])
+def test_int8_all_pairs_in_cluster_order(n, d, k, vmax):
+    # all pairs over one buffer of at least 65,536 rows run with rows and
+    # columns grouped by their nearest sample row: every row's result equals
+    # the pass in id order (a second buffer holding the same data) and, on a
+    # sample of rows, the oracle's
+    r = np.random.default_rng(n + d + vmax)
+    base = r.integers(0, vmax + 1, size=(n, d)).astype(np.float32)
+    base[500:530] = base[77]                     # duplicates of one row
+    x = _dev(base)
+    say("case: int8 all pairs in cluster order n=%d d=%d k=%d values 0..%d" % (n, d, k, vmax))
+    ids, dist = _ann().ann_gt_knn(x, x, k, exclude_self=True)
+    ids2, dist2 = _ann().ann_gt_knn(x, x.clone(), k, exclude_self=True)
+    torch.cuda.synchronize()
+    ids, dist, ids2, dist2 = ids.cpu().numpy(), dist.cpu().numpy(), ids2.cpu().numpy(), dist2.cpu().numpy()
+    assert (ids == ids2).all()
+    assert (dist.view(np.uint32) == dist2.view(np.uint32)).all()
+    rows = np.concatenate([np.arange(0, n, n // 300), np.arange(500, 530), [77, n - 1]])
+    ref_ids, ref_d2 = oracle.knn(base, base[rows], k + 1)
+    for t, row in enumerate(rows):
+        keep = [j for j in range(k + 1) if ref_ids[t, j] != row][:k]
+        assert (ids[row] == ref_ids[t, keep]).all(), row
+        assert (dist[row] == ref_d2[t, keep].astype(np.float32)).all(), row
+
+
 def test_gt_knn_duplicates_tie_by_id_and_exclude_self():
     r = np.random.default_rng(3)
     base = r.integers(0, 4, size=(500, 32)).astype(np.float32)   # many exact ties
