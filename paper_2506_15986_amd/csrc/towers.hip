@@ -6,7 +6,7 @@
 // tower(x) = normalise(W2 . relu(W1 . x + b1) + b2), FP32 master weights with
 // BF16 working copies.  Each matrix product takes BF16 operands (rounded to
 // nearest even) and accumulates in FP32 on the matrix cores
-// (v_mfma_f32_16x16x16_bf16): the tower input, the weights, the hidden
+// (v_mfma_f32_16x16x32_bf16): the tower input, the weights, the hidden
 // activation after ReLU and, backwards, the pre-activation gradients entering
 // the weight and input products.  Bias, ReLU, normalisation, logits and
 // softmax stay in FP32.
@@ -20,7 +20,8 @@
 namespace ann {
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ inline uint16_t f2bf(float f)
@@ -52,7 +53,7 @@ struct GemmArgs {
 };
 
 constexpr int GT = 64;   // tile
-constexpr int GK = 16;   // k step
+constexpr int GK = 32;   // k step: one 16x16x32 product per block
 
 __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
 {
@@ -71,14 +72,18 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g)
             Bs[r][kk] = (n < g.N && k < g.K) ? g.B[(int64_t)n * g.sbn + (int64_t)k * g.sbk] : 0;
         }
         __syncthreads();
-        v4s a;
-        const int ar = 16 * w + (lane & 15), kq = 4 * (lane >> 4);
-        for (int q = 0; q < 4; ++q) a[q] = (short)As[ar][kq + q];
+        // each lane: eight consecutive k of its row (A) and column (B); the
+        // same k for both operands, so the products are those of the sum
+        v8s a;
+        const int ar = 16 * w + (lane & 15), kq = 8 * (lane >> 4);
+        for (int q = 0; q < 8; ++q) a[q] = (short)As[ar][kq + q];
         for (int b = 0; b < 4; ++b) {
-            v4s bv;
+            v8s bv;
             const int bc = 16 * b + (lane & 15);
-            for (int q = 0; q < 4; ++q) bv[q] = (short)Bs[bc][kq + q];
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[b], 0, 0, 0);
+            for (int q = 0; q < 8; ++q) bv[q] = (short)Bs[bc][kq + q];
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                             __builtin_bit_cast(v8bf, bv), acc[b],
+                                                             0, 0, 0);
         }
         __syncthreads();
     }
