@@ -6,14 +6,19 @@
 // (dim <= 256, four lanes per vector).
 //
 // One wavefront per query.  A pool entry is the 64-bit word (FP32 distance
-// bits << 32 | hub index): distances are non-negative, so the word order is
-// the (distance, index) order.  Each step expands the first unexpanded entry
-// (a ballot), tests its neighbours against the visited bitset in slot order,
-// computes the new neighbours' squared distances (four lanes per vector, two
-// shuffle steps) and inserts them one at a time in slot order, each where
-// the ballot of smaller pool entries puts it, if the pool has room or it
-// beats the last entry: the bounded best-first search of ann_search with
-// k = 1 and an exact visited set, without any LDS traffic for the pool.
+// bits << 32 | hub index), bit 31 marking "expanded": distances are
+// non-negative, so with that bit masked the word order is the (distance,
+// index) order.  Each step expands the first unexpanded entry (a ballot),
+// tests its neighbours against the visited bitset in slot order, computes the
+// new neighbours' squared distances (four lanes per vector, two shuffle
+// steps) and merges them into the pool at once: one pass over the new keys
+// gives every pool entry the number of new keys below it and every new key
+// the number of pool entries and of new keys below it, each word is written
+// to its merged place in LDS and the first L places are read back.  Keeping
+// the L smallest of pool and new keys is what inserting them one at a time
+// (when the pool has room or the key beats its last entry) keeps, so this is
+// the bounded best-first search of ann_search with k = 1 and an exact visited
+// set.
 #include "common.h"
 #include "internal.h"
 
@@ -21,13 +26,8 @@ namespace ann {
 namespace {
 
 constexpr uint64_t kEmpty64 = ~0ull;
-
-__device__ inline uint64_t shfl_up1(uint64_t v)
-{
-    const int lo = __shfl_up((int)(uint32_t)v, 1);
-    const int hi = __shfl_up((int)(uint32_t)(v >> 32), 1);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
+constexpr uint64_t kExp = 1ull << 31;           // "expanded", in the index half of a word
+constexpr uint64_t kKeyMask = ~kExp;
 
 __device__ inline uint64_t readlane64(uint64_t v, int l)
 {
@@ -54,6 +54,13 @@ struct HubArgs {
     int vis_words;   // bitset words per wavefront
 };
 
+// LDS of one wavefront: 64 merge words, 64 staged ids, the visited bitset
+// (a multiple of 16 bytes, so that every wavefront's words stay aligned)
+__host__ __device__ inline size_t hub_wave_lds(int vis_words)
+{
+    return ((size_t)64 * 8 + 64 * 4 + (size_t)vis_words * 4 + 15) / 16 * 16;
+}
+
 // T = float4 chunks per lane of a vector (the vector's dim / 16, rounded up)
 template <int T>
 __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
@@ -62,8 +69,10 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qi = blockIdx.x * 4 + wave;
     if (qi >= a.nq) return;                       // whole wavefront
-    uint32_t *vis = reinterpret_cast<uint32_t *>(hs_lds) + (size_t)wave * (a.vis_words + 64);
-    int32_t *stage = reinterpret_cast<int32_t *>(vis + a.vis_words);
+    unsigned char *wl = hs_lds + (size_t)wave * hub_wave_lds(a.vis_words);
+    uint64_t *merged = reinterpret_cast<uint64_t *>(wl);              // 64 words
+    int32_t *stage = reinterpret_cast<int32_t *>(wl + 64 * 8);         // 64 ids
+    uint32_t *vis = reinterpret_cast<uint32_t *>(wl + 64 * 8 + 64 * 4);
     for (int w = lane; w < a.vis_words; w += 64) vis[w] = 0u;
     const int chunks = a.dim >> 2;
     const int gl = lane & 3, grp = lane >> 2;
@@ -97,7 +106,6 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
     __builtin_amdgcn_wave_barrier();
     // the entry
     uint64_t P = kEmpty64;
-    bool ex = false;
     {
         const float d = dist(a.start);
         if (lane == 0) {
@@ -109,11 +117,11 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (;;) {
-        const uint64_t un = __ballot(lane < cnt && !ex);
+        const uint64_t un = __ballot(lane < cnt && !(P & kExp));
         if (!un) break;
         const int pl = __ffsll((unsigned long long)un) - 1;
-        const int p = (int)(uint32_t)readlane64(P, pl);
-        if (lane == pl) ex = true;
+        const int p = (int)((uint32_t)readlane64(P, pl) & 0xffffu);
+        if (lane == pl) P |= kExp;
         if (tr && lane == 0 && hops < a.trace_cap) tr[hops] = p;
         ++hops;
         const int32_t nb = lane < a.s ? a.graph[(size_t)p * a.s + lane] : -1;
@@ -138,28 +146,34 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
             const float d = dist(id);
             const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint32_t)id;
             const int nb_batch = m - b0 < 16 ? m - b0 : 16;
-            // insert in slot order, one at a time
+            // merge: the pool entry in lane j goes to j + (new keys below it);
+            // new key g (lane 4g) to (pool entries below it) + (new keys below
+            // it).  Keys are distinct (distinct indices), so "not below" is
+            // "above".
+            const uint64_t pk = P & kKeyMask;
+            int up = 0, below = 0, rank = 0;
             for (int g = 0; g < nb_batch; ++g) {
                 const uint64_t nk = readlane64(key, 4 * g);
-                if (cnt == a.L &&
-                    nk >= readlane64(P, __builtin_amdgcn_readfirstlane(cnt) - 1))
-                    continue;
-                const int pos = __popcll(__ballot(lane < cnt && P < nk));
-                const uint64_t Pu = shfl_up1(P);
-                const bool eu = __shfl_up((int)ex, 1) != 0;
-                if (lane > pos) {
-                    P = Pu;
-                    ex = eu;
-                } else if (lane == pos) {
-                    P = nk;
-                    ex = false;
-                }
-                cnt = cnt < a.L ? cnt + 1 : a.L;
+                const bool lt = nk < pk;
+                up += lt ? 1 : 0;
+                const int nbelow = __popcll(__ballot(lane < cnt && !lt));
+                below = lane == 4 * g ? nbelow : below;
+                rank += nk < key ? 1 : 0;
             }
+            const int ncnt = cnt + nb_batch < a.L ? cnt + nb_batch : a.L;
+            __builtin_amdgcn_wave_barrier();      // the last merge's reads of `merged` are done
+            if (lane < cnt && lane + up < ncnt) merged[lane + up] = P;
+            if ((lane & 3) == 0 && (lane >> 2) < nb_batch && below + rank < ncnt)
+                merged[below + rank] = key;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            P = lane < ncnt ? merged[lane] : kEmpty64;
+            cnt = ncnt;
         }
     }
     if (lane == 0) {
-        a.best[qi] = (int32_t)(uint32_t)P;
+        a.best[qi] = (int32_t)((uint32_t)P & 0xffffu);
         a.best_d2[qi] = __uint_as_float((uint32_t)(P >> 32));
         if (a.stats) {
             a.stats[2 * qi] = ndc;
@@ -185,7 +199,7 @@ ann_status hub_search_launch(const float *emb, int n_hubs, int dim, const int32_
 {
     HubArgs a{emb, n_hubs, dim, graph, s, qemb, nq, start, L, best, best_d2, stats,
               trace, trace ? trace_cap : 0, (n_hubs + 31) / 32};
-    const size_t lds = (size_t)4 * (a.vis_words + 64) * 4;
+    const size_t lds = 4 * hub_wave_lds(a.vis_words);
     const dim3 grid((unsigned)((nq + 3) / 4));
     const int T = (dim / 4 + 3) / 4;
     if (T <= 1) hipLaunchKernelGGL(hub_search_kernel<1>, grid, dim3(256), lds, st, a);
