@@ -28,6 +28,8 @@ namespace {
 constexpr uint64_t kEmpty64 = ~0ull;
 constexpr uint64_t kExp = 1ull << 31;           // "expanded", in the index half of a word
 constexpr uint64_t kKeyMask = ~kExp;
+constexpr int kQuadSwap1 = 0xB1;   // DPP quad permutation [1, 0, 3, 2]
+constexpr int kQuadSwap2 = 0x4E;   // DPP quad permutation [2, 3, 0, 1]
 
 __device__ inline uint64_t readlane64(uint64_t v, int l)
 {
@@ -84,21 +86,29 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
         q[t] = ch < chunks ? reinterpret_cast<const float4 *>(a.qemb)[(size_t)qi * chunks + ch]
                            : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    // squared distance of hub `id` (valid in the four lanes of the group)
+    // squared distance of hub `id` (valid in the four lanes of the group):
+    // all of a lane's chunks are requested before any is used (a chunk past
+    // the vector's end re-reads chunk 0 and adds nothing), and the group's
+    // four partial sums meet through two DPP quad permutations
     auto dist = [&](int id) {
-        float acc = 0.f;
+        float4 x[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int ch = gl + 4 * t;
-            if (ch < chunks) {
-                const float4 x = e4[(size_t)id * chunks + ch];
-                const float dx = x.x - q[t].x, dy = x.y - q[t].y, dz = x.z - q[t].z,
-                            dw = x.w - q[t].w;
-                acc += dx * dx + dy * dy + dz * dz + dw * dw;
-            }
+            x[t] = e4[(size_t)id * chunks + (ch < chunks ? ch : 0)];
         }
-        acc += __shfl_xor(acc, 1);
-        acc += __shfl_xor(acc, 2);
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const float dx = x[t].x - q[t].x, dy = x[t].y - q[t].y, dz = x[t].z - q[t].z,
+                        dw = x[t].w - q[t].w;
+            const float part = dx * dx + dy * dy + dz * dz + dw * dw;
+            acc += gl + 4 * t < chunks ? part : 0.f;
+        }
+        acc += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), kQuadSwap1,
+                                                          0xf, 0xf, false));
+        acc += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), kQuadSwap2,
+                                                          0xf, 0xf, false));
         return acc;
     };
     int32_t *tr = a.trace ? a.trace + (size_t)qi * a.trace_cap : nullptr;
