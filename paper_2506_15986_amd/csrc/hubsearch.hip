@@ -11,10 +11,12 @@
 // index) order.  Each step expands the first unexpanded entry (a ballot),
 // tests its neighbours against the visited bitset in slot order, computes the
 // new neighbours' squared distances (four lanes per vector, two shuffle
-// steps) and merges them into the pool at once: one pass over the new keys
-// gives every pool entry the number of new keys below it and every new key
-// the number of pool entries and of new keys below it, each word is written
-// to its merged place in LDS and the first L places are read back.  Keeping
+// steps) and merges them into the pool at once: the keys that can enter
+// (all while the pool has room, else those below its last entry) are passed
+// over once, which gives every pool entry the number of them below it and
+// each of them the number of pool entries and of kept keys below it; each
+// word is written to its merged place in LDS and the first L places are read
+// back.  Keeping
 // the L smallest of pool and new keys is what inserting them one at a time
 // (when the pool has room or the key beats its last entry) keeps, so this is
 // the bounded best-first search of ann_search with k = 1 and an exact visited
@@ -156,25 +158,33 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
             const float d = dist(id);
             const uint64_t key = ((uint64_t)__float_as_uint(d) << 32) | (uint32_t)id;
             const int nb_batch = m - b0 < 16 ? m - b0 : 16;
-            // merge: the pool entry in lane j goes to j + (new keys below it);
-            // new key g (lane 4g) to (pool entries below it) + (new keys below
+            // the new keys that can enter: all while the pool has room, else
+            // those below its last entry (the others would be dropped by the
+            // merge anyway)
+            bool keep = (lane & 3) == 0 && (lane >> 2) < nb_batch;
+            if (cnt == a.L) keep = keep && key < (readlane64(P, a.L - 1) & kKeyMask);
+            const uint64_t km = __ballot(keep);
+            if (!km) continue;
+            const int nkeep = __popcll(km);
+            // merge: the pool entry in lane j goes to j + (kept keys below
+            // it); a kept key to (pool entries below it) + (kept keys below
             // it).  Keys are distinct (distinct indices), so "not below" is
             // "above".
             const uint64_t pk = P & kKeyMask;
             int up = 0, below = 0, rank = 0;
-            for (int g = 0; g < nb_batch; ++g) {
-                const uint64_t nk = readlane64(key, 4 * g);
+            for (uint64_t mm = km; mm; mm &= mm - 1) {
+                const int l = __ffsll((unsigned long long)mm) - 1;
+                const uint64_t nk = readlane64(key, l);
                 const bool lt = nk < pk;
                 up += lt ? 1 : 0;
                 const int nbelow = __popcll(__ballot(lane < cnt && !lt));
-                below = lane == 4 * g ? nbelow : below;
+                below = lane == l ? nbelow : below;
                 rank += nk < key ? 1 : 0;
             }
-            const int ncnt = cnt + nb_batch < a.L ? cnt + nb_batch : a.L;
+            const int ncnt = cnt + nkeep < a.L ? cnt + nkeep : a.L;
             __builtin_amdgcn_wave_barrier();      // the last merge's reads of `merged` are done
             if (lane < cnt && lane + up < ncnt) merged[lane + up] = P;
-            if ((lane & 3) == 0 && (lane >> 2) < nb_batch && below + rank < ncnt)
-                merged[below + rank] = key;
+            if (keep && below + rank < ncnt) merged[below + rank] = key;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
