@@ -343,12 +343,9 @@ struct Searcher {
                 nb = graph[(size_t)p * R + lane];
             K nkey = KT::kMax;
             uint32_t nid = beam::kEmpty;
-            pf_id = beam::kEmpty;
             if (npos >= 0) {
                 nkey = keys(cur)[npos];
                 nid = ids(cur)[npos] & beam::kIdMask;
-                pf_id = nid;
-                pf_nb = lane < R ? graph[(size_t)nid * R + lane] : -1;
             }
             beam::wave_sync();
             if (lane == 0) {
@@ -362,6 +359,11 @@ struct Searcher {
             uint64_t fb = __ballot(fresh);
             const int m = __popcll(fb);
             if (fresh) si[__popcll(fb & ((1ull << lane) - 1ull))] = (uint32_t)nb;
+            // the old pool's next unexpanded row, requested once this row is
+            // through the filter: requested before, the wait for this row
+            // would wait for it as well
+            pf_id = nid;
+            if (npos >= 0) pf_nb = lane < R ? graph[(size_t)nid * R + lane] : -1;
             beam::wave_sync();
             if (m == 0) continue;
             distances(m);
