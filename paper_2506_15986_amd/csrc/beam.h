@@ -80,7 +80,16 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ inline int lane_id() { return __lane_id(); }
+// The lane's index, opaque to the optimiser: values derived from it (LDS and
+// global addresses of per-lane rows) are then recomputed where they are used
+// instead of being hoisted out of the hop loop and held in registers for the
+// whole launch, which keeps the search kernel's register count down.
+__device__ inline int lane_id()
+{
+    int l = __lane_id();
+    asm volatile("" : "+v"(l));
+    return l;
+}
 
 // first index j in [0, cnt) with !(a[j] < key)
 template <typename K>

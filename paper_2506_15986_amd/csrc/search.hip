@@ -7,14 +7,17 @@
 // order is kept), gathers their vectors in groups of G lanes with 16-byte
 // loads (G*16 contiguous bytes per group and instruction), reduces the FP32
 // (or FP64) squared L2 distance with lane shuffles, and merges the new keys
-// into the pool (binary-search insertion points, ranks among the new keys,
-// occupancy bits for the old entries' places, ping-pong buffers).  Keys are
+// into the pool (ping-pong buffers).  For FP32 keys and pools of up to 256
+// entries every lane holds its pool entries as 64-bit words and one pass over
+// the new keys counts, per compare mask, each new key's insertion point and
+// rank and each entry's shift; otherwise insertion points come from binary
+// searches and the old entries' places from occupancy bits.  Keys are
 // (distance, id), so ties go to the smaller id.
 //
 // When the visited filter is a hash table that had to drop an id, a dropped
 // node may be seen again.  Its key is recomputed bit-identically, so it is
-// either still in the pool (found by the merge's rank search and dropped as
-// a duplicate) or it was rejected or evicted while the pool was full, and
+// either still in the pool (equal to the entry at its insertion point, and
+// dropped as a duplicate) or it was rejected or evicted while the pool was full, and
 // since the pool's last key only decreases once the pool is full it is
 // rejected again: the expansion order and results are those of an exact
 // visited set; only the executed distance count grows.

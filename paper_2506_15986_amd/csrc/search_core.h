@@ -202,10 +202,146 @@ struct Searcher {
         }
     }
 
+    // Merge for FP32 keys and pools of at most 64 * CM entries.  Lane l reads
+    // pool entries l, l + 64, ... as 64-bit words (key << 32 | id, expanded
+    // bit masked and kept aside for the write-back).  One pass over the
+    // new keys gives each new key its insertion point (the count of smaller
+    // pool words: one compare mask per word) and its rank among the new
+    // keys, and each pool entry the count of new keys above it.  A new key
+    // equal to the pool entry at its insertion point is a rediscovered node:
+    // it is dropped and taken back out of the counts.  Then new key l goes
+    // to place pos + rank and pool entry j to j + (new keys below it), all
+    // at once, into the other pool buffer.
+    template <int CM>
+    __device__ __forceinline__ void merge_words(int m, int Lq, int &cursor, uint32_t &pf_id,
+                                                int &pf_nb, K nkey, uint32_t nid, SearchResult &r)
+    {
+        const int lane = beam::lane_id();
+        const K *ak = keys(cur);
+        const uint32_t *ai = ids(cur);
+        // entries past cnt are read too (they lie inside the wave's LDS:
+        // each pool array is followed by at least 64 entries of another) and
+        // replaced by ~0; lane + 64 c < cnt is tested as lane < cnt - 64 c
+        uint64_t P[CM];
+        uint32_t ex = 0;   // expanded bits, bit c for word c
+#pragma unroll
+        for (int c = 0; c < CM; ++c) {
+            const uint32_t id = ai[lane + 64 * c];
+            const uint64_t w = ((uint64_t)ak[lane + 64 * c] << 32) | (id & beam::kIdMask);
+            ex |= (id >> 31) << c;
+            P[c] = lane < cnt - 64 * c ? w : ~0ull;
+        }
+        bool valid = lane < m;
+        K kk = KT::kMax;
+        uint32_t ii = beam::kEmpty;
+        uint64_t S = ~0ull;
+        if (valid) {
+            kk = sk[lane];
+            ii = si[lane];
+            S = ((uint64_t)kk << 32) | ii;
+        }
+        // a full pool takes only keys below its last entry (a word below
+        // ~0: ids are below 2^31)
+        if (cnt == Lq) {
+            const uint64_t last = ((uint64_t)ak[cnt - 1] << 32) | (ai[cnt - 1] & beam::kIdMask);
+            valid = valid && S < last;
+        }
+        const uint64_t vmask = __ballot(valid);
+        if (!vmask) return;
+        int ltc[CM];
+#pragma unroll
+        for (int c = 0; c < CM; ++c) ltc[c] = 0;
+        int rank = 0, pos = 0;
+        for (uint64_t mm = vmask; mm; mm &= mm - 1) {
+            const int t = __ffsll((unsigned long long)mm) - 1;
+            const uint64_t s = beam::readlane(S, t);
+            int below = 0;
+#pragma unroll
+            for (int c = 0; c < CM; ++c) {
+                const bool lt = P[c] < s;
+                below += __popcll(__ballot(lt));
+                ltc[c] += lt ? 1 : 0;
+            }
+            pos = lane == t ? below : pos;
+            rank += s < S ? 1 : 0;
+        }
+        // rediscovered nodes (a forgetful filter's repeats): equal to the
+        // pool entry at their insertion point
+        bool dup = false;
+        if (valid) {
+            const int pj = pos < cnt ? pos : 0;
+            dup = pos < cnt && ak[pj] == kk && (ai[pj] & beam::kIdMask) == ii;
+        }
+        const uint64_t dmask = __ballot(dup);
+        const int nv = __popcll(vmask);
+        int mv = nv;
+        if (dmask) {
+            r.dups += __popcll(dmask);
+            mv -= __popcll(dmask);
+            if (mv == 0) return;
+            for (uint64_t mm = dmask; mm; mm &= mm - 1) {
+                const int t = __ffsll((unsigned long long)mm) - 1;
+                const uint64_t s = beam::readlane(S, t);
+                const int pt = __builtin_amdgcn_readlane(pos, t);
+#pragma unroll
+                for (int c = 0; c < CM; ++c) ltc[c] += (lane >= pt - 64 * c) ? 1 : 0;
+                rank -= s < S ? 1 : 0;
+            }
+            valid = valid && !dup;
+        }
+        // the smallest new key: expanded next if it beats the old pool's
+        // next unexpanded entry
+        const int l0 = __ffsll((unsigned long long)__ballot(valid && rank == 0)) - 1;
+        const K k0 = beam::readlane(kk, l0);
+        const uint32_t i0 = beam::readlane(ii, l0);
+        const int f0 = beam::readlane(pos, l0);
+        if (beam::key_less(k0, i0, nkey, nid)) {
+            pf_id = i0;
+            pf_nb = lane < R ? graph[(size_t)i0 * R + lane] : -1;
+        }
+        K *bk = keys(cur ^ 1);
+        uint32_t *bi = ids(cur ^ 1);
+        const int outn = __builtin_amdgcn_readfirstlane((cnt + mv < Lq) ? cnt + mv : Lq);
+        const int fnew = pos + rank;
+        if (valid && fnew < Lq) {
+            bk[fnew] = kk;
+            bi[fnew] = ii;
+        }
+#pragma unroll
+        for (int c = 0; c < CM; ++c) {
+            const int o = lane + (64 * c + nv) - ltc[c];
+            if (lane < cnt - 64 * c && o < outn) {
+                bk[o] = (K)(P[c] >> 32);
+                bi[o] = (uint32_t)P[c] | (((ex >> c) & 1u) << 31);
+            }
+        }
+        // the cursor's entry moves up by the new keys below it
+        const int oc = cursor + __popcll(__ballot(valid && pos <= cursor));
+        cursor = __builtin_amdgcn_readfirstlane(f0 < oc ? f0 : oc);
+        cnt = outn;
+        cur ^= 1;
+        beam::wave_sync();
+    }
+
     // Merges the m new keys (sk/si) into the pool.  Updates the cursor and,
     // when the best new key will be expanded next, the prefetched row.
     __device__ __forceinline__ void merge(int m, int Lq, int &cursor, uint32_t &pf_id, int &pf_nb,
                                           K nkey, uint32_t nid, SearchResult &r)
+    {
+        if constexpr (!F64) {
+            if (pool_cap <= 64) return merge_words<1>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            if (pool_cap <= 128) return merge_words<2>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            if (pool_cap <= 192) return merge_words<3>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            if (pool_cap <= 256) return merge_words<4>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+        }
+        merge_search(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+    }
+
+    // The general merge (FP64 keys, or pools past 256 entries): insertion
+    // points by binary search, ranks by a scalar loop over the new keys,
+    // occupancy bits for the old entries' places.
+    __device__ __forceinline__ void merge_search(int m, int Lq, int &cursor, uint32_t &pf_id,
+                                                 int &pf_nb, K nkey, uint32_t nid, SearchResult &r)
     {
         const int lane = beam::lane_id();
         // ---- merge the new keys into the pool.  A new key's place is its
