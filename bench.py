@@ -185,6 +185,8 @@ def main():
                     help="queues leg: t_pos:P:N triples, comma separated (t_neg stays 15)")
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
     ap.add_argument("--pipe", type=int, default=2, help="batches in flight in the pipelined steps")
+    ap.add_argument("--pipe-replay", action="store_true",
+                    help="with --load-state, also time the pipelined steps")
     ap.add_argument("--shuffle-queries", type=int, default=0,
                     help="permute the test queries with this seed (0: generator order)")
     ap.add_argument("--save-state", default="")
@@ -314,7 +316,36 @@ def main():
              min(ms for _, ms in times if ms >= 0), times[0][1]))
         return best, rows
 
-    def pipelined(b, g_entry, g_search, L, plan, model):
+    def pipe_candidates(plan, rows, label):
+        """Search plans tried for the pipelined steps.  With two batches in
+        flight the next search's wavefronts and the entry stage need compute
+        units while the current search still runs, so a persistent grid that
+        fills the GPU is not always best there: the tuned plan and the best
+        plan of the other gather group (from the single-launch autotuner's
+        rows) are each tried with their own and with four wavefronts per
+        workgroup, with the full grid and with grids of 16 down to 12
+        wavefronts per compute unit."""
+        if state is not None and state.get("pipe_plan_%s" % label):
+            return [ann.make_plan(**state["pipe_plan_%s" % label])]
+        if state is not None or args.no_tune:
+            return [plan]
+        bases = [plan]
+        other = sorted((r for r in rows if r["group"] != plan.group and r["ms"] >= 0
+                        and r.get("waves_per_query", 1) == 1), key=lambda r: r["ms"])
+        if other:
+            bases.append(ann.make_plan(**{f: v for f, v in other[0].items() if f != "ms"}))
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        out = []
+        for bp in bases:
+            own = max(1, int(bp.waves_per_block))
+            # several wavefronts per query fix the workgroup at that many
+            for wpb in sorted({own, 4}) if int(bp.waves_per_query) <= 1 else [own]:
+                for wpc in (0, 16, 15, 14, 13, 12):
+                    out.append(ann.make_plan(**dict(bp.as_dict(), waves_per_block=wpb,
+                                                    blocks=(wpc * cus) // wpb)))
+        return out
+
+    def pipelined(b, L, plan, model, rows, label):
         """The same K steps with PIPE batches in flight: the entry stage runs
         on its own stream, and the searches of consecutive batches on PIPE
         streams (one per buffer set), so the next batch's search fills the
@@ -322,47 +353,73 @@ def main():
         order each buffer's entry stage after its previous search and each
         search after its entry stage.  With the tail filled that way, the
         searches take their queries as given (plan.query_order), which
-        measured faster here than widest-expected-first."""
-        pplan = ann.make_plan(**dict(plan.as_dict(), query_order=ann.ANN_ORDER_AS_GIVEN))
-        extra = [ann.QueryBatch(base_d, index.graph, index.medoid, q_d, kk,
-                                torch.full((nq,), L, dtype=torch.int32, device=dev), k, plan=pplan,
-                                model=model, entry_ids=None if model is not None else b.entry_ids)
-                 for _ in range(PIPE)]
-        pairs = [(bx.graph_exec(ann.ANN_STAGE_ENTRY) if model is not None else None,
-                  bx.graph_exec(ann.ANN_STAGE_SEARCH)) for bx in extra]
-        s_e = torch.cuda.Stream(device=dev)
-        s_s = [torch.cuda.Stream(device=dev) for _ in range(PIPE)]
-        ready = [torch.cuda.Event() for _ in range(PIPE)]
-        done = [torch.cuda.Event() for _ in range(PIPE)]
-        for x in range(PIPE):
-            done[x].record(s_s[x])
+        measured faster here than widest-expected-first.  The search plan is
+        the fastest of pipe_candidates over a short pipelined run (35 steps
+        each); every candidate's results are compared with the timed batch's."""
+        # streams with hardware queues of their own: on ordinary streams the
+        # two searches may share a queue and then run one after the other
+        s_e = ann.dedicated_stream(0, dev)
+        s_s = [ann.dedicated_stream(1 + x, dev) for x in range(PIPE)]
 
-        def pstep(i):
-            x = i % PIPE
-            ge, gs = pairs[x]
-            if ge is not None:
-                s_e.wait_event(done[x])
-                ge.launch(stream=s_e)
-                ready[x].record(s_e)
-                s_s[x].wait_event(ready[x])
-            gs.launch(stream=s_s[x])
-            done[x].record(s_s[x])
+        def run(cand, steps, warmup):
+            pplan = ann.make_plan(**dict(cand.as_dict(), query_order=ann.ANN_ORDER_AS_GIVEN))
+            extra = [ann.QueryBatch(base_d, index.graph, index.medoid, q_d, kk,
+                                    torch.full((nq,), L, dtype=torch.int32, device=dev), k,
+                                    plan=pplan, model=model,
+                                    entry_ids=None if model is not None else b.entry_ids)
+                     for _ in range(PIPE)]
+            pairs = [(bx.graph_exec(ann.ANN_STAGE_ENTRY) if model is not None else None,
+                      bx.graph_exec(ann.ANN_STAGE_SEARCH)) for bx in extra]
+            ready = [torch.cuda.Event() for _ in range(PIPE)]
+            done = [torch.cuda.Event() for _ in range(PIPE)]
+            for x in range(PIPE):
+                done[x].record(s_s[x])
 
-        for i in range(args.warmup):
-            pstep(i)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        for i in range(args.steps):
-            pstep(i)
-        torch.cuda.synchronize()
-        wall = time.time() - t0
-        same = all(bool((bx.ids.cpu().numpy() == b.ids.cpu().numpy()).all()) for bx in extra)
-        for pr in pairs:
-            for gx in pr:
-                if gx is not None:
-                    gx.close()
-        res = dict(qps=round(nq * args.steps / wall, 1),
-                   ms_per_step=round(wall * 1000.0 / args.steps, 4), results_equal=same)
+            def pstep(i):
+                x = i % PIPE
+                ge, gs = pairs[x]
+                if ge is not None:
+                    s_e.wait_event(done[x])
+                    ge.launch(stream=s_e)
+                    ready[x].record(s_e)
+                    s_s[x].wait_event(ready[x])
+                gs.launch(stream=s_s[x])
+                done[x].record(s_s[x])
+
+            for i in range(warmup):
+                pstep(i)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            for i in range(steps):
+                pstep(i)
+            torch.cuda.synchronize()
+            wall = time.time() - t0
+            same = all(bool((bx.ids.cpu().numpy() == b.ids.cpu().numpy()).all()) for bx in extra)
+            for pr in pairs:
+                for gx in pr:
+                    if gx is not None:
+                        gx.close()
+            del extra
+            return wall * 1000.0 / steps, same
+
+        cands = pipe_candidates(plan, rows, label)
+        trials = []
+        best = cands[0]
+        if len(cands) > 1:
+            for cand in cands:
+                ms, same = run(cand, 35, 5)
+                trials.append(dict(group=int(cand.group), waves_per_block=int(cand.waves_per_block),
+                                   visited_log2=int(cand.visited_log2), blocks=int(cand.blocks),
+                                   ms_per_step=round(ms, 4), results_equal=same))
+            ok = [(t["ms_per_step"], i) for i, t in enumerate(trials) if t["results_equal"]]
+            best = cands[min(ok)[1]] if ok else plan
+            log("pipelined plan: %d candidates, best group %d, %d waves/workgroup, %d workgroups "
+                "(%.3f ms/step; full grid of the tuned plan %.3f)" %
+                (len(cands), best.group, best.waves_per_block, best.blocks,
+                 min(t["ms_per_step"] for t in trials), trials[0]["ms_per_step"]))
+        ms, same = run(best, args.steps, args.warmup)
+        res = dict(qps=round(nq * 1000.0 / ms, 1), ms_per_step=round(ms, 4), results_equal=same,
+                   plan=best.as_dict(), candidates=trials)
         res["batches_in_flight"] = PIPE
         log("pipelined steps (%d batches in flight): %.3f ms/step -> %.0f QPS (results equal: %s)" %
             (PIPE, res["ms_per_step"], res["qps"], same))
@@ -399,7 +456,8 @@ def main():
         wall = time.time() - t0
         search_ms = [e[1].elapsed_time(e[2]) for e in evs]
         entry_ms = [e[0].elapsed_time(e[1]) for e in evs]
-        pipe = pipelined(b, g_entry, g_search, L, plan, model) if state is None else None
+        pipe = (pipelined(b, L, plan, model, tune_rows, label)
+                if state is None or args.pipe_replay else None)
         ids, dist = b.ids.cpu().numpy(), b.dist.cpu().numpy()
         rec = float(recall_at(ids, gt).mean())
         rec_t = float(recall_tie_aware(dist, gtd).mean())
@@ -706,6 +764,7 @@ def main():
                 L_gate=L_gate, L_medoid=med["L"] if med else None,
                 medoid_reached=med["reached_target"] if med else None, gate_sweep=g_rows,
                 medoid_sweep=med_rows, plan_gate=gres["plan"],
+                pipe_plan_gate=gres.get("pipelined", {}).get("plan"),
                 plan_medoid=med["plan"] if med else None, exact_gate=exacts.get("gate"),
                 exact_medoid=exacts.get("medoid")))
             log("state saved to %s" % args.save_state)

@@ -747,6 +747,19 @@ ann_status ann_query_graph_create(const ann_query_batch *batch, int32_t stages,
 ann_status ann_query_graph_launch(ann_query_graph *graph, void *stream);
 void ann_query_graph_destroy(ann_query_graph *graph);
 
+/* A stream with a hardware queue of its own, for running batches side by
+ * side (pipelined batches, serving slots).  Ordinary streams share a small
+ * pool of hardware queues, and two streams that land on one queue run their
+ * launches one after the other, so whether two batches overlap depends on how
+ * many streams the process has created before.  This stream is created with a
+ * compute-unit mask naming every compute unit of the current device, which
+ * gives it a queue outside that pool; its priority is the default.  *out
+ * receives the hipStream_t; release it with ann_stream_destroy (which waits
+ * for the stream's pending work).  Errors: ANN_EINVAL for a NULL out,
+ * ANN_EDEVICE when the runtime refuses. */
+ann_status ann_stream_create(void **out);
+void ann_stream_destroy(void *stream);
+
 #ifdef __cplusplus
 }
 #endif

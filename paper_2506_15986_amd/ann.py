@@ -1011,6 +1011,9 @@ _sig("ann_query_graph_create", _I32, ctypes.POINTER(ann_query_batch), _I32,
 _sig("ann_query_graph_launch", _I32, ctypes.c_void_p, _P)
 _lib.ann_query_graph_destroy.restype = None
 _lib.ann_query_graph_destroy.argtypes = [ctypes.c_void_p]
+_sig("ann_stream_create", _I32, ctypes.POINTER(ctypes.c_void_p))
+_lib.ann_stream_destroy.restype = None
+_lib.ann_stream_destroy.argtypes = [ctypes.c_void_p]
 
 
 def ann_search_plan_lds(plan: ann_search_plan, n: int, dim: int) -> int:
@@ -1153,3 +1156,32 @@ def ann_query_graph_launch(graph: QueryGraph, stream=None):
 
 def ann_query_graph_destroy(graph: QueryGraph):
     graph.close()
+
+
+def ann_stream_create(device=None) -> torch.cuda.ExternalStream:
+    """A stream with a hardware queue of its own (ann_stream_create), as a
+    torch stream.  The HIP stream lives until ann_stream_destroy; nothing
+    destroys it implicitly (not at garbage collection, not at exit)."""
+    h = ctypes.c_void_p()
+    with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+        _check(_lib.ann_stream_create(ctypes.byref(h)))
+        return torch.cuda.ExternalStream(h.value)
+
+
+def ann_stream_destroy(stream: torch.cuda.ExternalStream):
+    """Destroys a stream from ann_stream_create (waits for its pending work)."""
+    _lib.ann_stream_destroy(ctypes.c_void_p(stream.cuda_stream))
+
+
+_DEDICATED: dict = {}
+
+
+def dedicated_stream(i: int, device=None) -> torch.cuda.ExternalStream:
+    """Stream i of a per-device set made by ann_stream_create on first use and
+    kept for the life of the process, so that repeated pipelines and servers
+    reuse the same hardware queues instead of asking for new ones."""
+    dv = torch.device(device if device is not None else torch.cuda.current_device())
+    key = (dv.index if dv.index is not None else torch.cuda.current_device(), int(i))
+    if key not in _DEDICATED:
+        _DEDICATED[key] = ann_stream_create(key[0])
+    return _DEDICATED[key]

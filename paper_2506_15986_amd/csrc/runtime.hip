@@ -5,6 +5,8 @@
 #include "common.h"
 #include "internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <new>
 #include <vector>
 
@@ -299,4 +301,25 @@ extern "C" void ann_query_graph_destroy(ann_query_graph *graph)
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     if (graph->graph) (void)hipGraphDestroy(graph->graph);
     delete graph;
+}
+
+extern "C" ann_status ann_stream_create(void **out)
+{
+    ANN_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    int dev = 0, cus = 0;
+    ANN_HIP(hipGetDevice(&dev));
+    ANN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (cus <= 0) return fail(ANN_EDEVICE, "device reports %d compute units", cus);
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0xFFFFFFFFu);
+    if (cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
+    hipStream_t st = nullptr;
+    ANN_HIP(hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()));
+    *out = st;
+    return ANN_OK;
+}
+
+extern "C" void ann_stream_destroy(void *stream)
+{
+    if (stream) (void)hipStreamDestroy(static_cast<hipStream_t>(stream));
 }

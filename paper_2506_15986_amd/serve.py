@@ -87,7 +87,9 @@ class _Stream:
 
     def __init__(self, server: "Server"):
         sv = server
-        self.stream = torch.cuda.Stream(device=sv.device)
+        # a hardware queue of its own, so that the slots' launches overlap
+        self.stream = ann.dedicated_stream(len(sv.streams_made), sv.device)
+        sv.streams_made.append(self)
         m = sv.launch_rows
         self.batch = ann.QueryBatch(sv.base, sv.graph, sv.medoid, sv.q[:m], sv.k[:m], sv.L[:m],
                                     sv.k_max, plan=sv.plan, model=sv.model,
@@ -143,6 +145,7 @@ class Server:
         self.hids = torch.empty((P, self.k_max), dtype=torch.int32, pin_memory=True)
         self.hdist = torch.empty((P, self.k_max), dtype=torch.float32, pin_memory=True)
         self.pool = RowPool(P)
+        self.streams_made: list = []
         self.streams = [_Stream(self) for _ in range(slots)]
         self.slot_rows = self.launch_rows
         self.queue: collections.deque[Request] = collections.deque()

@@ -141,6 +141,40 @@ def test_search_only_graph_from_the_medoid_matches_oracle():
     gx.close()
 
 
+def test_batches_side_by_side_on_streams_with_their_own_queues():
+    # two batches' graphs replayed at once on ann_stream_create streams, with
+    # capped persistent grids so that both launches are resident together;
+    # each batch's rows equal the oracle's
+    ann = _ann()
+    ix = int_index()
+    base, g, q = _dev(ix["base"]), _dev(ix["graph"]), _dev(ix["q"])
+    ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, 48)
+    plan = ann.default_plan(base.shape[0], base.shape[1], g.shape[1], 48)
+    plan = ann.make_plan(**dict(plan.as_dict(), waves_per_block=4, blocks=64,
+                                waves_per_query=1))
+    say("case: two dedicated streams, plan %s" % plan)
+    streams = [ann.ann_stream_create() for _ in range(2)]
+    batches = [ann.QueryBatch(base, g, ix["medoid"], q, 10, 48, 10, plan=plan) for _ in range(2)]
+    graphs = [bx.graph_exec(ann.ANN_STAGE_SEARCH) for bx in batches]
+    for r in range(3):
+        for bx in batches:
+            bx.ids.fill_(-7)
+        torch.cuda.synchronize()
+        for gx, st in zip(graphs, streams):
+            gx.launch(stream=st)
+        torch.cuda.synchronize()
+        for bx in batches:
+            assert (bx.ids.cpu().numpy() == ref["ids"]).all(), r
+    for gx in graphs:
+        gx.close()
+    for st in streams:
+        ann.ann_stream_destroy(st)
+    torch.cuda.synchronize()
+    say("case: the process-wide dedicated streams")
+    assert ann.dedicated_stream(0).cuda_stream == ann.dedicated_stream(0).cuda_stream
+    assert ann.dedicated_stream(0).cuda_stream != ann.dedicated_stream(1).cuda_stream
+
+
 def test_autotune_on_float_data_and_a_tuned_hub_plan():
     # grid data: FP32 distances are not exact, so plans of different gather
     # groups may order near-ties differently; each group checks against its own

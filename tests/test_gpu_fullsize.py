@@ -179,6 +179,37 @@ def test_gate_search_in_the_bench_configuration_at_1m(full):
                                                                 ref["hops"].mean()))
     assert rec >= 0.949
     gx.close()
+    say("case: the pipelined steps' configuration: two batches in flight on streams with "
+        "queues of their own, 4-wave workgroups, 14 wavefronts per compute unit, queries as given")
+    cus = torch.cuda.get_device_properties(bd.device).multi_processor_count
+    pplan = ann.make_plan(**dict(plan.as_dict(), waves_per_block=4, blocks=14 * cus // 4,
+                                 waves_per_query=1, query_order=ann.ANN_ORDER_AS_GIVEN))
+    pb = [ann.QueryBatch(bd, index.graph, index.medoid, qd, kk, LL, 10, plan=pplan,
+                         model=gm.model) for _ in range(2)]
+    ge = [bx.graph_exec(ann.ANN_STAGE_ENTRY) for bx in pb]
+    gs = [bx.graph_exec(ann.ANN_STAGE_SEARCH) for bx in pb]
+    se, ss = ann.dedicated_stream(0), [ann.dedicated_stream(1 + x) for x in range(2)]
+    ready, done = [torch.cuda.Event() for _ in range(2)], [torch.cuda.Event() for _ in range(2)]
+    for bx in pb:
+        bx.ids.fill_(-7)
+    torch.cuda.synchronize()
+    for x in range(2):
+        done[x].record(ss[x])
+    for step in range(6):
+        x = step % 2
+        se.wait_event(done[x])
+        ge[x].launch(stream=se)
+        ready[x].record(se)
+        ss[x].wait_event(ready[x])
+        gs[x].launch(stream=ss[x])
+        done[x].record(ss[x])
+    torch.cuda.synchronize()
+    for bx in pb:
+        assert (bx.ids.cpu().numpy() == ids).all()
+        assert (bx.dist.cpu().numpy().view(np.uint32) == dist.view(np.uint32)).all()
+        assert (bx.stats.cpu().numpy()[:, 2] == st[:, 2]).all()
+    for gp in ge + gs:
+        gp.close()
 
 
 # ---------------------------------------------------------------------------
