@@ -3,7 +3,8 @@
 //
 // One wavefront (64 lanes) owns one query at a time.  Its state lives in a
 // private slice of LDS:
-//   pool   two ping-pong arrays of at most pool_cap entries (key, id), kept
+//   pool   one array (merged in place) or two ping-pong arrays of at most
+//          pool_cap entries (key, id), kept
 //          sorted by (key, id); bit 31 of id marks "expanded"
 //   stage  64 entries for the candidates of the current hop
 //   vis    the visited filter: an exact bitset when the id range fits, else

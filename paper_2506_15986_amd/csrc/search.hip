@@ -7,11 +7,12 @@
 // order is kept), gathers their vectors in groups of G lanes with 16-byte
 // loads (G*16 contiguous bytes per group and instruction), reduces the FP32
 // (or FP64) squared L2 distance with lane shuffles, and merges the new keys
-// into the pool (ping-pong buffers).  For FP32 keys and pools of up to 256
-// entries every lane holds its pool entries as 64-bit words and one pass over
-// the new keys counts, per compare mask, each new key's insertion point and
-// rank and each entry's shift; otherwise insertion points come from binary
-// searches and the old entries' places from occupancy bits.  Keys are
+// into the pool.  For FP32 keys and pools of up to 256 entries every lane
+// holds its pool entries as 64-bit words and one pass over the new keys
+// counts, per compare mask, each new key's insertion point and rank and each
+// entry's shift, and the merged pool is written back in place; otherwise
+// insertion points come from binary searches, the old entries' places from
+// occupancy bits, and the merge goes to a second (ping-pong) buffer.  Keys are
 // (distance, id), so ties go to the smaller id.
 //
 // When the visited filter is a hash table that had to drop an id, a dropped

@@ -39,13 +39,22 @@ struct SearchResult {
     bool lost;
 };
 
-// LDS bytes one wavefront needs: the query vector, two pool buffers of
+// Pools merged from registers (FP32 keys, at most 256 entries) are written
+// back in place, so they need one buffer; the general merge reads one
+// buffer and writes the other.
+inline __host__ __device__ bool pool_in_place(int pool_cap, bool f64)
+{
+    return !f64 && pool_cap <= 256;
+}
+
+// LDS bytes one wavefront needs: the query vector, one or two pool buffers of
 // (key, id), the staging row of 64 (key, id) and the visited filter's words.
 inline size_t wave_lds_bytes(int pool_cap, const beam::FilterShape &f, bool f64, int dim)
 {
     size_t ks = f64 ? 8 : 4;
-    size_t b = ((size_t)dim * 4 + 15) / 16 * 16 + 2 * (size_t)pool_cap * ks + 64 * ks +
-               2 * (size_t)pool_cap * 4 + 64 * 4 + 64 + (size_t)f.words * 4;
+    size_t bufs = pool_in_place(pool_cap, f64) ? 1 : 2;
+    size_t b = ((size_t)dim * 4 + 15) / 16 * 16 + bufs * (size_t)pool_cap * ks + 64 * ks +
+               bufs * (size_t)pool_cap * 4 + 64 * 4 + 64 + (size_t)f.words * 4;
     return (b + 15) / 16 * 16;
 }
 
@@ -78,19 +87,26 @@ struct Searcher {
                           int64_t n_, const float *base, int dim, const int32_t *graph_, int R_)
     {
         const size_t ks = sizeof(K);
+        const bool one = pool_in_place(pcap, F64);
         unsigned char *p = lds;
         ql = reinterpret_cast<float4 *>(p);
         p += ((size_t)dim * 4 + 15) / 16 * 16;
         pk0 = reinterpret_cast<K *>(p);
         p += pcap * ks;
-        pk1 = reinterpret_cast<K *>(p);
-        p += pcap * ks;
+        pk1 = pk0;
+        if (!one) {
+            pk1 = reinterpret_cast<K *>(p);
+            p += pcap * ks;
+        }
         sk = reinterpret_cast<K *>(p);
         p += 64 * ks;
         pi0 = reinterpret_cast<uint32_t *>(p);
         p += pcap * 4;
-        pi1 = reinterpret_cast<uint32_t *>(p);
-        p += pcap * 4;
+        pi1 = pi0;
+        if (!one) {
+            pi1 = reinterpret_cast<uint32_t *>(p);
+            p += pcap * 4;
+        }
         si = reinterpret_cast<uint32_t *>(p);
         p += 64 * 4;
         p += 64;
@@ -211,7 +227,8 @@ struct Searcher {
     // equal to the pool entry at its insertion point is a rediscovered node:
     // it is dropped and taken back out of the counts.  Then new key l goes
     // to place pos + rank and pool entry j to j + (new keys below it), all
-    // at once, into the other pool buffer.
+    // at once, back into the same buffer (every read of the pool is done
+    // before the first write).
     template <int CM>
     __device__ __forceinline__ void merge_words(int m, int Lq, int &cursor, uint32_t &pf_id,
                                                 int &pf_nb, K nkey, uint32_t nid, SearchResult &r)
@@ -299,6 +316,9 @@ struct Searcher {
             pf_id = i0;
             pf_nb = lane < R ? graph[(size_t)i0 * R + lane] : -1;
         }
+        // the pool's reads are all done: the merged pool goes to the same
+        // buffer (keys(cur ^ 1) is keys(cur) for pools merged in place)
+        beam::wave_sync();
         K *bk = keys(cur ^ 1);
         uint32_t *bi = ids(cur ^ 1);
         const int outn = __builtin_amdgcn_readfirstlane((cnt + mv < Lq) ? cnt + mv : Lq);
@@ -329,6 +349,7 @@ struct Searcher {
                                           K nkey, uint32_t nid, SearchResult &r)
     {
         if constexpr (!F64) {
+            // the pools that pool_in_place gives one buffer
             if (pool_cap <= 64) return merge_words<1>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
             if (pool_cap <= 128) return merge_words<2>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
             if (pool_cap <= 192) return merge_words<3>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
