@@ -555,14 +555,40 @@ def main():
         splan, _ = ann.ann_autotune_search(base_d, index.graph, qm_d, em, index.medoid, k_mix,
                                            L_mix, 100, Lmax)
         log("serving plan (tuned on the mix): %s" % splan)
-        srv = serve.Server(base_d, index.graph, index.medoid, model=model, slots=4,
-                           slot_rows=4096, k_max=100, L_max=Lmax, plan=splan)
-        out = dict(mix="30% shifted queries, k 10/100", L_by_k=Lk, plan=splan.as_dict(), loads=[],
-                   theta=theta, theta_sweep=theta_rows,
-                   fallbacks=int((em == index.medoid).sum().item()))
         reps = 16
         qs = np.concatenate([qm] * reps)
         truth = np.concatenate([gt100] * reps)
+        # the launches of the 4 streams overlap, so as for the pipelined steps
+        # the tuned plan is also tried with persistent grids that leave room
+        # for the other streams' launches (four-wave workgroups, 16 / 14 / 12
+        # wavefronts per CU); the plan with the best saturated throughput on
+        # one 160,000-query run serves
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        cands = [splan]
+        wq = max(1, int(splan.waves_per_query))
+        wpb = 4 if wq == 1 else wq
+        for wpc in (16, 14, 12):
+            cands.append(ann.make_plan(**dict(splan.as_dict(), waves_per_block=wpb,
+                                              blocks=(wpc * cus) // wpb)))
+        trials = []
+        for cp in cands:
+            sv = serve.Server(base_d, index.graph, index.medoid, model=model, slots=4,
+                              slot_rows=4096, k_max=100, L_max=Lmax, plan=cp)
+            sv.serve(serve.poisson_schedule(qm, 1e12, sizes=(1, 512),
+                                            kL=((10, Lk[10]), (100, Lk[100])), seed=7))
+            r = sv.serve(serve.poisson_schedule(qs, 1e12, sizes=(1, 512),
+                                                kL=((10, Lk[10]), (100, Lk[100])), seed=7))
+            trials.append(dict(waves_per_block=int(cp.waves_per_block), blocks=int(cp.blocks),
+                               qps=r["qps"]))
+            del sv
+        splan = cands[max(range(len(cands)), key=lambda i: trials[i]["qps"])]
+        log("serving plan: %s (saturated QPS per candidate grid: %s)" %
+            (splan, [(t["blocks"], round(t["qps"])) for t in trials]))
+        srv = serve.Server(base_d, index.graph, index.medoid, model=model, slots=4,
+                           slot_rows=4096, k_max=100, L_max=Lmax, plan=splan)
+        out = dict(mix="30% shifted queries, k 10/100", L_by_k=Lk, plan=splan.as_dict(), loads=[],
+                   theta=theta, theta_sweep=theta_rows, plan_trials=trials,
+                   fallbacks=int((em == index.medoid).sum().item()))
         # capacity: every request waiting at the start (the server saturated);
         # the median of three runs
         srv.serve(serve.poisson_schedule(qm, 1e12, sizes=(1, 512),
