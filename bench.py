@@ -133,6 +133,19 @@ def recall_tie_aware(dist: np.ndarray, truth_dist: np.ndarray, k: int = 10) -> n
     return (dist[:, :k].astype(np.float64) <= lim + 1e-5 * np.maximum(lim, 1e-6)).sum(1) / float(k)
 
 
+def finite(x):
+    """The value with every non-finite float replaced by None, so that the
+    summary line is strict JSON (a medoid-fallback threshold of -inf means
+    "never falls back")."""
+    if isinstance(x, float):
+        return x if np.isfinite(x) else None
+    if isinstance(x, dict):
+        return {k: finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite(v) for v in x]
+    return x
+
+
 def serving_summary(sv):
     """The serving leg's headline figures for the summary line."""
     if not sv:
@@ -912,7 +925,7 @@ def main():
         with open(args.details, "w") as f:
             json.dump(full, f, indent=1, default=str)
         log("full record written to %s" % args.details)
-    line = json.dumps(summary, separators=(",", ":"))
+    line = json.dumps(finite(summary), separators=(",", ":"), allow_nan=False)
     sys.stderr.flush()
     print(line, flush=True)
 
