@@ -124,9 +124,12 @@ def test_kernel_names_unique_across_translation_units():
 
 
 def _lds(pool_cap, filter_words, fp64=False, dim=128):
+    # FP32 pools of up to 256 entries are merged in place (one buffer), the
+    # others in two ping-pong buffers
     ks = 8 if fp64 else 4
-    b = (dim * 4 + 15) // 16 * 16 + 2 * pool_cap * ks + 64 * ks + 2 * pool_cap * 4 + 64 * 4 + 64 + \
-        filter_words * 4
+    bufs = 1 if (not fp64 and pool_cap <= 256) else 2
+    b = (dim * 4 + 15) // 16 * 16 + bufs * pool_cap * ks + 64 * ks + bufs * pool_cap * 4 + \
+        64 * 4 + 64 + filter_words * 4
     return (b + 15) // 16 * 16
 
 
@@ -150,6 +153,10 @@ def test_plan_lds_and_filter_forms():
     # 2^25 ids with 2^10 sets: 15-bit tags still fit
     assert lds(P(), 1 << 25) == _lds(64, 2048)
     assert lds(P(fp64=1), 10_000) == _lds(64, 313, fp64=True)
+    # in place up to 256 entries, two buffers beyond
+    assert lds(P(pool_cap=256), 10_000) == _lds(256, 313)
+    assert lds(P(pool_cap=272), 10_000) == _lds(272, 313)
+    assert _lds(272, 313) - _lds(256, 313) > 16 * 8
     assert lds(P(filter=7), 10_000) == 0                                  # invalid form
 
 
