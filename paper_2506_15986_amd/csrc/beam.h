@@ -194,7 +194,8 @@ __device__ inline double group_sum(double v)
 //            multiply modulo 2^b (b = bits of n) is a bijection on [0, 2^b);
 //            its top bits pick the set and the rest is the tag, so (set, tag)
 //            names exactly one id and a tag match is never a false "seen".
-//            A full set evicts one way (the evicted id is forgotten).
+//            A set keeps its four newest tags; a fifth pushes out the
+//            oldest (the evicted id is forgotten).
 //   kId32    open-addressing table of 32-bit ids with bounded linear probing;
 //            an id that finds no free slot in the probe run is not recorded.
 // Forgetting is safe for the results (see the search kernel's header) and is
@@ -259,23 +260,18 @@ struct Visited {
         const uint32_t set = h >> tag_bits;
         const uint32_t tag = h & ((1u << tag_bits) - 1u);
         const uint32_t rep = tag * 0x00010001u;
-        uint32_t *w = t + 2 * set;
+        // a set is one 64-bit word of four 16-bit ways, newest in the low
+        // half: a new tag is shifted in and the oldest way falls out (first
+        // in, first out), so no way has to be chosen
+        unsigned long long *w = reinterpret_cast<unsigned long long *>(t) + set;
 #pragma unroll 1
         for (int it = 0; it < 8; ++it) {
-            const uint32_t w0 = __atomic_load_n(&w[0], __ATOMIC_RELAXED);
-            const uint32_t w1 = __atomic_load_n(&w[1], __ATOMIC_RELAXED);
+            const unsigned long long old = __atomic_load_n(w, __ATOMIC_RELAXED);
+            const uint32_t w0 = (uint32_t)old, w1 = (uint32_t)(old >> 32);
             if (zero_halves(w0 ^ rep) | zero_halves(w1 ^ rep)) return false;
-            // way: first empty half (an empty half holds 0xFFFF), else evict
-            // the way picked by the tag's low bits
-            const uint32_t e0 = zero_halves(~w0), e1 = zero_halves(~w1);
-            const uint32_t way = e0 ? ((e0 & 0x8000u) ? 0u : 1u)
-                                    : (e1 ? ((e1 & 0x8000u) ? 2u : 3u) : (tag & 3u));
-            const bool evict = (e0 | e1) == 0u;
-            const uint32_t old = (way & 2u) ? w1 : w0;
-            const uint32_t nw = (way & 1u) ? ((old & 0xFFFFu) | (tag << 16))
-                                           : ((old & 0xFFFF0000u) | tag);
-            if (atomicCAS(&w[way >> 1], old, nw) == old) {
-                if (evict) lost = true;
+            const unsigned long long nw = (old << 16) | tag;
+            if (atomicCAS(w, old, nw) == old) {
+                if ((uint32_t)(old >> 48) != kTagEmpty) lost = true;
                 return true;
             }
         }
