@@ -126,6 +126,10 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
         }
     }
     int cnt = 1, ndc = 1, hops = 0;
+    // the adjacency row of the old pool's next unexpanded entry, requested
+    // one step ahead; used only when that entry is the node expanded next
+    int pre_node = -1;
+    int32_t pre_nb = -1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (;;) {
@@ -136,12 +140,20 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
         if (lane == pl) P |= kExp;
         if (tr && lane == 0 && hops < a.trace_cap) tr[hops] = p;
         ++hops;
-        const int32_t nb = lane < a.s ? a.graph[(size_t)p * a.s + lane] : -1;
+        const int32_t nb = p == pre_node ? pre_nb
+                                         : (lane < a.s ? a.graph[(size_t)p * a.s + lane] : -1);
         bool fresh = false;
         if (nb >= 0 && nb < a.n_hubs) {
             const uint32_t bit = 1u << (nb & 31);
             fresh = !(atomicOr(&vis[nb >> 5], bit) & bit);
         }
+        // requested after the expanded row has been consumed, so that no
+        // wait for that row also waits for this one
+        const uint64_t un2 = un & (un - 1);
+        pre_node = un2 ? (int)((uint32_t)readlane64(P, __ffsll((unsigned long long)un2) - 1) &
+                               0xffffu)
+                       : -1;
+        if (pre_node >= 0) pre_nb = lane < a.s ? a.graph[(size_t)pre_node * a.s + lane] : -1;
         const uint64_t fb = __ballot(fresh);
         const int m = __popcll(fb);
         if (m == 0) continue;
