@@ -40,6 +40,15 @@ __device__ inline uint64_t readlane64(uint64_t v, int l)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// v with lane l replaced by the wave-uniform value x: one v_writelane_b32
+// (clang exposes no builtin for it here), its lane select in M0, since a
+// VALU instruction reads at most one SGPR on this target
+__device__ inline int writelane(int v, int x, int l)
+{
+    asm("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(x), "s"(l) : "m0");
+    return v;
+}
+
 struct HubArgs {
     const float *emb;
     int n_hubs;
@@ -65,8 +74,9 @@ __host__ __device__ inline size_t hub_wave_lds(int vis_words)
     return ((size_t)64 * 8 + 64 * 4 + (size_t)vis_words * 4 + 15) / 16 * 16;
 }
 
-// T = float4 chunks per lane of a vector (the vector's dim / 16, rounded up)
-template <int T>
+// T = float4 chunks per lane of a vector (the vector's dim / 16, rounded up);
+// FULL: the dim is exactly 16 T, so every lane's chunks are inside the vector
+template <int T, bool FULL>
 __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
 {
     extern __shared__ __align__(16) unsigned char hs_lds[];
@@ -85,8 +95,9 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int ch = gl + 4 * t;
-        q[t] = ch < chunks ? reinterpret_cast<const float4 *>(a.qemb)[(size_t)qi * chunks + ch]
-                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        q[t] = FULL || ch < chunks
+                   ? reinterpret_cast<const float4 *>(a.qemb)[(size_t)qi * chunks + ch]
+                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     // squared distance of hub `id` (valid in the four lanes of the group):
     // all of a lane's chunks are requested before any is used (a chunk past
@@ -97,7 +108,7 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int ch = gl + 4 * t;
-            x[t] = e4[(size_t)id * chunks + (ch < chunks ? ch : 0)];
+            x[t] = e4[(size_t)id * chunks + (FULL || ch < chunks ? ch : 0)];
         }
         float acc = 0.f;
 #pragma unroll
@@ -105,7 +116,7 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
             const float dx = x[t].x - q[t].x, dy = x[t].y - q[t].y, dz = x[t].z - q[t].z,
                         dw = x[t].w - q[t].w;
             const float part = dx * dx + dy * dy + dz * dz + dw * dw;
-            acc += gl + 4 * t < chunks ? part : 0.f;
+            acc += FULL || gl + 4 * t < chunks ? part : 0.f;
         }
         acc += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), kQuadSwap1,
                                                           0xf, 0xf, false));
@@ -133,7 +144,8 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (;;) {
-        const uint64_t un = __ballot(lane < cnt && !(P & kExp));
+        // lanes at or beyond cnt hold kEmpty64, whose expanded bit is set
+        const uint64_t un = __ballot(!(P & kExp));
         if (!un) break;
         const int pl = __ffsll((unsigned long long)un) - 1;
         const int p = (int)((uint32_t)readlane64(P, pl) & 0xffffu);
@@ -181,7 +193,9 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
             // merge: the pool entry in lane j goes to j + (kept keys below
             // it); a kept key to (pool entries below it) + (kept keys below
             // it).  Keys are distinct (distinct indices), so "not below" is
-            // "above".
+            // "above".  An empty lane's word (kEmpty64 with the expanded bit
+            // cleared) is above every key, so the pool entries below a key
+            // are the lanes whose word is not above it.
             const uint64_t pk = P & kKeyMask;
             int up = 0, below = 0, rank = 0;
             for (uint64_t mm = km; mm; mm &= mm - 1) {
@@ -189,8 +203,7 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
                 const uint64_t nk = readlane64(key, l);
                 const bool lt = nk < pk;
                 up += lt ? 1 : 0;
-                const int nbelow = __popcll(__ballot(lane < cnt && !lt));
-                below = lane == l ? nbelow : below;
+                below = writelane(below, __popcll(~__ballot(lt)), l);
                 rank += nk < key ? 1 : 0;
             }
             const int ncnt = cnt + nkeep < a.L ? cnt + nkeep : a.L;
@@ -216,6 +229,15 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
         for (int t = hops + lane; t < a.trace_cap; t += 64) tr[t] = -1;
 }
 
+template <int T>
+void launch_hub(const HubArgs &a, dim3 grid, size_t lds, hipStream_t st)
+{
+    if (a.dim / 4 == 4 * T)
+        hipLaunchKernelGGL((hub_search_kernel<T, true>), grid, dim3(256), lds, st, a);
+    else
+        hipLaunchKernelGGL((hub_search_kernel<T, false>), grid, dim3(256), lds, st, a);
+}
+
 }  // namespace
 
 bool hub_search_supported(int n_hubs, int dim, int s, int L)
@@ -234,11 +256,11 @@ ann_status hub_search_launch(const float *emb, int n_hubs, int dim, const int32_
     const size_t lds = 4 * hub_wave_lds(a.vis_words);
     const dim3 grid((unsigned)((nq + 3) / 4));
     const int T = (dim / 4 + 3) / 4;
-    if (T <= 1) hipLaunchKernelGGL(hub_search_kernel<1>, grid, dim3(256), lds, st, a);
-    else if (T <= 2) hipLaunchKernelGGL(hub_search_kernel<2>, grid, dim3(256), lds, st, a);
-    else if (T <= 4) hipLaunchKernelGGL(hub_search_kernel<4>, grid, dim3(256), lds, st, a);
-    else if (T <= 8) hipLaunchKernelGGL(hub_search_kernel<8>, grid, dim3(256), lds, st, a);
-    else hipLaunchKernelGGL(hub_search_kernel<16>, grid, dim3(256), lds, st, a);
+    if (T <= 1) launch_hub<1>(a, grid, lds, st);
+    else if (T <= 2) launch_hub<2>(a, grid, lds, st);
+    else if (T <= 4) launch_hub<4>(a, grid, lds, st);
+    else if (T <= 8) launch_hub<8>(a, grid, lds, st);
+    else launch_hub<16>(a, grid, lds, st);
     ANN_LAUNCHED();
     return ANN_OK;
 }
