@@ -42,10 +42,14 @@ __device__ inline uint64_t readlane64(uint64_t v, int l)
 
 // v with lane l replaced by the wave-uniform value x: one v_writelane_b32
 // (clang exposes no builtin for it here), its lane select in M0, since a
-// VALU instruction reads at most one SGPR on this target
+// VALU instruction reads at most one SGPR on this target; M0 is a reserved
+// register, so its value is kept in an SGPR of the statement's own and put back
 __device__ inline int writelane(int v, int x, int l)
 {
-    asm("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(x), "s"(l) : "m0");
+    int keep;
+    asm("s_mov_b32 %1, m0\n\ts_mov_b32 m0, %3\n\tv_writelane_b32 %0, %2, m0\n\ts_mov_b32 m0, %1"
+        : "+v"(v), "=&s"(keep)
+        : "s"(x), "s"(l));
     return v;
 }
 
@@ -105,10 +109,12 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
     // four partial sums meet through two DPP quad permutations
     auto dist = [&](int id) {
         float4 x[T];
+        // id < 2^16 and chunks <= 64: the row offset is a 24-bit product
+        const float4 *row = e4 + (size_t)__umul24((unsigned)id, (unsigned)chunks);
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int ch = gl + 4 * t;
-            x[t] = e4[(size_t)id * chunks + (FULL || ch < chunks ? ch : 0)];
+            x[t] = row[FULL || ch < chunks ? ch : 0];
         }
         float acc = 0.f;
 #pragma unroll
@@ -154,11 +160,13 @@ __global__ void __launch_bounds__(256) hub_search_kernel(HubArgs a)
         ++hops;
         const int32_t nb = p == pre_node ? pre_nb
                                          : (lane < a.s ? a.graph[(size_t)p * a.s + lane] : -1);
-        bool fresh = false;
-        if (nb >= 0 && nb < a.n_hubs) {
-            const uint32_t bit = 1u << (nb & 31);
-            fresh = !(atomicOr(&vis[nb >> 5], bit) & bit);
-        }
+        // the word's old bits come out of the branch, not a flag, so that the
+        // test below is one compare mask
+        const bool inb = nb >= 0 && nb < a.n_hubs;
+        const uint32_t bit = 1u << (nb & 31);
+        uint32_t old = bit;
+        if (inb) old = atomicOr(&vis[nb >> 5], bit);
+        const bool fresh = !(old & bit);
         // requested after the expanded row has been consumed, so that no
         // wait for that row also waits for this one
         const uint64_t un2 = un & (un - 1);
