@@ -104,14 +104,18 @@ enum { ANN_ORDER_WIDEST_FIRST = 0, ANN_ORDER_AS_GIVEN = 1 };
 /* Visited filter forms (per wavefront, in LDS).  Every form answers "seen"
  * only for ids it was given; the hash forms may forget an id, which costs a
  * repeated distance computation but never changes the results.
- *   AUTO   BITSET when n bits fit in the TAG16 table's bytes, else TAG16 when
- *          its tags fit in 15 bits, else ID32
+ *   AUTO   BITSET when n bits fit in the TAG16 table's bytes, else TAG12 when
+ *          its tags fit in 11 bits, else TAG16 when they fit in 15, else ID32
  *   BITSET one bit per id (exact); needs ceil(n/32) <= 2^visited_log2 words
  *   TAG16  4-way set-associative table of 16-bit tags, 2 bytes per slot; an
  *          invertible hash makes (set, tag) name one id; needs
  *          ceil(log2 n) - (visited_log2 - 2) <= 15
- *   ID32   linear-probing table of 32-bit ids, 4 bytes per slot */
-enum { ANN_FILTER_AUTO = 0, ANN_FILTER_BITSET = 1, ANN_FILTER_TAG16 = 2, ANN_FILTER_ID32 = 3 };
+ *   ID32   linear-probing table of 32-bit ids, 4 bytes per slot
+ *   TAG12  as TAG16 with five 12-bit ways per 64-bit set in the same bytes
+ *          (2^visited_log2 / 4 sets, 5 slots each); needs
+ *          ceil(log2 n) - (visited_log2 - 2) <= 11 */
+enum { ANN_FILTER_AUTO = 0, ANN_FILTER_BITSET = 1, ANN_FILTER_TAG16 = 2, ANN_FILTER_ID32 = 3,
+       ANN_FILTER_TAG12 = 4 };
 
 /* Fills *plan with the default plan for (n, dim, R, L_max).  host pointer. */
 ann_status ann_default_plan(int64_t n, int32_t dim, int32_t R, int32_t L_max,

@@ -23,7 +23,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 ANN_OK, ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE, ANN_ENOTSUP = 0, 1, 2, 3, 4
-ANN_FILTER_AUTO, ANN_FILTER_BITSET, ANN_FILTER_TAG16, ANN_FILTER_ID32 = 0, 1, 2, 3
+ANN_FILTER_AUTO, ANN_FILTER_BITSET, ANN_FILTER_TAG16, ANN_FILTER_ID32, ANN_FILTER_TAG12 = 0, 1, 2, 3, 4
 ANN_ORDER_WIDEST_FIRST, ANN_ORDER_AS_GIVEN = 0, 1
 OP = dict(search=1, build_graph=2, gt_knn=3, select_hubs=4, entry_select=5, make_labels=6,
           hub_features=7, train_step=8)

@@ -196,11 +196,14 @@ __device__ inline double group_sum(double v)
 //            names exactly one id and a tag match is never a false "seen".
 //            A set keeps its four newest tags; a fifth pushes out the
 //            oldest (the evicted id is forgotten).
+//   kTag12   the same hashing with five 12-bit ways per 64-bit set (tags of
+//            at most 11 bits, so the all-ones way is never a tag): 25 % more
+//            slots than kTag16 in the same bytes.
 //   kId32    open-addressing table of 32-bit ids with bounded linear probing;
 //            an id that finds no free slot in the probe run is not recorded.
 // Forgetting is safe for the results (see the search kernel's header) and is
 // reported through `lost`.
-enum FilterKind { kBitset = 1, kTag16 = 2, kId32 = 3 };
+enum FilterKind { kBitset = 1, kTag16 = 2, kId32 = 3, kTag12 = 4 };
 
 constexpr uint32_t kHashMul = 0x9E3779B1u;
 constexpr uint32_t kTagEmpty = 0xFFFFu;
@@ -209,12 +212,13 @@ constexpr uint32_t kTagEmpty = 0xFFFFu;
 // the code (and the registers) of one form only.
 template <int KIND>
 struct Visited {
-    static_assert(KIND == kBitset || KIND == kTag16 || KIND == kId32, "filter form");
+    static_assert(KIND == kBitset || KIND == kTag16 || KIND == kId32 || KIND == kTag12,
+                  "filter form");
     uint32_t *t;
     int words;          // 32-bit words to clear
-    int log2cap;        // kId32: slots; kTag16: slots (4 per set)
-    int tag_bits;       // kTag16: b - log2(sets), <= 15
-    uint32_t hmask;     // kTag16: 2^b - 1
+    int log2cap;        // kId32: slots; kTag16: slots (4 per set); kTag12: 4 x sets
+    int tag_bits;       // tag forms: b - log2(sets), <= 15 (kTag16) or <= 11 (kTag12)
+    uint32_t hmask;     // tag forms: 2^b - 1
 
     __device__ inline void clear() const
     {
@@ -233,6 +237,7 @@ struct Visited {
             return (old & bit) == 0;
         }
         if (KIND == kTag16) return insert_tag(id, lost);
+        if (KIND == kTag12) return insert_tag12(id, lost);
         const uint32_t mask = (1u << log2cap) - 1u;
         uint32_t h = (id * kHashMul) >> (32 - log2cap);
 #pragma unroll 1
@@ -278,12 +283,43 @@ struct Visited {
         lost = true;
         return true;
     }
+
+    // Five 12-bit ways in bits 0..59 of a 64-bit set word, newest lowest; a
+    // way of x is zero exactly when (x - ones) & ~x keeps its top bit (the
+    // same borrow argument as for the 16-bit halves, over five fields).  A
+    // cleared set reads all ones: every way is 0xFFF, above any 11-bit tag.
+    __device__ inline bool insert_tag12(uint32_t id, bool &lost) const
+    {
+        constexpr unsigned long long kOnes = 0x001001001001001ull;
+        constexpr unsigned long long kTops = 0x800800800800800ull;
+        constexpr unsigned long long kWays = 0x0FFFFFFFFFFFFFFFull;
+        const uint32_t h = (id * kHashMul) & hmask;
+        const uint32_t set = h >> tag_bits;
+        const unsigned long long tag = h & ((1u << tag_bits) - 1u);
+        const unsigned long long rep = tag * kOnes;
+        unsigned long long *w = reinterpret_cast<unsigned long long *>(t) + set;
+#pragma unroll 1
+        for (int it = 0; it < 8; ++it) {
+            const unsigned long long old = __atomic_load_n(w, __ATOMIC_RELAXED);
+            const unsigned long long x = old ^ rep;
+            if ((x - kOnes) & ~x & kTops) return false;
+            const unsigned long long nw = ((old << 12) | tag) & kWays;
+            if (atomicCAS(w, old, nw) == old) {
+                if (((old >> 48) & 0xFFFu) != 0xFFFu) lost = true;
+                return true;
+            }
+        }
+        lost = true;
+        return true;
+    }
 };
 
 // Filter layout for a launch: kind, table words and tag width.  kind_req 0
-// picks the bitset when it is no larger than the table, else kTag16 when the
-// tag fits in 15 bits, else kId32.  Returns false for a form that cannot hold
-// n (a bitset larger than the table, or tags wider than 15 bits).
+// picks the bitset when it is no larger than the table, else kTag12 when the
+// tag fits in 11 bits, else kTag16 when it fits in 15, else kId32.  Returns
+// false for a form that cannot hold n (a bitset larger than the table, or
+// tags wider than the form's ways allow).  Both tag forms use 2^log2cap / 4
+// sets of 64 bits.
 struct FilterShape {
     int kind, words, tag_bits;
     uint32_t hmask;
@@ -305,7 +341,9 @@ __host__ __device__ inline bool filter_shape(int kind_req, int log2cap, int64_t 
     const int tbits = b - sets_log2;
     int kind = kind_req;
     if (kind == 0)
-        kind = bitset_words <= ((int64_t)1 << log2cap) / 2 ? kBitset : (tbits <= 15 ? kTag16 : kId32);
+        kind = bitset_words <= ((int64_t)1 << log2cap) / 2
+                   ? kBitset
+                   : (tbits <= 11 ? kTag12 : (tbits <= 15 ? kTag16 : kId32));
     f.kind = kind;
     f.tag_bits = tbits;
     f.hmask = b >= 32 ? 0xFFFFFFFFu : (uint32_t)(((uint64_t)1 << b) - 1u);
@@ -313,9 +351,9 @@ __host__ __device__ inline bool filter_shape(int kind_req, int log2cap, int64_t 
         f.words = (int)bitset_words;
         return bitset_words <= ((int64_t)1 << log2cap);
     }
-    if (kind == kTag16) {
+    if (kind == kTag16 || kind == kTag12) {
         f.words = 1 << (log2cap - 1);
-        return tbits <= 15;
+        return tbits <= (kind == kTag16 ? 15 : 11);
     }
     if (kind == kId32) {
         f.words = 1 << log2cap;

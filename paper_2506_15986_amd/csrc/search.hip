@@ -188,6 +188,7 @@ ann_status launch_search(const SearchArgs &a, int blocks, int wpb, hipStream_t s
     switch (a.filter.kind) {
     case kBitset: return launch_one<G, CPL, F64, kBitset>(a, blocks, wpb, st);
     case kTag16: return launch_one<G, CPL, F64, kTag16>(a, blocks, wpb, st);
+    case kTag12: return launch_one<G, CPL, F64, kTag12>(a, blocks, wpb, st);
     case kId32: return launch_one<G, CPL, F64, kId32>(a, blocks, wpb, st);
     default: break;
     }
@@ -237,7 +238,7 @@ ann_status validate_plan(const ann_search_plan &p)
                 "plan.waves_per_block must be 1, 2 or 4");
     ANN_REQUIRE(p.blocks >= 0, "plan.blocks must be >= 0");
     ANN_REQUIRE(p.fp64 == 0 || p.fp64 == 1, "plan.fp64 must be 0 or 1");
-    ANN_REQUIRE(p.filter >= ANN_FILTER_AUTO && p.filter <= ANN_FILTER_ID32,
+    ANN_REQUIRE(p.filter >= ANN_FILTER_AUTO && p.filter <= ANN_FILTER_TAG12,
                 "plan.filter must be one of ANN_FILTER_*");
     ANN_REQUIRE(p.waves_per_query >= 0 && p.waves_per_query <= 4 && p.waves_per_query != 3,
                 "plan.waves_per_query must be 1, 2 or 4 (0 = 1)");

@@ -106,6 +106,7 @@ ann_status by_filter(const SearchArgs &a, int blocks, hipStream_t st)
     switch (a.filter.kind) {
     case kBitset: return launch_mw<CPL, kBitset, W>(a, blocks, st);
     case kTag16: return launch_mw<CPL, kTag16, W>(a, blocks, st);
+    case kTag12: return launch_mw<CPL, kTag12, W>(a, blocks, st);
     case kId32: return launch_mw<CPL, kId32, W>(a, blocks, st);
     default: break;
     }

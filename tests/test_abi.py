@@ -141,8 +141,16 @@ def test_plan_lds_and_filter_forms():
     lds = lambda p, n: ann.ann_search_plan_lds(p, n, 128)
     # 10k ids: 313 bitset words fit in the 2048-word tag table -> bitset
     assert lds(P(), 10_000) == _lds(64, 313)
-    # 1M ids: 31,250 bitset words do not -> 16-bit tags, 2 bytes per slot
+    # 1M ids: 31,250 bitset words do not -> 10-bit tags in 12-bit ways, five
+    # to a 64-bit set, in the bytes of 16-bit tags at 2 bytes per slot
     assert lds(P(), 1_000_000) == _lds(64, 2048)
+    assert lds(P(filter=ann.ANN_FILTER_TAG12), 1_000_000) == _lds(64, 2048)
+    assert lds(P(filter=ann.ANN_FILTER_TAG16), 1_000_000) == _lds(64, 2048)
+    # 12-bit ways hold tags of at most 11 bits: 2^21 ids with 2^10 sets fit,
+    # 2^22 do not (AUTO then takes 16-bit tags, same bytes)
+    assert lds(P(filter=ann.ANN_FILTER_TAG12), 1 << 21) == _lds(64, 2048)
+    assert lds(P(filter=ann.ANN_FILTER_TAG12), 1 << 22) == 0
+    assert lds(P(), 1 << 22) == _lds(64, 2048)
     assert lds(P(visited_log2=10), 1_000_000) == _lds(64, 512)
     assert lds(P(filter=ann.ANN_FILTER_ID32), 1_000_000) == _lds(64, 4096)
     assert lds(P(filter=ann.ANN_FILTER_BITSET), 1_000_000) == 0        # cannot hold 1M bits
@@ -158,6 +166,7 @@ def test_plan_lds_and_filter_forms():
     assert lds(P(pool_cap=272), 10_000) == _lds(272, 313)
     assert _lds(272, 313) - _lds(256, 313) > 16 * 8
     assert lds(P(filter=7), 10_000) == 0                                  # invalid form
+    assert lds(P(filter=5), 10_000) == 0
 
 
 def test_autotune_candidates():

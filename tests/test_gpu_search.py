@@ -118,7 +118,7 @@ def test_uneven_k_L_and_entries():
     assert np.isinf(got["dist"][ref["ids"] < 0]).all()
 
 
-@pytest.mark.parametrize("filt", ["tag16", "id32"])
+@pytest.mark.parametrize("filt", ["tag16", "tag12", "id32"])
 def test_lossy_visited_table_keeps_results_exact(filt):
     # 10k ids need 313 bitset words; 2^8 slots forces a hash table, which
     # forgets ids: results, hops and the unique count stay exact
@@ -126,7 +126,7 @@ def test_lossy_visited_table_keeps_results_exact(filt):
     ix = int_index()
     nq, L = ix["q"].shape[0], 100
     say("case: lossy visited L=%d filter=%s" % (L, filt))
-    kind = dict(tag16=ann.ANN_FILTER_TAG16, id32=ann.ANN_FILTER_ID32)[filt]
+    kind = dict(tag16=ann.ANN_FILTER_TAG16, tag12=ann.ANN_FILTER_TAG12, id32=ann.ANN_FILTER_ID32)[filt]
     plan = _plan(ix, L, visited_log2=8, filter=kind)
     got = _run(ix, None, [10] * nq, [L] * nq, plan, trace_cap=4096)
     ref = oracle.search(ix["base"], ix["graph"], ix["q"], ix["medoid"], 10, L, trace_cap=4096)
@@ -189,14 +189,14 @@ def test_group16_and_multiwave_blocks_agree():
         assert (got["stats"][:, 1] == ref["ndc"]).all(), kw
 
 
-@pytest.mark.parametrize("filt", ["bitset", "tag16", "id32"])
+@pytest.mark.parametrize("filt", ["bitset", "tag16", "tag12", "id32"])
 def test_every_filter_form_matches_oracle_exactly_when_large(filt):
     # a table big enough never to forget: ids, hops and both counts exact
     ann = _ann()
     ix = int_index()
     nq, L = ix["q"].shape[0], 64
     kind = dict(bitset=ann.ANN_FILTER_BITSET, tag16=ann.ANN_FILTER_TAG16,
-                id32=ann.ANN_FILTER_ID32)[filt]
+                tag12=ann.ANN_FILTER_TAG12, id32=ann.ANN_FILTER_ID32)[filt]
     say("case: filter=%s exact" % filt)
     plan = _plan(ix, L, visited_log2=14, filter=kind)
     got = _run(ix, None, [10] * nq, [L] * nq, plan, trace_cap=2048)
