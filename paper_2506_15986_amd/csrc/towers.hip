@@ -184,6 +184,141 @@ __global__ void hub_input_kernel(const float *base, int dim, const int32_t *hub_
     }
 }
 
+// ------------------------------------------------- fused inference forward
+// The forward of one tower for inference (no intermediates kept), one
+// wavefront per 16 rows: x * in_scale rounded to BF16, the first product
+// with bias and ReLU rounded to BF16 into LDS, the second product with bias,
+// and the per-row normalisation.  Every step is the arithmetic of the
+// training forward in the same order: the same operand rounding, the same
+// lane layout and sequence of 32-deep MFMA steps per output element (the
+// generic GEMM's), and the normalisation's sums and shuffles of
+// normalise_kernel, so the embeddings are the same bits.
+// HB = hidden / 16, DB = dout / 16; din % 8 == 0.
+struct TowerInfer {
+    const float *x;
+    const int32_t *idx;   // row i of the input is x row idx[i] (NULL: row i)
+    int rows, din;
+    float scale;
+    const uint16_t *W1b;
+    const float *b1;
+    const uint16_t *W2b;
+    const float *b2;
+    float *out;
+};
+
+template <int HB, int DB>
+__global__ void __launch_bounds__(64) tower_infer_kernel(TowerInfer a)
+{
+    constexpr int HID = 16 * HB, DOUT = 16 * DB;
+    __shared__ __align__(16) uint16_t H[16][HID + 8];
+    __shared__ float Z[16][DOUT + 1];
+    const int lane = threadIdx.x;
+    const int rl = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);
+    const int r0 = blockIdx.x * 16;
+    const int row = r0 + rl;
+    const bool live = row < a.rows;
+    const float *xr = a.x + (live ? (int64_t)(a.idx ? a.idx[row] : row) * a.din : 0);
+    v4f acc[HB];
+#pragma unroll
+    for (int b = 0; b < HB; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < a.din; k0 += 32) {
+        const int k = k0 + kq;
+        v8s av;
+        if (live && k < a.din) {
+            const float4 lo = *reinterpret_cast<const float4 *>(xr + k);
+            const float4 hi = *reinterpret_cast<const float4 *>(xr + k + 4);
+            av[0] = (short)f2bf(lo.x * a.scale);
+            av[1] = (short)f2bf(lo.y * a.scale);
+            av[2] = (short)f2bf(lo.z * a.scale);
+            av[3] = (short)f2bf(lo.w * a.scale);
+            av[4] = (short)f2bf(hi.x * a.scale);
+            av[5] = (short)f2bf(hi.y * a.scale);
+            av[6] = (short)f2bf(hi.z * a.scale);
+            av[7] = (short)f2bf(hi.w * a.scale);
+        } else {
+            av = v8s{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int b = 0; b < HB; ++b) {
+            const v8s bv = k < a.din
+                               ? *reinterpret_cast<const v8s *>(a.W1b + (size_t)(16 * b + rl) * a.din + k)
+                               : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                             __builtin_bit_cast(v8bf, bv), acc[b],
+                                                             0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < HB; ++b) {
+        const int n = 16 * b + rl;
+        const float bias = a.b1[n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float v = acc[b][i] + bias;
+            v = v > 0.f ? v : 0.f;
+            H[rq + i][n] = f2bf(v);
+        }
+    }
+    __syncthreads();
+    v4f acc2[DB];
+#pragma unroll
+    for (int b = 0; b < DB; ++b) acc2[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < HID; k0 += 32) {
+        const v8s av = *reinterpret_cast<const v8s *>(&H[rl][k0 + kq]);
+#pragma unroll
+        for (int b = 0; b < DB; ++b) {
+            const v8s bv = *reinterpret_cast<const v8s *>(a.W2b + (size_t)(16 * b + rl) * HID + k0 + kq);
+            acc2[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                              __builtin_bit_cast(v8bf, bv), acc2[b],
+                                                              0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+        const int n = 16 * b + rl;
+        const float bias = a.b2[n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Z[rq + i][n] = acc2[b][i] + bias;
+    }
+    __syncthreads();
+    // normalise_kernel's arithmetic, one row at a time
+    for (int r = 0; r < 16 && r0 + r < a.rows; ++r) {
+        float s = 0.f;
+        for (int c = lane; c < DOUT; c += 64) s += Z[r][c] * Z[r][c];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        const float nrm = sqrtf(s);
+        for (int c = lane; c < DOUT; c += 64) a.out[(int64_t)(r0 + r) * DOUT + c] = Z[r][c] / nrm;
+    }
+}
+
+template <int HB>
+bool launch_infer_d(const TowerInfer &a, int dout, hipStream_t st)
+{
+    const dim3 grid((unsigned)((a.rows + 15) / 16));
+    switch (dout) {
+    case 32: hipLaunchKernelGGL((tower_infer_kernel<HB, 2>), grid, dim3(64), 0, st, a); return true;
+    case 64: hipLaunchKernelGGL((tower_infer_kernel<HB, 4>), grid, dim3(64), 0, st, a); return true;
+    case 128: hipLaunchKernelGGL((tower_infer_kernel<HB, 8>), grid, dim3(64), 0, st, a); return true;
+    default: return false;
+    }
+}
+
+// launches the fused forward when the shapes and alignments allow it
+bool tower_infer(const ann_tower &w, const float *x, const int32_t *idx, int rows, float *out,
+                 hipStream_t st)
+{
+    if (w.din < 8 || w.din % 8 || !aligned(x, 16) || !aligned(w.W1b, 16) || !aligned(w.W2b, 16))
+        return false;
+    const TowerInfer a{x, idx, rows, w.din, w.in_scale, w.W1b, w.b1, w.W2b, w.b2, out};
+    switch (w.hidden) {
+    case 64: return launch_infer_d<4>(a, w.dout, st);
+    case 128: return launch_infer_d<8>(a, w.dout, st);
+    case 256: return launch_infer_d<16>(a, w.dout, st);
+    default: return false;
+    }
+}
+
 // one wavefront per row: e = z / |z|, keeps |z|
 __global__ void normalise_kernel(const float *z, int rows, int cols, float *e, float *nrm)
 {
@@ -555,6 +690,10 @@ size_t train_hub_ws(int bh, int P, int N, int din_q, int din_h, int hidden, int 
 ann_status tower_forward_run(const ann_tower &w, const float *x, const int32_t *idx, int rows,
                              float *out, void *ws, hipStream_t st)
 {
+    if (rows > 0 && tower_infer(w, x, idx, rows, out, st)) {
+        ANN_LAUNCHED();
+        return ANN_OK;
+    }
     Carve cv{static_cast<unsigned char *>(ws)};
     TowerBufs b = carve_tower(cv, rows, w.din, w.hidden, w.dout);
     b.e = out;
