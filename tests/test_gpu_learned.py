@@ -61,6 +61,32 @@ def test_tower_forward_matches_oracle():
     assert not unc, unc
 
 
+def test_fused_tower_forward_equals_generic_forward():
+    # inference runs both layers and the normalisation in one kernel when the
+    # input rows are 16-byte aligned; a row pointer 4 bytes off takes the
+    # generic path (input rounding, two GEMMs, normalisation).  The two must
+    # give the same bits: same roundings, same MFMA step order, same sums.
+    ix, km, hub_in, qp, hp = _setup()
+    ann = _ann()
+    xi = int_index()["q"].astype(np.float32)
+    qpi = synth.tower_init(ix["w"], [(128, 128), (64, 128)])
+    hp256 = synth.tower_init(ix["w"], [(256, hub_in.shape[1]), (128, 256)])
+    for name, params, x, scale in (("query 32-128-64", qp, ix["q"], 1.0),
+                                   ("hub 64-128-64", hp, hub_in, 1.0),
+                                   ("query 128-128-64, scaled", qpi, xi, 1.0 / 256),
+                                   ("hub 64-256-128", hp256, hub_in, 1.0)):
+        say("case: fused against generic tower forward, %s" % name)
+        t = ann.Tower(*params, in_scale=scale)
+        xa = _dev(np.ascontiguousarray(x, dtype=np.float32))
+        buf = torch.empty(xa.numel() + 1, dtype=torch.float32, device=xa.device)
+        xm = buf[1:].view(xa.shape)
+        xm.copy_(xa)
+        assert xa.data_ptr() % 16 == 0 and xm.data_ptr() % 16 == 4
+        ea, em = t.forward(xa), t.forward(xm)
+        torch.cuda.synchronize()
+        assert torch.equal(ea.view(torch.int32), em.view(torch.int32)), name
+
+
 def _rel(a, b):
     return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30)
 
