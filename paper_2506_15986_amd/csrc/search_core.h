@@ -39,12 +39,12 @@ struct SearchResult {
     bool lost;
 };
 
-// Pools merged from registers (FP32 keys, at most 256 entries) are written
+// Pools merged from registers (FP32 keys, at most 512 entries) are written
 // back in place, so they need one buffer; the general merge reads one
 // buffer and writes the other.
 inline __host__ __device__ bool pool_in_place(int pool_cap, bool f64)
 {
-    return !f64 && pool_cap <= 256;
+    return !f64 && pool_cap <= 512;
 }
 
 // LDS bytes one wavefront needs: the query vector, one or two pool buffers of
@@ -354,11 +354,15 @@ struct Searcher {
             if (pool_cap <= 128) return merge_words<2>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
             if (pool_cap <= 192) return merge_words<3>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
             if (pool_cap <= 256) return merge_words<4>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            if (pool_cap <= 320) return merge_words<5>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            if (pool_cap <= 384) return merge_words<6>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            if (pool_cap <= 448) return merge_words<7>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
+            if (pool_cap <= 512) return merge_words<8>(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
         }
         merge_search(m, Lq, cursor, pf_id, pf_nb, nkey, nid, r);
     }
 
-    // The general merge (FP64 keys, or pools past 256 entries): insertion
+    // The general merge (FP64 keys, or pools past 512 entries): insertion
     // points by binary search, ranks by a scalar loop over the new keys,
     // occupancy bits for the old entries' places.
     __device__ __forceinline__ void merge_search(int m, int Lq, int &cursor, uint32_t &pf_id,

@@ -124,10 +124,10 @@ def test_kernel_names_unique_across_translation_units():
 
 
 def _lds(pool_cap, filter_words, fp64=False, dim=128):
-    # FP32 pools of up to 256 entries are merged in place (one buffer), the
+    # FP32 pools of up to 512 entries are merged in place (one buffer), the
     # others in two ping-pong buffers
     ks = 8 if fp64 else 4
-    bufs = 1 if (not fp64 and pool_cap <= 256) else 2
+    bufs = 1 if (not fp64 and pool_cap <= 512) else 2
     b = (dim * 4 + 15) // 16 * 16 + bufs * pool_cap * ks + 64 * ks + bufs * pool_cap * 4 + \
         64 * 4 + 64 + filter_words * 4
     return (b + 15) // 16 * 16
@@ -161,10 +161,15 @@ def test_plan_lds_and_filter_forms():
     # 2^25 ids with 2^10 sets: 15-bit tags still fit
     assert lds(P(), 1 << 25) == _lds(64, 2048)
     assert lds(P(fp64=1), 10_000) == _lds(64, 313, fp64=True)
-    # in place up to 256 entries, two buffers beyond
+    # in place up to 512 entries, two buffers beyond
     assert lds(P(pool_cap=256), 10_000) == _lds(256, 313)
     assert lds(P(pool_cap=272), 10_000) == _lds(272, 313)
-    assert _lds(272, 313) - _lds(256, 313) > 16 * 8
+    assert lds(P(pool_cap=512), 10_000) == _lds(512, 313)
+    assert lds(P(pool_cap=528), 10_000) == _lds(528, 313)
+    assert _lds(528, 313) - _lds(512, 313) > 512 * 8
+    assert _lds(272, 313) - _lds(256, 313) == 16 * 8
+    # FP64 keys always take two buffers
+    assert lds(P(pool_cap=256, fp64=1), 10_000) == _lds(256, 313, fp64=True)
     assert lds(P(filter=7), 10_000) == 0                                  # invalid form
     assert lds(P(filter=5), 10_000) == 0
 
