@@ -197,7 +197,10 @@ def main():
     ap.add_argument("--queue-variants", default="3:16:48",
                     help="queues leg: t_pos:P:N triples, comma separated (t_neg stays 15)")
     ap.add_argument("--no-tune", action="store_true", help="time the default plan")
-    ap.add_argument("--pipe", type=int, default=2, help="batches in flight in the pipelined steps")
+    ap.add_argument("--pipe", type=int, default=2, help="searches in flight in the pipelined steps")
+    ap.add_argument("--pipe-buffers", type=int, default=0,
+                    help="buffer sets of the pipelined steps (0: one more than the searches in "
+                         "flight, so that a batch's entry stage runs ahead of its search)")
     ap.add_argument("--pipe-replay", action="store_true",
                     help="with --load-state, also time the pipelined steps")
     ap.add_argument("--shuffle-queries", type=int, default=0,
@@ -217,6 +220,7 @@ def main():
         sys.exit(2)
     legs = set(args.legs.split(","))
     PIPE = max(2, args.pipe)
+    NBUF = max(PIPE, args.pipe_buffers) if args.pipe_buffers else PIPE + 1
     targets = sorted(set([TARGET] + [float(x) for x in args.targets.split(",") if x]))
 
     import torch
@@ -359,12 +363,16 @@ def main():
         return out
 
     def pipelined(b, L, plan, model, rows, label):
-        """The same K steps with PIPE batches in flight: the entry stage runs
+        """The same K steps with PIPE searches in flight: the entry stage runs
         on its own stream, and the searches of consecutive batches on PIPE
-        streams (one per buffer set), so the next batch's search fills the
-        compute units that the current one's last queries leave idle.  Events
-        order each buffer's entry stage after its previous search and each
-        search after its entry stage.  With the tail filled that way, the
+        streams in turn, so the next batch's search fills the compute units
+        that the current one's last queries leave idle.  NBUF buffer sets
+        (PIPE + 1 by default) are used in turn; events order each buffer's
+        entry stage after the last search on those buffers and each search
+        after its entry stage.  With PIPE buffer sets the entry stage of a
+        batch waits for the search two batches back and then for compute
+        units beside the other stream's running search, which could hold
+        every other step back; one more set lets it run a step ahead.  With the tail filled that way, the
         searches take their queries as given (plan.query_order), which
         measured faster here than widest-expected-first.  The search plan is
         the fastest of pipe_candidates over a short pipelined run (35 steps
@@ -380,24 +388,28 @@ def main():
                                     torch.full((nq,), L, dtype=torch.int32, device=dev), k,
                                     plan=pplan, model=model,
                                     entry_ids=None if model is not None else b.entry_ids)
-                     for _ in range(PIPE)]
+                     for _ in range(NBUF)]
             pairs = [(bx.graph_exec(ann.ANN_STAGE_ENTRY) if model is not None else None,
                       bx.graph_exec(ann.ANN_STAGE_SEARCH)) for bx in extra]
-            ready = [torch.cuda.Event() for _ in range(PIPE)]
-            done = [torch.cuda.Event() for _ in range(PIPE)]
-            for x in range(PIPE):
-                done[x].record(s_s[x])
+            ready = [torch.cuda.Event() for _ in range(NBUF)]
+            done = [torch.cuda.Event() for _ in range(NBUF)]
+            for x in range(NBUF):
+                done[x].record(s_s[x % PIPE])
 
             def pstep(i):
-                x = i % PIPE
+                # buffer set i % NBUF, search stream i % PIPE: a stream runs its
+                # searches in order, so at most PIPE are in flight, and with one
+                # buffer set more than that a batch's entry stage waits only for
+                # the search before the previous one on its buffers
+                x, ss = i % NBUF, s_s[i % PIPE]
                 ge, gs = pairs[x]
                 if ge is not None:
                     s_e.wait_event(done[x])
                     ge.launch(stream=s_e)
                     ready[x].record(s_e)
-                    s_s[x].wait_event(ready[x])
-                gs.launch(stream=s_s[x])
-                done[x].record(s_s[x])
+                    ss.wait_event(ready[x])
+                gs.launch(stream=ss)
+                done[x].record(ss)
 
             for i in range(warmup):
                 pstep(i)
@@ -434,6 +446,7 @@ def main():
         res = dict(qps=round(nq * 1000.0 / ms, 1), ms_per_step=round(ms, 4), results_equal=same,
                    plan=best.as_dict(), candidates=trials)
         res["batches_in_flight"] = PIPE
+        res["buffer_sets"] = NBUF
         log("pipelined steps (%d batches in flight): %.3f ms/step -> %.0f QPS (results equal: %s)" %
             (PIPE, res["ms_per_step"], res["qps"], same))
         return res
