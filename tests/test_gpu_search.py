@@ -287,6 +287,28 @@ def test_group4_matches_oracle(d):
         assert (got["dist"] == ref["d2"].astype(np.float32)).all(), fp64
 
 
+@pytest.mark.parametrize("L", [272, 330, 420, 512])
+def test_pool_of_5_to_8_words_per_lane_matches_oracle(L):
+    # pools of 257..512 entries are merged in place from 5..8 pool words per
+    # lane (pool_cap = L rounded up to 16: 272, 336, 432, 512); integer data,
+    # so FP32 distances are exact and everything must be the oracle's bits
+    ix = int_index()
+    nq = 24
+    q = ix["q"][:nq]
+    sub = dict(ix, q=q)
+    plan = _plan(ix, L)
+    assert 256 < plan.pool_cap <= 512
+    say("case: L = %d (pool %d), k = 100" % (L, plan.pool_cap))
+    ref = oracle.search(ix["base"], ix["graph"], q, ix["medoid"], 100, L, trace_cap=1024)
+    got = _run(sub, None, [100] * nq, [L] * nq, plan, trace_cap=1024)
+    assert (got["ids"] == ref["ids"]).all()
+    assert (got["dist"] == ref["d2"].astype(np.float32)).all()
+    assert (got["stats"][:, 2] == ref["hops"]).all()
+    assert (got["trace"] == ref["trace"]).all()
+    ok = (got["stats"][:, 3] & 1) == 0
+    assert (got["stats"][ok, 0] == ref["ndc"][ok]).all()
+
+
 def test_pool_wider_than_512_matches_oracle():
     # beam widths up to the 1024-entry pool (k = 100 at 10M points needs them)
     ix = int_index()
