@@ -123,13 +123,16 @@ __global__ void __launch_bounds__(256) order_key_kernel(const float *base, int64
 
 // counting sort of the bins, largest first, in one workgroup: counts in LDS,
 // a descending exclusive scan (thread t owns places ORDER_PER_THREAD * t ...
-// of the descending bin list), then each query takes the next place of its bin
+// of the descending bin list), then each query takes the next place of its bin.
+// It also zeroes the search's work counter (it runs just before the search on
+// the same stream, so the search launch needs no reset of its own).
 __global__ void __launch_bounds__(1024) order_sort_kernel(const uint32_t *key, int nq,
-                                                          int32_t *order)
+                                                          int32_t *order, uint32_t *counter)
 {
     __shared__ uint32_t hist[ORDER_BINS];
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
+    if (t == 0) *counter = 0u;
     for (int i = t; i < ORDER_BINS; i += 1024) hist[i] = 0u;
     __syncthreads();
     for (int q = t; q < nq; q += 1024) atomicAdd(&hist[key[q]], 1u);
@@ -173,7 +176,7 @@ ann_status launch_one(const SearchArgs &a, int blocks, int wpb, hipStream_t st)
     int need = (a.nq + wpb - 1) / wpb;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
-    {
+    if (!a.order) {   // with the query-order pre-pass its sort kernel zeroed it
         ann_status rs = reset_work_counter(a.counter, st);
         if (rs != ANN_OK) return rs;
     }
@@ -314,7 +317,7 @@ ann_status search_launch(const float *base, int64_t n, int32_t dim, const int32_
         hipLaunchKernelGGL(order_key_kernel, dim3((nq + 3) / 4), dim3(256), 0, st, base, n, dim,
                            queries, nq, entry_ids, medoid, L, key);
         ANN_LAUNCHED();
-        hipLaunchKernelGGL(order_sort_kernel, dim3(1), dim3(1024), 0, st, key, nq, order);
+        hipLaunchKernelGGL(order_sort_kernel, dim3(1), dim3(1024), 0, st, key, nq, order, counter);
         ANN_LAUNCHED();
         a.order = order;
     }

@@ -91,7 +91,7 @@ ann_status launch_mw(const SearchArgs &a, int blocks, hipStream_t st)
     }
     if (blocks > a.nq) blocks = a.nq;
     if (blocks < 1) blocks = 1;
-    {
+    if (!a.order) {   // with the query-order pre-pass its sort kernel zeroed it
         ann_status rs = reset_work_counter(a.counter, st);
         if (rs != ANN_OK) return rs;
     }
